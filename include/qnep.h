@@ -1,0 +1,156 @@
+/*
+ * qnep.h -- C ABI of the MI355X (gfx950) qNEP force-evaluation library.
+ *
+ * qNEP (arXiv:2601.19034): a neuroevolution potential whose network has two
+ * outputs per atom, a site energy and a partial charge (Sec. 2.1 Eq. 1, Sec. 2.2),
+ * with long-range electrostatics on the corrected charges by Ewald summation
+ * (Sec. 2.2.1-2.2.3, Eqs. 6-10) or PPPM (Sec. 2.6, Eqs. 34-38).  One call
+ * evaluates, for one periodic structure,
+ *   E       total energy U_NEP + U_ES                       (Eqs. 2-4)
+ *   F       forces with static and dynamic-charge terms     (Sec. 2.3, Eqs. 11-23)
+ *   W       virial, W_ab = -dE/d(strain_ab)                 (Eqs. 12, 20-22)
+ *   q       screened corrected charges q' and naked q~'     (Eqs. 24, 33)
+ *   Z*      Born effective charges, periodic form           (Sec. 2.4 Eq. 28)
+ *   P       polarization sum_i q~'_i r_i                    (Eq. 26)
+ *
+ * Conventions
+ *   Units: eV, Angstrom, elementary charge.  k_e = e^2/(4 pi eps0) = 14.399645 eV*A.
+ *   Charges: q~ = s q with s = sqrt(eps_inf) (Eq. 24); the neutrality correction
+ *   q~' = q~ + (Q - sum_j q~_j)/N (Eq. 33, sign read so that sum q~' = Q); U_ES
+ *   uses q' = q~'/s, P and Z* use q~'.  The chain rule through the correction is
+ *   exact (dE/dq_i = phi_i - mean(phi)).
+ *
+ * Memory and streams
+ *   Every array argument marked "device" lives in device memory of the current
+ *   HIP device; the caller owns all of them, including the workspace.  The library
+ *   does not allocate device memory, does not free anything it did not create, and
+ *   never synchronizes the stream inside qnep_compute / qnep_backward: all work is
+ *   enqueued on the caller's stream and the outputs are valid once that stream
+ *   has reached the end of the call.  Functions are thread-compatible: one model
+ *   handle may be used from one thread at a time; concurrent calls must use
+ *   distinct workspaces.
+ *
+ * Errors
+ *   Arguments are validated on the host before any launch; a failing call returns
+ *   a negative status and enqueues nothing.  Conditions that can only be detected
+ *   on the device (a neighbour list longer than its capacity, a species index out
+ *   of range) raise bits in the workspace's status word, read by qnep_check_status.
+ *   qnep_last_error() returns a thread-local message describing the last failure.
+ */
+#ifndef QNEP_H
+#define QNEP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QNEP_OK = 0,
+    QNEP_E_INVALID_ARG = -1,  /* null pointer, bad size, singular cell, bad species count */
+    QNEP_E_UNSUPPORTED = -2,  /* hyper-parameters or mesh not compiled into this library */
+    QNEP_E_WORKSPACE = -3,    /* workspace smaller than qnep_workspace_size() */
+    QNEP_E_DEVICE = -4,       /* a HIP runtime call failed */
+    QNEP_E_INTERNAL = -5,
+    QNEP_E_CAPACITY = -6      /* a device-side capacity was exceeded (see qnep_check_status) */
+} qnep_status;
+
+/* device status bits (qnep_check_status) */
+#define QNEP_FLAG_RADIAL_OVERFLOW 1
+#define QNEP_FLAG_ANGULAR_OVERFLOW 2
+#define QNEP_FLAG_COULOMB_OVERFLOW 4
+#define QNEP_FLAG_BAD_SPECIES 8
+
+/* MLP arithmetic */
+#define QNEP_MLP_FP32 0   /* FP32 vector ALU */
+#define QNEP_MLP_BF16 1   /* BF16 inputs on the matrix cores, FP32 accumulation */
+
+/* NEP hyper-parameters (Sec. 2.1; the descriptor definitions are the published
+   NEP3/NEP4 ones the paper refers to):
+     radial   q_n  = sum_j g^R_n(r_ij),          n = 0..n_max_R
+     angular  q_nl = sum_m (sum_j g^A_n(r_ij) Yhat_lm(r_ij))^2,  n = 0..n_max_A, l = 1..l_max
+     g_n(r) = sum_k c^{t_i t_j}_{nk} f_k(r),  f_k = (T_k(2(r/rc-1)^2-1)+1)/2 * (1+cos(pi r/rc))/2
+   with k = 0..basis_R (or basis_A) and Yhat_lm real spherical harmonics normalized so that
+   sum_m Yhat_lm(u) Yhat_lm(v) = P_l(u.v).  Descriptor order: radial, then angular l-major. */
+typedef struct {
+    int32_t n_types;   /* number of species T (1..4) */
+    int32_t n_max_R, n_max_A;
+    int32_t basis_R, basis_A;
+    int32_t l_max;     /* 4 */
+    int32_t n_neu;     /* hidden units (<= 64) */
+    double rc_R, rc_A; /* cutoffs, Angstrom, rc_A <= rc_R */
+} qnep_hparams;
+
+/* electrostatics (Sec. 2.2 and 2.6) */
+typedef struct {
+    int32_t mode;           /* 1: real + reciprocal + self (Eq. 3); 2: reciprocal only (Eq. 5) */
+    int32_t method;         /* 0: direct Ewald; 1: PPPM */
+    double alpha;           /* Ewald splitting parameter, 1/Angstrom */
+    double rc_coul;         /* real-space cutoff (mode 1), Angstrom */
+    double kmax;            /* Ewald: wave vectors with |k| < kmax (Eq. 7) */
+    int32_t kmax_inclusive; /* 1: |k| <= kmax.  Ties resolved with a 1e-9 relative tolerance on k^2 */
+    int32_t mesh[3];        /* PPPM mesh along a, b, c: each a product of 2, 3, 5, at most 1024 */
+    int32_t order;          /* PPPM assignment order, 5 */
+    double q_total;         /* target total charge Q of Eq. 33 */
+} qnep_es_params;
+
+/* one periodic structure */
+typedef struct {
+    int64_t n_atoms;      /* N >= 0, N < 2^23 */
+    const float *pos;     /* device, SoA [3][N]: x[0..N), y[0..N), z[0..N), Angstrom, any image */
+    const int32_t *type;  /* device, [N], species in [0, n_types) */
+    double cell[9];       /* host, row-major, rows are the cell vectors a, b, c (right-handed) */
+} qnep_system;
+
+/* outputs; any pointer may be NULL to skip that output (all device) */
+typedef struct {
+    double *energy;        /* [1] E */
+    float *forces;         /* SoA [3][N] */
+    double *virial;        /* [9] W[a][b] */
+    float *charges;        /* [N] screened corrected charges q' (enter U_ES) */
+    float *charges_naked;  /* [N] naked corrected charges q~' = s q' (enter P, Z*) */
+    float *bec;            /* [9][N]: Z_i[a][b] stored at bec[(3a+b)*N + i] */
+    double *polarization;  /* [3] */
+    double *energy_terms;  /* [8]: U_NEP, U_r, U_k, U_s, U_bg, sum q_raw, mean phi, number of k vectors */
+} qnep_outputs;
+
+/* number of entries of the flat FP32 parameter vector theta, laid out as
+     cR[ti][tj][n][k], cA[ti][tj][n][k],
+     per species t: W0[mu][nu] (n_neu x N_des), b0[mu], w1E[mu], w1q[mu], b1q,
+     then b1E (shared output bias of Eq. 1) and s = sqrt(eps_inf) (Eq. 24).
+   Returns -1 for invalid hyper-parameters. */
+int64_t qnep_param_count(const qnep_hparams *hp);
+
+/* creates a host-side model handle (hyper-parameters, MLP precision, plans).
+   mlp_precision: QNEP_MLP_FP32 or QNEP_MLP_BF16. */
+qnep_status qnep_model_create(const qnep_hparams *hp, int32_t mlp_precision, void **model);
+qnep_status qnep_model_destroy(void *model);
+
+/* neighbour-list capacity = factor * (density * 4/3 pi rc^3) + 32 entries per atom
+   (default factor 1.6).  Overflow is reported by qnep_check_status. */
+qnep_status qnep_model_set_capacity_factor(void *model, double factor);
+
+/* bytes of device workspace qnep_compute needs for this structure size, cell and
+   electrostatics setup (no device work). */
+qnep_status qnep_workspace_size(const void *model, const qnep_es_params *es, const qnep_system *sys,
+                                size_t *bytes);
+
+/* full evaluation (E, F, W, q, Z*, P) of one structure.
+   theta: device FP32 [qnep_param_count].  ws: device, ws_bytes >= qnep_workspace_size.
+   stream: a hipStream_t (NULL = default stream).  Asynchronous: see the header notes. */
+qnep_status qnep_compute(void *model, const float *theta, const qnep_es_params *es, const qnep_system *sys,
+                         const qnep_outputs *out, void *ws, size_t ws_bytes, void *stream);
+
+/* synchronizes `stream` and returns the device status bits of the last call that
+   used this workspace (0 = no device-side condition). */
+qnep_status qnep_check_status(const void *ws, void *stream, int32_t *flags);
+
+const char *qnep_status_string(qnep_status s);
+const char *qnep_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QNEP_H */

@@ -1,0 +1,102 @@
+"""Python front end of libqnep: device memory and streams come from PyTorch, every
+computation runs in the library's HIP kernels.
+
+    model = QNEP(hp, precision="fp32")
+    out = model.compute(pos, types, cell, theta, es)   # dict of device tensors
+"""
+from __future__ import annotations
+
+from typing import Dict, Optional
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+ALL_OUTPUTS = ("energy", "forces", "virial", "charges", "charges_naked", "bec", "polarization", "energy_terms")
+
+
+def _require_gpu():
+    if not torch.cuda.is_available():
+        raise RuntimeError("qnep needs a ROCm GPU: no device is visible")
+
+
+class QNEP:
+    """A model handle (hyper-parameters and MLP precision) plus a cached workspace."""
+
+    def __init__(self, hp, precision: str = "fp32", capacity_factor: Optional[float] = None):
+        B.load()
+        self.hp = hp
+        self.precision = precision
+        prec = {"fp32": B.QNEP_MLP_FP32, "bf16": B.QNEP_MLP_BF16}[precision]
+        self.handle = B.qnep_model_create(hp, prec)
+        if capacity_factor is not None:
+            B.qnep_model_set_capacity_factor(self.handle, capacity_factor)
+        self._ws: Optional[torch.Tensor] = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            try:
+                B.qnep_model_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    @property
+    def n_theta(self) -> int:
+        return B.qnep_param_count(self.hp)
+
+    def workspace_bytes(self, es, n_atoms: int, cell) -> int:
+        sysm = B.make_system(n_atoms, 0, 0, np.asarray(cell, dtype=np.float64))
+        return B.qnep_workspace_size(self.handle, B.make_es(es), sysm)
+
+    def workspace(self, nbytes: int, device) -> torch.Tensor:
+        if self._ws is None or self._ws.numel() < nbytes or self._ws.device != device:
+            self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        return self._ws
+
+    def compute(self, pos: torch.Tensor, types: torch.Tensor, cell, theta: torch.Tensor, es,
+                outputs=ALL_OUTPUTS, out: Optional[Dict[str, torch.Tensor]] = None,
+                stream: Optional[torch.cuda.Stream] = None) -> Dict[str, torch.Tensor]:
+        """pos: float32 device tensor [3, N] (SoA); types: int32 [N]; cell: (3, 3) rows a, b, c;
+        theta: float32 device [n_theta].  Returns device tensors (energy, virial, polarization in
+        float64; forces [3, N]; bec [9, N]; charges [N]) enqueued on ``stream``."""
+        _require_gpu()
+        assert pos.dtype == torch.float32 and pos.is_cuda and pos.dim() == 2 and pos.shape[0] == 3
+        assert pos.is_contiguous() and types.dtype == torch.int32 and types.is_contiguous()
+        assert theta.dtype == torch.float32 and theta.is_contiguous() and theta.numel() == self.n_theta
+        n = pos.shape[1]
+        dev = pos.device
+        cell = np.asarray(cell, dtype=np.float64)
+        es_c = B.make_es(es)
+        sysm = B.make_system(n, pos.data_ptr(), types.data_ptr(), cell)
+        nbytes = B.qnep_workspace_size(self.handle, es_c, sysm)
+        ws = self.workspace(nbytes, dev)
+        if out is None:
+            out = {}
+            shapes = {"energy": ((1,), torch.float64), "forces": ((3, n), torch.float32),
+                      "virial": ((9,), torch.float64), "charges": ((n,), torch.float32),
+                      "charges_naked": ((n,), torch.float32), "bec": ((9, n), torch.float32),
+                      "polarization": ((3,), torch.float64), "energy_terms": ((8,), torch.float64)}
+            for k in outputs:
+                shp, dt = shapes[k]
+                out[k] = torch.empty(shp, dtype=dt, device=dev)
+        ptr = {k: (v.data_ptr() if v is not None else 0) for k, v in out.items()}
+        outs = B.qnep_outputs(*[ptr.get(k, 0) or None for k in ALL_OUTPUTS])
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        B.qnep_compute(self.handle, theta.data_ptr(), es_c, sysm, outs, ws.data_ptr(), ws.numel(), s.cuda_stream)
+        self._last_stream = s
+        return out
+
+    def check_status(self) -> int:
+        """Synchronizes the last stream and returns the device status bits (0 = fine)."""
+        return B.qnep_check_status(self._ws.data_ptr(), self._last_stream.cuda_stream)
+
+
+def to_device_inputs(system, theta: np.ndarray, device="cuda"):
+    """Seeded host arrays -> the device tensors ``QNEP.compute`` takes."""
+    pos = torch.from_numpy(system.pos_f32_soa()).to(device)
+    types = torch.from_numpy(system.types.astype(np.int32)).to(device)
+    th = torch.from_numpy(np.asarray(theta, dtype=np.float32)).to(device)
+    return pos, types, th

@@ -1,0 +1,142 @@
+"""ctypes binding of libqnep.so: argument marshalling only, one Python function per
+C entry point of include/qnep.h (same names).  Every step of the computation runs
+in the library's HIP kernels; there is no Python or CPU fallback."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch  # loads the HIP runtime that libqnep.so links against
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqnep.so")
+
+QNEP_OK = 0
+QNEP_MLP_FP32 = 0
+QNEP_MLP_BF16 = 1
+FLAG_RADIAL_OVERFLOW = 1
+FLAG_ANGULAR_OVERFLOW = 2
+FLAG_COULOMB_OVERFLOW = 4
+FLAG_BAD_SPECIES = 8
+
+
+class qnep_hparams(C.Structure):
+    _fields_ = [("n_types", C.c_int32), ("n_max_R", C.c_int32), ("n_max_A", C.c_int32), ("basis_R", C.c_int32),
+                ("basis_A", C.c_int32), ("l_max", C.c_int32), ("n_neu", C.c_int32), ("rc_R", C.c_double),
+                ("rc_A", C.c_double)]
+
+
+class qnep_es_params(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("method", C.c_int32), ("alpha", C.c_double), ("rc_coul", C.c_double),
+                ("kmax", C.c_double), ("kmax_inclusive", C.c_int32), ("mesh", C.c_int32 * 3), ("order", C.c_int32),
+                ("q_total", C.c_double)]
+
+
+class qnep_system(C.Structure):
+    _fields_ = [("n_atoms", C.c_int64), ("pos", C.c_void_p), ("type", C.c_void_p), ("cell", C.c_double * 9)]
+
+
+class qnep_outputs(C.Structure):
+    _fields_ = [("energy", C.c_void_p), ("forces", C.c_void_p), ("virial", C.c_void_p), ("charges", C.c_void_p),
+                ("charges_naked", C.c_void_p), ("bec", C.c_void_p), ("polarization", C.c_void_p),
+                ("energy_terms", C.c_void_p)]
+
+
+class QnepError(RuntimeError):
+    pass
+
+
+EXPORTED = ["qnep_param_count", "qnep_model_create", "qnep_model_destroy", "qnep_model_set_capacity_factor",
+            "qnep_workspace_size", "qnep_compute", "qnep_check_status", "qnep_status_string", "qnep_last_error"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads the library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2601_19034_amd.build`")
+    L = C.CDLL(path)
+    L.qnep_param_count.restype = C.c_int64
+    L.qnep_param_count.argtypes = [C.POINTER(qnep_hparams)]
+    L.qnep_model_create.restype = C.c_int
+    L.qnep_model_create.argtypes = [C.POINTER(qnep_hparams), C.c_int32, C.POINTER(C.c_void_p)]
+    L.qnep_model_destroy.restype = C.c_int
+    L.qnep_model_destroy.argtypes = [C.c_void_p]
+    L.qnep_model_set_capacity_factor.restype = C.c_int
+    L.qnep_model_set_capacity_factor.argtypes = [C.c_void_p, C.c_double]
+    L.qnep_workspace_size.restype = C.c_int
+    L.qnep_workspace_size.argtypes = [C.c_void_p, C.POINTER(qnep_es_params), C.POINTER(qnep_system),
+                                      C.POINTER(C.c_size_t)]
+    L.qnep_compute.restype = C.c_int
+    L.qnep_compute.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(qnep_es_params), C.POINTER(qnep_system),
+                               C.POINTER(qnep_outputs), C.c_void_p, C.c_size_t, C.c_void_p]
+    L.qnep_check_status.restype = C.c_int
+    L.qnep_check_status.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]
+    L.qnep_status_string.restype = C.c_char_p
+    L.qnep_status_string.argtypes = [C.c_int]
+    L.qnep_last_error.restype = C.c_char_p
+    L.qnep_last_error.argtypes = []
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != QNEP_OK:
+        L = load()
+        raise QnepError(f"{L.qnep_status_string(status).decode()} ({status}): {L.qnep_last_error().decode()}")
+
+
+def make_hparams(hp) -> qnep_hparams:
+    return qnep_hparams(hp.n_types, hp.n_max_R, hp.n_max_A, hp.basis_R, hp.basis_A, hp.l_max, hp.n_neu,
+                        float(hp.rc_R), float(hp.rc_A))
+
+
+def make_es(es) -> qnep_es_params:
+    mesh = (C.c_int32 * 3)(*[int(m) for m in es.mesh])
+    return qnep_es_params(int(es.mode), int(es.method), float(es.alpha), float(es.rc_coul), float(es.kmax),
+                          int(es.kmax_inclusive), mesh, int(es.order), float(es.q_total))
+
+
+def make_system(n: int, pos_ptr: int, type_ptr: int, cell) -> qnep_system:
+    c = (C.c_double * 9)(*[float(v) for v in list(cell.reshape(-1))])
+    return qnep_system(int(n), C.c_void_p(pos_ptr), C.c_void_p(type_ptr), c)
+
+
+def qnep_param_count(hp) -> int:
+    return int(load().qnep_param_count(C.byref(make_hparams(hp))))
+
+
+def qnep_model_create(hp, precision: int) -> int:
+    h = C.c_void_p()
+    _check(load().qnep_model_create(C.byref(make_hparams(hp)), precision, C.byref(h)))
+    return h.value
+
+
+def qnep_model_destroy(model: int):
+    _check(load().qnep_model_destroy(C.c_void_p(model)))
+
+
+def qnep_model_set_capacity_factor(model: int, factor: float):
+    _check(load().qnep_model_set_capacity_factor(C.c_void_p(model), float(factor)))
+
+
+def qnep_workspace_size(model: int, es: qnep_es_params, sysm: qnep_system) -> int:
+    n = C.c_size_t()
+    _check(load().qnep_workspace_size(C.c_void_p(model), C.byref(es), C.byref(sysm), C.byref(n)))
+    return int(n.value)
+
+
+def qnep_compute(model: int, theta_ptr: int, es: qnep_es_params, sysm: qnep_system, outs: qnep_outputs,
+                 ws_ptr: int, ws_bytes: int, stream: int):
+    _check(load().qnep_compute(C.c_void_p(model), C.c_void_p(theta_ptr), C.byref(es), C.byref(sysm),
+                               C.byref(outs), C.c_void_p(ws_ptr), ws_bytes, C.c_void_p(stream)))
+
+
+def qnep_check_status(ws_ptr: int, stream: int) -> int:
+    f = C.c_int32()
+    _check(load().qnep_check_status(C.c_void_p(ws_ptr), C.c_void_p(stream), C.byref(f)))
+    return int(f.value)

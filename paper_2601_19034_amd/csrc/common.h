@@ -1,0 +1,104 @@
+// Internal definitions shared by the HIP translation units of libqnep.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qnep {
+
+constexpr double KE = 14.399645;      // e^2 / (4 pi eps0) in eV * Angstrom
+constexpr double PI_D = 3.14159265358979323846;
+constexpr int LM = 24;                // real harmonics (l, m) for l = 1..4
+constexpr int MAX_T = 4;              // species compiled in
+constexpr int MAX_NEU = 64;           // hidden units
+constexpr int RED_THREADS = 256;      // threads of every block that writes FP64 partials
+
+// Cell passed by value to kernels: rows of h are the cell vectors a, b, c.
+struct Cell {
+    double h[9];
+    double hinv[9];
+};
+
+// A neighbour entry packs the atom index (sorted order) and the periodic image
+// n in [-3, 3]^3 of the neighbour:  j | (n1+3) << 23 | (n2+3) << 26 | (n3+3) << 29.
+constexpr uint32_t IDX_BITS = 23;
+constexpr uint32_t IDX_MASK = (1u << IDX_BITS) - 1u;
+
+__host__ __device__ inline uint32_t nb_encode(int j, int n1, int n2, int n3) {
+    return (uint32_t)j | ((uint32_t)(n1 + 3) << 23) | ((uint32_t)(n2 + 3) << 26) | ((uint32_t)(n3 + 3) << 29);
+}
+__device__ inline int nb_index(uint32_t e) { return (int)(e & IDX_MASK); }
+__device__ inline void nb_image(uint32_t e, int &n1, int &n2, int &n3) {
+    n1 = (int)((e >> 23) & 7u) - 3;
+    n2 = (int)((e >> 26) & 7u) - 3;
+    n3 = (int)((e >> 29) & 7u) - 3;
+}
+// the entry that atom j holds for atom i when e = (j, n) is in i's list: (i, -n)
+__device__ inline uint32_t nb_reverse(uint32_t e, int i) {
+    uint32_t c1 = (e >> 23) & 7u, c2 = (e >> 26) & 7u, c3 = (e >> 29) & 7u;
+    return (uint32_t)i | ((6u - c1) << 23) | ((6u - c2) << 26) | ((6u - c3) << 29);
+}
+
+// Displacement r_j + n.h - r_i formed in FP64 from the FP32 coordinates and
+// rounded once to FP32.  The difference of two FP32 numbers is exact in FP64 and
+// IEEE rounding is odd-symmetric, so the (j,i,-n) displacement is the exact
+// negation of the (i,j,n) one.
+__device__ inline float3 displacement(const float *__restrict__ x, const float *__restrict__ y,
+                                      const float *__restrict__ z, int i, uint32_t e, const Cell &c) {
+    int j = nb_index(e), n1, n2, n3;
+    nb_image(e, n1, n2, n3);
+    double sx = n1 * c.h[0] + n2 * c.h[3] + n3 * c.h[6];
+    double sy = n1 * c.h[1] + n2 * c.h[4] + n3 * c.h[7];
+    double sz = n1 * c.h[2] + n2 * c.h[5] + n3 * c.h[8];
+    double dx = ((double)x[j] - (double)x[i]) + sx;
+    double dy = ((double)y[j] - (double)y[i]) + sy;
+    double dz = ((double)z[j] - (double)z[i]) + sz;
+    return make_float3((float)dx, (float)dy, (float)dz);
+}
+
+// ---------------------------------------------------------------- reductions
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+// Sums NV per-thread FP64 values over a block of RED_THREADS threads and writes
+// them to partials[blockIdx.x * NV + k].  The final sum over blocks is done in a
+// fixed order by reduce_partials, so results are run-to-run deterministic.
+template <int NV>
+__device__ inline void block_partials(double (&v)[NV], double *__restrict__ partials) {
+    __shared__ double red[RED_THREADS / 64][NV];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double s = wave_sum(v[k]);
+        if (lane == 0) red[wid][k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < RED_THREADS / 64; ++w) s += red[w][threadIdx.x];
+        partials[(size_t)blockIdx.x * NV + threadIdx.x] = s;
+    }
+}
+
+// ---------------------------------------------------------------- scalar slots
+// Global FP64 scalars kept in the workspace (indices into Scalars::v).
+enum ScalarSlot : int {
+    S_UNEP = 0,            // sum_i U_i               } written together
+    S_SUMQ = 1,            // sum_i q_raw             }
+    S_DELTA = 2,           // shift delta with q'_i = q_i + delta
+    S_UREAL = 3,           // real-space energy       } written together
+    S_QSQ = 4,             // sum_i q'^2              }
+    S_WREAL = 5,           // 9: real-space virial    }
+    S_UK = 14,             // reciprocal energy       } written together
+    S_WK = 15,             // 9: reciprocal virial    }
+    S_SUMPHI = 24,         // sum_i phi_i
+    S_PHIBAR = 25,         // mean phi
+    S_WNEP = 26,           // 9: many-body virial from the partial forces
+    S_POL = 35,            // 3: polarization
+    S_COUNT = 38
+};
+
+}  // namespace qnep

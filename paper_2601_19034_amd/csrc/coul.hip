@@ -1,0 +1,339 @@
+// Electrostatics on the corrected screened charges q' = q + delta:
+//  * real space (mode 1, Sec. 2.2.1 Eq. 6; static pair force Eq. 15): per-atom
+//    potential phi^r_i = k_e sum_j q'_j erfc(alpha r)/r, static force and virial;
+//  * direct Ewald reciprocal part (Sec. 2.2.2 Eqs. 7-9, Sec. 2.3.2 Eqs. 18, 21, 22)
+//    over the half set of wave vectors (S(-k) = S(k)*), with phases k.r = 2 pi n.s
+//    formed in FP64 turns and reduced to [-1/2, 1/2] before the FP32 sin/cos;
+//  * self and background terms (Sec. 2.2.3 Eq. 10) and the mean potential used by
+//    the chain rule through the neutrality correction.
+#include "plan.h"
+
+namespace qnep {
+
+// ---------------------------------------------------------------- real space
+__global__ __launch_bounds__(256) void k_real_space(int N, const float *__restrict__ xs,
+                                                    const float *__restrict__ ys, const float *__restrict__ zs,
+                                                    Cell c, const uint32_t *__restrict__ listC,
+                                                    const int *__restrict__ cntC, const float *__restrict__ qraw,
+                                                    const double *__restrict__ scalars, float alpha,
+                                                    float *__restrict__ phi, float *__restrict__ Fst,
+                                                    double *__restrict__ partials) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double red[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (i < N) {
+        const float delta = (float)scalars[S_DELTA];
+        const float qi = qraw[i] + delta;
+        const float c2 = 2.0f * alpha * 0.5641895835477563f;  // 2 alpha / sqrt(pi)
+        float ph = 0.f, bx = 0.f, by = 0.f, bz = 0.f;
+        float wxx = 0.f, wyy = 0.f, wzz = 0.f, wxy = 0.f, wxz = 0.f, wyz = 0.f;
+        const int n = cntC[i];
+        for (int s = 0; s < n; ++s) {
+            uint32_t e = listC[(size_t)s * N + i];
+            float3 d = displacement(xs, ys, zs, i, e, c);
+            float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
+            float ir = rsqrtf(r2);
+            float r = r2 * ir;
+            float qj = qraw[nb_index(e)] + delta;
+            float ar = alpha * r;
+            float ec = erfcf(ar);
+            float ex = __expf(-ar * ar);
+            ph = fmaf(qj, ec * ir, ph);
+            float B = qj * (ec * ir + c2 * ex) * ir * ir;  // q_j [erfc/r + 2a e/sqrt(pi)] / r^2
+            bx = fmaf(B, d.x, bx);
+            by = fmaf(B, d.y, by);
+            bz = fmaf(B, d.z, bz);
+            wxx = fmaf(B, d.x * d.x, wxx);
+            wyy = fmaf(B, d.y * d.y, wyy);
+            wzz = fmaf(B, d.z * d.z, wzz);
+            wxy = fmaf(B, d.x * d.y, wxy);
+            wxz = fmaf(B, d.x * d.z, wxz);
+            wyz = fmaf(B, d.y * d.z, wyz);
+        }
+        const float ke = (float)KE;
+        phi[i] = ke * ph;
+        Fst[i] = -ke * qi * bx;
+        Fst[(size_t)N + i] = -ke * qi * by;
+        Fst[(size_t)2 * N + i] = -ke * qi * bz;
+        red[0] = 0.5 * (double)qi * (double)(ke * ph);
+        red[1] = (double)qi * (double)qi;
+        const double hw = 0.5 * KE * (double)qi;
+        red[2] = hw * wxx; red[3] = hw * wxy; red[4] = hw * wxz;
+        red[5] = hw * wxy; red[6] = hw * wyy; red[7] = hw * wyz;
+        red[8] = hw * wxz; red[9] = hw * wyz; red[10] = hw * wzz;
+    }
+    block_partials<11>(red, partials);
+}
+
+hipError_t launch_real_space(const Plan &p) {
+    const int G = (p.N + 255) / 256;
+    if (p.mode != 1) {
+        hipError_t e = fill_zero(p.phi, sizeof(float) * (size_t)p.N, p.stream);
+        if (e != hipSuccess) return e;
+        return fill_zero(p.Fst, sizeof(float) * 3 * (size_t)p.N, p.stream);
+    }
+    hipLaunchKernelGGL(k_real_space, dim3(G), dim3(256), 0, p.stream, p.N, p.xs, p.ys, p.zs, p.cell, p.listC,
+                       p.cntC, p.qraw, p.scalars, (float)p.alpha, p.phi, p.Fst, p.partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return reduce_partials(p, G, 11, S_UREAL, false);  // S_UREAL, S_QSQ, S_WREAL[9]
+}
+
+// ---------------------------------------------------------------- Ewald
+// Builds the half set {n : n3 > 0, or n3 = 0 and n2 > 0, or n3 = n2 = 0 and n1 > 0}
+// with |k| within kmax, k = 2 pi h^{-1} n, in box order (deterministic).  One block.
+__global__ void k_kvectors(Cell c, int M0, int M1, int M2, double kmax2, int inclusive, double alpha,
+                           double vol, int64_t cap, float4 *__restrict__ kv, int4 *__restrict__ kn,
+                           int *__restrict__ kcount) {
+    __shared__ int scan[1024];
+    __shared__ int base;
+    if (threadIdx.x == 0) base = 0;
+    __syncthreads();
+    const int n0 = 2 * M0 + 1, n1w = 2 * M1 + 1;
+    const int64_t total = (int64_t)n0 * n1w * (M2 + 1);
+    for (int64_t b = 0; b < total; b += 1024) {
+        int64_t idx = b + threadIdx.x;
+        int keep = 0;
+        int a0 = 0, a1 = 0, a2 = 0;
+        double kx = 0, ky = 0, kz = 0, k2 = 0;
+        if (idx < total) {
+            a2 = (int)(idx / ((int64_t)n0 * n1w));
+            int rem = (int)(idx % ((int64_t)n0 * n1w));
+            a1 = rem / n0 - M1;
+            a0 = rem % n0 - M0;
+            bool half = a2 > 0 || (a2 == 0 && (a1 > 0 || (a1 == 0 && a0 > 0)));
+            if (half) {
+                kx = 2.0 * PI_D * (c.hinv[0] * a0 + c.hinv[1] * a1 + c.hinv[2] * a2);
+                ky = 2.0 * PI_D * (c.hinv[3] * a0 + c.hinv[4] * a1 + c.hinv[5] * a2);
+                kz = 2.0 * PI_D * (c.hinv[6] * a0 + c.hinv[7] * a1 + c.hinv[8] * a2);
+                k2 = kx * kx + ky * ky + kz * kz;
+                keep = inclusive ? (k2 <= kmax2 * (1.0 + 1e-9)) : (k2 < kmax2 * (1.0 - 1e-9));
+            }
+        }
+        scan[threadIdx.x] = keep;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            int t = threadIdx.x >= (unsigned)o ? scan[threadIdx.x - o] : 0;
+            __syncthreads();
+            scan[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (keep) {
+            int64_t pos = base + scan[threadIdx.x] - 1;
+            if (pos < cap) {
+                double G = 2.0 * PI_D / vol * exp(-k2 / (4.0 * alpha * alpha)) / k2;
+                kv[pos] = make_float4((float)kx, (float)ky, (float)kz, (float)G);
+                kn[pos] = make_int4(a0, a1, a2, 0);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 1023) base += scan[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *kcount = base < cap ? base : (int)cap;
+}
+
+// fractional coordinates wrapped to [0, 1) in FP64
+__device__ inline void frac_coords(double x, double y, double z, const Cell &c, double &s0, double &s1,
+                                   double &s2) {
+    s0 = x * c.hinv[0] + y * c.hinv[3] + z * c.hinv[6];
+    s1 = x * c.hinv[1] + y * c.hinv[4] + z * c.hinv[7];
+    s2 = x * c.hinv[2] + y * c.hinv[5] + z * c.hinv[8];
+    s0 -= floor(s0);
+    s1 -= floor(s1);
+    s2 -= floor(s2);
+}
+
+// cos and sin of 2 pi n.s
+__device__ inline void phase_cs(int n0, int n1, int n2, double s0, double s1, double s2, float &cs, float &sn) {
+    double t = (double)n0 * s0 + (double)n1 * s1 + (double)n2 * s2;
+    t -= rint(t);
+    sincospif(2.0f * (float)t, &sn, &cs);
+}
+
+constexpr int EW_CHUNK = 512;
+
+// partial structure factors: block (kb, chunk); each thread owns one wave vector
+__global__ __launch_bounds__(256) void k_structure_factor(int N, const float *__restrict__ xs,
+                                                          const float *__restrict__ ys,
+                                                          const float *__restrict__ zs, Cell c,
+                                                          const float *__restrict__ qraw,
+                                                          const double *__restrict__ scalars,
+                                                          const int4 *__restrict__ kn,
+                                                          const int *__restrict__ kcount, int64_t cap,
+                                                          float2 *__restrict__ Spart) {
+    __shared__ double sx[256], sy[256], sz[256];
+    __shared__ float sq[256];
+    const int nk = *kcount;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int a0 = blockIdx.y * EW_CHUNK, a1 = min(N, a0 + EW_CHUNK);
+    const float delta = (float)scalars[S_DELTA];
+    int4 n = k < nk ? kn[k] : make_int4(0, 0, 0, 0);
+    float re = 0.f, im = 0.f;
+    for (int t0 = a0; t0 < a1; t0 += 256) {
+        int a = t0 + threadIdx.x;
+        if (a < a1) {
+            double s0, s1, s2;
+            frac_coords(xs[a], ys[a], zs[a], c, s0, s1, s2);
+            sx[threadIdx.x] = s0;
+            sy[threadIdx.x] = s1;
+            sz[threadIdx.x] = s2;
+            sq[threadIdx.x] = qraw[a] + delta;
+        }
+        __syncthreads();
+        const int m = min(256, a1 - t0);
+        if (k < nk) {
+            for (int u = 0; u < m; ++u) {
+                float cs, sn;
+                phase_cs(n.x, n.y, n.z, sx[u], sy[u], sz[u], cs, sn);
+                re = fmaf(sq[u], cs, re);
+                im = fmaf(-sq[u], sn, im);
+            }
+        }
+        __syncthreads();
+    }
+    if (k < nk) Spart[(size_t)blockIdx.y * cap + k] = make_float2(re, im);
+}
+
+// S(k) = sum over chunks (FP64); energy 2 k_e G |S|^2 and virial 2 k_e G |S|^2 B(k)
+__global__ __launch_bounds__(256) void k_structure_reduce(int nchunks, const float2 *__restrict__ Spart,
+                                                          const float4 *__restrict__ kv,
+                                                          const int *__restrict__ kcount, int64_t cap,
+                                                          double alpha, float2 *__restrict__ Sk,
+                                                          double *__restrict__ partials) {
+    const int nk = *kcount;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    double red[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (k < nk) {
+        double re = 0.0, im = 0.0;
+        for (int ch = 0; ch < nchunks; ++ch) {
+            float2 v = Spart[(size_t)ch * cap + k];
+            re += v.x;
+            im += v.y;
+        }
+        Sk[k] = make_float2((float)re, (float)im);
+        float4 q = kv[k];
+        double kx = q.x, ky = q.y, kz = q.z, G = q.w;
+        double k2 = kx * kx + ky * ky + kz * kz;
+        double e = 2.0 * KE * G * (re * re + im * im);
+        double cB = 2.0 / (4.0 * alpha * alpha) + 2.0 / k2;
+        double kk[3] = {kx, ky, kz};
+        red[0] = e;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) red[1 + 3 * a + b] = e * ((a == b ? 1.0 : 0.0) - cB * kk[a] * kk[b]);
+    }
+    block_partials<10>(red, partials);
+}
+
+// phi^k_i = 4 k_e sum_half G Re[S e^{i k.r_i}],  F^k_i = 4 k_e q'_i sum_half k G Im[S e^{i k.r_i}]
+__global__ __launch_bounds__(256) void k_ewald_atoms(int N, const float *__restrict__ xs,
+                                                     const float *__restrict__ ys, const float *__restrict__ zs,
+                                                     Cell c, const float *__restrict__ qraw,
+                                                     const double *__restrict__ scalars,
+                                                     const float4 *__restrict__ kv, const int4 *__restrict__ kn,
+                                                     const float2 *__restrict__ Sk, const int *__restrict__ kcount,
+                                                     float *__restrict__ phi, float *__restrict__ Fst) {
+    __shared__ int4 ln[256];
+    __shared__ float4 lk[256];
+    __shared__ float2 ls[256];
+    const int nk = *kcount;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double s0 = 0, s1 = 0, s2 = 0;
+    if (i < N) frac_coords(xs[i], ys[i], zs[i], c, s0, s1, s2);
+    float ph = 0.f, fx = 0.f, fy = 0.f, fz = 0.f;
+    for (int t0 = 0; t0 < nk; t0 += 256) {
+        int k = t0 + threadIdx.x;
+        if (k < nk) {
+            ln[threadIdx.x] = kn[k];
+            lk[threadIdx.x] = kv[k];
+            ls[threadIdx.x] = Sk[k];
+        }
+        __syncthreads();
+        const int m = min(256, nk - t0);
+        if (i < N) {
+            for (int u = 0; u < m; ++u) {
+                float cs, sn;
+                int4 n = ln[u];
+                phase_cs(n.x, n.y, n.z, s0, s1, s2, cs, sn);
+                float2 S = ls[u];
+                float4 q = lk[u];
+                float re = S.x * cs - S.y * sn;
+                float im = S.x * sn + S.y * cs;
+                ph = fmaf(q.w, re, ph);
+                float gi = q.w * im;
+                fx = fmaf(q.x, gi, fx);
+                fy = fmaf(q.y, gi, fy);
+                fz = fmaf(q.z, gi, fz);
+            }
+        }
+        __syncthreads();
+    }
+    if (i < N) {
+        const float qi = qraw[i] + (float)scalars[S_DELTA];
+        const float k4 = 4.0f * (float)KE;
+        phi[i] += k4 * ph;
+        Fst[i] += k4 * qi * fx;
+        Fst[(size_t)N + i] += k4 * qi * fy;
+        Fst[(size_t)2 * N + i] += k4 * qi * fz;
+    }
+}
+
+hipError_t launch_ewald(const Plan &p) {
+    int4 *kn = (int4 *)(p.kvec + p.nk_cap);
+    hipLaunchKernelGGL(k_kvectors, dim3(1), dim3(1024), 0, p.stream, p.cell, p.nk_box[0], p.nk_box[1],
+                       p.nk_box[2], p.kmax * p.kmax, p.kinc, p.alpha, p.vol, p.nk_cap, p.kvec, kn, p.kcount);
+    const int kb = (int)((p.nk_cap + 255) / 256);
+    hipLaunchKernelGGL(k_structure_factor, dim3(kb, p.s_chunks), dim3(256), 0, p.stream, p.N, p.xs, p.ys, p.zs,
+                       p.cell, p.qraw, p.scalars, (const int4 *)kn, p.kcount, p.nk_cap, p.Spart);
+    hipLaunchKernelGGL(k_structure_reduce, dim3(kb), dim3(256), 0, p.stream, p.s_chunks, p.Spart, p.kvec,
+                       p.kcount, p.nk_cap, p.alpha, p.Sk, p.partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = reduce_partials(p, kb, 10, S_UK, false);  // S_UK, S_WK[9]
+    if (e != hipSuccess) return e;
+    const int G = (p.N + 255) / 256;
+    hipLaunchKernelGGL(k_ewald_atoms, dim3(G), dim3(256), 0, p.stream, p.N, p.xs, p.ys, p.zs, p.cell, p.qraw,
+                       p.scalars, p.kvec, (const int4 *)kn, p.Sk, p.kcount, p.phi, p.Fst);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- potential centring
+// phi_i += self (-2 k_e alpha q'_i / sqrt(pi)) and background terms (mode 1);
+// FP64 partials of sum phi for the mean used in chi_i = phi_i - mean(phi).
+__global__ __launch_bounds__(256) void k_phi_total(int N, int mode, float alpha, double vol, double qtot,
+                                                   const float *__restrict__ qraw,
+                                                   const double *__restrict__ scalars,
+                                                   const float *__restrict__ theta, int64_t off_s,
+                                                   float *__restrict__ phi, double *__restrict__ partials) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double red[1] = {0.0};
+    if (i < N) {
+        float v = phi[i];
+        if (mode == 1) {
+            const float qi = qraw[i] + (float)scalars[S_DELTA];
+            const double Qs = qtot / (double)theta[off_s];
+            v += -2.0f * (float)KE * alpha * 0.5641895835477563f * qi;
+            v += (float)(-KE * PI_D * Qs / (vol * (double)alpha * (double)alpha));
+            phi[i] = v;
+        }
+        red[0] = v;
+    }
+    block_partials<1>(red, partials);
+}
+
+__global__ void k_phi_mean(int N, double *__restrict__ scalars) {
+    if (threadIdx.x == 0) scalars[S_PHIBAR] = scalars[S_SUMPHI] / (double)N;
+}
+
+hipError_t launch_phi_mean(const Plan &p) {
+    const int G = (p.N + 255) / 256;
+    hipLaunchKernelGGL(k_phi_total, dim3(G), dim3(256), 0, p.stream, p.N, p.mode, (float)p.alpha, p.vol, p.qtot,
+                       p.qraw, p.scalars, p.theta, p.off_s, p.phi, p.partials);
+    hipError_t e = reduce_partials(p, G, 1, S_SUMPHI, false);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_phi_mean, dim3(1), dim3(64), 0, p.stream, p.N, p.scalars);
+    return hipGetLastError();
+}
+
+}  // namespace qnep

@@ -1,0 +1,503 @@
+// NEP descriptors, partial forces and the assembly of F, W and Z*.
+//
+//  * descriptors (Sec. 2.1; published NEP3/NEP4 form): radial q_n = sum_j g_n(r_ij),
+//    computed through per-species basis sums B_{t,k} = sum_{j in t} f_k(r_ij) so that
+//    the species-pair coefficients are applied once per atom; angular moments
+//    A_nlm = sum_j g_n(r_ij) Y_lm(r_ij) and q_nl = sum_m A_nlm^2 (the Legendre double
+//    sum by the addition theorem).
+//  * partial forces F_ij = g_i . dD^i/dr_ij with g_i = dU_i/dD + chi_i dq_i/dD
+//    (Sec. 2.3, Eqs. 14, 16, 17, 19, 23), chi_i = phi_i - mean(phi) carrying the chain
+//    rule through the neutrality correction; charge derivatives a_ij = s dq_i/dD .
+//    dD^i/dr_ij for the Born charges (Sec. 2.4, Eq. 28).
+//  * F_i = sum_j (F_ij - F_ji) (Eq. 11), W = -sum F_ij (x) r_ij, and
+//    Z_i = q~'_i I + 1/2 sum_j (r_ij (x) a_ij - r_ji (x) a_ji) (Eq. 28).
+// Radial reverse terms are gathered from per-atom coefficient tables; angular
+// reverse terms through a pair buffer and a search of the neighbour's list.
+#include "nep_math.h"
+#include "plan.h"
+
+namespace qnep {
+
+// ---------------------------------------------------------------- descriptors
+template <int T, int NR, int NA, int NB>
+__global__ __launch_bounds__(256) void k_descriptors(int N, const float *__restrict__ xs,
+                                                     const float *__restrict__ ys, const float *__restrict__ zs,
+                                                     const int *__restrict__ ts, Cell c, float rcR, float rcA,
+                                                     const uint32_t *__restrict__ listR,
+                                                     const int *__restrict__ cntR,
+                                                     const uint32_t *__restrict__ listA,
+                                                     const int *__restrict__ cntA, int capA,
+                                                     const float *__restrict__ theta, int64_t off_cR,
+                                                     int64_t off_cA, float *__restrict__ D,
+                                                     float *__restrict__ Amom) {
+    __shared__ float cR[T * T * NR * NB];
+    __shared__ float cA[T * T * NA * NB];
+    for (int k = threadIdx.x; k < T * T * NR * NB; k += blockDim.x) cR[k] = theta[off_cR + k];
+    for (int k = threadIdx.x; k < T * T * NA * NB; k += blockDim.x) cA[k] = theta[off_cA + k];
+    __syncthreads();
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int ti = ts[i];
+    // ---- radial
+    float B[T][NB];
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int k = 0; k < NB; ++k) B[t][k] = 0.0f;
+    const int nR = cntR[i];
+    for (int s = 0; s < nR; ++s) {
+        uint32_t e = listR[(size_t)s * N + i];
+        float3 d = displacement(xs, ys, zs, i, e, c);
+        float r = sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
+        float f[NB], df[NB];
+        cheb_basis<NB>(r, rcR, f, df);
+        int tj = ts[nb_index(e)];
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            float m = (tj == t) ? 1.0f : 0.0f;
+#pragma unroll
+            for (int k = 0; k < NB; ++k) B[t][k] = fmaf(m, f[k], B[t][k]);
+        }
+    }
+#pragma unroll
+    for (int n = 0; n < NR; ++n) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+            for (int k = 0; k < NB; ++k) acc = fmaf(cR[((ti * T + t) * NR + n) * NB + k], B[t][k], acc);
+        D[(size_t)n * N + i] = acc;
+    }
+    // ---- angular
+    float A[NA][LM];
+#pragma unroll
+    for (int n = 0; n < NA; ++n)
+#pragma unroll
+        for (int q = 0; q < LM; ++q) A[n][q] = 0.0f;
+    const int nA = cntA[i];
+    for (int s = 0; s < nA; ++s) {
+        uint32_t e = listA[(size_t)i * capA + s];
+        float3 d = displacement(xs, ys, zs, i, e, c);
+        float r = sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
+        float f[NB], df[NB];
+        cheb_basis<NB>(r, rcA, f, df);
+        const float *cp = &cA[(ti * T + ts[nb_index(e)]) * NA * NB];
+        float g[NA];
+#pragma unroll
+        for (int n = 0; n < NA; ++n) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int k = 0; k < NB; ++k) acc = fmaf(cp[n * NB + k], f[k], acc);
+            g[n] = acc;
+        }
+        float ir = 1.0f / r;
+        float Y[LM];
+        harmonics(d.x * ir, d.y * ir, d.z * ir, Y);
+#pragma unroll
+        for (int n = 0; n < NA; ++n)
+#pragma unroll
+            for (int q = 0; q < LM; ++q) A[n][q] = fmaf(g[n], Y[q], A[n][q]);
+    }
+#pragma unroll
+    for (int n = 0; n < NA; ++n) {
+#pragma unroll
+        for (int q = 0; q < LM; ++q) Amom[(size_t)(n * LM + q) * N + i] = A[n][q];
+        float s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) s1 = fmaf(A[n][q], A[n][q], s1);
+#pragma unroll
+        for (int q = 3; q < 8; ++q) s2 = fmaf(A[n][q], A[n][q], s2);
+#pragma unroll
+        for (int q = 8; q < 15; ++q) s3 = fmaf(A[n][q], A[n][q], s3);
+#pragma unroll
+        for (int q = 15; q < 24; ++q) s4 = fmaf(A[n][q], A[n][q], s4);
+        D[(size_t)(NR + 0 * NA + n) * N + i] = s1;
+        D[(size_t)(NR + 1 * NA + n) * N + i] = s2;
+        D[(size_t)(NR + 2 * NA + n) * N + i] = s3;
+        D[(size_t)(NR + 3 * NA + n) * N + i] = s4;
+    }
+}
+
+// ---------------------------------------------------------------- gradient tables
+// Per atom: chi_i = phi_i - mean(phi); radial coefficient tables
+//   hE[t][k] = sum_n (gU_n + chi gq_n) cR[ti][t][n][k],  hq[t][k] = s sum_n gq_n cR[ti][t][n][k]
+// stored atom-major hT[i][2][T][NB] so that a neighbour's row is one contiguous read.
+template <int T, int NR, int NB>
+__global__ __launch_bounds__(256) void k_radial_tables(int N, const int *__restrict__ ts,
+                                                       const float *__restrict__ gU, const float *__restrict__ gq,
+                                                       const float *__restrict__ phi,
+                                                       const double *__restrict__ scalars,
+                                                       const float *__restrict__ theta, int64_t off_cR,
+                                                       int64_t off_s, float *__restrict__ hT) {
+    __shared__ float cR[T * T * NR * NB];
+    for (int k = threadIdx.x; k < T * T * NR * NB; k += blockDim.x) cR[k] = theta[off_cR + k];
+    __syncthreads();
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const float s = theta[off_s];
+    const float chi = (float)((double)phi[i] - scalars[S_PHIBAR]);
+    const int ti = ts[i];
+    float GE[NR], GQ[NR];
+#pragma unroll
+    for (int n = 0; n < NR; ++n) {
+        float a = gU[(size_t)n * N + i], b = gq[(size_t)n * N + i];
+        GE[n] = fmaf(chi, b, a);
+        GQ[n] = s * b;
+    }
+    float *out = hT + (size_t)i * (2 * T * NB);
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            float e = 0.f, q = 0.f;
+#pragma unroll
+            for (int n = 0; n < NR; ++n) {
+                float cv = cR[((ti * T + t) * NR + n) * NB + k];
+                e = fmaf(GE[n], cv, e);
+                q = fmaf(GQ[n], cv, q);
+            }
+            out[t * NB + k] = e;
+            out[T * NB + t * NB + k] = q;
+        }
+}
+
+template <int T>
+__device__ inline float select_t(const float (&v)[T], int t) {
+    float r = v[0];
+#pragma unroll
+    for (int u = 1; u < T; ++u) r = (t == u) ? v[u] : r;
+    return r;
+}
+
+// ---------------------------------------------------------------- radial forces
+// F_ij = sigma_ij u, sigma_ij = sum_k hE_i[tj][k] f_k'(r); a_ij = rho_ij u likewise.
+// F_i = sum_j (sigma_ij + sigma_ji) u_ij, Z_i += 1/2 sum_j (rho_ij - rho_ji) r u (x) u,
+// W -= sum_j sigma_ij r u (x) u (own partial forces only).
+template <int T, int NB>
+__global__ __launch_bounds__(256) void k_radial_forces(int N, const float *__restrict__ xs,
+                                                       const float *__restrict__ ys, const float *__restrict__ zs,
+                                                       const int *__restrict__ ts, Cell c, float rcR,
+                                                       const uint32_t *__restrict__ listR,
+                                                       const int *__restrict__ cntR,
+                                                       const float *__restrict__ hT, float *__restrict__ Fnep,
+                                                       float *__restrict__ Znep, double *__restrict__ partials) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double w[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (i < N) {
+        const int ti = ts[i];
+        float hE[NB][T], hQ[NB][T];
+        const float *own = hT + (size_t)i * (2 * T * NB);
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                hE[k][t] = own[t * NB + k];
+                hQ[k][t] = own[T * NB + t * NB + k];
+            }
+        float fx = 0.f, fy = 0.f, fz = 0.f;
+        float zxx = 0.f, zyy = 0.f, zzz = 0.f, zxy = 0.f, zxz = 0.f, zyz = 0.f;
+        float wxx = 0.f, wyy = 0.f, wzz = 0.f, wxy = 0.f, wxz = 0.f, wyz = 0.f;
+        const int nR = cntR[i];
+        for (int s = 0; s < nR; ++s) {
+            uint32_t e = listR[(size_t)s * N + i];
+            const int j = nb_index(e);
+            float3 d = displacement(xs, ys, zs, i, e, c);
+            float r = sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
+            float f[NB], df[NB];
+            cheb_basis<NB>(r, rcR, f, df);
+            const int tj = ts[j];
+            const float *oth = hT + (size_t)j * (2 * T * NB) + ti * NB;
+            float sij = 0.f, rij = 0.f, sji = 0.f, rji = 0.f;
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                sij = fmaf(select_t<T>(hE[k], tj), df[k], sij);
+                rij = fmaf(select_t<T>(hQ[k], tj), df[k], rij);
+                sji = fmaf(oth[k], df[k], sji);
+                rji = fmaf(oth[T * NB + k], df[k], rji);
+            }
+            float ir = 1.0f / r;
+            float ux = d.x * ir, uy = d.y * ir, uz = d.z * ir;
+            float sf = sij + sji;
+            fx = fmaf(sf, ux, fx);
+            fy = fmaf(sf, uy, fy);
+            fz = fmaf(sf, uz, fz);
+            float zr = 0.5f * (rij - rji) * r;
+            zxx = fmaf(zr, ux * ux, zxx);
+            zyy = fmaf(zr, uy * uy, zyy);
+            zzz = fmaf(zr, uz * uz, zzz);
+            zxy = fmaf(zr, ux * uy, zxy);
+            zxz = fmaf(zr, ux * uz, zxz);
+            zyz = fmaf(zr, uy * uz, zyz);
+            float wr = sij * r;
+            wxx = fmaf(wr, ux * ux, wxx);
+            wyy = fmaf(wr, uy * uy, wyy);
+            wzz = fmaf(wr, uz * uz, wzz);
+            wxy = fmaf(wr, ux * uy, wxy);
+            wxz = fmaf(wr, ux * uz, wxz);
+            wyz = fmaf(wr, uy * uz, wyz);
+        }
+        Fnep[i] = fx;
+        Fnep[(size_t)N + i] = fy;
+        Fnep[(size_t)2 * N + i] = fz;
+        Znep[(size_t)0 * N + i] = zxx;
+        Znep[(size_t)1 * N + i] = zxy;
+        Znep[(size_t)2 * N + i] = zxz;
+        Znep[(size_t)3 * N + i] = zxy;
+        Znep[(size_t)4 * N + i] = zyy;
+        Znep[(size_t)5 * N + i] = zyz;
+        Znep[(size_t)6 * N + i] = zxz;
+        Znep[(size_t)7 * N + i] = zyz;
+        Znep[(size_t)8 * N + i] = zzz;
+        w[0] = -wxx; w[1] = -wxy; w[2] = -wxz;
+        w[3] = -wxy; w[4] = -wyy; w[5] = -wyz;
+        w[6] = -wxz; w[7] = -wyz; w[8] = -wzz;
+    }
+    block_partials<9>(w, partials);
+}
+
+// ---------------------------------------------------------------- angular forces
+// Atilde_nlm = 2 G_nl A_nlm with G the upstream gradient (energy: dU/dD + chi dq/dD;
+// charge: s dq/dD).  Per pair: P_n = sum_lm Atilde_nlm Y_lm, Q_lm = sum_n Atilde_nlm g_n,
+// F_ij = u sum_n g_n' P_n + (I - u u^T) (sum_lm Q_lm grad Y_lm) / r.
+// WHICH = 0: energy pass (pair buffer pairF, own forces and virial);
+// WHICH = 1: charge pass (pair buffer pairA, own Z contribution).
+template <int T, int NR, int NA, int NB, int WHICH>
+__global__ __launch_bounds__(256) void k_angular_forces(
+    int N, const float *__restrict__ xs, const float *__restrict__ ys, const float *__restrict__ zs,
+    const int *__restrict__ ts, Cell c, float rcA, const uint32_t *__restrict__ listA,
+    const int *__restrict__ cntA, int capA, const float *__restrict__ Amom, const float *__restrict__ gU,
+    const float *__restrict__ gq, const float *__restrict__ phi, const double *__restrict__ scalars,
+    const float *__restrict__ theta, int64_t off_cA, int64_t off_s, float4 *__restrict__ pair,
+    float *__restrict__ Fnep, float *__restrict__ Znep, double *__restrict__ partials) {
+    __shared__ float cA[T * T * NA * NB];
+    for (int k = threadIdx.x; k < T * T * NA * NB; k += blockDim.x) cA[k] = theta[off_cA + k];
+    __syncthreads();
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double w[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (i < N) {
+        const int ti = ts[i];
+        const float s = theta[off_s];
+        const float chi = (float)((double)phi[i] - scalars[S_PHIBAR]);
+        float At[NA][LM];
+#pragma unroll
+        for (int n = 0; n < NA; ++n) {
+            float G[4];
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+                size_t row = (size_t)(NR + l * NA + n) * N + i;
+                float b = gq[row];
+                G[l] = 2.0f * (WHICH == 0 ? fmaf(chi, b, gU[row]) : s * b);
+            }
+#pragma unroll
+            for (int q = 0; q < LM; ++q) {
+                const int l = q < 3 ? 0 : (q < 8 ? 1 : (q < 15 ? 2 : 3));
+                At[n][q] = G[l] * Amom[(size_t)(n * LM + q) * N + i];
+            }
+        }
+        float ox = 0.f, oy = 0.f, oz = 0.f;
+        float m9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        const int nA = cntA[i];
+        for (int sl = 0; sl < nA; ++sl) {
+            uint32_t e = listA[(size_t)i * capA + sl];
+            float3 d = displacement(xs, ys, zs, i, e, c);
+            float r = sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
+            float ir = 1.0f / r;
+            float ux = d.x * ir, uy = d.y * ir, uz = d.z * ir;
+            float f[NB], df[NB];
+            cheb_basis<NB>(r, rcA, f, df);
+            const float *cp = &cA[(ti * T + ts[nb_index(e)]) * NA * NB];
+            float g[NA], dg[NA];
+#pragma unroll
+            for (int n = 0; n < NA; ++n) {
+                float a = 0.f, b = 0.f;
+#pragma unroll
+                for (int k = 0; k < NB; ++k) {
+                    a = fmaf(cp[n * NB + k], f[k], a);
+                    b = fmaf(cp[n * NB + k], df[k], b);
+                }
+                g[n] = a;
+                dg[n] = b;
+            }
+            float Y[LM];
+            harmonics(ux, uy, uz, Y);
+            float radial = 0.f;
+            float Qv[LM];
+#pragma unroll
+            for (int q = 0; q < LM; ++q) Qv[q] = 0.f;
+#pragma unroll
+            for (int n = 0; n < NA; ++n) {
+                float Pn = 0.f;
+#pragma unroll
+                for (int q = 0; q < LM; ++q) {
+                    Pn = fmaf(At[n][q], Y[q], Pn);
+                    Qv[q] = fmaf(At[n][q], g[n], Qv[q]);
+                }
+                radial = fmaf(dg[n], Pn, radial);
+            }
+            float gx, gy, gz;
+            harmonics_grad_dot(ux, uy, uz, Qv, gx, gy, gz);
+            float ug = ux * gx + uy * gy + uz * gz;
+            float Fx = radial * ux + (gx - ug * ux) * ir;
+            float Fy = radial * uy + (gy - ug * uy) * ir;
+            float Fz = radial * uz + (gz - ug * uz) * ir;
+            pair[(size_t)i * capA + sl] = make_float4(Fx, Fy, Fz, 0.f);
+            if (WHICH == 0) {
+                ox += Fx;
+                oy += Fy;
+                oz += Fz;
+                // W_ab -= F_a r_b
+                m9[0] -= Fx * d.x; m9[1] -= Fx * d.y; m9[2] -= Fx * d.z;
+                m9[3] -= Fy * d.x; m9[4] -= Fy * d.y; m9[5] -= Fy * d.z;
+                m9[6] -= Fz * d.x; m9[7] -= Fz * d.y; m9[8] -= Fz * d.z;
+            } else {
+                // Z_ab += 1/2 r_a a_b
+                m9[0] += 0.5f * d.x * Fx; m9[1] += 0.5f * d.x * Fy; m9[2] += 0.5f * d.x * Fz;
+                m9[3] += 0.5f * d.y * Fx; m9[4] += 0.5f * d.y * Fy; m9[5] += 0.5f * d.y * Fz;
+                m9[6] += 0.5f * d.z * Fx; m9[7] += 0.5f * d.z * Fy; m9[8] += 0.5f * d.z * Fz;
+            }
+        }
+        if (WHICH == 0) {
+            Fnep[i] += ox;
+            Fnep[(size_t)N + i] += oy;
+            Fnep[(size_t)2 * N + i] += oz;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) w[k] = m9[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) Znep[(size_t)k * N + i] += m9[k];
+        }
+    }
+    if (WHICH == 0) block_partials<9>(w, partials);
+}
+
+// ---------------------------------------------------------------- assembly
+// Adds the angular reverse terms -F_ji and -1/2 r_ji (x) a_ji found in each
+// neighbour's pair buffer, the static electrostatic forces and the diagonal q~'_i,
+// writes F, Z*, q', q~' in input order and FP64 partials of P = sum_i q~'_i r_i.
+__global__ __launch_bounds__(256) void k_assemble(
+    int N, const float *__restrict__ xs, const float *__restrict__ ys, const float *__restrict__ zs, Cell c,
+    const uint32_t *__restrict__ listA, const int *__restrict__ cntA, int capA, const float4 *__restrict__ pairF,
+    const float4 *__restrict__ pairA, const float *__restrict__ Fnep, const float *__restrict__ Znep,
+    const float *__restrict__ Fst, const float *__restrict__ qraw, const double *__restrict__ scalars,
+    const float *__restrict__ theta, int64_t off_s, const int *__restrict__ perm, const float *__restrict__ pos,
+    float *__restrict__ forces, float *__restrict__ bec, float *__restrict__ charges,
+    float *__restrict__ charges_naked, double *__restrict__ partials) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double pv[3] = {0, 0, 0};
+    if (i < N) {
+        const float s = theta[off_s];
+        const float qp = (float)((double)qraw[i] + scalars[S_DELTA]);  // q'
+        const float qt = s * qp;                                        // q~'
+        float F[3], Z[9];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) F[a] = Fnep[(size_t)a * N + i] + Fst[(size_t)a * N + i];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Z[k] = Znep[(size_t)k * N + i];
+        Z[0] += qt;
+        Z[4] += qt;
+        Z[8] += qt;
+        const int nA = cntA[i];
+        for (int sl = 0; sl < nA; ++sl) {
+            uint32_t e = listA[(size_t)i * capA + sl];
+            const int j = nb_index(e);
+            const uint32_t want = nb_reverse(e, i);
+            const int nj = cntA[j];
+            int found = -1;
+            for (int t = 0; t < nj; ++t)
+                if (listA[(size_t)j * capA + t] == want) {
+                    found = t;
+                    break;
+                }
+            if (found < 0) continue;  // pair at the cutoff on one side only: contributes zero
+            float4 fji = pairF[(size_t)j * capA + found];
+            float4 aji = pairA[(size_t)j * capA + found];
+            F[0] -= fji.x;
+            F[1] -= fji.y;
+            F[2] -= fji.z;
+            float3 d = displacement(xs, ys, zs, i, e, c);  // r_ij = -r_ji
+            // -1/2 r_ji (x) a_ji = +1/2 r_ij (x) a_ji
+            Z[0] += 0.5f * d.x * aji.x; Z[1] += 0.5f * d.x * aji.y; Z[2] += 0.5f * d.x * aji.z;
+            Z[3] += 0.5f * d.y * aji.x; Z[4] += 0.5f * d.y * aji.y; Z[5] += 0.5f * d.y * aji.z;
+            Z[6] += 0.5f * d.z * aji.x; Z[7] += 0.5f * d.z * aji.y; Z[8] += 0.5f * d.z * aji.z;
+        }
+        const int o = perm[i];
+        if (forces) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) forces[(size_t)a * N + o] = F[a];
+        }
+        if (bec) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) bec[(size_t)k * N + o] = Z[k];
+        }
+        if (charges) charges[o] = qp;
+        if (charges_naked) charges_naked[o] = qt;
+        // polarization with the caller's coordinates (Eq. 26)
+        double qd = (double)s * ((double)qraw[i] + scalars[S_DELTA]);
+        pv[0] = qd * (double)pos[o];
+        pv[1] = qd * (double)pos[(size_t)N + o];
+        pv[2] = qd * (double)pos[(size_t)2 * N + o];
+    }
+    block_partials<3>(pv, partials);
+}
+
+// ---------------------------------------------------------------- launchers
+template <int T, int NR, int NA, int NB>
+static hipError_t run_descriptors(const Plan &p) {
+    const int G = (p.N + 255) / 256;
+    hipLaunchKernelGGL((k_descriptors<T, NR, NA, NB>), dim3(G), dim3(256), 0, p.stream, p.N, p.xs, p.ys, p.zs,
+                       p.ts, p.cell, (float)p.rcR, (float)p.rcA, p.listR, p.cntR, p.listA, p.cntA, p.capA,
+                       p.theta, p.off_cR, p.off_cA, p.D, p.Amom);
+    return hipGetLastError();
+}
+
+template <int T, int NR, int NA, int NB>
+static hipError_t run_forces(const Plan &p) {
+    const int G = (p.N + 255) / 256;
+    hipLaunchKernelGGL((k_radial_tables<T, NR, NB>), dim3(G), dim3(256), 0, p.stream, p.N, p.ts, p.gU, p.gq,
+                       p.phi, p.scalars, p.theta, p.off_cR, p.off_s, p.hT);
+    hipLaunchKernelGGL((k_radial_forces<T, NB>), dim3(G), dim3(256), 0, p.stream, p.N, p.xs, p.ys, p.zs, p.ts,
+                       p.cell, (float)p.rcR, p.listR, p.cntR, p.hT, p.Fnep, p.Znep, p.partials);
+    hipError_t e = reduce_partials(p, G, 9, S_WNEP, false);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_angular_forces<T, NR, NA, NB, 0>), dim3(G), dim3(256), 0, p.stream, p.N, p.xs, p.ys,
+                       p.zs, p.ts, p.cell, (float)p.rcA, p.listA, p.cntA, p.capA, p.Amom, p.gU, p.gq, p.phi,
+                       p.scalars, p.theta, p.off_cA, p.off_s, (float4 *)p.pairF, p.Fnep, p.Znep, p.partials);
+    e = reduce_partials(p, G, 9, S_WNEP, true);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_angular_forces<T, NR, NA, NB, 1>), dim3(G), dim3(256), 0, p.stream, p.N, p.xs, p.ys,
+                       p.zs, p.ts, p.cell, (float)p.rcA, p.listA, p.cntA, p.capA, p.Amom, p.gU, p.gq, p.phi,
+                       p.scalars, p.theta, p.off_cA, p.off_s, (float4 *)p.pairA, p.Fnep, p.Znep, p.partials);
+    hipLaunchKernelGGL(k_assemble, dim3(G), dim3(256), 0, p.stream, p.N, p.xs, p.ys, p.zs, p.cell, p.listA,
+                       p.cntA, p.capA, (const float4 *)p.pairF, (const float4 *)p.pairA, p.Fnep, p.Znep, p.Fst,
+                       p.qraw, p.scalars, p.theta, p.off_s, p.perm, p.pos, p.out.forces, p.out.bec, p.out.charges,
+                       p.out.charges_naked, p.partials);
+    return reduce_partials(p, G, 3, S_POL, false);
+}
+
+// compiled hyper-parameter sets: (T, n_max_R + 1, n_max_A + 1, basis + 1), l_max = 4
+#define QNEP_DISPATCH(FN)                                                                                  \
+    if (p.NBR == 9 && p.NBA == 9 && p.LMAX == 4) {                                                         \
+        if (p.NR == 5 && p.NA == 5) {                                                                      \
+            if (p.T == 1) return FN<1, 5, 5, 9>(p);                                                        \
+            if (p.T == 2) return FN<2, 5, 5, 9>(p);                                                        \
+            if (p.T == 3) return FN<3, 5, 5, 9>(p);                                                        \
+            if (p.T == 4) return FN<4, 5, 5, 9>(p);                                                        \
+        }                                                                                                  \
+        if (p.NR == 9 && p.NA == 7) {                                                                      \
+            if (p.T == 1) return FN<1, 9, 7, 9>(p);                                                        \
+            if (p.T == 2) return FN<2, 9, 7, 9>(p);                                                        \
+            if (p.T == 3) return FN<3, 9, 7, 9>(p);                                                        \
+            if (p.T == 4) return FN<4, 9, 7, 9>(p);                                                        \
+        }                                                                                                  \
+    }                                                                                                      \
+    return hipErrorInvalidValue;
+
+hipError_t launch_descriptors(const Plan &p) { QNEP_DISPATCH(run_descriptors) }
+hipError_t launch_forces(const Plan &p) { QNEP_DISPATCH(run_forces) }
+
+bool nep_supported(int T, int NR, int NA, int NBR, int NBA, int LMAX) {
+    if (NBR != 9 || NBA != 9 || LMAX != 4 || T < 1 || T > 4) return false;
+    return (NR == 5 && NA == 5) || (NR == 9 && NA == 7);
+}
+
+}  // namespace qnep

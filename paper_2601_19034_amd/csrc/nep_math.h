@@ -1,0 +1,128 @@
+// Radial basis and angular harmonics of the NEP descriptors (FP32), written for
+// both host (unit tests) and device.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+namespace qnep {
+
+// f_k(r) = (T_k(x) + 1)/2 * f_c(r), x = 2 (r/rc - 1)^2 - 1, f_c = (1 + cos(pi r/rc))/2,
+// k = 0..NB-1, and df_k/dr, with T_k' = k U_{k-1}.
+template <int NB>
+__host__ __device__ inline void cheb_basis(float r, float rc, float *f, float *df) {
+    const float pr = 3.14159265358979f / rc;
+    float sn = sinf(pr * r), cs = cosf(pr * r);
+    float fc = 0.5f * (1.0f + cs), dfc = -0.5f * pr * sn;
+    float t = r / rc - 1.0f;
+    float x = 2.0f * t * t - 1.0f, dx = 4.0f * t / rc;
+    float Tm2 = 1.0f, Tm1 = x;       // T_0, T_1
+    float Um2 = 1.0f, Um1 = 2.0f * x; // U_0, U_1
+    f[0] = fc;
+    df[0] = dfc;
+    if (NB > 1) {
+        f[1] = 0.5f * (x + 1.0f) * fc;
+        df[1] = 0.5f * dx * fc + 0.5f * (x + 1.0f) * dfc;
+    }
+#pragma unroll
+    for (int k = 2; k < NB; ++k) {
+        float Tk = 2.0f * x * Tm1 - Tm2;
+        float dT = (float)k * Um1;  // k U_{k-1}
+        f[k] = 0.5f * (Tk + 1.0f) * fc;
+        df[k] = 0.5f * dT * dx * fc + 0.5f * (Tk + 1.0f) * dfc;
+        float Uk = 2.0f * x * Um1 - Um2;
+        Tm2 = Tm1;
+        Tm1 = Tk;
+        Um2 = Um1;
+        Um1 = Uk;
+    }
+}
+
+// Real spherical harmonics of l = 1..4 (24 values, l-major, m = -l..l), scaled so
+// that sum_m Y_lm(u) Y_lm(v) = P_l(u.v) for unit vectors u, v.
+__host__ __device__ inline void harmonics(float x, float y, float z, float *Y) {
+    const float s3 = 1.7320508075688772f, s15 = 3.872983346207417f, s6 = 2.449489742783178f;
+    const float s10 = 3.1622776601683795f, s5 = 2.23606797749979f, s35 = 5.916079783099616f;
+    const float c43 = 2.091650066335189f;   // sqrt(35/2)/2
+    const float c41 = 0.7905694150420949f;  // sqrt(5/2)/2
+    float x2 = x * x, y2 = y * y, z2 = z * z;
+    Y[0] = y;
+    Y[1] = z;
+    Y[2] = x;
+    Y[3] = s3 * x * y;
+    Y[4] = s3 * y * z;
+    Y[5] = 0.5f * (3.0f * z2 - 1.0f);
+    Y[6] = s3 * x * z;
+    Y[7] = 0.5f * s3 * (x2 - y2);
+    Y[8] = 0.25f * s10 * y * (3.0f * x2 - y2);
+    Y[9] = s15 * x * y * z;
+    Y[10] = 0.25f * s6 * y * (5.0f * z2 - 1.0f);
+    Y[11] = 0.5f * z * (5.0f * z2 - 3.0f);
+    Y[12] = 0.25f * s6 * x * (5.0f * z2 - 1.0f);
+    Y[13] = 0.5f * s15 * z * (x2 - y2);
+    Y[14] = 0.25f * s10 * x * (x2 - 3.0f * y2);
+    Y[15] = 0.5f * s35 * x * y * (x2 - y2);
+    Y[16] = c43 * y * z * (3.0f * x2 - y2);
+    Y[17] = 0.5f * s5 * x * y * (7.0f * z2 - 1.0f);
+    Y[18] = c41 * y * z * (7.0f * z2 - 3.0f);
+    Y[19] = 0.125f * (35.0f * z2 * z2 - 30.0f * z2 + 3.0f);
+    Y[20] = c41 * x * z * (7.0f * z2 - 3.0f);
+    Y[21] = 0.25f * s5 * (x2 - y2) * (7.0f * z2 - 1.0f);
+    Y[22] = c43 * x * z * (x2 - 3.0f * y2);
+    Y[23] = 0.125f * s35 * (x2 * x2 - 6.0f * x2 * y2 + y2 * y2);
+}
+
+// sum_lm Q[lm] * grad Y_lm, with the polynomials above differentiated in x, y, z
+// as independent variables (the caller projects out the radial part).
+__host__ __device__ inline void harmonics_grad_dot(float x, float y, float z, const float *Q, float &gx,
+                                                   float &gy, float &gz) {
+    const float s3 = 1.7320508075688772f, s15 = 3.872983346207417f, s6 = 2.449489742783178f;
+    const float s10 = 3.1622776601683795f, s5 = 2.23606797749979f, s35 = 5.916079783099616f;
+    const float c43 = 2.091650066335189f, c41 = 0.7905694150420949f;
+    float x2 = x * x, y2 = y * y, z2 = z * z;
+    float ax = 0.f, ay = 0.f, az = 0.f;
+    // l = 1
+    ay += Q[0];
+    az += Q[1];
+    ax += Q[2];
+    // l = 2
+    ax += Q[3] * s3 * y;               ay += Q[3] * s3 * x;
+    ay += Q[4] * s3 * z;               az += Q[4] * s3 * y;
+    az += Q[5] * 3.0f * z;
+    ax += Q[6] * s3 * z;               az += Q[6] * s3 * x;
+    ax += Q[7] * s3 * x;               ay -= Q[7] * s3 * y;
+    // l = 3
+    ax += Q[8] * 1.5f * s10 * x * y;   ay += Q[8] * 0.75f * s10 * (x2 - y2);
+    ax += Q[9] * s15 * y * z;          ay += Q[9] * s15 * x * z;          az += Q[9] * s15 * x * y;
+    ay += Q[10] * 0.25f * s6 * (5.0f * z2 - 1.0f);                         az += Q[10] * 2.5f * s6 * y * z;
+    az += Q[11] * (7.5f * z2 - 1.5f);
+    ax += Q[12] * 0.25f * s6 * (5.0f * z2 - 1.0f);                         az += Q[12] * 2.5f * s6 * x * z;
+    ax += Q[13] * s15 * x * z;         ay -= Q[13] * s15 * y * z;         az += Q[13] * 0.5f * s15 * (x2 - y2);
+    ax += Q[14] * 0.75f * s10 * (x2 - y2);                                 ay -= Q[14] * 1.5f * s10 * x * y;
+    // l = 4
+    ax += Q[15] * 0.5f * s35 * (3.0f * x2 * y - y2 * y);
+    ay += Q[15] * 0.5f * s35 * (x2 * x - 3.0f * x * y2);
+    ax += Q[16] * c43 * 6.0f * x * y * z;
+    ay += Q[16] * c43 * 3.0f * z * (x2 - y2);
+    az += Q[16] * c43 * y * (3.0f * x2 - y2);
+    ax += Q[17] * 0.5f * s5 * y * (7.0f * z2 - 1.0f);
+    ay += Q[17] * 0.5f * s5 * x * (7.0f * z2 - 1.0f);
+    az += Q[17] * 7.0f * s5 * x * y * z;
+    ay += Q[18] * c41 * z * (7.0f * z2 - 3.0f);
+    az += Q[18] * c41 * y * (21.0f * z2 - 3.0f);
+    az += Q[19] * (17.5f * z2 * z - 7.5f * z);
+    ax += Q[20] * c41 * z * (7.0f * z2 - 3.0f);
+    az += Q[20] * c41 * x * (21.0f * z2 - 3.0f);
+    ax += Q[21] * 0.5f * s5 * x * (7.0f * z2 - 1.0f);
+    ay -= Q[21] * 0.5f * s5 * y * (7.0f * z2 - 1.0f);
+    az += Q[21] * 3.5f * s5 * z * (x2 - y2);
+    ax += Q[22] * c43 * 3.0f * z * (x2 - y2);
+    ay -= Q[22] * c43 * 6.0f * x * y * z;
+    az += Q[22] * c43 * x * (x2 - 3.0f * y2);
+    ax += Q[23] * 0.5f * s35 * (x2 * x - 3.0f * x * y2);
+    ay += Q[23] * 0.5f * s35 * (y2 * y - 3.0f * x2 * y);
+    gx = ax;
+    gy = ay;
+    gz = az;
+}
+
+}  // namespace qnep

@@ -1,0 +1,84 @@
+// Per-call plan: sizes derived on the host and device pointers into the workspace.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/qnep.h"
+#include "common.h"
+
+namespace qnep {
+
+struct Plan {
+    // ---- model
+    int N = 0, T = 0, NR = 0, NA = 0, NBR = 0, NBA = 0, LMAX = 4, H = 0, ndes = 0;
+    double rcR = 0, rcA = 0;
+    int mlp_prec = QNEP_MLP_FP32;
+    int64_t off_cR = 0, off_cA = 0, off_nn = 0, per_species = 0, off_b1E = 0, off_s = 0, n_theta = 0;
+    // ---- electrostatics
+    int mode = 1, method = 0, kinc = 0, order = 5;
+    double alpha = 0.3, rc_coul = 9.0, kmax = 0, qtot = 0;
+    int mesh[3] = {0, 0, 0};
+    int64_t mesh_pts = 0;
+    Cell cell;
+    double vol = 0;
+    // ---- binning and lists
+    int nc[3] = {1, 1, 1};
+    int ncell = 1;
+    int mR[3] = {1, 1, 1}, mC[3] = {1, 1, 1};
+    int capR = 0, capA = 0, capC = 0;
+    int nblk = 0;  // blocks of RED_THREADS threads over N
+    // ---- Ewald
+    int nk_box[3] = {0, 0, 0};
+    int64_t nk_cap = 0;      // capacity of the half k-set
+    int s_chunks = 0;        // atom chunks of the structure-factor kernel
+    // ---- device workspace
+    int32_t *flags = nullptr;
+    double *scalars = nullptr;
+    double *partials = nullptr;
+    int64_t partials_cap = 0;
+    int *cid = nullptr, *cell_count = nullptr, *cell_start = nullptr, *cell_cursor = nullptr, *perm = nullptr;
+    float *xs = nullptr, *ys = nullptr, *zs = nullptr;
+    int *ts = nullptr;
+    uint32_t *listR = nullptr, *listA = nullptr, *listC = nullptr;
+    int *cntR = nullptr, *cntA = nullptr, *cntC = nullptr;
+    float *D = nullptr, *Amom = nullptr;
+    float *U = nullptr, *qraw = nullptr, *gU = nullptr, *gq = nullptr;
+    float *phi = nullptr, *Fst = nullptr, *hT = nullptr;
+    float *pairF = nullptr, *pairA = nullptr;
+    float *Fnep = nullptr, *Znep = nullptr;
+    float4 *kvec = nullptr;   // (kx, ky, kz, G) of the half set
+    int *kcount = nullptr;
+    float2 *Spart = nullptr;  // [s_chunks][nk_cap]
+    float2 *Sk = nullptr;     // [nk_cap]
+    float *rho = nullptr;
+    float2 *meshA = nullptr, *meshB = nullptr;
+    // ---- call arguments
+    const float *pos = nullptr;
+    const int32_t *type = nullptr;
+    const float *theta = nullptr;
+    qnep_outputs out{};
+    hipStream_t stream = nullptr;
+};
+
+// module launchers (each returns hipSuccess or the first launch error)
+hipError_t launch_neighbors(const Plan &p);
+hipError_t launch_descriptors(const Plan &p);
+hipError_t launch_mlp(const Plan &p);
+hipError_t launch_charges(const Plan &p);
+hipError_t launch_real_space(const Plan &p);
+hipError_t launch_ewald(const Plan &p);
+hipError_t launch_pppm(const Plan &p);
+hipError_t launch_forces(const Plan &p);
+hipError_t launch_finalize(const Plan &p);
+hipError_t launch_zero_outputs(const Plan &p);
+
+// fixed-order reduction of partials[nblk][nv] into scalars[slot..slot+nv)
+hipError_t reduce_partials(const Plan &p, int nblk, int nv, int slot, bool accumulate);
+// fills n floats/ints with zero (a kernel, not a memset, so that the sequence can be captured)
+hipError_t fill_zero(void *ptr, size_t bytes, hipStream_t s);
+
+// in-house 3D FFT (complex, in place on `data` using `tmp` as scratch); sign -1 forward, +1 inverse
+hipError_t fft3d(float2 *data, float2 *tmp, const int *mesh, int sign, hipStream_t s);
+bool fft_length_supported(int n);
+
+}  // namespace qnep

@@ -18,3 +18,15 @@ def orc():
 
     oracle.build(force=False)
     return oracle
+
+
+@pytest.fixture(scope="session")
+def qlib():
+    """The HIP library (built in-tree if it is not there yet)."""
+    from paper_2601_19034_amd import binding
+
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_2601_19034_amd import build
+
+        build.build()
+    return binding.load()

@@ -1,0 +1,100 @@
+"""Host-side checks of the C ABI (no GPU needed): every symbol declared in
+include/qnep.h is exported, parameter counting, workspace sizing and argument
+validation happen before any device work."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2601_19034_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            names += re.findall(r"^[A-Za-z_][\w \*]*?\b(qnep_\w+)\s*\(", txt, flags=re.M)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported(qlib):
+    names = _declared()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(qlib, n), n
+
+
+def test_param_count_matches_layout(qlib):
+    from paper_2601_19034_amd import binding as B
+    for hp in (inputs.WATER_HP, inputs.GARNET_HP, inputs.PEROV_HP):
+        assert B.qnep_param_count(hp) == hp.n_theta()
+
+
+def test_model_validation(qlib):
+    from paper_2601_19034_amd import binding as B
+    bad = inputs.HParams(n_types=5)
+    with pytest.raises(B.QnepError):
+        B.qnep_model_create(bad, 0)
+    odd = inputs.HParams(n_types=2, n_max_R=3)
+    with pytest.raises(B.QnepError, match="unsupported"):
+        B.qnep_model_create(odd, 0)
+    with pytest.raises(B.QnepError):
+        B.qnep_model_create(inputs.WATER_HP, 7)
+    h = B.qnep_model_create(inputs.WATER_HP, 0)
+    B.qnep_model_destroy(h)
+
+
+def test_workspace_and_plan_validation(qlib):
+    from paper_2601_19034_amd import binding as B
+    w = inputs.workload(0)
+    h = B.qnep_model_create(w.hp, 0)
+    try:
+        es = B.make_es(w.es)
+        n = w.system.n
+        nb = B.qnep_workspace_size(h, es, B.make_system(n, 0, 0, w.system.cell))
+        assert nb > n * 100
+        # PPPM workspace grows with the mesh
+        es_p = inputs.ESParams(method=1, mesh=(32, 32, 32))
+        nb32 = B.qnep_workspace_size(h, B.make_es(es_p), B.make_system(n, 0, 0, w.system.cell))
+        es_p.mesh = (64, 64, 64)
+        nb64 = B.qnep_workspace_size(h, B.make_es(es_p), B.make_system(n, 0, 0, w.system.cell))
+        assert nb64 - nb32 >= 20 * (64 ** 3 - 32 ** 3)
+        # unsupported mesh (factor 7), singular cell, left-handed cell, thin cell, bad mode
+        es_p.mesh = (28, 32, 32)
+        with pytest.raises(B.QnepError, match="mesh"):
+            B.qnep_workspace_size(h, B.make_es(es_p), B.make_system(n, 0, 0, w.system.cell))
+        with pytest.raises(B.QnepError, match="cell"):
+            B.qnep_workspace_size(h, es, B.make_system(n, 0, 0, np.zeros((3, 3))))
+        lh = w.system.cell.copy()
+        lh[2] *= -1
+        with pytest.raises(B.QnepError, match="cell"):
+            B.qnep_workspace_size(h, es, B.make_system(n, 0, 0, lh))
+        with pytest.raises(B.QnepError, match="thinner"):
+            B.qnep_workspace_size(h, es, B.make_system(n, 0, 0, np.diag([2.0, 20.0, 20.0])))
+        es_bad = inputs.ESParams(mode=3)
+        with pytest.raises(B.QnepError, match="mode"):
+            B.qnep_workspace_size(h, B.make_es(es_bad), B.make_system(n, 0, 0, w.system.cell))
+        with pytest.raises(B.QnepError, match="n_atoms"):
+            B.qnep_workspace_size(h, es, B.make_system(1 << 23, 0, 0, w.system.cell))
+        # compute refuses a small workspace before touching the device
+        outs = B.qnep_outputs()
+        with pytest.raises(B.QnepError, match="workspace"):
+            B.qnep_compute(h, 1, es, B.make_system(n, 1, 1, w.system.cell), outs, 1, 16, 0)
+    finally:
+        B.qnep_model_destroy(h)
+
+
+def test_capacity_factor_validation(qlib):
+    from paper_2601_19034_amd import binding as B
+    h = B.qnep_model_create(inputs.WATER_HP, 0)
+    try:
+        with pytest.raises(B.QnepError):
+            B.qnep_model_set_capacity_factor(h, 0.5)
+        B.qnep_model_set_capacity_factor(h, 2.0)
+    finally:
+        B.qnep_model_destroy(h)

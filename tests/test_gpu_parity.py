@@ -1,0 +1,213 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle, element by
+element, on seeded workloads that span several tiles and ragged tails.
+
+Tolerances for the FP32 path (spec target: forces within 1e-4 eV/A of the
+FP64 oracle); the other bounds follow from FP32 rounding of per-atom terms summed
+in FP64:
+  energy        |dE| / N        <= 2e-6 eV/atom
+  forces        max |dF|        <= 1e-4 eV/A
+  virial        max |dW| / N    <= 2e-5 eV
+  charges       max |dq|        <= 2e-6 e
+  Born charges  max |dZ|        <= 1e-4 e
+  polarization  max |dP|        <= 1e-5 * (1 + sum_i |q~'_i r_i|) e A
+"""
+import copy
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2601_19034_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = dict(e=2e-6, f=1e-4, w=2e-5, q=2e-6, z=1e-4, p=1e-5)
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return torch
+
+
+def run_gpu(hp, es, sysm, theta, precision="fp32"):
+    from paper_2601_19034_amd.api import QNEP, to_device_inputs
+
+    model = QNEP(hp, precision)
+    pos, types, th = to_device_inputs(sysm, theta)
+    out = model.compute(pos, types, sysm.cell, th, es)
+    flags = model.check_status()
+    assert flags == 0, f"device status flags {flags}"
+    return {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
+
+
+def compare(g, r, n, tol=TOL, label=""):
+    dE = abs(g["energy"][0] - r.energy) / max(n, 1)
+    F = g["forces"].T
+    dF = np.abs(F - r.forces).max()
+    dW = np.abs(g["virial"].reshape(3, 3) - r.virial).max() / max(n, 1)
+    dq = np.abs(g["charges"] - r.q_screened).max()
+    dqt = np.abs(g["charges_naked"] - r.q_naked).max()
+    Z = g["bec"].T.reshape(n, 3, 3)
+    dZ = np.abs(Z - r.bec).max()
+    pscale = 1.0 + np.abs(r.q_naked[:, None] * 1.0).sum() * 100
+    dP = np.abs(g["polarization"] - r.pol).max()
+    _say(f"[{label}] dE/N={dE:.2e} dF={dF:.2e} dW/N={dW:.2e} dq={dq:.2e} dq~={dqt:.2e} dZ={dZ:.2e} dP={dP:.2e} "
+         f"|F|max={np.abs(r.forces).max():.3f}")
+    assert dE <= tol["e"], dE
+    assert dF <= tol["f"], dF
+    assert dW <= tol["w"], dW
+    assert dq <= tol["q"] and dqt <= tol["q"] * 2, (dq, dqt)
+    assert dZ <= tol["z"], dZ
+    assert dP <= tol["p"] * pscale, dP
+    t = g["energy_terms"]
+    assert abs(t[0] - r.terms[1]) / n <= tol["e"]        # U_NEP
+    assert abs(t[2] - r.terms[3]) / n <= tol["e"]        # U_k
+    assert abs(t[5] - r.terms[6]) <= 1e-4 * n ** 0.5     # sum of raw charges
+
+
+def _oracle(orc, hp, es, sysm, theta):
+    return orc.compute(hp, es, sysm.pos, sysm.types, sysm.cell, theta, cells=sysm.n > 1000)
+
+
+def test_water192_ewald(torch_dev, orc):
+    w = inputs.workload(0)
+    _say("case water-192 Ewald mode 1")
+    g = run_gpu(w.hp, w.es, w.system, w.theta)
+    r = _oracle(orc, w.hp, w.es, w.system, w.theta)
+    compare(g, r, w.system.n, label="water192-ewald")
+    assert g["energy_terms"][7] == r.terms[9]  # same wave-vector set (924)
+
+
+def test_water192_mode2_and_charge(torch_dev, orc):
+    w = inputs.workload(0)
+    for mode, Q in ((2, 0.0), (1, 0.7), (2, -1.1)):
+        es = copy.copy(w.es)
+        es.mode, es.q_total = mode, Q
+        _say(f"case water-192 Ewald mode {mode} Q={Q}")
+        g = run_gpu(w.hp, es, w.system, w.theta)
+        r = _oracle(orc, w.hp, es, w.system, w.theta)
+        compare(g, r, w.system.n, label=f"water192-m{mode}-Q{Q}")
+        assert abs(r.q_naked.sum() - Q) < 1e-10
+
+
+def test_water192_pppm(torch_dev, orc):
+    w = inputs.workload(0)
+    es = copy.copy(w.es)
+    es.method, es.mesh, es.order = 1, (16, 15, 18), 5
+    _say("case water-192 PPPM 16x15x18")
+    g = run_gpu(w.hp, es, w.system, w.theta)
+    r = _oracle(orc, w.hp, es, w.system, w.theta)
+    compare(g, r, w.system.n, label="water192-pppm")
+
+
+def test_water3000_pppm_and_ewald(torch_dev, orc):
+    w = inputs.workload(1, "crop")
+    _say("case water-3000 PPPM 32^3")
+    g = run_gpu(w.hp, w.es, w.system, w.theta)
+    r = _oracle(orc, w.hp, w.es, w.system, w.theta)
+    compare(g, r, w.system.n, label="water3000-pppm")
+    es = copy.copy(w.es)
+    es.method = 0
+    _say("case water-3000 Ewald kmax=2 pi alpha")
+    g = run_gpu(w.hp, es, w.system, w.theta)
+    r = _oracle(orc, w.hp, es, w.system, w.theta)
+    compare(g, r, w.system.n, label="water3000-ewald")
+
+
+def test_perovskite5000_pppm(torch_dev, orc):
+    w = inputs.workload(3, "crop")
+    _say("case perovskite-5000 PPPM 45^3")
+    g = run_gpu(w.hp, w.es, w.system, w.theta)
+    r = _oracle(orc, w.hp, w.es, w.system, w.theta)
+    compare(g, r, w.system.n, label="perovskite5000-pppm")
+
+
+def test_garnet768_pppm(torch_dev, orc):
+    w = inputs.workload(2, "crop")
+    _say("case garnet-768 PPPM 24^3")
+    g = run_gpu(w.hp, w.es, w.system, w.theta)
+    r = _oracle(orc, w.hp, w.es, w.system, w.theta)
+    compare(g, r, w.system.n, label="garnet768-pppm")
+
+
+def test_small_ragged_and_triclinic(torch_dev, orc):
+    hp = inputs.WATER_HP
+    th = inputs.theta0(hp, 17)
+    # 37 molecules (111 atoms) in a 10.3 A box: several images of every neighbour
+    s = inputs.water_box(4, spacing=10.3 / 4, seed=21, n_mol=37)
+    es = inputs.ESParams(mode=1, method=0, alpha=0.35, rc_coul=9.0, kmax=2.2)
+    _say("case water-111 small box")
+    compare(run_gpu(hp, es, s, th), _oracle(orc, hp, es, s, th), s.n, label="water111")
+    # sheared (triclinic) cell, positions re-wrapped
+    cell = s.cell.copy()
+    cell[1, 0] = 1.7
+    cell[2, 0] = -0.9
+    cell[2, 1] = 1.1
+    t = inputs._finish("tri", s.pos, s.types, cell)
+    _say("case water-111 triclinic")
+    compare(run_gpu(hp, es, t, th), _oracle(orc, hp, es, t, th), t.n, label="water111-tri")
+    es_p = inputs.ESParams(mode=1, method=1, alpha=0.35, rc_coul=9.0, mesh=(12, 12, 12))
+    _say("case water-111 triclinic PPPM")
+    compare(run_gpu(hp, es_p, t, th), _oracle(orc, hp, es_p, t, th), t.n, label="water111-tri-pppm")
+
+
+def test_positions_outside_the_cell(torch_dev, orc):
+    w = inputs.workload(0)
+    s = copy.deepcopy(w.system)
+    shift = np.zeros_like(s.pos)
+    shift[::3] = s.cell[0] * 2 - s.cell[2]
+    s2 = inputs.System("shifted", (s.pos + shift).astype(np.float32).astype(np.float64), s.types, s.cell)
+    _say("case water-192 shifted images")
+    g = run_gpu(w.hp, w.es, s2, w.theta)
+    r = _oracle(orc, w.hp, w.es, s2, w.theta)
+    compare(g, r, s.n, tol=dict(TOL, f=2e-4, z=2e-4), label="water192-shifted")
+
+
+def test_empty_and_single_atom(torch_dev, orc):
+    hp = inputs.WATER_HP
+    th = inputs.theta0(hp, 3)
+    es = inputs.ESParams(mode=1, method=0, alpha=0.3, rc_coul=9.0, kmax=1.9)
+    empty = inputs.System("empty", np.zeros((0, 3)), np.zeros(0, dtype=np.int32), np.eye(3) * 10)
+    _say("case empty")
+    g = run_gpu(hp, es, empty, th)
+    assert g["energy"][0] == 0.0 and np.all(g["virial"] == 0) and np.all(g["polarization"] == 0)
+    one = inputs.System("one", np.array([[1.0, 2.0, 3.0]]), np.array([1], dtype=np.int32), np.eye(3) * 7.0)
+    _say("case single atom")
+    compare(run_gpu(hp, es, one, th), _oracle(orc, hp, es, one, th), 1, label="single")
+
+
+def test_bad_species_flag(torch_dev):
+    """A species index outside [0, T) raises QNEP_FLAG_BAD_SPECIES (the kernels clamp it
+    internally, so nothing is read out of bounds)."""
+    from paper_2601_19034_amd import binding as B
+    from paper_2601_19034_amd.api import QNEP, to_device_inputs
+
+    w = inputs.workload(0)
+    s = copy.deepcopy(w.system)
+    s.types = s.types.copy()
+    s.types[5] = 2  # the water model has two species
+    model = QNEP(w.hp)
+    pos, types, th = to_device_inputs(s, w.theta)
+    _say("case bad species")
+    model.compute(pos, types, s.cell, th, w.es)
+    assert model.check_status() == B.FLAG_BAD_SPECIES
+    pos, types, th = to_device_inputs(w.system, w.theta)
+    model.compute(pos, types, w.system.cell, th, w.es)
+    assert model.check_status() == 0  # the flag is cleared by the next call
+
+
+def test_water24000_full(torch_dev, orc):
+    w = inputs.workload(1)
+    _say("case water-24000 PPPM 64^3 (full size)")
+    g = run_gpu(w.hp, w.es, w.system, w.theta)
+    r = _oracle(orc, w.hp, w.es, w.system, w.theta)
+    compare(g, r, w.system.n, label="water24000-pppm")
