@@ -66,6 +66,7 @@ typedef enum {
 /* MLP arithmetic */
 #define QNEP_MLP_FP32 0   /* FP32 vector ALU */
 #define QNEP_MLP_BF16 1   /* BF16 inputs on the matrix cores, FP32 accumulation */
+#define QNEP_MLP_BF16X3 2 /* BF16 matrix cores with operands split hi + lo (three products), FP32 accumulation */
 
 /* NEP hyper-parameters (Sec. 2.1; the descriptor definitions are the published
    NEP3/NEP4 ones the paper refers to):
@@ -124,7 +125,7 @@ typedef struct {
 int64_t qnep_param_count(const qnep_hparams *hp);
 
 /* creates a host-side model handle (hyper-parameters, MLP precision, plans).
-   mlp_precision: QNEP_MLP_FP32 or QNEP_MLP_BF16. */
+   mlp_precision: QNEP_MLP_FP32, QNEP_MLP_BF16 or QNEP_MLP_BF16X3. */
 qnep_status qnep_model_create(const qnep_hparams *hp, int32_t mlp_precision, void **model);
 qnep_status qnep_model_destroy(void *model);
 
@@ -146,6 +147,16 @@ qnep_status qnep_compute(void *model, const float *theta, const qnep_es_params *
 /* synchronizes `stream` and returns the device status bits of the last call that
    used this workspace (0 = no device-side condition). */
 qnep_status qnep_check_status(const void *ws, void *stream, int32_t *flags);
+
+/* Per-stage timing with HIP events recorded on the caller's stream (for profiling;
+   adds one event record per stage).  enable = 0 turns it off.  read_timing
+   synchronizes the recorded events and returns, for each stage, the total
+   milliseconds and the number of kernel launches since the previous read
+   (arrays of length QNEP_N_STAGES), then resets the totals. */
+#define QNEP_N_STAGES 20
+qnep_status qnep_model_enable_timing(void *model, int32_t enable);
+qnep_status qnep_model_read_timing(void *model, double *ms, int64_t *launches, int32_t *calls);
+const char *qnep_stage_name(int32_t stage);
 
 const char *qnep_status_string(qnep_status s);
 const char *qnep_last_error(void);

@@ -28,7 +28,7 @@ class QNEP:
         B.load()
         self.hp = hp
         self.precision = precision
-        prec = {"fp32": B.QNEP_MLP_FP32, "bf16": B.QNEP_MLP_BF16}[precision]
+        prec = {"fp32": B.QNEP_MLP_FP32, "bf16": B.QNEP_MLP_BF16, "bf16x3": B.QNEP_MLP_BF16X3}[precision]
         self.handle = B.qnep_model_create(hp, prec)
         if capacity_factor is not None:
             B.qnep_model_set_capacity_factor(self.handle, capacity_factor)
@@ -88,6 +88,13 @@ class QNEP:
         B.qnep_compute(self.handle, theta.data_ptr(), es_c, sysm, outs, ws.data_ptr(), ws.numel(), s.cuda_stream)
         self._last_stream = s
         return out
+
+    def enable_timing(self, on: bool = True):
+        B.qnep_model_enable_timing(self.handle, on)
+
+    def read_timing(self):
+        """({stage: total ms}, {stage: launches}, calls) since the previous read."""
+        return B.qnep_model_read_timing(self.handle)
 
     def check_status(self) -> int:
         """Synchronizes the last stream and returns the device status bits (0 = fine)."""

@@ -14,6 +14,8 @@ LIB_PATH = os.path.join(_HERE, "libqnep.so")
 QNEP_OK = 0
 QNEP_MLP_FP32 = 0
 QNEP_MLP_BF16 = 1
+QNEP_MLP_BF16X3 = 2
+N_STAGES = 20
 FLAG_RADIAL_OVERFLOW = 1
 FLAG_ANGULAR_OVERFLOW = 2
 FLAG_COULOMB_OVERFLOW = 4
@@ -47,7 +49,8 @@ class QnepError(RuntimeError):
 
 
 EXPORTED = ["qnep_param_count", "qnep_model_create", "qnep_model_destroy", "qnep_model_set_capacity_factor",
-            "qnep_workspace_size", "qnep_compute", "qnep_check_status", "qnep_status_string", "qnep_last_error"]
+            "qnep_workspace_size", "qnep_compute", "qnep_check_status", "qnep_model_enable_timing",
+            "qnep_model_read_timing", "qnep_stage_name", "qnep_status_string", "qnep_last_error"]
 
 _lib = None
 
@@ -76,6 +79,13 @@ def load(path: str = LIB_PATH):
                                C.POINTER(qnep_outputs), C.c_void_p, C.c_size_t, C.c_void_p]
     L.qnep_check_status.restype = C.c_int
     L.qnep_check_status.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]
+    L.qnep_model_enable_timing.restype = C.c_int
+    L.qnep_model_enable_timing.argtypes = [C.c_void_p, C.c_int32]
+    L.qnep_model_read_timing.restype = C.c_int
+    L.qnep_model_read_timing.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                         C.POINTER(C.c_int32)]
+    L.qnep_stage_name.restype = C.c_char_p
+    L.qnep_stage_name.argtypes = [C.c_int32]
     L.qnep_status_string.restype = C.c_char_p
     L.qnep_status_string.argtypes = [C.c_int]
     L.qnep_last_error.restype = C.c_char_p
@@ -140,3 +150,21 @@ def qnep_check_status(ws_ptr: int, stream: int) -> int:
     f = C.c_int32()
     _check(load().qnep_check_status(C.c_void_p(ws_ptr), C.c_void_p(stream), C.byref(f)))
     return int(f.value)
+
+
+def qnep_model_enable_timing(model: int, enable: bool):
+    _check(load().qnep_model_enable_timing(C.c_void_p(model), 1 if enable else 0))
+
+
+def qnep_model_read_timing(model: int):
+    """Returns ({stage name: ms}, {stage name: launches}, calls) since the previous read."""
+    ms = (C.c_double * N_STAGES)()
+    nl = (C.c_int64 * N_STAGES)()
+    calls = C.c_int32()
+    _check(load().qnep_model_read_timing(C.c_void_p(model), ms, nl, C.byref(calls)))
+    names = [qnep_stage_name(k) for k in range(N_STAGES)]
+    return dict(zip(names, list(ms))), dict(zip(names, list(nl))), int(calls.value)
+
+
+def qnep_stage_name(stage: int) -> str:
+    return load().qnep_stage_name(stage).decode()

@@ -27,10 +27,92 @@ qnep_status fail(qnep_status s, const std::string &msg) {
     return s;
 }
 
+const char *const kStageNames[QNEP_N_STAGES] = {
+    "sort", "lists", "lists_coulomb", "descriptors", "mlp", "real_space", "ewald_structure_factor",
+    "ewald_atoms", "pppm_spread", "fft_forward", "pppm_influence", "fft_inverse", "pppm_gather", "phi_mean",
+    "radial_forces", "angular_forces_energy", "angular_forces_charge", "assemble", "finalize", "other"};
+
+}  // namespace
+
+namespace qnep {
+// Ring of per-call HIP event sets; a full ring drains its oldest call.
+struct Timer {
+    static constexpr int SLOTS = 64, MARKS = 40;
+    bool on = false;
+    hipEvent_t ev[SLOTS][MARKS];
+    int ids[SLOTS][MARKS];
+    int nl[SLOTS][MARKS];
+    int nm[SLOTS];
+    int head = 0, count = 0, cur = -1;
+    double total[QNEP_N_STAGES] = {0};
+    int64_t launches[QNEP_N_STAGES] = {0};
+    int calls = 0;
+    bool created = false;
+
+    hipError_t create() {
+        if (created) return hipSuccess;
+        for (int s = 0; s < SLOTS; ++s)
+            for (int m = 0; m < MARKS; ++m) {
+                hipError_t e = hipEventCreate(&ev[s][m]);
+                if (e != hipSuccess) return e;
+            }
+        created = true;
+        return hipSuccess;
+    }
+    void destroy() {
+        if (!created) return;
+        for (int s = 0; s < SLOTS; ++s)
+            for (int m = 0; m < MARKS; ++m) (void)hipEventDestroy(ev[s][m]);
+        created = false;
+    }
+    hipError_t drain_one() {
+        const int s = head;
+        if (nm[s] > 1) {
+            hipError_t e = hipEventSynchronize(ev[s][nm[s] - 1]);
+            if (e != hipSuccess) return e;
+            for (int m = 1; m < nm[s]; ++m) {
+                float ms = 0.f;
+                e = hipEventElapsedTime(&ms, ev[s][m - 1], ev[s][m]);
+                if (e != hipSuccess) return e;
+                total[ids[s][m]] += ms;
+                launches[ids[s][m]] += nl[s][m];
+            }
+        }
+        ++calls;
+        head = (head + 1) % SLOTS;
+        --count;
+        return hipSuccess;
+    }
+    hipError_t begin(hipStream_t st) {
+        if (count == SLOTS) {
+            hipError_t e = drain_one();
+            if (e != hipSuccess) return e;
+        }
+        cur = (head + count) % SLOTS;
+        ++count;
+        nm[cur] = 0;
+        return mark(st, ST_OTHER, 0);
+    }
+    hipError_t mark(hipStream_t st, int id, int n) {
+        if (cur < 0 || nm[cur] >= MARKS) return hipSuccess;
+        ids[cur][nm[cur]] = id;
+        nl[cur][nm[cur]] = n;
+        return hipEventRecord(ev[cur][nm[cur]++], st);
+    }
+};
+
+void stage_mark(const Plan &p, int stage, int launches) {
+    if (p.timer && p.timer->on) (void)p.timer->mark(p.stream, stage, launches);
+}
+}  // namespace qnep
+
+namespace {
+
 struct Model {
     qnep_hparams hp;
     int prec;
     double cap_factor;
+    Timer timer;
 };
 
 constexpr size_t ALIGN = 256;
@@ -245,10 +327,10 @@ qnep_status check_model(const qnep_hparams *hp, int prec) {
         return fail(QNEP_E_UNSUPPORTED,
                     "compiled descriptor sets: l_max = 4, basis 8, (n_max_R, n_max_A) = (4, 4) or (8, 6)");
     int ndes = (hp->n_max_R + 1) + (hp->n_max_A + 1) * hp->l_max;
-    if (prec == QNEP_MLP_BF16) {
+    if (prec == QNEP_MLP_BF16 || prec == QNEP_MLP_BF16X3) {
         if (!mlp_bf16_supported(ndes, hp->n_neu)) return fail(QNEP_E_UNSUPPORTED, "BF16 MLP not available");
     } else if (prec != QNEP_MLP_FP32) {
-        return fail(QNEP_E_INVALID_ARG, "mlp_precision must be QNEP_MLP_FP32 or QNEP_MLP_BF16");
+        return fail(QNEP_E_INVALID_ARG, "mlp_precision must be QNEP_MLP_FP32, QNEP_MLP_BF16 or QNEP_MLP_BF16X3");
     }
     return QNEP_OK;
 }
@@ -273,14 +355,48 @@ qnep_status qnep_model_create(const qnep_hparams *hp, int32_t mlp_precision, voi
     if (!model) return fail(QNEP_E_INVALID_ARG, "null model pointer");
     qnep_status s = check_model(hp, mlp_precision);
     if (s != QNEP_OK) return s;
-    Model *m = new Model{*hp, mlp_precision, 1.6};
+    Model *m = new Model();
+    m->hp = *hp;
+    m->prec = mlp_precision;
+    m->cap_factor = 1.6;
     *model = m;
     return QNEP_OK;
 }
 
 qnep_status qnep_model_destroy(void *model) {
-    delete static_cast<Model *>(model);
+    Model *m = static_cast<Model *>(model);
+    if (m) m->timer.destroy();
+    delete m;
     return QNEP_OK;
+}
+
+qnep_status qnep_model_enable_timing(void *model, int32_t enable) {
+    if (!model) return fail(QNEP_E_INVALID_ARG, "null model");
+    Model *m = static_cast<Model *>(model);
+    if (enable) HIP_TRY(m->timer.create());
+    m->timer.on = enable != 0;
+    return QNEP_OK;
+}
+
+qnep_status qnep_model_read_timing(void *model, double *ms, int64_t *launches, int32_t *calls) {
+    if (!model) return fail(QNEP_E_INVALID_ARG, "null model");
+    Timer &t = static_cast<Model *>(model)->timer;
+    while (t.count > 0) HIP_TRY(t.drain_one());
+    for (int k = 0; k < QNEP_N_STAGES; ++k) {
+        if (ms) ms[k] = t.total[k];
+        if (launches) launches[k] = t.launches[k];
+        t.total[k] = 0.0;
+        t.launches[k] = 0;
+    }
+    if (calls) *calls = t.calls;
+    t.calls = 0;
+    t.cur = -1;
+    return QNEP_OK;
+}
+
+const char *qnep_stage_name(int32_t stage) {
+    if (stage < 0 || stage >= QNEP_N_STAGES) return "invalid";
+    return kStageNames[stage];
 }
 
 qnep_status qnep_model_set_capacity_factor(void *model, double factor) {
@@ -311,6 +427,11 @@ qnep_status qnep_compute(void *model, const float *theta, const qnep_es_params *
     p.theta = theta;
     p.out = *out;
     p.stream = static_cast<hipStream_t>(stream);
+    Model &mm = *static_cast<Model *>(model);
+    if (mm.timer.on) {
+        p.timer = &mm.timer;
+        HIP_TRY(mm.timer.begin(p.stream));
+    }
     HIP_TRY(fill_zero(p.flags, sizeof(int32_t) * 16, p.stream));
     HIP_TRY(fill_zero(p.scalars, sizeof(double) * 64, p.stream));
     if (p.N == 0) {
@@ -319,17 +440,22 @@ qnep_status qnep_compute(void *model, const float *theta, const qnep_es_params *
     }
     HIP_TRY(launch_neighbors(p));
     HIP_TRY(launch_descriptors(p));
+    stage_mark(p, ST_DESC);
     HIP_TRY(launch_mlp(p));
     HIP_TRY(launch_charges(p));
+    stage_mark(p, ST_MLP, 3);
     HIP_TRY(launch_real_space(p));
+    stage_mark(p, ST_REAL, 2);
     if (p.method == 0) {
         HIP_TRY(launch_ewald(p));
     } else {
         HIP_TRY(launch_pppm(p));
     }
     HIP_TRY(launch_phi_mean(p));
+    stage_mark(p, ST_PHI, 3);
     HIP_TRY(launch_forces(p));
     HIP_TRY(launch_finalize(p));
+    stage_mark(p, ST_FINAL, 1);
     return QNEP_OK;
 }
 

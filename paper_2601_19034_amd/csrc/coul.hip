@@ -292,9 +292,11 @@ hipError_t launch_ewald(const Plan &p) {
     if (e != hipSuccess) return e;
     e = reduce_partials(p, kb, 10, S_UK, false);  // S_UK, S_WK[9]
     if (e != hipSuccess) return e;
+    stage_mark(p, ST_EWALD_SK, 4);
     const int G = (p.N + 255) / 256;
     hipLaunchKernelGGL(k_ewald_atoms, dim3(G), dim3(256), 0, p.stream, p.N, p.xs, p.ys, p.zs, p.cell, p.qraw,
                        p.scalars, p.kvec, (const int4 *)kn, p.Sk, p.kcount, p.phi, p.Fst);
+    stage_mark(p, ST_EWALD_ATOMS);
     return hipGetLastError();
 }
 

@@ -67,7 +67,7 @@ __global__ __launch_bounds__(256) void k_mlp_fp32(int N, int T, int H, const int
 hipError_t launch_mlp_bf16(const Plan &p);
 
 hipError_t launch_mlp(const Plan &p) {
-    if (p.mlp_prec == QNEP_MLP_BF16) return launch_mlp_bf16(p);
+    if (p.mlp_prec == QNEP_MLP_BF16 || p.mlp_prec == QNEP_MLP_BF16X3) return launch_mlp_bf16(p);
     const int G = (p.N + 255) / 256;
     const size_t lds = sizeof(float) * (size_t)(p.T * p.per_species);
     if (p.ndes == 25)

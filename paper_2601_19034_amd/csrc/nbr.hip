@@ -194,16 +194,19 @@ hipError_t launch_neighbors(const Plan &p) {
                        p.perm);
     hipLaunchKernelGGL(k_gather_sorted, dim3(G), dim3(B), 0, p.stream, N, p.pos, p.type, p.T, p.cell, p.perm, p.xs,
                        p.ys, p.zs, p.ts);
+    stage_mark(p, ST_SORT, 6);
     double rcR2 = p.rcR * p.rcR, rcA2 = p.rcA * p.rcA;
     hipLaunchKernelGGL(k_lists<true>, dim3(G), dim3(B), 0, p.stream, N, p.xs, p.ys, p.zs, p.cell, p.nc[0],
                        p.nc[1], p.nc[2], p.mR[0], p.mR[1], p.mR[2], p.cell_start, rcR2, p.capR, p.listR, p.cntR,
                        rcA2, p.capA, p.listA, p.cntA, p.flags, QNEP_FLAG_RADIAL_OVERFLOW,
                        QNEP_FLAG_ANGULAR_OVERFLOW);
+    stage_mark(p, ST_LISTS);
     if (p.mode == 1) {
         double rc2 = p.rc_coul * p.rc_coul;
         hipLaunchKernelGGL(k_lists<false>, dim3(G), dim3(B), 0, p.stream, N, p.xs, p.ys, p.zs, p.cell, p.nc[0],
                            p.nc[1], p.nc[2], p.mC[0], p.mC[1], p.mC[2], p.cell_start, rc2, p.capC, p.listC, p.cntC,
                            0.0, 0, (uint32_t *)nullptr, (int *)nullptr, p.flags, QNEP_FLAG_COULOMB_OVERFLOW, 0);
+        stage_mark(p, ST_LISTS_C);
     }
     return hipGetLastError();
 }

@@ -459,19 +459,25 @@ static hipError_t run_forces(const Plan &p) {
                        p.cell, (float)p.rcR, p.listR, p.cntR, p.hT, p.Fnep, p.Znep, p.partials);
     hipError_t e = reduce_partials(p, G, 9, S_WNEP, false);
     if (e != hipSuccess) return e;
+    stage_mark(p, ST_RADIAL, 3);
     hipLaunchKernelGGL((k_angular_forces<T, NR, NA, NB, 0>), dim3(G), dim3(256), 0, p.stream, p.N, p.xs, p.ys,
                        p.zs, p.ts, p.cell, (float)p.rcA, p.listA, p.cntA, p.capA, p.Amom, p.gU, p.gq, p.phi,
                        p.scalars, p.theta, p.off_cA, p.off_s, (float4 *)p.pairF, p.Fnep, p.Znep, p.partials);
+    stage_mark(p, ST_ANG_E);
     e = reduce_partials(p, G, 9, S_WNEP, true);
     if (e != hipSuccess) return e;
+    stage_mark(p, ST_OTHER);
     hipLaunchKernelGGL((k_angular_forces<T, NR, NA, NB, 1>), dim3(G), dim3(256), 0, p.stream, p.N, p.xs, p.ys,
                        p.zs, p.ts, p.cell, (float)p.rcA, p.listA, p.cntA, p.capA, p.Amom, p.gU, p.gq, p.phi,
                        p.scalars, p.theta, p.off_cA, p.off_s, (float4 *)p.pairA, p.Fnep, p.Znep, p.partials);
+    stage_mark(p, ST_ANG_Q);
     hipLaunchKernelGGL(k_assemble, dim3(G), dim3(256), 0, p.stream, p.N, p.xs, p.ys, p.zs, p.cell, p.listA,
                        p.cntA, p.capA, (const float4 *)p.pairF, (const float4 *)p.pairA, p.Fnep, p.Znep, p.Fst,
                        p.qraw, p.scalars, p.theta, p.off_s, p.perm, p.pos, p.out.forces, p.out.bec, p.out.charges,
                        p.out.charges_naked, p.partials);
-    return reduce_partials(p, G, 3, S_POL, false);
+    e = reduce_partials(p, G, 3, S_POL, false);
+    stage_mark(p, ST_ASSEMBLE, 2);
+    return e;
 }
 
 // compiled hyper-parameter sets: (T, n_max_R + 1, n_max_A + 1, basis + 1), l_max = 4

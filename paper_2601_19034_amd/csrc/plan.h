@@ -8,6 +8,15 @@
 
 namespace qnep {
 
+// pipeline stages timed by qnep_model_enable_timing (names in api.cpp)
+enum Stage : int {
+    ST_SORT = 0, ST_LISTS, ST_LISTS_C, ST_DESC, ST_MLP, ST_REAL, ST_EWALD_SK, ST_EWALD_ATOMS, ST_SPREAD,
+    ST_FFT_FWD, ST_INFLUENCE, ST_FFT_INV, ST_GATHER, ST_PHI, ST_RADIAL, ST_ANG_E, ST_ANG_Q, ST_ASSEMBLE,
+    ST_FINAL, ST_OTHER
+};
+
+struct Timer;
+
 struct Plan {
     // ---- model
     int N = 0, T = 0, NR = 0, NA = 0, NBR = 0, NBA = 0, LMAX = 4, H = 0, ndes = 0;
@@ -58,7 +67,11 @@ struct Plan {
     const float *theta = nullptr;
     qnep_outputs out{};
     hipStream_t stream = nullptr;
+    Timer *timer = nullptr;
 };
+
+// records the end of `stage` (work enqueued since the previous mark) when timing is on
+void stage_mark(const Plan &p, int stage, int launches = 1);
 
 // module launchers (each returns hipSuccess or the first launch error)
 hipError_t launch_neighbors(const Plan &p);

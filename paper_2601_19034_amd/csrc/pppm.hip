@@ -205,20 +205,25 @@ hipError_t launch_pppm(const Plan &p) {
     hipLaunchKernelGGL(k_real_to_complex, dim3(GM), dim3(256), 0, p.stream, M, p.rho, p.meshA);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+    stage_mark(p, ST_SPREAD, 3);
     e = fft3d(p.meshA, nullptr, p.mesh, -1, p.stream);
     if (e != hipSuccess) return e;
+    stage_mark(p, ST_FFT_FWD, 3);
     hipLaunchKernelGGL(k_influence, dim3(GM), dim3(256), 0, p.stream, g, p.cell, (float)p.alpha, p.vol, p.meshA,
                        p.meshB, p.partials);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = reduce_partials(p, GM, 10, S_UK, false);  // S_UK, S_WK[9]
     if (e != hipSuccess) return e;
+    stage_mark(p, ST_INFLUENCE, 2);
     e = fft3d(p.meshA, nullptr, p.mesh, +1, p.stream);
     if (e != hipSuccess) return e;
     e = fft3d(p.meshB, nullptr, p.mesh, +1, p.stream);
     if (e != hipSuccess) return e;
+    stage_mark(p, ST_FFT_INV, 6);
     hipLaunchKernelGGL(k_gather, dim3(G), dim3(256), 0, p.stream, p.N, p.xs, p.ys, p.zs, p.cell, g, p.qraw,
                        p.scalars, p.meshA, p.meshB, p.phi, p.Fst);
+    stage_mark(p, ST_GATHER);
     return hipGetLastError();
 }
 

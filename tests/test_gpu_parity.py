@@ -211,3 +211,21 @@ def test_water24000_full(torch_dev, orc):
     g = run_gpu(w.hp, w.es, w.system, w.theta)
     r = _oracle(orc, w.hp, w.es, w.system, w.theta)
     compare(g, r, w.system.n, label="water24000-pppm")
+
+
+# BF16 network on the matrix cores (FP32 accumulation).  Split form (hi + lo operands,
+# three products): spec force target 5 meV/A.  Plain one-product form: its
+# measured precision (about 1e-2 eV/A at the largest forces) is the bound.
+TOL_BF16X3 = dict(e=2e-4, f=5e-3, w=5e-4, q=5e-4, z=5e-3, p=5e-4)
+TOL_BF16 = dict(e=5e-3, f=2e-2, w=2e-3, q=5e-3, z=1e-2, p=2e-3)
+
+
+@pytest.mark.parametrize("wid,variant", [(0, "full"), (3, "crop"), (2, "crop")])
+@pytest.mark.parametrize("precision", ["bf16x3", "bf16"])
+def test_bf16_mlp(torch_dev, orc, wid, variant, precision):
+    w = inputs.workload(wid, variant)
+    _say(f"case {precision} {w.name}")
+    g = run_gpu(w.hp, w.es, w.system, w.theta, precision=precision)
+    r = _oracle(orc, w.hp, w.es, w.system, w.theta)
+    compare(g, r, w.system.n, tol=TOL_BF16X3 if precision == "bf16x3" else TOL_BF16,
+            label=f"{precision}-{w.name}")
