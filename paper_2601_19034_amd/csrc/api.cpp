@@ -14,6 +14,7 @@ namespace qnep {
 bool nep_supported(int T, int NR, int NA, int NBR, int NBA, int LMAX);
 hipError_t launch_phi_mean(const Plan &p);
 bool mlp_bf16_supported(int ndes, int H);
+int radial_table_row(int NB);
 }  // namespace qnep
 
 using namespace qnep;
@@ -231,7 +232,7 @@ qnep_status make_plan(const Model &m, const qnep_es_params *es, const qnep_syste
         return fail(QNEP_E_INVALID_ARG, "cell must be non-singular and right-handed");
     double w[3];
     cell_widths(p.cell.h, p.vol, w);
-    const double rbin = std::max(p.rcR, p.rcA);
+    const double rbin = 0.5 * std::max(p.rcR, p.rcA);
     for (int a = 0; a < 3; ++a) {
         p.nc[a] = std::max(1, (int)std::floor(w[a] / rbin));
         p.mR[a] = (int)std::ceil(rbin * p.nc[a] / w[a] - 1e-12);
@@ -245,7 +246,6 @@ qnep_status make_plan(const Model &m, const qnep_es_params *es, const qnep_syste
     const double density = p.N / p.vol;
     p.capR = capacity(density, p.rcR, m.cap_factor);
     p.capA = capacity(density, p.rcA, m.cap_factor);
-    p.capC = p.mode == 1 ? capacity(density, p.rc_coul, m.cap_factor) : 0;
     p.nblk = (p.N + RED_THREADS - 1) / RED_THREADS;
     int64_t red_blocks = std::max(p.nblk, 1);
     if (p.method == 0) {
@@ -277,19 +277,14 @@ qnep_status make_plan(const Model &m, const qnep_es_params *es, const qnep_syste
     p.cell_count = c.take<int>(p.ncell);
     p.cell_start = c.take<int>(p.ncell + 1);
     p.cell_cursor = c.take<int>(p.ncell);
+    p.scan_tmp = c.take<int>((p.ncell + 1023) / 1024 + 1);
     p.perm = c.take<int>(N);
-    p.xs = c.take<float>(N);
-    p.ys = c.take<float>(N);
-    p.zs = c.take<float>(N);
+    p.xyzt = c.take<float4>(N);
     p.ts = c.take<int>(N);
     p.listR = c.take<uint32_t>((size_t)p.capR * N);
     p.cntR = c.take<int>(N);
     p.listA = c.take<uint32_t>((size_t)p.capA * N);
     p.cntA = c.take<int>(N);
-    if (p.mode == 1) {
-        p.listC = c.take<uint32_t>((size_t)p.capC * N);
-        p.cntC = c.take<int>(N);
-    }
     p.D = c.take<float>((size_t)p.ndes * N);
     p.Amom = c.take<float>((size_t)p.NA * LM * N);
     p.U = c.take<float>(N);
@@ -298,7 +293,7 @@ qnep_status make_plan(const Model &m, const qnep_es_params *es, const qnep_syste
     p.gq = c.take<float>((size_t)p.ndes * N);
     p.phi = c.take<float>(N);
     p.Fst = c.take<float>(3 * (size_t)N);
-    p.hT = c.take<float>((size_t)2 * p.T * p.NBR * N);
+    p.hT = c.take<float>((size_t)2 * p.T * radial_table_row(p.NBR) * N);
     p.pairF = c.take<float>((size_t)4 * p.capA * N);
     p.pairA = c.take<float>((size_t)4 * p.capA * N);
     p.Fnep = c.take<float>(3 * (size_t)N);

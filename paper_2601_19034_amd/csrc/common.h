@@ -38,22 +38,49 @@ __device__ inline uint32_t nb_reverse(uint32_t e, int i) {
     return (uint32_t)i | ((6u - c1) << 23) | ((6u - c2) << 26) | ((6u - c3) << 29);
 }
 
-// Displacement r_j + n.h - r_i formed in FP64 from the FP32 coordinates and
-// rounded once to FP32.  The difference of two FP32 numbers is exact in FP64 and
-// IEEE rounding is odd-symmetric, so the (j,i,-n) displacement is the exact
-// negation of the (i,j,n) one.
-__device__ inline float3 displacement(const float *__restrict__ x, const float *__restrict__ y,
-                                      const float *__restrict__ z, int i, uint32_t e, const Cell &c) {
-    int j = nb_index(e), n1, n2, n3;
-    nb_image(e, n1, n2, n3);
-    double sx = n1 * c.h[0] + n2 * c.h[3] + n3 * c.h[6];
-    double sy = n1 * c.h[1] + n2 * c.h[4] + n3 * c.h[7];
-    double sz = n1 * c.h[2] + n2 * c.h[5] + n3 * c.h[8];
-    double dx = ((double)x[j] - (double)x[i]) + sx;
-    double dy = ((double)y[j] - (double)y[i]) + sy;
-    double dz = ((double)z[j] - (double)z[i]) + sz;
-    return make_float3((float)dx, (float)dy, (float)dz);
+__device__ inline int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+// bin of a (wrapped) position: floor(s_a n_a) with s = r h^{-1} in FP64, clamped
+__device__ inline void bin_of(float4 p, const Cell &c, int nc0, int nc1, int nc2, int *ci) {
+    const int nc[3] = {nc0, nc1, nc2};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double s = (double)p.x * c.hinv[a] + (double)p.y * c.hinv[3 + a] + (double)p.z * c.hinv[6 + a];
+        int k = (int)floor(s * nc[a]);
+        ci[a] = k < 0 ? 0 : (k >= nc[a] ? nc[a] - 1 : k);
+    }
 }
+
+// Lattice shift n.h of one periodic image, in FP64 and rounded to FP32.
+struct ImageShift {
+    double sx, sy, sz;
+    float fx, fy, fz;
+    __device__ ImageShift(const Cell &c, int n1, int n2, int n3) {
+        sx = n1 * c.h[0] + n2 * c.h[3] + n3 * c.h[6];
+        sy = n1 * c.h[1] + n2 * c.h[4] + n3 * c.h[7];
+        sz = n1 * c.h[2] + n2 * c.h[5] + n3 * c.h[8];
+        fx = (float)sx;
+        fy = (float)sy;
+        fz = (float)sz;
+    }
+    // r_j + n.h - r_i formed in FP64 from the FP32 coordinates and rounded once to
+    // FP32.  The difference of two FP32 numbers is exact in FP64 and IEEE rounding is
+    // odd-symmetric, so the (j, i, -n) displacement is the exact negation of (i, j, n).
+    __device__ float3 exact(float4 pi, float4 pj) const {
+        return make_float3((float)(((double)pj.x - (double)pi.x) + sx), (float)(((double)pj.y - (double)pi.y) + sy),
+                           (float)(((double)pj.z - (double)pi.z) + sz));
+    }
+};
+
+// displacement to the neighbour encoded in e, from atom i at position pi
+__device__ inline float3 displacement(float4 pi, const float4 *__restrict__ xyzt, uint32_t e, const Cell &c) {
+    int n1, n2, n3;
+    nb_image(e, n1, n2, n3);
+    ImageShift sh(c, n1, n2, n3);
+    return sh.exact(pi, xyzt[nb_index(e)]);
+}
+
+__device__ inline int species_of(float4 p) { return __float_as_int(p.w); }
 
 // ---------------------------------------------------------------- reductions
 __device__ inline double wave_sum(double v) {

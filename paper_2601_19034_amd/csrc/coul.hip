@@ -11,43 +11,69 @@
 namespace qnep {
 
 // ---------------------------------------------------------------- real space
-__global__ __launch_bounds__(256) void k_real_space(int N, const float *__restrict__ xs,
-                                                    const float *__restrict__ ys, const float *__restrict__ zs,
-                                                    Cell c, const uint32_t *__restrict__ listC,
-                                                    const int *__restrict__ cntC, const float *__restrict__ qraw,
+// One thread per sorted atom walks the bin stencil of the real-space cutoff directly
+// (no stored list): candidates are screened in FP32, decided with the FP64
+// displacement rounded to FP32, and contribute phi^r_i, the static pair force
+// F_i = -k_e q'_i sum_j q'_j [erfc(a r)/r + 2a e^{-a^2 r^2}/sqrt(pi)] r_ij / r^2 and the
+// pair virial (each unordered pair is seen from both atoms with weight 1/2).
+__global__ __launch_bounds__(256) void k_real_space(int N, const float4 *__restrict__ xyzt, Cell c, int nc0,
+                                                    int nc1, int nc2, int m0, int m1, int m2,
+                                                    const int *__restrict__ start, double rc2,
+                                                    const float *__restrict__ qraw,
                                                     const double *__restrict__ scalars, float alpha,
                                                     float *__restrict__ phi, float *__restrict__ Fst,
                                                     double *__restrict__ partials) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double red[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (i < N) {
+        const float4 pi = xyzt[i];
+        int ci[3];
+        bin_of(pi, c, nc0, nc1, nc2, ci);
+        const float rc2_hi = (float)(rc2 * (1.0 + 1e-4));
         const float delta = (float)scalars[S_DELTA];
         const float qi = qraw[i] + delta;
         const float c2 = 2.0f * alpha * 0.5641895835477563f;  // 2 alpha / sqrt(pi)
         float ph = 0.f, bx = 0.f, by = 0.f, bz = 0.f;
         float wxx = 0.f, wyy = 0.f, wzz = 0.f, wxy = 0.f, wxz = 0.f, wyz = 0.f;
-        const int n = cntC[i];
-        for (int s = 0; s < n; ++s) {
-            uint32_t e = listC[(size_t)s * N + i];
-            float3 d = displacement(xs, ys, zs, i, e, c);
-            float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
-            float ir = rsqrtf(r2);
-            float r = r2 * ir;
-            float qj = qraw[nb_index(e)] + delta;
-            float ar = alpha * r;
-            float ec = erfcf(ar);
-            float ex = __expf(-ar * ar);
-            ph = fmaf(qj, ec * ir, ph);
-            float B = qj * (ec * ir + c2 * ex) * ir * ir;  // q_j [erfc/r + 2a e/sqrt(pi)] / r^2
-            bx = fmaf(B, d.x, bx);
-            by = fmaf(B, d.y, by);
-            bz = fmaf(B, d.z, bz);
-            wxx = fmaf(B, d.x * d.x, wxx);
-            wyy = fmaf(B, d.y * d.y, wyy);
-            wzz = fmaf(B, d.z * d.z, wzz);
-            wxy = fmaf(B, d.x * d.y, wxy);
-            wxz = fmaf(B, d.x * d.z, wxz);
-            wyz = fmaf(B, d.y * d.z, wyz);
+        for (int d0 = -m0; d0 <= m0; ++d0) {
+            int u0 = ci[0] + d0, i0 = floor_div(u0, nc0), w0 = u0 - i0 * nc0;
+            for (int d1 = -m1; d1 <= m1; ++d1) {
+                int u1 = ci[1] + d1, i1 = floor_div(u1, nc1), w1 = u1 - i1 * nc1;
+                for (int d2 = -m2; d2 <= m2; ++d2) {
+                    int u2 = ci[2] + d2, i2 = floor_div(u2, nc2), w2 = u2 - i2 * nc2;
+                    ImageShift sh(c, i0, i1, i2);
+                    const bool self_img = (i0 == 0 && i1 == 0 && i2 == 0);
+                    const int lin = (w0 * nc1 + w1) * nc2 + w2;
+                    const int b = start[lin], e = start[lin + 1];
+                    for (int j = b; j < e; ++j) {
+                        const float4 pj = xyzt[j];
+                        float fx = (pj.x - pi.x) + sh.fx, fy = (pj.y - pi.y) + sh.fy, fz = (pj.z - pi.z) + sh.fz;
+                        if (fx * fx + fy * fy + fz * fz >= rc2_hi) continue;
+                        if (self_img && j == i) continue;
+                        const float3 d = sh.exact(pi, pj);
+                        const double r2d = (double)d.x * d.x + (double)d.y * d.y + (double)d.z * d.z;
+                        if (r2d >= rc2) continue;
+                        const float r2 = (float)r2d;
+                        const float ir = rsqrtf(r2);
+                        const float r = r2 * ir;
+                        const float qj = qraw[j] + delta;
+                        const float ar = alpha * r;
+                        const float ec = erfcf(ar);
+                        const float ex = __expf(-ar * ar);
+                        ph = fmaf(qj, ec * ir, ph);
+                        const float B = qj * (ec * ir + c2 * ex) * ir * ir;
+                        bx = fmaf(B, d.x, bx);
+                        by = fmaf(B, d.y, by);
+                        bz = fmaf(B, d.z, bz);
+                        wxx = fmaf(B, d.x * d.x, wxx);
+                        wyy = fmaf(B, d.y * d.y, wyy);
+                        wzz = fmaf(B, d.z * d.z, wzz);
+                        wxy = fmaf(B, d.x * d.y, wxy);
+                        wxz = fmaf(B, d.x * d.z, wxz);
+                        wyz = fmaf(B, d.y * d.z, wyz);
+                    }
+                }
+            }
         }
         const float ke = (float)KE;
         phi[i] = ke * ph;
@@ -71,8 +97,9 @@ hipError_t launch_real_space(const Plan &p) {
         if (e != hipSuccess) return e;
         return fill_zero(p.Fst, sizeof(float) * 3 * (size_t)p.N, p.stream);
     }
-    hipLaunchKernelGGL(k_real_space, dim3(G), dim3(256), 0, p.stream, p.N, p.xs, p.ys, p.zs, p.cell, p.listC,
-                       p.cntC, p.qraw, p.scalars, (float)p.alpha, p.phi, p.Fst, p.partials);
+    hipLaunchKernelGGL(k_real_space, dim3(G), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, p.nc[0], p.nc[1],
+                       p.nc[2], p.mC[0], p.mC[1], p.mC[2], p.cell_start, p.rc_coul * p.rc_coul, p.qraw, p.scalars,
+                       (float)p.alpha, p.phi, p.Fst, p.partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return reduce_partials(p, G, 11, S_UREAL, false);  // S_UREAL, S_QSQ, S_WREAL[9]
@@ -153,9 +180,7 @@ __device__ inline void phase_cs(int n0, int n1, int n2, double s0, double s1, do
 constexpr int EW_CHUNK = 512;
 
 // partial structure factors: block (kb, chunk); each thread owns one wave vector
-__global__ __launch_bounds__(256) void k_structure_factor(int N, const float *__restrict__ xs,
-                                                          const float *__restrict__ ys,
-                                                          const float *__restrict__ zs, Cell c,
+__global__ __launch_bounds__(256) void k_structure_factor(int N, const float4 *__restrict__ xyzt, Cell c,
                                                           const float *__restrict__ qraw,
                                                           const double *__restrict__ scalars,
                                                           const int4 *__restrict__ kn,
@@ -173,7 +198,8 @@ __global__ __launch_bounds__(256) void k_structure_factor(int N, const float *__
         int a = t0 + threadIdx.x;
         if (a < a1) {
             double s0, s1, s2;
-            frac_coords(xs[a], ys[a], zs[a], c, s0, s1, s2);
+            const float4 pa = xyzt[a];
+            frac_coords(pa.x, pa.y, pa.z, c, s0, s1, s2);
             sx[threadIdx.x] = s0;
             sy[threadIdx.x] = s1;
             sz[threadIdx.x] = s2;
@@ -227,9 +253,8 @@ __global__ __launch_bounds__(256) void k_structure_reduce(int nchunks, const flo
 }
 
 // phi^k_i = 4 k_e sum_half G Re[S e^{i k.r_i}],  F^k_i = 4 k_e q'_i sum_half k G Im[S e^{i k.r_i}]
-__global__ __launch_bounds__(256) void k_ewald_atoms(int N, const float *__restrict__ xs,
-                                                     const float *__restrict__ ys, const float *__restrict__ zs,
-                                                     Cell c, const float *__restrict__ qraw,
+__global__ __launch_bounds__(256) void k_ewald_atoms(int N, const float4 *__restrict__ xyzt, Cell c,
+                                                     const float *__restrict__ qraw,
                                                      const double *__restrict__ scalars,
                                                      const float4 *__restrict__ kv, const int4 *__restrict__ kn,
                                                      const float2 *__restrict__ Sk, const int *__restrict__ kcount,
@@ -240,7 +265,10 @@ __global__ __launch_bounds__(256) void k_ewald_atoms(int N, const float *__restr
     const int nk = *kcount;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double s0 = 0, s1 = 0, s2 = 0;
-    if (i < N) frac_coords(xs[i], ys[i], zs[i], c, s0, s1, s2);
+    if (i < N) {
+        const float4 pa = xyzt[i];
+        frac_coords(pa.x, pa.y, pa.z, c, s0, s1, s2);
+    }
     float ph = 0.f, fx = 0.f, fy = 0.f, fz = 0.f;
     for (int t0 = 0; t0 < nk; t0 += 256) {
         int k = t0 + threadIdx.x;
@@ -284,7 +312,7 @@ hipError_t launch_ewald(const Plan &p) {
     hipLaunchKernelGGL(k_kvectors, dim3(1), dim3(1024), 0, p.stream, p.cell, p.nk_box[0], p.nk_box[1],
                        p.nk_box[2], p.kmax * p.kmax, p.kinc, p.alpha, p.vol, p.nk_cap, p.kvec, kn, p.kcount);
     const int kb = (int)((p.nk_cap + 255) / 256);
-    hipLaunchKernelGGL(k_structure_factor, dim3(kb, p.s_chunks), dim3(256), 0, p.stream, p.N, p.xs, p.ys, p.zs,
+    hipLaunchKernelGGL(k_structure_factor, dim3(kb, p.s_chunks), dim3(256), 0, p.stream, p.N, p.xyzt,
                        p.cell, p.qraw, p.scalars, (const int4 *)kn, p.kcount, p.nk_cap, p.Spart);
     hipLaunchKernelGGL(k_structure_reduce, dim3(kb), dim3(256), 0, p.stream, p.s_chunks, p.Spart, p.kvec,
                        p.kcount, p.nk_cap, p.alpha, p.Sk, p.partials);
@@ -294,7 +322,7 @@ hipError_t launch_ewald(const Plan &p) {
     if (e != hipSuccess) return e;
     stage_mark(p, ST_EWALD_SK, 4);
     const int G = (p.N + 255) / 256;
-    hipLaunchKernelGGL(k_ewald_atoms, dim3(G), dim3(256), 0, p.stream, p.N, p.xs, p.ys, p.zs, p.cell, p.qraw,
+    hipLaunchKernelGGL(k_ewald_atoms, dim3(G), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, p.qraw,
                        p.scalars, p.kvec, (const int4 *)kn, p.Sk, p.kcount, p.phi, p.Fst);
     stage_mark(p, ST_EWALD_ATOMS);
     return hipGetLastError();

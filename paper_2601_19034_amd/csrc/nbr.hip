@@ -1,9 +1,12 @@
 // Spatial binning, deterministic counting sort into cell order, and image-aware
-// neighbour lists (radial with its angular sub-list; Coulomb).
+// neighbour lists (radial with its angular sub-list).
 //
-// The NEP cutoffs (Sec. 2.1) and the real-space cutoff of Sec. 2.2.1 define the
-// lists; every (j, n) with |r_j + n.h - r_i| < rc and (j, n) != (i, 0) is listed,
-// so cells thinner than 2 rc (several images of one atom) are handled exactly.
+// The NEP cutoffs (Sec. 2.1) define the lists; every (j, n) with
+// |r_j + n.h - r_i| < rc and (j, n) != (i, 0) is listed, so cells thinner than 2 rc
+// (several images of one atom) are handled exactly.  Bins are about rc_R / 2 wide;
+// a stencil of (2m+1)^3 bins is walked unwrapped so that each (bin, image) pair is
+// visited once.  Candidates are screened in FP32 and decided with the FP64
+// displacement rounded to FP32 (the same rule every kernel uses).
 #include "plan.h"
 
 namespace qnep {
@@ -30,33 +33,55 @@ __global__ void k_bin(int N, const float *__restrict__ pos, const int32_t *__res
     if (t < 0 || t >= T) atomicOr(flags, QNEP_FLAG_BAD_SPECIES);
 }
 
-// exclusive scan of count[0..n) into start[0..n]; one block of 1024 threads
-__global__ void k_scan(int n, const int *__restrict__ count, int *__restrict__ start, int *__restrict__ cursor) {
-    __shared__ int buf[1024];
+// three-phase exclusive scan of count[0..n) into start[0..n] (and cursor = start)
+constexpr int SCAN_B = 1024;
+
+__device__ inline int block_scan_inclusive(int v, int *buf) {
+    buf[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < SCAN_B; o <<= 1) {
+        int t = threadIdx.x >= (unsigned)o ? buf[threadIdx.x - o] : 0;
+        __syncthreads();
+        buf[threadIdx.x] += t;
+        __syncthreads();
+    }
+    return buf[threadIdx.x];
+}
+
+__global__ void k_scan_blocks(int n, const int *__restrict__ count, int *__restrict__ start,
+                              int *__restrict__ bsum) {
+    __shared__ int buf[SCAN_B];
+    int i = blockIdx.x * SCAN_B + threadIdx.x;
+    int v = i < n ? count[i] : 0;
+    int inc = block_scan_inclusive(v, buf);
+    if (i < n) start[i] = inc - v;
+    if (threadIdx.x == SCAN_B - 1) bsum[blockIdx.x] = inc;
+}
+
+__global__ void k_scan_top(int nb, int *__restrict__ bsum, int *__restrict__ total) {
+    __shared__ int buf[SCAN_B];
     __shared__ int carry;
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
-    for (int base = 0; base < n; base += 1024) {
+    for (int base = 0; base < nb; base += SCAN_B) {
         int i = base + threadIdx.x;
-        int v = i < n ? count[i] : 0;
-        buf[threadIdx.x] = v;
+        int v = i < nb ? bsum[i] : 0;
+        int inc = block_scan_inclusive(v, buf);
+        if (i < nb) bsum[i] = carry + inc - v;
         __syncthreads();
-        for (int o = 1; o < 1024; o <<= 1) {
-            int t = threadIdx.x >= o ? buf[threadIdx.x - o] : 0;
-            __syncthreads();
-            buf[threadIdx.x] += t;
-            __syncthreads();
-        }
-        if (i < n) {
-            int ex = carry + buf[threadIdx.x] - v;
-            start[i] = ex;
-            cursor[i] = ex;
-        }
-        __syncthreads();
-        if (threadIdx.x == 1023) carry += buf[1023];
+        if (threadIdx.x == SCAN_B - 1) carry += inc;
         __syncthreads();
     }
-    if (threadIdx.x == 0) start[n] = carry;
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ void k_scan_add(int n, const int *__restrict__ bsum, int *__restrict__ start, int *__restrict__ cursor) {
+    int i = blockIdx.x * SCAN_B + threadIdx.x;
+    if (i < n) {
+        int v = start[i] + bsum[blockIdx.x];
+        start[i] = v;
+        cursor[i] = v;
+    }
 }
 
 __global__ void k_scatter(int N, const int *__restrict__ cid, int *__restrict__ cursor, int *__restrict__ perm) {
@@ -66,7 +91,7 @@ __global__ void k_scatter(int N, const int *__restrict__ cid, int *__restrict__ 
     perm[slot] = i;
 }
 
-// order the atoms of each cell by their input index (makes the sort deterministic)
+// order the atoms of each bin by their input index (makes the sort deterministic)
 __global__ void k_cell_sort(int ncell, const int *__restrict__ start, int *__restrict__ perm) {
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
@@ -81,11 +106,11 @@ __global__ void k_cell_sort(int ncell, const int *__restrict__ start, int *__res
     }
 }
 
-// sorted SoA copies; positions are moved into the cell by whole lattice vectors
-// only (atoms already inside keep their exact FP32 coordinates)
-__global__ void k_gather_sorted(int N, const float *__restrict__ pos, const int32_t *__restrict__ type, int T, Cell c,
-                                const int *__restrict__ perm, float *__restrict__ xs, float *__restrict__ ys,
-                                float *__restrict__ zs, int *__restrict__ ts) {
+// sorted packed copies (x, y, z, species bits); positions are moved into the cell by
+// whole lattice vectors only (atoms already inside keep their exact FP32 coordinates)
+__global__ void k_gather_sorted(int N, const float *__restrict__ pos, const int32_t *__restrict__ type, int T,
+                                Cell c, const int *__restrict__ perm, float4 *__restrict__ xyzt,
+                                int *__restrict__ ts) {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= N) return;
     int i = perm[s];
@@ -98,65 +123,51 @@ __global__ void k_gather_sorted(int N, const float *__restrict__ pos, const int3
         y -= n[0] * c.h[1] + n[1] * c.h[4] + n[2] * c.h[7];
         z -= n[0] * c.h[2] + n[1] * c.h[5] + n[2] * c.h[8];
     }
-    xs[s] = (float)x;
-    ys[s] = (float)y;
-    zs[s] = (float)z;
     // species outside [0, T) were flagged by k_bin; clamp so that no kernel indexes past its tables
     int t = type[i];
-    ts[s] = t < 0 ? 0 : (t >= T ? T - 1 : t);
+    t = t < 0 ? 0 : (t >= T ? T - 1 : t);
+    xyzt[s] = make_float4((float)x, (float)y, (float)z, __int_as_float(t));
+    ts[s] = t;
 }
 
 // ---------------------------------------------------------------- lists
-// One thread per sorted atom walks the (2m+1)^3 stencil of cells, unwrapped so
-// that each (cell, image) pair is visited once.  Main list: slot-major
-// list[k * N + i].  Optional sub-list (r < rc_sub): atom-major sub[i * cap_sub + k].
-template <bool SUB>
-__global__ void k_lists(int N, const float *__restrict__ xs, const float *__restrict__ ys,
-                        const float *__restrict__ zs, Cell c, int nc0, int nc1, int nc2, int m0, int m1, int m2,
-                        const int *__restrict__ start, double rc2, int cap, uint32_t *__restrict__ list,
-                        int *__restrict__ cnt, double rs2, int cap_sub, uint32_t *__restrict__ sub,
-                        int *__restrict__ cnt_sub, int32_t *__restrict__ flags, int flag_main, int flag_sub) {
+// One thread per sorted atom.  Main list: slot-major list[k * N + i].  Sub-list
+// (r < rc_sub): atom-major sub[i * cap_sub + k].
+__global__ __launch_bounds__(256) void k_lists(int N, const float4 *__restrict__ xyzt, Cell c, int nc0, int nc1,
+                                               int nc2, int m0, int m1, int m2, const int *__restrict__ start,
+                                               double rc2, int cap, uint32_t *__restrict__ list,
+                                               int *__restrict__ cnt, double rs2, int cap_sub,
+                                               uint32_t *__restrict__ sub, int *__restrict__ cnt_sub,
+                                               int32_t *__restrict__ flags) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
-    double xi = xs[i], yi = ys[i], zi = zs[i];
-    int ci[3], nc[3] = {nc0, nc1, nc2};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        double s = xi * c.hinv[a] + yi * c.hinv[3 + a] + zi * c.hinv[6 + a];
-        int k = (int)floor(s * nc[a]);
-        ci[a] = k < 0 ? 0 : (k >= nc[a] ? nc[a] - 1 : k);
-    }
+    const float4 pi = xyzt[i];
+    int ci[3];
+    bin_of(pi, c, nc0, nc1, nc2, ci);
+    const float rc2_hi = (float)(rc2 * (1.0 + 1e-4));
     int n_main = 0, n_sub = 0;
     for (int d0 = -m0; d0 <= m0; ++d0) {
-        int u0 = ci[0] + d0;
-        int i0 = (int)floor((double)u0 / nc0);
-        int w0 = u0 - i0 * nc0;
+        int u0 = ci[0] + d0, i0 = floor_div(u0, nc0), w0 = u0 - i0 * nc0;
         for (int d1 = -m1; d1 <= m1; ++d1) {
-            int u1 = ci[1] + d1;
-            int i1 = (int)floor((double)u1 / nc1);
-            int w1 = u1 - i1 * nc1;
+            int u1 = ci[1] + d1, i1 = floor_div(u1, nc1), w1 = u1 - i1 * nc1;
             for (int d2 = -m2; d2 <= m2; ++d2) {
-                int u2 = ci[2] + d2;
-                int i2 = (int)floor((double)u2 / nc2);
-                int w2 = u2 - i2 * nc2;
-                double sx = i0 * c.h[0] + i1 * c.h[3] + i2 * c.h[6];
-                double sy = i0 * c.h[1] + i1 * c.h[4] + i2 * c.h[7];
-                double sz = i0 * c.h[2] + i1 * c.h[5] + i2 * c.h[8];
-                bool self_img = (i0 == 0 && i1 == 0 && i2 == 0);
-                int lin = (w0 * nc1 + w1) * nc2 + w2;
-                int b = start[lin], e = start[lin + 1];
+                int u2 = ci[2] + d2, i2 = floor_div(u2, nc2), w2 = u2 - i2 * nc2;
+                ImageShift sh(c, i0, i1, i2);
+                const bool self_img = (i0 == 0 && i1 == 0 && i2 == 0);
+                const int lin = (w0 * nc1 + w1) * nc2 + w2;
+                const int b = start[lin], e = start[lin + 1];
                 for (int j = b; j < e; ++j) {
+                    const float4 pj = xyzt[j];
+                    float fx = (pj.x - pi.x) + sh.fx, fy = (pj.y - pi.y) + sh.fy, fz = (pj.z - pi.z) + sh.fz;
+                    if (fx * fx + fy * fy + fz * fz >= rc2_hi) continue;
                     if (self_img && j == i) continue;
-                    double dx = ((double)xs[j] - xi) + sx;
-                    double dy = ((double)ys[j] - yi) + sy;
-                    double dz = ((double)zs[j] - zi) + sz;
-                    float fx = (float)dx, fy = (float)dy, fz = (float)dz;
-                    double r2 = (double)fx * fx + (double)fy * fy + (double)fz * fz;
+                    float3 d = sh.exact(pi, pj);
+                    double r2 = (double)d.x * d.x + (double)d.y * d.y + (double)d.z * d.z;
                     if (r2 < rc2) {
                         uint32_t code = nb_encode(j, i0, i1, i2);
                         if (n_main < cap) list[(size_t)n_main * N + i] = code;
                         ++n_main;
-                        if (SUB && r2 < rs2) {
+                        if (r2 < rs2) {
                             if (n_sub < cap_sub) sub[(size_t)i * cap_sub + n_sub] = code;
                             ++n_sub;
                         }
@@ -166,17 +177,15 @@ __global__ void k_lists(int N, const float *__restrict__ xs, const float *__rest
         }
     }
     if (n_main > cap) {
-        atomicOr(flags, flag_main);
+        atomicOr(flags, QNEP_FLAG_RADIAL_OVERFLOW);
         n_main = cap;
     }
-    cnt[i] = n_main;
-    if (SUB) {
-        if (n_sub > cap_sub) {
-            atomicOr(flags, flag_sub);
-            n_sub = cap_sub;
-        }
-        cnt_sub[i] = n_sub;
+    if (n_sub > cap_sub) {
+        atomicOr(flags, QNEP_FLAG_ANGULAR_OVERFLOW);
+        n_sub = cap_sub;
     }
+    cnt[i] = n_main;
+    cnt_sub[i] = n_sub;
 }
 
 hipError_t launch_neighbors(const Plan &p) {
@@ -187,27 +196,23 @@ hipError_t launch_neighbors(const Plan &p) {
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_bin, dim3(G), dim3(B), 0, p.stream, N, p.pos, p.type, p.T, p.cell, p.nc[0], p.nc[1],
                        p.nc[2], p.cid, p.cell_count, p.flags);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, p.stream, p.ncell, p.cell_count, p.cell_start,
+    const int nsb = (p.ncell + SCAN_B - 1) / SCAN_B;
+    hipLaunchKernelGGL(k_scan_blocks, dim3(nsb), dim3(SCAN_B), 0, p.stream, p.ncell, p.cell_count, p.cell_start,
+                       p.scan_tmp);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_B), 0, p.stream, nsb, p.scan_tmp, p.cell_start + p.ncell);
+    hipLaunchKernelGGL(k_scan_add, dim3(nsb), dim3(SCAN_B), 0, p.stream, p.ncell, p.scan_tmp, p.cell_start,
                        p.cell_cursor);
     hipLaunchKernelGGL(k_scatter, dim3(G), dim3(B), 0, p.stream, N, p.cid, p.cell_cursor, p.perm);
     hipLaunchKernelGGL(k_cell_sort, dim3((p.ncell + B - 1) / B), dim3(B), 0, p.stream, p.ncell, p.cell_start,
                        p.perm);
-    hipLaunchKernelGGL(k_gather_sorted, dim3(G), dim3(B), 0, p.stream, N, p.pos, p.type, p.T, p.cell, p.perm, p.xs,
-                       p.ys, p.zs, p.ts);
-    stage_mark(p, ST_SORT, 6);
+    hipLaunchKernelGGL(k_gather_sorted, dim3(G), dim3(B), 0, p.stream, N, p.pos, p.type, p.T, p.cell, p.perm,
+                       p.xyzt, p.ts);
+    stage_mark(p, ST_SORT, 8);
     double rcR2 = p.rcR * p.rcR, rcA2 = p.rcA * p.rcA;
-    hipLaunchKernelGGL(k_lists<true>, dim3(G), dim3(B), 0, p.stream, N, p.xs, p.ys, p.zs, p.cell, p.nc[0],
-                       p.nc[1], p.nc[2], p.mR[0], p.mR[1], p.mR[2], p.cell_start, rcR2, p.capR, p.listR, p.cntR,
-                       rcA2, p.capA, p.listA, p.cntA, p.flags, QNEP_FLAG_RADIAL_OVERFLOW,
-                       QNEP_FLAG_ANGULAR_OVERFLOW);
+    hipLaunchKernelGGL(k_lists, dim3(G), dim3(B), 0, p.stream, N, p.xyzt, p.cell, p.nc[0], p.nc[1], p.nc[2],
+                       p.mR[0], p.mR[1], p.mR[2], p.cell_start, rcR2, p.capR, p.listR, p.cntR, rcA2, p.capA,
+                       p.listA, p.cntA, p.flags);
     stage_mark(p, ST_LISTS);
-    if (p.mode == 1) {
-        double rc2 = p.rc_coul * p.rc_coul;
-        hipLaunchKernelGGL(k_lists<false>, dim3(G), dim3(B), 0, p.stream, N, p.xs, p.ys, p.zs, p.cell, p.nc[0],
-                           p.nc[1], p.nc[2], p.mC[0], p.mC[1], p.mC[2], p.cell_start, rc2, p.capC, p.listC, p.cntC,
-                           0.0, 0, (uint32_t *)nullptr, (int *)nullptr, p.flags, QNEP_FLAG_COULOMB_OVERFLOW, 0);
-        stage_mark(p, ST_LISTS_C);
-    }
     return hipGetLastError();
 }
 
@@ -227,26 +232,25 @@ hipError_t fill_zero(void *ptr, size_t bytes, hipStream_t s) {
     return hipGetLastError();
 }
 
+// one block per reduced value; fixed-order tree, so the result is deterministic
 __global__ void k_reduce_partials(const double *__restrict__ partials, int nblk, int nv, double *__restrict__ out,
                                   int accumulate) {
     __shared__ double red[256];
-    for (int k = 0; k < nv; ++k) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < nblk; b += 256) s += partials[(size_t)b * nv + k];
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) out[k] = accumulate ? out[k] + red[0] : red[0];
+    const int k = blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) s += partials[(size_t)b * nv + k];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
+    if (threadIdx.x == 0) out[k] = accumulate ? out[k] + red[0] : red[0];
 }
 
 hipError_t reduce_partials(const Plan &p, int nblk, int nv, int slot, bool accumulate) {
-    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, p.stream, p.partials, nblk, nv,
-                       p.scalars + slot, accumulate ? 1 : 0);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(nv), dim3(256), 0, p.stream, p.partials, nblk, nv, p.scalars + slot,
+                       accumulate ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -18,12 +18,16 @@
 
 namespace qnep {
 
+// padded row length of the per-atom radial coefficient tables (16-byte multiples)
+template <int NB>
+struct Pad4 {
+    static constexpr int v = (NB + 3) / 4 * 4;
+};
+
 // ---------------------------------------------------------------- descriptors
 template <int T, int NR, int NA, int NB>
-__global__ __launch_bounds__(256) void k_descriptors(int N, const float *__restrict__ xs,
-                                                     const float *__restrict__ ys, const float *__restrict__ zs,
-                                                     const int *__restrict__ ts, Cell c, float rcR, float rcA,
-                                                     const uint32_t *__restrict__ listR,
+__global__ __launch_bounds__(256) void k_descriptors(int N, const float4 *__restrict__ xyzt, Cell c, float rcR,
+                                                     float rcA, const uint32_t *__restrict__ listR,
                                                      const int *__restrict__ cntR,
                                                      const uint32_t *__restrict__ listA,
                                                      const int *__restrict__ cntA, int capA,
@@ -37,7 +41,8 @@ __global__ __launch_bounds__(256) void k_descriptors(int N, const float *__restr
     __syncthreads();
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
-    const int ti = ts[i];
+    const float4 pi = xyzt[i];
+    const int ti = species_of(pi);
     // ---- radial
     float B[T][NB];
 #pragma unroll
@@ -46,15 +51,18 @@ __global__ __launch_bounds__(256) void k_descriptors(int N, const float *__restr
         for (int k = 0; k < NB; ++k) B[t][k] = 0.0f;
     const int nR = cntR[i];
     for (int s = 0; s < nR; ++s) {
-        uint32_t e = listR[(size_t)s * N + i];
-        float3 d = displacement(xs, ys, zs, i, e, c);
-        float r = sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
+        const uint32_t e = listR[(size_t)s * N + i];
+        const float4 pj = xyzt[nb_index(e)];
+        int n1, n2, n3;
+        nb_image(e, n1, n2, n3);
+        const float3 d = ImageShift(c, n1, n2, n3).exact(pi, pj);
+        const float r = sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
         float f[NB], df[NB];
         cheb_basis<NB>(r, rcR, f, df);
-        int tj = ts[nb_index(e)];
+        const int tj = species_of(pj);
 #pragma unroll
         for (int t = 0; t < T; ++t) {
-            float m = (tj == t) ? 1.0f : 0.0f;
+            const float m = (tj == t) ? 1.0f : 0.0f;
 #pragma unroll
             for (int k = 0; k < NB; ++k) B[t][k] = fmaf(m, f[k], B[t][k]);
         }
@@ -76,12 +84,15 @@ __global__ __launch_bounds__(256) void k_descriptors(int N, const float *__restr
         for (int q = 0; q < LM; ++q) A[n][q] = 0.0f;
     const int nA = cntA[i];
     for (int s = 0; s < nA; ++s) {
-        uint32_t e = listA[(size_t)i * capA + s];
-        float3 d = displacement(xs, ys, zs, i, e, c);
-        float r = sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
+        const uint32_t e = listA[(size_t)i * capA + s];
+        const float4 pj = xyzt[nb_index(e)];
+        int n1, n2, n3;
+        nb_image(e, n1, n2, n3);
+        const float3 d = ImageShift(c, n1, n2, n3).exact(pi, pj);
+        const float r = sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
         float f[NB], df[NB];
         cheb_basis<NB>(r, rcA, f, df);
-        const float *cp = &cA[(ti * T + ts[nb_index(e)]) * NA * NB];
+        const float *cp = &cA[(ti * T + species_of(pj)) * NA * NB];
         float g[NA];
 #pragma unroll
         for (int n = 0; n < NA; ++n) {
@@ -90,7 +101,7 @@ __global__ __launch_bounds__(256) void k_descriptors(int N, const float *__restr
             for (int k = 0; k < NB; ++k) acc = fmaf(cp[n * NB + k], f[k], acc);
             g[n] = acc;
         }
-        float ir = 1.0f / r;
+        const float ir = 1.0f / r;
         float Y[LM];
         harmonics(d.x * ir, d.y * ir, d.z * ir, Y);
 #pragma unroll
@@ -121,7 +132,8 @@ __global__ __launch_bounds__(256) void k_descriptors(int N, const float *__restr
 // ---------------------------------------------------------------- gradient tables
 // Per atom: chi_i = phi_i - mean(phi); radial coefficient tables
 //   hE[t][k] = sum_n (gU_n + chi gq_n) cR[ti][t][n][k],  hq[t][k] = s sum_n gq_n cR[ti][t][n][k]
-// stored atom-major hT[i][2][T][NB] so that a neighbour's row is one contiguous read.
+// stored atom-major hT[i][2][T][NBP] (rows padded to 16 bytes) so that a neighbour's
+// row for one species is a few aligned vector loads.
 template <int T, int NR, int NB>
 __global__ __launch_bounds__(256) void k_radial_tables(int N, const int *__restrict__ ts,
                                                        const float *__restrict__ gU, const float *__restrict__ gq,
@@ -129,6 +141,7 @@ __global__ __launch_bounds__(256) void k_radial_tables(int N, const int *__restr
                                                        const double *__restrict__ scalars,
                                                        const float *__restrict__ theta, int64_t off_cR,
                                                        int64_t off_s, float *__restrict__ hT) {
+    constexpr int NBP = Pad4<NB>::v;
     __shared__ float cR[T * T * NR * NB];
     for (int k = threadIdx.x; k < T * T * NR * NB; k += blockDim.x) cR[k] = theta[off_cR + k];
     __syncthreads();
@@ -144,29 +157,23 @@ __global__ __launch_bounds__(256) void k_radial_tables(int N, const int *__restr
         GE[n] = fmaf(chi, b, a);
         GQ[n] = s * b;
     }
-    float *out = hT + (size_t)i * (2 * T * NB);
+    float *out = hT + (size_t)i * (2 * T * NBP);
 #pragma unroll
     for (int t = 0; t < T; ++t)
 #pragma unroll
-        for (int k = 0; k < NB; ++k) {
+        for (int k = 0; k < NBP; ++k) {
             float e = 0.f, q = 0.f;
+            if (k < NB) {
 #pragma unroll
-            for (int n = 0; n < NR; ++n) {
-                float cv = cR[((ti * T + t) * NR + n) * NB + k];
-                e = fmaf(GE[n], cv, e);
-                q = fmaf(GQ[n], cv, q);
+                for (int n = 0; n < NR; ++n) {
+                    float cv = cR[((ti * T + t) * NR + n) * NB + k];
+                    e = fmaf(GE[n], cv, e);
+                    q = fmaf(GQ[n], cv, q);
+                }
             }
-            out[t * NB + k] = e;
-            out[T * NB + t * NB + k] = q;
+            out[t * NBP + k] = e;
+            out[T * NBP + t * NBP + k] = q;
         }
-}
-
-template <int T>
-__device__ inline float select_t(const float (&v)[T], int t) {
-    float r = v[0];
-#pragma unroll
-    for (int u = 1; u < T; ++u) r = (t == u) ? v[u] : r;
-    return r;
 }
 
 // ---------------------------------------------------------------- radial forces
@@ -174,61 +181,69 @@ __device__ inline float select_t(const float (&v)[T], int t) {
 // F_i = sum_j (sigma_ij + sigma_ji) u_ij, Z_i += 1/2 sum_j (rho_ij - rho_ji) r u (x) u,
 // W -= sum_j sigma_ij r u (x) u (own partial forces only).
 template <int T, int NB>
-__global__ __launch_bounds__(256) void k_radial_forces(int N, const float *__restrict__ xs,
-                                                       const float *__restrict__ ys, const float *__restrict__ zs,
-                                                       const int *__restrict__ ts, Cell c, float rcR,
+__global__ __launch_bounds__(256) void k_radial_forces(int N, const float4 *__restrict__ xyzt, Cell c, float rcR,
                                                        const uint32_t *__restrict__ listR,
                                                        const int *__restrict__ cntR,
                                                        const float *__restrict__ hT, float *__restrict__ Fnep,
                                                        float *__restrict__ Znep, double *__restrict__ partials) {
+    constexpr int NBP = Pad4<NB>::v;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double w[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (i < N) {
-        const int ti = ts[i];
-        float hE[NB][T], hQ[NB][T];
-        const float *own = hT + (size_t)i * (2 * T * NB);
-#pragma unroll
-        for (int t = 0; t < T; ++t)
-#pragma unroll
-            for (int k = 0; k < NB; ++k) {
-                hE[k][t] = own[t * NB + k];
-                hQ[k][t] = own[T * NB + t * NB + k];
-            }
+        const float4 pi = xyzt[i];
+        const int ti = species_of(pi);
         float fx = 0.f, fy = 0.f, fz = 0.f;
         float zxx = 0.f, zyy = 0.f, zzz = 0.f, zxy = 0.f, zxz = 0.f, zyz = 0.f;
         float wxx = 0.f, wyy = 0.f, wzz = 0.f, wxy = 0.f, wxz = 0.f, wyz = 0.f;
+        const float *own = hT + (size_t)i * (2 * T * NBP);
         const int nR = cntR[i];
         for (int s = 0; s < nR; ++s) {
-            uint32_t e = listR[(size_t)s * N + i];
+            const uint32_t e = listR[(size_t)s * N + i];
             const int j = nb_index(e);
-            float3 d = displacement(xs, ys, zs, i, e, c);
-            float r = sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
+            const float4 pj = xyzt[j];
+            int n1, n2, n3;
+            nb_image(e, n1, n2, n3);
+            const float3 d = ImageShift(c, n1, n2, n3).exact(pi, pj);
+            const float r = sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
             float f[NB], df[NB];
             cheb_basis<NB>(r, rcR, f, df);
-            const int tj = ts[j];
-            const float *oth = hT + (size_t)j * (2 * T * NB) + ti * NB;
+            const int tj = species_of(pj);
+            // own tables for the neighbour's species (rows are 16-byte aligned)
+            const float4 *oe = reinterpret_cast<const float4 *>(own + tj * NBP);
+            const float4 *oq = reinterpret_cast<const float4 *>(own + T * NBP + tj * NBP);
+            const float4 *ne = reinterpret_cast<const float4 *>(hT + (size_t)j * (2 * T * NBP) + ti * NBP);
+            const float4 *nq = reinterpret_cast<const float4 *>(hT + (size_t)j * (2 * T * NBP) + T * NBP + ti * NBP);
             float sij = 0.f, rij = 0.f, sji = 0.f, rji = 0.f;
 #pragma unroll
-            for (int k = 0; k < NB; ++k) {
-                sij = fmaf(select_t<T>(hE[k], tj), df[k], sij);
-                rij = fmaf(select_t<T>(hQ[k], tj), df[k], rij);
-                sji = fmaf(oth[k], df[k], sji);
-                rji = fmaf(oth[T * NB + k], df[k], rji);
+            for (int k4 = 0; k4 < NBP / 4; ++k4) {
+                const float4 a = oe[k4], b = oq[k4], x = ne[k4], y = nq[k4];
+                const float av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
+                const float xv[4] = {x.x, x.y, x.z, x.w}, yv[4] = {y.x, y.y, y.z, y.w};
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int k = 4 * k4 + u;
+                    if (k < NB) {
+                        sij = fmaf(av[u], df[k], sij);
+                        rij = fmaf(bv[u], df[k], rij);
+                        sji = fmaf(xv[u], df[k], sji);
+                        rji = fmaf(yv[u], df[k], rji);
+                    }
+                }
             }
-            float ir = 1.0f / r;
-            float ux = d.x * ir, uy = d.y * ir, uz = d.z * ir;
-            float sf = sij + sji;
+            const float ir = 1.0f / r;
+            const float ux = d.x * ir, uy = d.y * ir, uz = d.z * ir;
+            const float sf = sij + sji;
             fx = fmaf(sf, ux, fx);
             fy = fmaf(sf, uy, fy);
             fz = fmaf(sf, uz, fz);
-            float zr = 0.5f * (rij - rji) * r;
+            const float zr = 0.5f * (rij - rji) * r;
             zxx = fmaf(zr, ux * ux, zxx);
             zyy = fmaf(zr, uy * uy, zyy);
             zzz = fmaf(zr, uz * uz, zzz);
             zxy = fmaf(zr, ux * uy, zxy);
             zxz = fmaf(zr, ux * uz, zxz);
             zyz = fmaf(zr, uy * uz, zyz);
-            float wr = sij * r;
+            const float wr = sij * r;
             wxx = fmaf(wr, ux * ux, wxx);
             wyy = fmaf(wr, uy * uy, wyy);
             wzz = fmaf(wr, uz * uz, wzz);
@@ -263,8 +278,7 @@ __global__ __launch_bounds__(256) void k_radial_forces(int N, const float *__res
 // WHICH = 1: charge pass (pair buffer pairA, own Z contribution).
 template <int T, int NR, int NA, int NB, int WHICH>
 __global__ __launch_bounds__(256) void k_angular_forces(
-    int N, const float *__restrict__ xs, const float *__restrict__ ys, const float *__restrict__ zs,
-    const int *__restrict__ ts, Cell c, float rcA, const uint32_t *__restrict__ listA,
+    int N, const float4 *__restrict__ xyzt, Cell c, float rcA, const uint32_t *__restrict__ listA,
     const int *__restrict__ cntA, int capA, const float *__restrict__ Amom, const float *__restrict__ gU,
     const float *__restrict__ gq, const float *__restrict__ phi, const double *__restrict__ scalars,
     const float *__restrict__ theta, int64_t off_cA, int64_t off_s, float4 *__restrict__ pair,
@@ -275,7 +289,8 @@ __global__ __launch_bounds__(256) void k_angular_forces(
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double w[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (i < N) {
-        const int ti = ts[i];
+        const float4 pi = xyzt[i];
+        const int ti = species_of(pi);
         const float s = theta[off_s];
         const float chi = (float)((double)phi[i] - scalars[S_PHIBAR]);
         float At[NA][LM];
@@ -298,14 +313,17 @@ __global__ __launch_bounds__(256) void k_angular_forces(
         float m9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         const int nA = cntA[i];
         for (int sl = 0; sl < nA; ++sl) {
-            uint32_t e = listA[(size_t)i * capA + sl];
-            float3 d = displacement(xs, ys, zs, i, e, c);
-            float r = sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
-            float ir = 1.0f / r;
-            float ux = d.x * ir, uy = d.y * ir, uz = d.z * ir;
+            const uint32_t e = listA[(size_t)i * capA + sl];
+            const float4 pj = xyzt[nb_index(e)];
+            int n1, n2, n3;
+            nb_image(e, n1, n2, n3);
+            const float3 d = ImageShift(c, n1, n2, n3).exact(pi, pj);
+            const float r = sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
+            const float ir = 1.0f / r;
+            const float ux = d.x * ir, uy = d.y * ir, uz = d.z * ir;
             float f[NB], df[NB];
             cheb_basis<NB>(r, rcA, f, df);
-            const float *cp = &cA[(ti * T + ts[nb_index(e)]) * NA * NB];
+            const float *cp = &cA[(ti * T + species_of(pj)) * NA * NB];
             float g[NA], dg[NA];
 #pragma unroll
             for (int n = 0; n < NA; ++n) {
@@ -336,10 +354,10 @@ __global__ __launch_bounds__(256) void k_angular_forces(
             }
             float gx, gy, gz;
             harmonics_grad_dot(ux, uy, uz, Qv, gx, gy, gz);
-            float ug = ux * gx + uy * gy + uz * gz;
-            float Fx = radial * ux + (gx - ug * ux) * ir;
-            float Fy = radial * uy + (gy - ug * uy) * ir;
-            float Fz = radial * uz + (gz - ug * uz) * ir;
+            const float ug = ux * gx + uy * gy + uz * gz;
+            const float Fx = radial * ux + (gx - ug * ux) * ir;
+            const float Fy = radial * uy + (gy - ug * uy) * ir;
+            const float Fz = radial * uz + (gz - ug * uz) * ir;
             pair[(size_t)i * capA + sl] = make_float4(Fx, Fy, Fz, 0.f);
             if (WHICH == 0) {
                 ox += Fx;
@@ -370,24 +388,40 @@ __global__ __launch_bounds__(256) void k_angular_forces(
     if (WHICH == 0) block_partials<9>(w, partials);
 }
 
+// slot of `want` in atom j's angular list (-1 if absent); rows are 16-byte aligned
+__device__ inline int find_slot(const uint32_t *__restrict__ listA, int j, int capA, int nj, uint32_t want) {
+    const uint4 *row = reinterpret_cast<const uint4 *>(listA + (size_t)j * capA);
+    for (int t4 = 0; 4 * t4 < nj; ++t4) {
+        // entries at or past nj are stale and must not match
+        const uint4 v = row[t4];
+        const int b = 4 * t4;
+        if (v.x == want) return b;
+        if (v.y == want && b + 1 < nj) return b + 1;
+        if (v.z == want && b + 2 < nj) return b + 2;
+        if (v.w == want && b + 3 < nj) return b + 3;
+    }
+    return -1;
+}
+
 // ---------------------------------------------------------------- assembly
 // Adds the angular reverse terms -F_ji and -1/2 r_ji (x) a_ji found in each
 // neighbour's pair buffer, the static electrostatic forces and the diagonal q~'_i,
 // writes F, Z*, q', q~' in input order and FP64 partials of P = sum_i q~'_i r_i.
 __global__ __launch_bounds__(256) void k_assemble(
-    int N, const float *__restrict__ xs, const float *__restrict__ ys, const float *__restrict__ zs, Cell c,
-    const uint32_t *__restrict__ listA, const int *__restrict__ cntA, int capA, const float4 *__restrict__ pairF,
-    const float4 *__restrict__ pairA, const float *__restrict__ Fnep, const float *__restrict__ Znep,
-    const float *__restrict__ Fst, const float *__restrict__ qraw, const double *__restrict__ scalars,
-    const float *__restrict__ theta, int64_t off_s, const int *__restrict__ perm, const float *__restrict__ pos,
-    float *__restrict__ forces, float *__restrict__ bec, float *__restrict__ charges,
-    float *__restrict__ charges_naked, double *__restrict__ partials) {
+    int N, const float4 *__restrict__ xyzt, Cell c, const uint32_t *__restrict__ listA,
+    const int *__restrict__ cntA, int capA, const float4 *__restrict__ pairF, const float4 *__restrict__ pairA,
+    const float *__restrict__ Fnep, const float *__restrict__ Znep, const float *__restrict__ Fst,
+    const float *__restrict__ qraw, const double *__restrict__ scalars, const float *__restrict__ theta,
+    int64_t off_s, const int *__restrict__ perm, const float *__restrict__ pos, float *__restrict__ forces,
+    float *__restrict__ bec, float *__restrict__ charges, float *__restrict__ charges_naked,
+    double *__restrict__ partials) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double pv[3] = {0, 0, 0};
     if (i < N) {
         const float s = theta[off_s];
         const float qp = (float)((double)qraw[i] + scalars[S_DELTA]);  // q'
         const float qt = s * qp;                                        // q~'
+        const float4 pi = xyzt[i];
         float F[3], Z[9];
 #pragma unroll
         for (int a = 0; a < 3; ++a) F[a] = Fnep[(size_t)a * N + i] + Fst[(size_t)a * N + i];
@@ -398,23 +432,16 @@ __global__ __launch_bounds__(256) void k_assemble(
         Z[8] += qt;
         const int nA = cntA[i];
         for (int sl = 0; sl < nA; ++sl) {
-            uint32_t e = listA[(size_t)i * capA + sl];
+            const uint32_t e = listA[(size_t)i * capA + sl];
             const int j = nb_index(e);
-            const uint32_t want = nb_reverse(e, i);
-            const int nj = cntA[j];
-            int found = -1;
-            for (int t = 0; t < nj; ++t)
-                if (listA[(size_t)j * capA + t] == want) {
-                    found = t;
-                    break;
-                }
+            const int found = find_slot(listA, j, capA, cntA[j], nb_reverse(e, i));
             if (found < 0) continue;  // pair at the cutoff on one side only: contributes zero
-            float4 fji = pairF[(size_t)j * capA + found];
-            float4 aji = pairA[(size_t)j * capA + found];
+            const float4 fji = pairF[(size_t)j * capA + found];
+            const float4 aji = pairA[(size_t)j * capA + found];
             F[0] -= fji.x;
             F[1] -= fji.y;
             F[2] -= fji.z;
-            float3 d = displacement(xs, ys, zs, i, e, c);  // r_ij = -r_ji
+            const float3 d = displacement(pi, xyzt, e, c);  // r_ij = -r_ji
             // -1/2 r_ji (x) a_ji = +1/2 r_ij (x) a_ji
             Z[0] += 0.5f * d.x * aji.x; Z[1] += 0.5f * d.x * aji.y; Z[2] += 0.5f * d.x * aji.z;
             Z[3] += 0.5f * d.y * aji.x; Z[4] += 0.5f * d.y * aji.y; Z[5] += 0.5f * d.y * aji.z;
@@ -432,7 +459,7 @@ __global__ __launch_bounds__(256) void k_assemble(
         if (charges) charges[o] = qp;
         if (charges_naked) charges_naked[o] = qt;
         // polarization with the caller's coordinates (Eq. 26)
-        double qd = (double)s * ((double)qraw[i] + scalars[S_DELTA]);
+        const double qd = (double)s * ((double)qraw[i] + scalars[S_DELTA]);
         pv[0] = qd * (double)pos[o];
         pv[1] = qd * (double)pos[(size_t)N + o];
         pv[2] = qd * (double)pos[(size_t)2 * N + o];
@@ -444,9 +471,9 @@ __global__ __launch_bounds__(256) void k_assemble(
 template <int T, int NR, int NA, int NB>
 static hipError_t run_descriptors(const Plan &p) {
     const int G = (p.N + 255) / 256;
-    hipLaunchKernelGGL((k_descriptors<T, NR, NA, NB>), dim3(G), dim3(256), 0, p.stream, p.N, p.xs, p.ys, p.zs,
-                       p.ts, p.cell, (float)p.rcR, (float)p.rcA, p.listR, p.cntR, p.listA, p.cntA, p.capA,
-                       p.theta, p.off_cR, p.off_cA, p.D, p.Amom);
+    hipLaunchKernelGGL((k_descriptors<T, NR, NA, NB>), dim3(G), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell,
+                       (float)p.rcR, (float)p.rcA, p.listR, p.cntR, p.listA, p.cntA, p.capA, p.theta, p.off_cR,
+                       p.off_cA, p.D, p.Amom);
     return hipGetLastError();
 }
 
@@ -455,25 +482,25 @@ static hipError_t run_forces(const Plan &p) {
     const int G = (p.N + 255) / 256;
     hipLaunchKernelGGL((k_radial_tables<T, NR, NB>), dim3(G), dim3(256), 0, p.stream, p.N, p.ts, p.gU, p.gq,
                        p.phi, p.scalars, p.theta, p.off_cR, p.off_s, p.hT);
-    hipLaunchKernelGGL((k_radial_forces<T, NB>), dim3(G), dim3(256), 0, p.stream, p.N, p.xs, p.ys, p.zs, p.ts,
-                       p.cell, (float)p.rcR, p.listR, p.cntR, p.hT, p.Fnep, p.Znep, p.partials);
+    hipLaunchKernelGGL((k_radial_forces<T, NB>), dim3(G), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell,
+                       (float)p.rcR, p.listR, p.cntR, p.hT, p.Fnep, p.Znep, p.partials);
     hipError_t e = reduce_partials(p, G, 9, S_WNEP, false);
     if (e != hipSuccess) return e;
     stage_mark(p, ST_RADIAL, 3);
-    hipLaunchKernelGGL((k_angular_forces<T, NR, NA, NB, 0>), dim3(G), dim3(256), 0, p.stream, p.N, p.xs, p.ys,
-                       p.zs, p.ts, p.cell, (float)p.rcA, p.listA, p.cntA, p.capA, p.Amom, p.gU, p.gq, p.phi,
-                       p.scalars, p.theta, p.off_cA, p.off_s, (float4 *)p.pairF, p.Fnep, p.Znep, p.partials);
+    hipLaunchKernelGGL((k_angular_forces<T, NR, NA, NB, 0>), dim3(G), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell,
+                       (float)p.rcA, p.listA, p.cntA, p.capA, p.Amom, p.gU, p.gq, p.phi, p.scalars, p.theta,
+                       p.off_cA, p.off_s, (float4 *)p.pairF, p.Fnep, p.Znep, p.partials);
     stage_mark(p, ST_ANG_E);
     e = reduce_partials(p, G, 9, S_WNEP, true);
     if (e != hipSuccess) return e;
     stage_mark(p, ST_OTHER);
-    hipLaunchKernelGGL((k_angular_forces<T, NR, NA, NB, 1>), dim3(G), dim3(256), 0, p.stream, p.N, p.xs, p.ys,
-                       p.zs, p.ts, p.cell, (float)p.rcA, p.listA, p.cntA, p.capA, p.Amom, p.gU, p.gq, p.phi,
-                       p.scalars, p.theta, p.off_cA, p.off_s, (float4 *)p.pairA, p.Fnep, p.Znep, p.partials);
+    hipLaunchKernelGGL((k_angular_forces<T, NR, NA, NB, 1>), dim3(G), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell,
+                       (float)p.rcA, p.listA, p.cntA, p.capA, p.Amom, p.gU, p.gq, p.phi, p.scalars, p.theta,
+                       p.off_cA, p.off_s, (float4 *)p.pairA, p.Fnep, p.Znep, p.partials);
     stage_mark(p, ST_ANG_Q);
-    hipLaunchKernelGGL(k_assemble, dim3(G), dim3(256), 0, p.stream, p.N, p.xs, p.ys, p.zs, p.cell, p.listA,
-                       p.cntA, p.capA, (const float4 *)p.pairF, (const float4 *)p.pairA, p.Fnep, p.Znep, p.Fst,
-                       p.qraw, p.scalars, p.theta, p.off_s, p.perm, p.pos, p.out.forces, p.out.bec, p.out.charges,
+    hipLaunchKernelGGL(k_assemble, dim3(G), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, p.listA, p.cntA, p.capA,
+                       (const float4 *)p.pairF, (const float4 *)p.pairA, p.Fnep, p.Znep, p.Fst, p.qraw, p.scalars,
+                       p.theta, p.off_s, p.perm, p.pos, p.out.forces, p.out.bec, p.out.charges,
                        p.out.charges_naked, p.partials);
     e = reduce_partials(p, G, 3, S_POL, false);
     stage_mark(p, ST_ASSEMBLE, 2);
@@ -505,5 +532,7 @@ bool nep_supported(int T, int NR, int NA, int NBR, int NBA, int LMAX) {
     if (NBR != 9 || NBA != 9 || LMAX != 4 || T < 1 || T > 4) return false;
     return (NR == 5 && NA == 5) || (NR == 9 && NA == 7);
 }
+
+int radial_table_row(int NB) { return (NB + 3) / 4 * 4; }
 
 }  // namespace qnep

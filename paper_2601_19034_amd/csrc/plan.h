@@ -34,7 +34,7 @@ struct Plan {
     int nc[3] = {1, 1, 1};
     int ncell = 1;
     int mR[3] = {1, 1, 1}, mC[3] = {1, 1, 1};
-    int capR = 0, capA = 0, capC = 0;
+    int capR = 0, capA = 0;
     int nblk = 0;  // blocks of RED_THREADS threads over N
     // ---- Ewald
     int nk_box[3] = {0, 0, 0};
@@ -46,10 +46,11 @@ struct Plan {
     double *partials = nullptr;
     int64_t partials_cap = 0;
     int *cid = nullptr, *cell_count = nullptr, *cell_start = nullptr, *cell_cursor = nullptr, *perm = nullptr;
-    float *xs = nullptr, *ys = nullptr, *zs = nullptr;
-    int *ts = nullptr;
-    uint32_t *listR = nullptr, *listA = nullptr, *listC = nullptr;
-    int *cntR = nullptr, *cntA = nullptr, *cntC = nullptr;
+    int *scan_tmp = nullptr;
+    float4 *xyzt = nullptr;  // sorted positions (x, y, z) with the species in w (as int bits)
+    int *ts = nullptr;       // sorted species
+    uint32_t *listR = nullptr, *listA = nullptr;
+    int *cntR = nullptr, *cntA = nullptr;
     float *D = nullptr, *Amom = nullptr;
     float *U = nullptr, *qraw = nullptr, *gU = nullptr, *gq = nullptr;
     float *phi = nullptr, *Fst = nullptr, *hT = nullptr;

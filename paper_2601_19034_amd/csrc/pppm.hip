@@ -46,16 +46,21 @@ __device__ inline int wrap_index(int j, int n) {
     return j < 0 ? j + n : j;
 }
 
-__global__ __launch_bounds__(256) void k_spread(int N, const float *__restrict__ xs, const float *__restrict__ ys,
-                                                const float *__restrict__ zs, Cell c, MeshGeom g,
+// The 64 lanes of a wave take atoms N/64 apart in the spatial order, so that one
+// atomic instruction of a wave touches 64 well-separated mesh points (atoms close in
+// space share mesh points and would serialize their atomics).
+__global__ __launch_bounds__(256) void k_spread(int N, const float4 *__restrict__ xyzt, Cell c, MeshGeom g,
                                                 const float *__restrict__ qraw, const double *__restrict__ scalars,
                                                 float *__restrict__ rho) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nw = (N + 63) / 64;
+    const int i = (gid & 63) * nw + (gid >> 6);
+    if (gid >= 64 * nw || i >= N) return;
     const float q = qraw[i] + (float)scalars[S_DELTA];
     int m0[3];
     float w[3][5];
-    mesh_stencil(xs[i], ys[i], zs[i], c, g, m0, w);
+    const float4 pa = xyzt[i];
+    mesh_stencil(pa.x, pa.y, pa.z, c, g, m0, w);
     int j0[5], j1[5], j2[5];
 #pragma unroll
     for (int t = 0; t < 5; ++t) {
@@ -98,60 +103,58 @@ __global__ __launch_bounds__(256) void k_influence(MeshGeom g, Cell c, float alp
                                                    float2 *__restrict__ A, float2 *__restrict__ Bm,
                                                    double *__restrict__ partials) {
     const int64_t M = (int64_t)g.n[0] * g.n[1] * g.n[2];
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double red[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    if (idx < M) {
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < M;
+         idx += (int64_t)gridDim.x * blockDim.x) {
         const int j2 = (int)(idx % g.n[2]);
         const int j1 = (int)((idx / g.n[2]) % g.n[1]);
         const int j0 = (int)(idx / ((int64_t)g.n[2] * g.n[1]));
         int nv[3] = {2 * j0 < g.n[0] ? j0 : j0 - g.n[0], 2 * j1 < g.n[1] ? j1 : j1 - g.n[1],
                      2 * j2 < g.n[2] ? j2 : j2 - g.n[2]};
-        float2 S = A[idx];
+        const float2 S = A[idx];
         if (nv[0] == 0 && nv[1] == 0 && nv[2] == 0) {
             A[idx] = make_float2(0.f, 0.f);
             Bm[idx] = make_float2(0.f, 0.f);
-        } else {
-            int nt[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) nt[a] = ((g.n[a] & 1) == 0 && 2 * nv[a] == -g.n[a]) ? 0 : nv[a];
-            double k[3], kt[3];
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                k[b] = 2.0 * PI_D * (c.hinv[3 * b] * nv[0] + c.hinv[3 * b + 1] * nv[1] + c.hinv[3 * b + 2] * nv[2]);
-                kt[b] = 2.0 * PI_D * (c.hinv[3 * b] * nt[0] + c.hinv[3 * b + 1] * nt[1] + c.hinv[3 * b + 2] * nt[2]);
-            }
-            const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
-            const double G = 2.0 * PI_D / vol * exp(-k2 / (4.0 * (double)alpha * alpha)) / k2;
-            float num = 1.0f, den = 1.0f;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                float x = (float)nv[a] / (float)g.n[a];
-                float sc = sinc_pi(x);
-                float sc2 = sc * sc;
-                num *= sc2 * sc2 * sc;
-                den *= alias_poly5(sinpif(x));
-            }
-            const float Gopt = (float)G * (num * num) / (den * den);
-            const double e = KE * (double)Gopt * ((double)S.x * S.x + (double)S.y * S.y);
-            const double cB = 2.0 / (4.0 * (double)alpha * alpha) + 2.0 / k2;
-            red[0] = e;
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) red[1 + 3 * a + b] = e * ((a == b ? 1.0 : 0.0) - cB * k[a] * k[b]);
-            const float2 X = make_float2(S.x * Gopt, S.y * Gopt);
-            const float2 iX = make_float2(-X.y, X.x);
-            const float kx = (float)kt[0], ky = (float)kt[1], kz = (float)kt[2];
-            A[idx] = make_float2(iX.x * (kz + 1.0f), iX.y * (kz + 1.0f));
-            Bm[idx] = make_float2(iX.x * kx - X.x * ky, iX.y * kx - X.y * ky);
+            continue;
         }
+        int nt[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) nt[a] = ((g.n[a] & 1) == 0 && 2 * nv[a] == -g.n[a]) ? 0 : nv[a];
+        float k[3], kt[3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            k[b] = (float)(2.0 * PI_D * (c.hinv[3 * b] * nv[0] + c.hinv[3 * b + 1] * nv[1] + c.hinv[3 * b + 2] * nv[2]));
+            kt[b] = (float)(2.0 * PI_D * (c.hinv[3 * b] * nt[0] + c.hinv[3 * b + 1] * nt[1] + c.hinv[3 * b + 2] * nt[2]));
+        }
+        const float k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+        const float G = (float)(2.0 * PI_D / vol) * __expf(-k2 / (4.0f * alpha * alpha)) / k2;
+        float num = 1.0f, den = 1.0f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float x = (float)nv[a] / (float)g.n[a];
+            const float sc = sinc_pi(x);
+            const float sc2 = sc * sc;
+            num *= sc2 * sc2 * sc;
+            den *= alias_poly5(sinpif(x));
+        }
+        const float Gopt = G * (num * num) / (den * den);
+        const float e = (float)KE * Gopt * (S.x * S.x + S.y * S.y);
+        const float cB = 2.0f / (4.0f * alpha * alpha) + 2.0f / k2;
+        red[0] += e;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) red[1 + 3 * a + b] += e * ((a == b ? 1.0f : 0.0f) - cB * k[a] * k[b]);
+        const float2 X = make_float2(S.x * Gopt, S.y * Gopt);
+        const float2 iX = make_float2(-X.y, X.x);
+        A[idx] = make_float2(iX.x * (kt[2] + 1.0f), iX.y * (kt[2] + 1.0f));
+        Bm[idx] = make_float2(iX.x * kt[0] - X.x * kt[1], iX.y * kt[0] - X.y * kt[1]);
     }
     block_partials<10>(red, partials);
 }
 
 // phi^k_i += 2 k_e sum_s W phi'_s,  F^k_i += -2 k_e q'_i sum_s W E_s
-__global__ __launch_bounds__(256) void k_gather(int N, const float *__restrict__ xs, const float *__restrict__ ys,
-                                                const float *__restrict__ zs, Cell c, MeshGeom g,
+__global__ __launch_bounds__(256) void k_gather(int N, const float4 *__restrict__ xyzt, Cell c, MeshGeom g,
                                                 const float *__restrict__ qraw, const double *__restrict__ scalars,
                                                 const float2 *__restrict__ A, const float2 *__restrict__ Bm,
                                                 float *__restrict__ phi, float *__restrict__ Fst) {
@@ -159,7 +162,8 @@ __global__ __launch_bounds__(256) void k_gather(int N, const float *__restrict__
     if (i >= N) return;
     int m0[3];
     float w[3][5];
-    mesh_stencil(xs[i], ys[i], zs[i], c, g, m0, w);
+    const float4 pa = xyzt[i];
+    mesh_stencil(pa.x, pa.y, pa.z, c, g, m0, w);
     int j0[5], j1[5], j2[5];
 #pragma unroll
     for (int t = 0; t < 5; ++t) {
@@ -199,8 +203,9 @@ hipError_t launch_pppm(const Plan &p) {
     const int G = (p.N + 255) / 256;
     hipError_t e = fill_zero(p.rho, sizeof(float) * (size_t)M, p.stream);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_spread, dim3(G), dim3(256), 0, p.stream, p.N, p.xs, p.ys, p.zs, p.cell, g, p.qraw,
-                       p.scalars, p.rho);
+    const int GS = (64 * ((p.N + 63) / 64) + 255) / 256;
+    hipLaunchKernelGGL(k_spread, dim3(GS), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, g, p.qraw, p.scalars,
+                       p.rho);
     const int GM = (int)((M + 255) / 256);
     hipLaunchKernelGGL(k_real_to_complex, dim3(GM), dim3(256), 0, p.stream, M, p.rho, p.meshA);
     e = hipGetLastError();
@@ -209,11 +214,12 @@ hipError_t launch_pppm(const Plan &p) {
     e = fft3d(p.meshA, nullptr, p.mesh, -1, p.stream);
     if (e != hipSuccess) return e;
     stage_mark(p, ST_FFT_FWD, 3);
-    hipLaunchKernelGGL(k_influence, dim3(GM), dim3(256), 0, p.stream, g, p.cell, (float)p.alpha, p.vol, p.meshA,
+    const int GI = GM < 2048 ? GM : 2048;
+    hipLaunchKernelGGL(k_influence, dim3(GI), dim3(256), 0, p.stream, g, p.cell, (float)p.alpha, p.vol, p.meshA,
                        p.meshB, p.partials);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = reduce_partials(p, GM, 10, S_UK, false);  // S_UK, S_WK[9]
+    e = reduce_partials(p, GI, 10, S_UK, false);  // S_UK, S_WK[9]
     if (e != hipSuccess) return e;
     stage_mark(p, ST_INFLUENCE, 2);
     e = fft3d(p.meshA, nullptr, p.mesh, +1, p.stream);
@@ -221,7 +227,7 @@ hipError_t launch_pppm(const Plan &p) {
     e = fft3d(p.meshB, nullptr, p.mesh, +1, p.stream);
     if (e != hipSuccess) return e;
     stage_mark(p, ST_FFT_INV, 6);
-    hipLaunchKernelGGL(k_gather, dim3(G), dim3(256), 0, p.stream, p.N, p.xs, p.ys, p.zs, p.cell, g, p.qraw,
+    hipLaunchKernelGGL(k_gather, dim3(G), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, g, p.qraw,
                        p.scalars, p.meshA, p.meshB, p.phi, p.Fst);
     stage_mark(p, ST_GATHER);
     return hipGetLastError();
