@@ -235,7 +235,7 @@ qnep_status make_plan(const Model &m, const qnep_es_params *es, const qnep_syste
     const double rbin = 0.5 * std::max(p.rcR, p.rcA);
     for (int a = 0; a < 3; ++a) {
         p.nc[a] = std::max(1, (int)std::floor(w[a] / rbin));
-        p.mR[a] = (int)std::ceil(rbin * p.nc[a] / w[a] - 1e-12);
+        p.mR[a] = (int)std::ceil(std::max(p.rcR, p.rcA) * p.nc[a] / w[a] - 1e-12);
         p.mC[a] = (int)std::ceil(p.rc_coul * p.nc[a] / w[a] - 1e-12);
         if (p.mR[a] < 1) p.mR[a] = 1;
         if (p.mC[a] < 1) p.mC[a] = 1;

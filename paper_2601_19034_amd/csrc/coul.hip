@@ -11,11 +11,13 @@
 namespace qnep {
 
 // ---------------------------------------------------------------- real space
-// One thread per sorted atom walks the bin stencil of the real-space cutoff directly
+// RS_LANES lanes share one sorted atom and split the (2m+1)^3 bins of its stencil
 // (no stored list): candidates are screened in FP32, decided with the FP64
 // displacement rounded to FP32, and contribute phi^r_i, the static pair force
 // F_i = -k_e q'_i sum_j q'_j [erfc(a r)/r + 2a e^{-a^2 r^2}/sqrt(pi)] r_ij / r^2 and the
 // pair virial (each unordered pair is seen from both atoms with weight 1/2).
+constexpr int RS_LANES = 16;
+
 __global__ __launch_bounds__(256) void k_real_space(int N, const float4 *__restrict__ xyzt, Cell c, int nc0,
                                                     int nc1, int nc2, int m0, int m1, int m2,
                                                     const int *__restrict__ start, double rc2,
@@ -23,80 +25,87 @@ __global__ __launch_bounds__(256) void k_real_space(int N, const float4 *__restr
                                                     const double *__restrict__ scalars, float alpha,
                                                     float *__restrict__ phi, float *__restrict__ Fst,
                                                     double *__restrict__ partials) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    double red[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = gtid / RS_LANES, sub = gtid % RS_LANES;
+    float acc[10];  // phi, B r (3), B r r (xx yy zz xy xz yz)
+#pragma unroll
+    for (int k = 0; k < 10; ++k) acc[k] = 0.f;
+    const float delta = (float)scalars[S_DELTA];
     if (i < N) {
         const float4 pi = xyzt[i];
         int ci[3];
         bin_of(pi, c, nc0, nc1, nc2, ci);
         const float rc2_hi = (float)(rc2 * (1.0 + 1e-4));
-        const float delta = (float)scalars[S_DELTA];
-        const float qi = qraw[i] + delta;
         const float c2 = 2.0f * alpha * 0.5641895835477563f;  // 2 alpha / sqrt(pi)
-        float ph = 0.f, bx = 0.f, by = 0.f, bz = 0.f;
-        float wxx = 0.f, wyy = 0.f, wzz = 0.f, wxy = 0.f, wxz = 0.f, wyz = 0.f;
-        for (int d0 = -m0; d0 <= m0; ++d0) {
-            int u0 = ci[0] + d0, i0 = floor_div(u0, nc0), w0 = u0 - i0 * nc0;
-            for (int d1 = -m1; d1 <= m1; ++d1) {
-                int u1 = ci[1] + d1, i1 = floor_div(u1, nc1), w1 = u1 - i1 * nc1;
-                for (int d2 = -m2; d2 <= m2; ++d2) {
-                    int u2 = ci[2] + d2, i2 = floor_div(u2, nc2), w2 = u2 - i2 * nc2;
-                    ImageShift sh(c, i0, i1, i2);
-                    const bool self_img = (i0 == 0 && i1 == 0 && i2 == 0);
-                    const int lin = (w0 * nc1 + w1) * nc2 + w2;
-                    const int b = start[lin], e = start[lin + 1];
-                    for (int j = b; j < e; ++j) {
-                        const float4 pj = xyzt[j];
-                        float fx = (pj.x - pi.x) + sh.fx, fy = (pj.y - pi.y) + sh.fy, fz = (pj.z - pi.z) + sh.fz;
-                        if (fx * fx + fy * fy + fz * fz >= rc2_hi) continue;
-                        if (self_img && j == i) continue;
-                        const float3 d = sh.exact(pi, pj);
-                        const double r2d = (double)d.x * d.x + (double)d.y * d.y + (double)d.z * d.z;
-                        if (r2d >= rc2) continue;
-                        const float r2 = (float)r2d;
-                        const float ir = rsqrtf(r2);
-                        const float r = r2 * ir;
-                        const float qj = qraw[j] + delta;
-                        const float ar = alpha * r;
-                        const float ec = erfcf(ar);
-                        const float ex = __expf(-ar * ar);
-                        ph = fmaf(qj, ec * ir, ph);
-                        const float B = qj * (ec * ir + c2 * ex) * ir * ir;
-                        bx = fmaf(B, d.x, bx);
-                        by = fmaf(B, d.y, by);
-                        bz = fmaf(B, d.z, bz);
-                        wxx = fmaf(B, d.x * d.x, wxx);
-                        wyy = fmaf(B, d.y * d.y, wyy);
-                        wzz = fmaf(B, d.z * d.z, wzz);
-                        wxy = fmaf(B, d.x * d.y, wxy);
-                        wxz = fmaf(B, d.x * d.z, wxz);
-                        wyz = fmaf(B, d.y * d.z, wyz);
-                    }
-                }
+        const int w1n = 2 * m1 + 1, w2n = 2 * m2 + 1;
+        const int nbins = (2 * m0 + 1) * w1n * w2n;
+        for (int bi = sub; bi < nbins; bi += RS_LANES) {
+            const int d0 = bi / (w1n * w2n) - m0, d1 = (bi / w2n) % w1n - m1, d2 = bi % w2n - m2;
+            const int u0 = ci[0] + d0, i0 = floor_div(u0, nc0), b0 = u0 - i0 * nc0;
+            const int u1 = ci[1] + d1, i1 = floor_div(u1, nc1), b1 = u1 - i1 * nc1;
+            const int u2 = ci[2] + d2, i2 = floor_div(u2, nc2), b2 = u2 - i2 * nc2;
+            ImageShift sh(c, i0, i1, i2);
+            const bool self_img = (i0 == 0 && i1 == 0 && i2 == 0);
+            const int lin = (b0 * nc1 + b1) * nc2 + b2;
+            const int jb = start[lin], je = start[lin + 1];
+            for (int j = jb; j < je; ++j) {
+                const float4 pj = xyzt[j];
+                const float fx = (pj.x - pi.x) + sh.fx, fy = (pj.y - pi.y) + sh.fy, fz = (pj.z - pi.z) + sh.fz;
+                if (fx * fx + fy * fy + fz * fz >= rc2_hi) continue;
+                if (self_img && j == i) continue;
+                const float3 d = sh.exact(pi, pj);
+                const double r2d = (double)d.x * d.x + (double)d.y * d.y + (double)d.z * d.z;
+                if (r2d >= rc2) continue;
+                const float r2 = (float)r2d;
+                const float ir = rsqrtf(r2);
+                const float r = r2 * ir;
+                const float qj = qraw[j] + delta;
+                const float ar = alpha * r;
+                const float ec = erfcf(ar);
+                const float ex = __expf(-ar * ar);
+                acc[0] = fmaf(qj, ec * ir, acc[0]);
+                const float B = qj * (ec * ir + c2 * ex) * ir * ir;
+                acc[1] = fmaf(B, d.x, acc[1]);
+                acc[2] = fmaf(B, d.y, acc[2]);
+                acc[3] = fmaf(B, d.z, acc[3]);
+                acc[4] = fmaf(B, d.x * d.x, acc[4]);
+                acc[5] = fmaf(B, d.y * d.y, acc[5]);
+                acc[6] = fmaf(B, d.z * d.z, acc[6]);
+                acc[7] = fmaf(B, d.x * d.y, acc[7]);
+                acc[8] = fmaf(B, d.x * d.z, acc[8]);
+                acc[9] = fmaf(B, d.y * d.z, acc[9]);
             }
         }
+    }
+#pragma unroll
+    for (int k = 0; k < 10; ++k)
+#pragma unroll
+        for (int o = RS_LANES / 2; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o, 64);
+    double red[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (i < N && sub == 0) {
+        const float qi = qraw[i] + delta;
         const float ke = (float)KE;
-        phi[i] = ke * ph;
-        Fst[i] = -ke * qi * bx;
-        Fst[(size_t)N + i] = -ke * qi * by;
-        Fst[(size_t)2 * N + i] = -ke * qi * bz;
-        red[0] = 0.5 * (double)qi * (double)(ke * ph);
+        phi[i] = ke * acc[0];
+        Fst[i] = -ke * qi * acc[1];
+        Fst[(size_t)N + i] = -ke * qi * acc[2];
+        Fst[(size_t)2 * N + i] = -ke * qi * acc[3];
+        red[0] = 0.5 * (double)qi * (double)(ke * acc[0]);
         red[1] = (double)qi * (double)qi;
         const double hw = 0.5 * KE * (double)qi;
-        red[2] = hw * wxx; red[3] = hw * wxy; red[4] = hw * wxz;
-        red[5] = hw * wxy; red[6] = hw * wyy; red[7] = hw * wyz;
-        red[8] = hw * wxz; red[9] = hw * wyz; red[10] = hw * wzz;
+        red[2] = hw * acc[4]; red[3] = hw * acc[7]; red[4] = hw * acc[8];
+        red[5] = hw * acc[7]; red[6] = hw * acc[5]; red[7] = hw * acc[9];
+        red[8] = hw * acc[8]; red[9] = hw * acc[9]; red[10] = hw * acc[6];
     }
     block_partials<11>(red, partials);
 }
 
 hipError_t launch_real_space(const Plan &p) {
-    const int G = (p.N + 255) / 256;
     if (p.mode != 1) {
         hipError_t e = fill_zero(p.phi, sizeof(float) * (size_t)p.N, p.stream);
         if (e != hipSuccess) return e;
         return fill_zero(p.Fst, sizeof(float) * 3 * (size_t)p.N, p.stream);
     }
+    const int G = (int)(((int64_t)p.N * RS_LANES + 255) / 256);
     hipLaunchKernelGGL(k_real_space, dim3(G), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, p.nc[0], p.nc[1],
                        p.nc[2], p.mC[0], p.mC[1], p.mC[2], p.cell_start, p.rc_coul * p.rc_coul, p.qraw, p.scalars,
                        (float)p.alpha, p.phi, p.Fst, p.partials);

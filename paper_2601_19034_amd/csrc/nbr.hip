@@ -131,8 +131,8 @@ __global__ void k_gather_sorted(int N, const float *__restrict__ pos, const int3
 }
 
 // ---------------------------------------------------------------- lists
-// One thread per sorted atom.  Main list: slot-major list[k * N + i].  Sub-list
-// (r < rc_sub): atom-major sub[i * cap_sub + k].
+// One thread per sorted atom.  Both lists are atom-major: list[i * cap + k] and,
+// for r < rc_sub, sub[i * cap_sub + k].
 __global__ __launch_bounds__(256) void k_lists(int N, const float4 *__restrict__ xyzt, Cell c, int nc0, int nc1,
                                                int nc2, int m0, int m1, int m2, const int *__restrict__ start,
                                                double rc2, int cap, uint32_t *__restrict__ list,
@@ -165,7 +165,7 @@ __global__ __launch_bounds__(256) void k_lists(int N, const float4 *__restrict__
                     double r2 = (double)d.x * d.x + (double)d.y * d.y + (double)d.z * d.z;
                     if (r2 < rc2) {
                         uint32_t code = nb_encode(j, i0, i1, i2);
-                        if (n_main < cap) list[(size_t)n_main * N + i] = code;
+                        if (n_main < cap) list[(size_t)i * cap + n_main] = code;
                         ++n_main;
                         if (r2 < rs2) {
                             if (n_sub < cap_sub) sub[(size_t)i * cap_sub + n_sub] = code;

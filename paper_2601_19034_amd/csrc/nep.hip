@@ -28,7 +28,7 @@ struct Pad4 {
 template <int T, int NR, int NA, int NB>
 __global__ __launch_bounds__(256) void k_descriptors(int N, const float4 *__restrict__ xyzt, Cell c, float rcR,
                                                      float rcA, const uint32_t *__restrict__ listR,
-                                                     const int *__restrict__ cntR,
+                                                     const int *__restrict__ cntR, int capR,
                                                      const uint32_t *__restrict__ listA,
                                                      const int *__restrict__ cntA, int capA,
                                                      const float *__restrict__ theta, int64_t off_cR,
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(256) void k_descriptors(int N, const float4 *__rest
         for (int k = 0; k < NB; ++k) B[t][k] = 0.0f;
     const int nR = cntR[i];
     for (int s = 0; s < nR; ++s) {
-        const uint32_t e = listR[(size_t)s * N + i];
+        const uint32_t e = listR[(size_t)i * capR + s];
         const float4 pj = xyzt[nb_index(e)];
         int n1, n2, n3;
         nb_image(e, n1, n2, n3);
@@ -180,25 +180,29 @@ __global__ __launch_bounds__(256) void k_radial_tables(int N, const int *__restr
 // F_ij = sigma_ij u, sigma_ij = sum_k hE_i[tj][k] f_k'(r); a_ij = rho_ij u likewise.
 // F_i = sum_j (sigma_ij + sigma_ji) u_ij, Z_i += 1/2 sum_j (rho_ij - rho_ji) r u (x) u,
 // W -= sum_j sigma_ij r u (x) u (own partial forces only).
+// RF_LANES lanes share one atom and split its neighbours; the sums are combined
+// across the lane group with butterfly shuffles.
+constexpr int RF_LANES = 16;
+
 template <int T, int NB>
 __global__ __launch_bounds__(256) void k_radial_forces(int N, const float4 *__restrict__ xyzt, Cell c, float rcR,
                                                        const uint32_t *__restrict__ listR,
-                                                       const int *__restrict__ cntR,
+                                                       const int *__restrict__ cntR, int capR,
                                                        const float *__restrict__ hT, float *__restrict__ Fnep,
                                                        float *__restrict__ Znep, double *__restrict__ partials) {
     constexpr int NBP = Pad4<NB>::v;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    double w[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = gtid / RF_LANES, sub = gtid % RF_LANES;
+    float acc[15];  // F (3), Z (xx yy zz xy xz yz), W (same order)
+#pragma unroll
+    for (int k = 0; k < 15; ++k) acc[k] = 0.f;
     if (i < N) {
         const float4 pi = xyzt[i];
         const int ti = species_of(pi);
-        float fx = 0.f, fy = 0.f, fz = 0.f;
-        float zxx = 0.f, zyy = 0.f, zzz = 0.f, zxy = 0.f, zxz = 0.f, zyz = 0.f;
-        float wxx = 0.f, wyy = 0.f, wzz = 0.f, wxy = 0.f, wxz = 0.f, wyz = 0.f;
         const float *own = hT + (size_t)i * (2 * T * NBP);
         const int nR = cntR[i];
-        for (int s = 0; s < nR; ++s) {
-            const uint32_t e = listR[(size_t)s * N + i];
+        for (int s = sub; s < nR; s += RF_LANES) {
+            const uint32_t e = listR[(size_t)i * capR + s];
             const int j = nb_index(e);
             const float4 pj = xyzt[j];
             int n1, n2, n3;
@@ -233,27 +237,28 @@ __global__ __launch_bounds__(256) void k_radial_forces(int N, const float4 *__re
             const float ir = 1.0f / r;
             const float ux = d.x * ir, uy = d.y * ir, uz = d.z * ir;
             const float sf = sij + sji;
-            fx = fmaf(sf, ux, fx);
-            fy = fmaf(sf, uy, fy);
-            fz = fmaf(sf, uz, fz);
-            const float zr = 0.5f * (rij - rji) * r;
-            zxx = fmaf(zr, ux * ux, zxx);
-            zyy = fmaf(zr, uy * uy, zyy);
-            zzz = fmaf(zr, uz * uz, zzz);
-            zxy = fmaf(zr, ux * uy, zxy);
-            zxz = fmaf(zr, ux * uz, zxz);
-            zyz = fmaf(zr, uy * uz, zyz);
-            const float wr = sij * r;
-            wxx = fmaf(wr, ux * ux, wxx);
-            wyy = fmaf(wr, uy * uy, wyy);
-            wzz = fmaf(wr, uz * uz, wzz);
-            wxy = fmaf(wr, ux * uy, wxy);
-            wxz = fmaf(wr, ux * uz, wxz);
-            wyz = fmaf(wr, uy * uz, wyz);
+            acc[0] = fmaf(sf, ux, acc[0]);
+            acc[1] = fmaf(sf, uy, acc[1]);
+            acc[2] = fmaf(sf, uz, acc[2]);
+            const float zr = 0.5f * (rij - rji) * r, wr = -sij * r;
+            const float uu[6] = {ux * ux, uy * uy, uz * uz, ux * uy, ux * uz, uy * uz};
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                acc[3 + k] = fmaf(zr, uu[k], acc[3 + k]);
+                acc[9 + k] = fmaf(wr, uu[k], acc[9 + k]);
+            }
         }
-        Fnep[i] = fx;
-        Fnep[(size_t)N + i] = fy;
-        Fnep[(size_t)2 * N + i] = fz;
+    }
+#pragma unroll
+    for (int k = 0; k < 15; ++k)
+#pragma unroll
+        for (int o = RF_LANES / 2; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o, 64);
+    double w[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (i < N && sub == 0) {
+        Fnep[i] = acc[0];
+        Fnep[(size_t)N + i] = acc[1];
+        Fnep[(size_t)2 * N + i] = acc[2];
+        const float zxx = acc[3], zyy = acc[4], zzz = acc[5], zxy = acc[6], zxz = acc[7], zyz = acc[8];
         Znep[(size_t)0 * N + i] = zxx;
         Znep[(size_t)1 * N + i] = zxy;
         Znep[(size_t)2 * N + i] = zxz;
@@ -263,9 +268,10 @@ __global__ __launch_bounds__(256) void k_radial_forces(int N, const float4 *__re
         Znep[(size_t)6 * N + i] = zxz;
         Znep[(size_t)7 * N + i] = zyz;
         Znep[(size_t)8 * N + i] = zzz;
-        w[0] = -wxx; w[1] = -wxy; w[2] = -wxz;
-        w[3] = -wxy; w[4] = -wyy; w[5] = -wyz;
-        w[6] = -wxz; w[7] = -wyz; w[8] = -wzz;
+        w[0] = acc[9]; w[4] = acc[10]; w[8] = acc[11];
+        w[1] = w[3] = acc[12];
+        w[2] = w[6] = acc[13];
+        w[5] = w[7] = acc[14];
     }
     block_partials<9>(w, partials);
 }
@@ -407,6 +413,9 @@ __device__ inline int find_slot(const uint32_t *__restrict__ listA, int j, int c
 // Adds the angular reverse terms -F_ji and -1/2 r_ji (x) a_ji found in each
 // neighbour's pair buffer, the static electrostatic forces and the diagonal q~'_i,
 // writes F, Z*, q', q~' in input order and FP64 partials of P = sum_i q~'_i r_i.
+// AS_LANES lanes share one atom and split its angular neighbours.
+constexpr int AS_LANES = 8;
+
 __global__ __launch_bounds__(256) void k_assemble(
     int N, const float4 *__restrict__ xyzt, Cell c, const uint32_t *__restrict__ listA,
     const int *__restrict__ cntA, int capA, const float4 *__restrict__ pairF, const float4 *__restrict__ pairA,
@@ -415,46 +424,54 @@ __global__ __launch_bounds__(256) void k_assemble(
     int64_t off_s, const int *__restrict__ perm, const float *__restrict__ pos, float *__restrict__ forces,
     float *__restrict__ bec, float *__restrict__ charges, float *__restrict__ charges_naked,
     double *__restrict__ partials) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    double pv[3] = {0, 0, 0};
+    const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = gtid / AS_LANES, sub = gtid % AS_LANES;
+    float acc[12];  // F (3), Z (9)
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = 0.f;
     if (i < N) {
-        const float s = theta[off_s];
-        const float qp = (float)((double)qraw[i] + scalars[S_DELTA]);  // q'
-        const float qt = s * qp;                                        // q~'
         const float4 pi = xyzt[i];
-        float F[3], Z[9];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) F[a] = Fnep[(size_t)a * N + i] + Fst[(size_t)a * N + i];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) Z[k] = Znep[(size_t)k * N + i];
-        Z[0] += qt;
-        Z[4] += qt;
-        Z[8] += qt;
         const int nA = cntA[i];
-        for (int sl = 0; sl < nA; ++sl) {
+        for (int sl = sub; sl < nA; sl += AS_LANES) {
             const uint32_t e = listA[(size_t)i * capA + sl];
             const int j = nb_index(e);
             const int found = find_slot(listA, j, capA, cntA[j], nb_reverse(e, i));
             if (found < 0) continue;  // pair at the cutoff on one side only: contributes zero
             const float4 fji = pairF[(size_t)j * capA + found];
             const float4 aji = pairA[(size_t)j * capA + found];
-            F[0] -= fji.x;
-            F[1] -= fji.y;
-            F[2] -= fji.z;
+            acc[0] -= fji.x;
+            acc[1] -= fji.y;
+            acc[2] -= fji.z;
             const float3 d = displacement(pi, xyzt, e, c);  // r_ij = -r_ji
             // -1/2 r_ji (x) a_ji = +1/2 r_ij (x) a_ji
-            Z[0] += 0.5f * d.x * aji.x; Z[1] += 0.5f * d.x * aji.y; Z[2] += 0.5f * d.x * aji.z;
-            Z[3] += 0.5f * d.y * aji.x; Z[4] += 0.5f * d.y * aji.y; Z[5] += 0.5f * d.y * aji.z;
-            Z[6] += 0.5f * d.z * aji.x; Z[7] += 0.5f * d.z * aji.y; Z[8] += 0.5f * d.z * aji.z;
+            const float dv[3] = {0.5f * d.x, 0.5f * d.y, 0.5f * d.z}, av[3] = {aji.x, aji.y, aji.z};
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) acc[3 + 3 * a + b] = fmaf(dv[a], av[b], acc[3 + 3 * a + b]);
         }
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+#pragma unroll
+        for (int o = AS_LANES / 2; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o, 64);
+    double pv[3] = {0, 0, 0};
+    if (i < N && sub == 0) {
+        const float s = theta[off_s];
+        const float qp = (float)((double)qraw[i] + scalars[S_DELTA]);  // q'
+        const float qt = s * qp;                                        // q~'
         const int o = perm[i];
         if (forces) {
 #pragma unroll
-            for (int a = 0; a < 3; ++a) forces[(size_t)a * N + o] = F[a];
+            for (int a = 0; a < 3; ++a)
+                forces[(size_t)a * N + o] = Fnep[(size_t)a * N + i] + Fst[(size_t)a * N + i] + acc[a];
         }
         if (bec) {
 #pragma unroll
-            for (int k = 0; k < 9; ++k) bec[(size_t)k * N + o] = Z[k];
+            for (int k = 0; k < 9; ++k) {
+                const float diag = (k == 0 || k == 4 || k == 8) ? qt : 0.0f;
+                bec[(size_t)k * N + o] = Znep[(size_t)k * N + i] + acc[3 + k] + diag;
+            }
         }
         if (charges) charges[o] = qp;
         if (charges_naked) charges_naked[o] = qt;
@@ -472,7 +489,7 @@ template <int T, int NR, int NA, int NB>
 static hipError_t run_descriptors(const Plan &p) {
     const int G = (p.N + 255) / 256;
     hipLaunchKernelGGL((k_descriptors<T, NR, NA, NB>), dim3(G), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell,
-                       (float)p.rcR, (float)p.rcA, p.listR, p.cntR, p.listA, p.cntA, p.capA, p.theta, p.off_cR,
+                       (float)p.rcR, (float)p.rcA, p.listR, p.cntR, p.capR, p.listA, p.cntA, p.capA, p.theta, p.off_cR,
                        p.off_cA, p.D, p.Amom);
     return hipGetLastError();
 }
@@ -482,9 +499,10 @@ static hipError_t run_forces(const Plan &p) {
     const int G = (p.N + 255) / 256;
     hipLaunchKernelGGL((k_radial_tables<T, NR, NB>), dim3(G), dim3(256), 0, p.stream, p.N, p.ts, p.gU, p.gq,
                        p.phi, p.scalars, p.theta, p.off_cR, p.off_s, p.hT);
-    hipLaunchKernelGGL((k_radial_forces<T, NB>), dim3(G), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell,
-                       (float)p.rcR, p.listR, p.cntR, p.hT, p.Fnep, p.Znep, p.partials);
-    hipError_t e = reduce_partials(p, G, 9, S_WNEP, false);
+    const int GR = (int)(((int64_t)p.N * RF_LANES + 255) / 256);
+    hipLaunchKernelGGL((k_radial_forces<T, NB>), dim3(GR), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell,
+                       (float)p.rcR, p.listR, p.cntR, p.capR, p.hT, p.Fnep, p.Znep, p.partials);
+    hipError_t e = reduce_partials(p, GR, 9, S_WNEP, false);
     if (e != hipSuccess) return e;
     stage_mark(p, ST_RADIAL, 3);
     hipLaunchKernelGGL((k_angular_forces<T, NR, NA, NB, 0>), dim3(G), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell,
@@ -498,11 +516,12 @@ static hipError_t run_forces(const Plan &p) {
                        (float)p.rcA, p.listA, p.cntA, p.capA, p.Amom, p.gU, p.gq, p.phi, p.scalars, p.theta,
                        p.off_cA, p.off_s, (float4 *)p.pairA, p.Fnep, p.Znep, p.partials);
     stage_mark(p, ST_ANG_Q);
-    hipLaunchKernelGGL(k_assemble, dim3(G), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, p.listA, p.cntA, p.capA,
+    const int GA = (int)(((int64_t)p.N * AS_LANES + 255) / 256);
+    hipLaunchKernelGGL(k_assemble, dim3(GA), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, p.listA, p.cntA, p.capA,
                        (const float4 *)p.pairF, (const float4 *)p.pairA, p.Fnep, p.Znep, p.Fst, p.qraw, p.scalars,
                        p.theta, p.off_s, p.perm, p.pos, p.out.forces, p.out.bec, p.out.charges,
                        p.out.charges_naked, p.partials);
-    e = reduce_partials(p, G, 3, S_POL, false);
+    e = reduce_partials(p, GA, 3, S_POL, false);
     stage_mark(p, ST_ASSEMBLE, 2);
     return e;
 }

@@ -46,16 +46,11 @@ __device__ inline int wrap_index(int j, int n) {
     return j < 0 ? j + n : j;
 }
 
-// The 64 lanes of a wave take atoms N/64 apart in the spatial order, so that one
-// atomic instruction of a wave touches 64 well-separated mesh points (atoms close in
-// space share mesh points and would serialize their atomics).
 __global__ __launch_bounds__(256) void k_spread(int N, const float4 *__restrict__ xyzt, Cell c, MeshGeom g,
                                                 const float *__restrict__ qraw, const double *__restrict__ scalars,
                                                 float *__restrict__ rho) {
-    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nw = (N + 63) / 64;
-    const int i = (gid & 63) * nw + (gid >> 6);
-    if (gid >= 64 * nw || i >= N) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
     const float q = qraw[i] + (float)scalars[S_DELTA];
     int m0[3];
     float w[3][5];
@@ -203,8 +198,7 @@ hipError_t launch_pppm(const Plan &p) {
     const int G = (p.N + 255) / 256;
     hipError_t e = fill_zero(p.rho, sizeof(float) * (size_t)M, p.stream);
     if (e != hipSuccess) return e;
-    const int GS = (64 * ((p.N + 63) / 64) + 255) / 256;
-    hipLaunchKernelGGL(k_spread, dim3(GS), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, g, p.qraw, p.scalars,
+    hipLaunchKernelGGL(k_spread, dim3(G), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, g, p.qraw, p.scalars,
                        p.rho);
     const int GM = (int)((M + 255) / 256);
     hipLaunchKernelGGL(k_real_to_complex, dim3(GM), dim3(256), 0, p.stream, M, p.rho, p.meshA);
