@@ -62,6 +62,7 @@ typedef enum {
 #define QNEP_FLAG_ANGULAR_OVERFLOW 2
 #define QNEP_FLAG_COULOMB_OVERFLOW 4
 #define QNEP_FLAG_BAD_SPECIES 8
+#define QNEP_FLAG_INTERNAL 16  /* an atom fell outside its charge-assignment tile (should not happen) */
 
 /* MLP arithmetic */
 #define QNEP_MLP_FP32 0   /* FP32 vector ALU */

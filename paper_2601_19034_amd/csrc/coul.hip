@@ -37,18 +37,23 @@ __global__ __launch_bounds__(256) void k_real_space(int N, const float4 *__restr
         bin_of(pi, c, nc0, nc1, nc2, ci);
         const float rc2_hi = (float)(rc2 * (1.0 + 1e-4));
         const float c2 = 2.0f * alpha * 0.5641895835477563f;  // 2 alpha / sqrt(pi)
-        const int w1n = 2 * m1 + 1, w2n = 2 * m2 + 1;
-        const int nbins = (2 * m0 + 1) * w1n * w2n;
-        for (int bi = sub; bi < nbins; bi += RS_LANES) {
-            const int d0 = bi / (w1n * w2n) - m0, d1 = (bi / w2n) % w1n - m1, d2 = bi % w2n - m2;
+        const int w1n = 2 * m1 + 1;
+        const int nrows = (2 * m0 + 1) * w1n;
+        const int zlo = ci[2] - m2, zhi = ci[2] + m2;
+        // a row of bins along c is one contiguous atom range per image along c
+        for (int ri = sub; ri < nrows * 4; ri += RS_LANES) {
+            const int row = ri >> 2, part = ri & 3;
+            const int d0 = row / w1n - m0, d1 = row % w1n - m1;
             const int u0 = ci[0] + d0, i0 = floor_div(u0, nc0), b0 = u0 - i0 * nc0;
             const int u1 = ci[1] + d1, i1 = floor_div(u1, nc1), b1 = u1 - i1 * nc1;
-            const int u2 = ci[2] + d2, i2 = floor_div(u2, nc2), b2 = u2 - i2 * nc2;
+            const int rowbase = (b0 * nc1 + b1) * nc2;
+            for (int i2 = floor_div(zlo, nc2); i2 <= floor_div(zhi, nc2); ++i2) {
+            const int za = max(zlo, i2 * nc2) - i2 * nc2, zb = min(zhi, i2 * nc2 + nc2 - 1) - i2 * nc2;
             ImageShift sh(c, i0, i1, i2);
             const bool self_img = (i0 == 0 && i1 == 0 && i2 == 0);
-            const int lin = (b0 * nc1 + b1) * nc2 + b2;
-            const int jb = start[lin], je = start[lin + 1];
-            for (int j = jb; j < je; ++j) {
+            const int jb0 = start[rowbase + za], je0 = start[rowbase + zb + 1];
+            // the four lanes of a row take every fourth atom of it
+            for (int j = jb0 + part; j < je0; j += 4) {
                 const float4 pj = xyzt[j];
                 const float fx = (pj.x - pi.x) + sh.fx, fy = (pj.y - pi.y) + sh.fy, fz = (pj.z - pi.z) + sh.fz;
                 if (fx * fx + fy * fy + fz * fz >= rc2_hi) continue;
@@ -74,6 +79,7 @@ __global__ __launch_bounds__(256) void k_real_space(int N, const float4 *__restr
                 acc[7] = fmaf(B, d.x * d.y, acc[7]);
                 acc[8] = fmaf(B, d.x * d.z, acc[8]);
                 acc[9] = fmaf(B, d.y * d.z, acc[9]);
+            }
             }
         }
     }

@@ -146,16 +146,18 @@ __global__ __launch_bounds__(256) void k_lists(int N, const float4 *__restrict__
     bin_of(pi, c, nc0, nc1, nc2, ci);
     const float rc2_hi = (float)(rc2 * (1.0 + 1e-4));
     int n_main = 0, n_sub = 0;
+    const int zlo = ci[2] - m2, zhi = ci[2] + m2;
     for (int d0 = -m0; d0 <= m0; ++d0) {
         int u0 = ci[0] + d0, i0 = floor_div(u0, nc0), w0 = u0 - i0 * nc0;
         for (int d1 = -m1; d1 <= m1; ++d1) {
             int u1 = ci[1] + d1, i1 = floor_div(u1, nc1), w1 = u1 - i1 * nc1;
-            for (int d2 = -m2; d2 <= m2; ++d2) {
-                int u2 = ci[2] + d2, i2 = floor_div(u2, nc2), w2 = u2 - i2 * nc2;
+            const int rowbase = (w0 * nc1 + w1) * nc2;
+            // bins along c are consecutive in the sort: one atom range per image along c
+            for (int i2 = floor_div(zlo, nc2); i2 <= floor_div(zhi, nc2); ++i2) {
+                const int za = max(zlo, i2 * nc2) - i2 * nc2, zb = min(zhi, i2 * nc2 + nc2 - 1) - i2 * nc2;
                 ImageShift sh(c, i0, i1, i2);
                 const bool self_img = (i0 == 0 && i1 == 0 && i2 == 0);
-                const int lin = (w0 * nc1 + w1) * nc2 + w2;
-                const int b = start[lin], e = start[lin + 1];
+                const int b = start[rowbase + za], e = start[rowbase + zb + 1];
                 for (int j = b; j < e; ++j) {
                     const float4 pj = xyzt[j];
                     float fx = (pj.x - pi.x) + sh.fx, fy = (pj.y - pi.y) + sh.fy, fz = (pj.z - pi.z) + sh.fz;

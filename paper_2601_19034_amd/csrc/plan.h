@@ -60,6 +60,8 @@ struct Plan {
     int *kcount = nullptr;
     float2 *Spart = nullptr;  // [s_chunks][nk_cap]
     float2 *Sk = nullptr;     // [nk_cap]
+    int tileB[3] = {0, 0, 0}, tileNb[3] = {0, 0, 0}, tileT[3] = {0, 0, 0};
+    float *tiles = nullptr;   // per-brick charge tiles of the atomic-free spread
     float *rho = nullptr;
     float2 *meshA = nullptr, *meshB = nullptr;
     // ---- call arguments

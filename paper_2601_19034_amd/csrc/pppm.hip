@@ -81,6 +81,141 @@ __global__ void k_real_to_complex(int64_t M, const float *__restrict__ rho, floa
     if (i < M) out[i] = make_float2(rho[i], 0.0f);
 }
 
+// ---------------------------------------------------------------- tiled spread
+// Atomic-free charge assignment.  A brick of B0 x B1 x B2 bins accumulates the
+// order-5 stencils of its atoms in an LDS tile (LDS atomics) that spans the mesh
+// points those atoms can reach, and stores the tile in its own slot; k_tile_gather
+// then forms each mesh point as the sum over the few tiles that cover it.  The
+// result is deterministic.  Tile origin along axis a: floor(b B_a N_a / nc_a) - 3.
+struct TileGeom {
+    int B[3], nb[3], T[3];
+};
+
+__device__ inline int tile_origin(int b, int B, int N, int nc) { return (int)(((int64_t)b * B * N) / nc) - 3; }
+
+__global__ __launch_bounds__(256) void k_spread_tiles(const float4 *__restrict__ xyzt, Cell c, MeshGeom g,
+                                                      int nc0, int nc1, int nc2, TileGeom tg,
+                                                      const int *__restrict__ start, const float *__restrict__ qraw,
+                                                      const double *__restrict__ scalars, float *__restrict__ tiles,
+                                                      int32_t *__restrict__ flags) {
+    extern __shared__ float tile[];
+    __shared__ int rowoff[65], rowbeg[64];
+    const int nc[3] = {nc0, nc1, nc2};
+    const int brick = blockIdx.x;
+    const int bi[3] = {brick / (tg.nb[1] * tg.nb[2]), (brick / tg.nb[2]) % tg.nb[1], brick % tg.nb[2]};
+    int lo[3], blo[3], bhi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        blo[a] = bi[a] * tg.B[a];
+        bhi[a] = min(blo[a] + tg.B[a], nc[a]);
+        lo[a] = tile_origin(bi[a], tg.B[a], g.n[a], nc[a]);
+    }
+    const int TV = tg.T[0] * tg.T[1] * tg.T[2];
+    for (int p = threadIdx.x; p < TV; p += blockDim.x) tile[p] = 0.0f;
+    const int ny = bhi[1] - blo[1];
+    const int nrows = (bhi[0] - blo[0]) * ny;
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int r = 0; r < nrows; ++r) {
+            const int x = blo[0] + r / ny, y = blo[1] + r % ny;
+            const int base = (x * nc1 + y) * nc2;
+            rowbeg[r] = start[base + blo[2]];
+            rowoff[r] = acc;
+            acc += start[base + bhi[2]] - rowbeg[r];
+        }
+        rowoff[nrows] = acc;
+    }
+    __syncthreads();
+    const int total = rowoff[nrows];
+    const float delta = (float)scalars[S_DELTA];
+    for (int t = threadIdx.x; t < total; t += blockDim.x) {
+        int r = 0;
+        while (rowoff[r + 1] <= t) ++r;
+        const int j = rowbeg[r] + (t - rowoff[r]);
+        const float4 p = xyzt[j];
+        const float q = qraw[j] + delta;
+        const double s[3] = {(double)p.x * c.hinv[0] + (double)p.y * c.hinv[3] + (double)p.z * c.hinv[6],
+                             (double)p.x * c.hinv[1] + (double)p.y * c.hinv[4] + (double)p.z * c.hinv[7],
+                             (double)p.x * c.hinv[2] + (double)p.y * c.hinv[5] + (double)p.z * c.hinv[8]};
+        int l[3];
+        float w[3][5];
+        bool ok = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double sa = s[a] - floor(s[a]);
+            // keep the atom next to its bin across the periodic seam (rounding at s = 1)
+            if (sa < (double)blo[a] / nc[a] - 0.5) sa += 1.0;
+            if (sa > (double)bhi[a] / nc[a] + 0.5) sa -= 1.0;
+            const double u = sa * g.n[a];
+            const double m = floor(u + 0.5);
+            bspline5((float)(u - m), w[a]);
+            l[a] = (int)m - 2 - lo[a];
+            ok = ok && l[a] >= 0 && l[a] + 4 < tg.T[a];
+        }
+        if (!ok) {
+            atomicOr(flags, QNEP_FLAG_INTERNAL);
+            continue;
+        }
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+            const float qa = q * w[0][a];
+#pragma unroll
+            for (int b = 0; b < 5; ++b) {
+                const float qab = qa * w[1][b];
+                float *row = tile + ((l[0] + a) * tg.T[1] + (l[1] + b)) * tg.T[2] + l[2];
+#pragma unroll
+                for (int e = 0; e < 5; ++e) atomicAdd(row + e, qab * w[2][e]);
+            }
+        }
+    }
+    __syncthreads();
+    float *out = tiles + (size_t)brick * TV;
+    for (int p = threadIdx.x; p < TV; p += blockDim.x) out[p] = tile[p];
+}
+
+// mesh point m <- sum of the tile entries that map to m (periodically); writes the
+// complex FFT input (rho, 0)
+__global__ __launch_bounds__(256) void k_tile_gather(MeshGeom g, int nc0, int nc1, int nc2, TileGeom tg,
+                                                     const float *__restrict__ tiles, float2 *__restrict__ out) {
+    const int64_t M = (int64_t)g.n[0] * g.n[1] * g.n[2];
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= M) return;
+    const int nc[3] = {nc0, nc1, nc2};
+    const int m[3] = {(int)(idx / ((int64_t)g.n[1] * g.n[2])), (int)((idx / g.n[2]) % g.n[1]), (int)(idx % g.n[2])};
+    int cb[3][8], cl[3][8], cn[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        cn[a] = 0;
+        const int N = g.n[a];
+        const int kr = tg.T[a] / N + 1;
+        for (int k = -kr; k <= kr; ++k) {
+            const int mm = m[a] + k * N;  // unwrapped mesh index
+            // tile(b) = [origin(b), origin(b) + T) holds mm only for b in [bmin, bmax]
+            const double scale = (double)nc[a] / ((double)tg.B[a] * N);
+            const int bmin = (int)floor((double)(mm - tg.T[a] + 5) * scale) - 1;
+            const int bmax = (int)floor((double)(mm + 3) * scale) + 1;
+            for (int b = bmin; b <= bmax; ++b) {
+                if (b < 0 || b >= tg.nb[a]) continue;
+                const int l = mm - tile_origin(b, tg.B[a], N, nc[a]);
+                if (l >= 0 && l < tg.T[a] && cn[a] < 8) {
+                    cb[a][cn[a]] = b;
+                    cl[a][cn[a]] = l;
+                    ++cn[a];
+                }
+            }
+        }
+    }
+    const int TV = tg.T[0] * tg.T[1] * tg.T[2];
+    float sum = 0.0f;
+    for (int x = 0; x < cn[0]; ++x)
+        for (int y = 0; y < cn[1]; ++y)
+            for (int z = 0; z < cn[2]; ++z) {
+                const int brick = (cb[0][x] * tg.nb[1] + cb[1][y]) * tg.nb[2] + cb[2][z];
+                sum += tiles[(size_t)brick * TV + ((size_t)cl[0][x] * tg.T[1] + cl[1][y]) * tg.T[2] + cl[2][z]];
+            }
+    out[idx] = make_float2(sum, 0.0f);
+}
+
 __device__ inline float alias_poly5(float z) {
     const float z2 = z * z;
     return 1.0f + z2 * (-5.0f / 3.0f + z2 * (7.0f / 9.0f + z2 * (-17.0f / 189.0f + z2 * (2.0f / 2835.0f))));
@@ -196,15 +331,34 @@ hipError_t launch_pppm(const Plan &p) {
     MeshGeom g{{p.mesh[0], p.mesh[1], p.mesh[2]}};
     const int64_t M = p.mesh_pts;
     const int G = (p.N + 255) / 256;
-    hipError_t e = fill_zero(p.rho, sizeof(float) * (size_t)M, p.stream);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_spread, dim3(G), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, g, p.qraw, p.scalars,
-                       p.rho);
     const int GM = (int)((M + 255) / 256);
-    hipLaunchKernelGGL(k_real_to_complex, dim3(GM), dim3(256), 0, p.stream, M, p.rho, p.meshA);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    stage_mark(p, ST_SPREAD, 3);
+    hipError_t e;
+    if (p.tiles) {
+        TileGeom tg;
+        for (int a = 0; a < 3; ++a) {
+            tg.B[a] = p.tileB[a];
+            tg.nb[a] = p.tileNb[a];
+            tg.T[a] = p.tileT[a];
+        }
+        const int nbricks = tg.nb[0] * tg.nb[1] * tg.nb[2];
+        const size_t lds = sizeof(float) * (size_t)tg.T[0] * tg.T[1] * tg.T[2];
+        hipLaunchKernelGGL(k_spread_tiles, dim3(nbricks), dim3(256), lds, p.stream, p.xyzt, p.cell, g, p.nc[0],
+                           p.nc[1], p.nc[2], tg, p.cell_start, p.qraw, p.scalars, p.tiles, p.flags);
+        hipLaunchKernelGGL(k_tile_gather, dim3(GM), dim3(256), 0, p.stream, g, p.nc[0], p.nc[1], p.nc[2], tg,
+                           p.tiles, p.meshA);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        stage_mark(p, ST_SPREAD, 2);
+    } else {
+        e = fill_zero(p.rho, sizeof(float) * (size_t)M, p.stream);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_spread, dim3(G), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, g, p.qraw, p.scalars,
+                           p.rho);
+        hipLaunchKernelGGL(k_real_to_complex, dim3(GM), dim3(256), 0, p.stream, M, p.rho, p.meshA);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        stage_mark(p, ST_SPREAD, 3);
+    }
     e = fft3d(p.meshA, nullptr, p.mesh, -1, p.stream);
     if (e != hipSuccess) return e;
     stage_mark(p, ST_FFT_FWD, 3);
