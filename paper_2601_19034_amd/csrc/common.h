@@ -72,12 +72,40 @@ struct ImageShift {
     }
 };
 
-// displacement to the neighbour encoded in e, from atom i at position pi
-__device__ inline float3 displacement(float4 pi, const float4 *__restrict__ xyzt, uint32_t e, const Cell &c) {
+// image bits of n = (0, 0, 0)
+constexpr uint32_t IMAGE_ZERO = 3u | (3u << 3) | (3u << 6);
+
+// Displacement to the neighbour j (position pj) encoded in e.  Without a lattice
+// shift the FP32 difference is the correctly rounded value, i.e. bitwise the FP64
+// result rounded once; only pairs across the periodic seam take the FP64 path.
+__device__ inline float3 pair_displacement(float4 pi, float4 pj, uint32_t e, const Cell &c) {
+    if ((e >> IDX_BITS) == IMAGE_ZERO) return make_float3(pj.x - pi.x, pj.y - pi.y, pj.z - pi.z);
     int n1, n2, n3;
     nb_image(e, n1, n2, n3);
-    ImageShift sh(c, n1, n2, n3);
-    return sh.exact(pi, xyzt[nb_index(e)]);
+    return ImageShift(c, n1, n2, n3).exact(pi, pj);
+}
+
+// displacement to the neighbour encoded in e, from atom i at position pi
+__device__ inline float3 displacement(float4 pi, const float4 *__restrict__ xyzt, uint32_t e, const Cell &c) {
+    return pair_displacement(pi, xyzt[nb_index(e)], e, c);
+}
+
+// erfc(x) for x >= 0 by the Chebyshev-fitted formula of Numerical Recipes
+// (Press et al., 2nd ed., Sec. 6.2, "erfcc"), fractional error below 1.2e-7:
+// erfc(x) = t exp(-x^2 + P(t)), t = 1 / (1 + x/2).
+__device__ inline float erfc_nr(float x) {
+    const float t = 1.0f / (1.0f + 0.5f * x);
+    float p = 0.17087277f;
+    p = fmaf(p, t, -0.82215223f);
+    p = fmaf(p, t, 1.48851587f);
+    p = fmaf(p, t, -1.13520398f);
+    p = fmaf(p, t, 0.27886807f);
+    p = fmaf(p, t, -0.18628806f);
+    p = fmaf(p, t, 0.09678418f);
+    p = fmaf(p, t, 0.37409196f);
+    p = fmaf(p, t, 1.00002368f);
+    p = fmaf(p, t, -1.26551223f);
+    return t * __expf(-x * x + p);
 }
 
 __device__ inline int species_of(float4 p) { return __float_as_int(p.w); }

@@ -53,9 +53,7 @@ __global__ __launch_bounds__(256) void k_descriptors(int N, const float4 *__rest
     for (int s = 0; s < nR; ++s) {
         const uint32_t e = listR[(size_t)i * capR + s];
         const float4 pj = xyzt[nb_index(e)];
-        int n1, n2, n3;
-        nb_image(e, n1, n2, n3);
-        const float3 d = ImageShift(c, n1, n2, n3).exact(pi, pj);
+        const float3 d = pair_displacement(pi, pj, e, c);
         const float r = sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
         float f[NB], df[NB];
         cheb_basis<NB>(r, rcR, f, df);
@@ -86,9 +84,7 @@ __global__ __launch_bounds__(256) void k_descriptors(int N, const float4 *__rest
     for (int s = 0; s < nA; ++s) {
         const uint32_t e = listA[(size_t)i * capA + s];
         const float4 pj = xyzt[nb_index(e)];
-        int n1, n2, n3;
-        nb_image(e, n1, n2, n3);
-        const float3 d = ImageShift(c, n1, n2, n3).exact(pi, pj);
+        const float3 d = pair_displacement(pi, pj, e, c);
         const float r = sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
         float f[NB], df[NB];
         cheb_basis<NB>(r, rcA, f, df);
@@ -205,9 +201,7 @@ __global__ __launch_bounds__(256) void k_radial_forces(int N, const float4 *__re
             const uint32_t e = listR[(size_t)i * capR + s];
             const int j = nb_index(e);
             const float4 pj = xyzt[j];
-            int n1, n2, n3;
-            nb_image(e, n1, n2, n3);
-            const float3 d = ImageShift(c, n1, n2, n3).exact(pi, pj);
+            const float3 d = pair_displacement(pi, pj, e, c);
             const float r = sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
             float f[NB], df[NB];
             cheb_basis<NB>(r, rcR, f, df);
@@ -321,9 +315,7 @@ __global__ __launch_bounds__(256) void k_angular_forces(
         for (int sl = 0; sl < nA; ++sl) {
             const uint32_t e = listA[(size_t)i * capA + sl];
             const float4 pj = xyzt[nb_index(e)];
-            int n1, n2, n3;
-            nb_image(e, n1, n2, n3);
-            const float3 d = ImageShift(c, n1, n2, n3).exact(pi, pj);
+            const float3 d = pair_displacement(pi, pj, e, c);
             const float r = sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
             const float ir = 1.0f / r;
             const float ux = d.x * ir, uy = d.y * ir, uz = d.z * ir;
