@@ -145,6 +145,20 @@ qnep_status qnep_workspace_size(const void *model, const qnep_es_params *es, con
 qnep_status qnep_compute(void *model, const float *theta, const qnep_es_params *es, const qnep_system *sys,
                          const qnep_outputs *out, void *ws, size_t ws_bytes, void *stream);
 
+/* Reverse mode for L = gE * E + gP . P (the adjoint of qnep_compute), recomputing the
+   forward pass (descriptors are not kept between calls).  Writes, when non-NULL:
+     d_pos   device FP32 SoA [3][N]  dL/dr_i = -gE F_i + sum_a gP_a Z_i[a][:]
+             (the polarization term uses the periodic Born charges of Eq. 28)
+     d_cell  device FP64 [9]         dL/dh for the row-major cell at fixed Cartesian
+             positions, gE h^{-T} (sum_i F_i (x) r_i - W)^T (energy term only)
+     d_theta device FP32 [n_theta]   exact dL/dtheta in the parameter layout above
+   gP may be NULL (zero).  ws must hold qnep_backward_workspace_size() bytes. */
+qnep_status qnep_backward_workspace_size(const void *model, const qnep_es_params *es, const qnep_system *sys,
+                                         size_t *bytes);
+qnep_status qnep_backward(void *model, const float *theta, const qnep_es_params *es, const qnep_system *sys,
+                          double gE, const double *gP, float *d_pos, double *d_cell, float *d_theta, void *ws,
+                          size_t ws_bytes, void *stream);
+
 /* synchronizes `stream` and returns the device status bits of the last call that
    used this workspace (0 = no device-side condition). */
 qnep_status qnep_check_status(const void *ws, void *stream, int32_t *flags);

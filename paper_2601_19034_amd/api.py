@@ -107,3 +107,61 @@ def to_device_inputs(system, theta: np.ndarray, device="cuda"):
     types = torch.from_numpy(system.types.astype(np.int32)).to(device)
     th = torch.from_numpy(np.asarray(theta, dtype=np.float32)).to(device)
     return pos, types, th
+
+
+def _backward(self, pos, types, cell, theta, es, gE: float = 1.0, gP=None, want=("pos", "cell", "theta"),
+              stream=None):
+    """Adjoint of ``compute`` for L = gE E + gP . P.  Returns a dict with
+    ``pos`` ([3, N] float32, dL/dr), ``cell`` ([3, 3] float64, dL/dh at fixed positions,
+    energy term) and ``theta`` ([n_theta] float32, exact dL/dtheta), all device tensors."""
+    _require_gpu()
+    n = pos.shape[1]
+    dev = pos.device
+    cell = np.asarray(cell, dtype=np.float64)
+    es_c = B.make_es(es)
+    sysm = B.make_system(n, pos.data_ptr(), types.data_ptr(), cell)
+    nbytes = B.qnep_backward_workspace_size(self.handle, es_c, sysm)
+    ws = self.workspace(nbytes, dev)
+    out = {}
+    if "pos" in want:
+        out["pos"] = torch.empty((3, n), dtype=torch.float32, device=dev)
+    if "cell" in want:
+        out["cell"] = torch.empty((3, 3), dtype=torch.float64, device=dev)
+    if "theta" in want:
+        out["theta"] = torch.empty(theta.numel(), dtype=torch.float32, device=dev)
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    B.qnep_backward(self.handle, theta.data_ptr(), es_c, sysm, gE, gP,
+                    out["pos"].data_ptr() if "pos" in out else 0, out["cell"].data_ptr() if "cell" in out else 0,
+                    out["theta"].data_ptr() if "theta" in out else 0, ws.data_ptr(), ws.numel(), s.cuda_stream)
+    self._last_stream = s
+    return out
+
+
+QNEP.backward = _backward
+
+
+class QnepFunction(torch.autograd.Function):
+    """E and P of one structure as differentiable functions of the positions ([3, N]),
+    the parameter vector and the cell ((3, 3) float64 tensor).  Forces, Born charges and
+    charges come back as non-differentiable extras.
+
+        E, P, extras = QnepFunction.apply(pos, theta, cell, model, types, es)
+    """
+
+    @staticmethod
+    def forward(ctx, pos, theta, cell, model, types, es):
+        cell_np = cell.detach().cpu().numpy()
+        out = model.compute(pos.detach(), types, cell_np, theta.detach(), es)
+        ctx.model, ctx.types, ctx.es, ctx.cell_np = model, types, es, cell_np
+        ctx.save_for_backward(pos, theta)
+        ctx.mark_non_differentiable(out["forces"], out["bec"], out["charges"])
+        return out["energy"][0], out["polarization"], out["forces"], out["bec"], out["charges"]
+
+    @staticmethod
+    def backward(ctx, gE, gP, *unused):
+        pos, theta = ctx.saved_tensors
+        ge = float(gE.detach().cpu()) if gE is not None else 0.0
+        gp = gP.detach().cpu().numpy().astype(np.float64) if gP is not None else None
+        g = ctx.model.backward(pos.detach(), ctx.types, ctx.cell_np, theta.detach(), ctx.es, ge, gp)
+        dcell = g["cell"].to("cpu") if ctx.needs_input_grad[2] else None
+        return g["pos"], g["theta"], dcell, None, None, None

@@ -50,7 +50,8 @@ class QnepError(RuntimeError):
 
 EXPORTED = ["qnep_param_count", "qnep_model_create", "qnep_model_destroy", "qnep_model_set_capacity_factor",
             "qnep_workspace_size", "qnep_compute", "qnep_check_status", "qnep_model_enable_timing",
-            "qnep_model_read_timing", "qnep_stage_name", "qnep_status_string", "qnep_last_error"]
+            "qnep_model_read_timing", "qnep_stage_name", "qnep_backward_workspace_size", "qnep_backward",
+            "qnep_status_string", "qnep_last_error"]
 
 _lib = None
 
@@ -168,3 +169,35 @@ def qnep_model_read_timing(model: int):
 
 def qnep_stage_name(stage: int) -> str:
     return load().qnep_stage_name(stage).decode()
+
+
+def _bind_backward(L):
+    L.qnep_backward_workspace_size.restype = C.c_int
+    L.qnep_backward_workspace_size.argtypes = [C.c_void_p, C.POINTER(qnep_es_params), C.POINTER(qnep_system),
+                                               C.POINTER(C.c_size_t)]
+    L.qnep_backward.restype = C.c_int
+    L.qnep_backward.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(qnep_es_params), C.POINTER(qnep_system),
+                                C.c_double, C.POINTER(C.c_double), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                C.c_size_t, C.c_void_p]
+
+
+def qnep_backward_workspace_size(model: int, es: qnep_es_params, sysm: qnep_system) -> int:
+    L = load()
+    if not getattr(L, "_bw_bound", False):
+        _bind_backward(L)
+        L._bw_bound = True
+    n = C.c_size_t()
+    _check(L.qnep_backward_workspace_size(C.c_void_p(model), C.byref(es), C.byref(sysm), C.byref(n)))
+    return int(n.value)
+
+
+def qnep_backward(model: int, theta_ptr: int, es: qnep_es_params, sysm: qnep_system, gE: float, gP,
+                  dpos_ptr: int, dcell_ptr: int, dtheta_ptr: int, ws_ptr: int, ws_bytes: int, stream: int):
+    L = load()
+    if not getattr(L, "_bw_bound", False):
+        _bind_backward(L)
+        L._bw_bound = True
+    gp = (C.c_double * 3)(*[float(v) for v in gP]) if gP is not None else None
+    _check(L.qnep_backward(C.c_void_p(model), C.c_void_p(theta_ptr), C.byref(es), C.byref(sysm), float(gE),
+                           gp, C.c_void_p(dpos_ptr or None), C.c_void_p(dcell_ptr or None),
+                           C.c_void_p(dtheta_ptr or None), C.c_void_p(ws_ptr), ws_bytes, C.c_void_p(stream)))

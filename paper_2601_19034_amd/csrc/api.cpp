@@ -190,7 +190,7 @@ int64_t count_half_k(const double *hi, int M0, int M1, int M2, double kmax, int 
 
 // Fills every size field of the plan and carves the workspace (dry run when base is null).
 qnep_status make_plan(const Model &m, const qnep_es_params *es, const qnep_system *sys, char *base, Plan &p,
-                      size_t *bytes) {
+                      size_t *bytes, bool backward = false) {
     const qnep_hparams &hp = m.hp;
     if (!es || !sys) return fail(QNEP_E_INVALID_ARG, "null es or system");
     if (sys->n_atoms < 0 || sys->n_atoms >= (int64_t)(1u << IDX_BITS))
@@ -334,8 +334,63 @@ qnep_status make_plan(const Model &m, const qnep_es_params *es, const qnep_syste
         p.meshA = c.take<float2>(p.mesh_pts);
         p.meshB = c.take<float2>(p.mesh_pts);
     }
+    if (backward) {
+        Backward &b = p.bw;
+        p.Bsum = c.take<float>((size_t)p.T * p.NBR * N);
+        b.Fout = c.take<float>(3 * (size_t)N);
+        b.Zout = c.take<float>(9 * (size_t)N);
+        b.energy = c.take<double>(1);
+        b.virial = c.take<double>(9);
+        b.pol = c.take<double>(3);
+        b.terms = c.take<double>(8);
+        b.Xvec = c.take<float>((size_t)(3 * p.H + 1) * N);
+        b.delta = c.take<float>((size_t)p.H * N);
+        b.Gam = c.take<float>((size_t)p.ndes * N);
+        b.Gc = c.take<float>((size_t)p.T * p.NA * p.NBA * N);
+        b.sums = c.take<double>(16);
+        b.sW0 = c.take<double>((size_t)p.T * p.H * p.ndes);
+        b.sVec = c.take<double>((size_t)p.T * (3 * p.H + 1));
+        b.sCR = c.take<double>((size_t)p.T * p.NR * p.T * p.NBR);
+        b.sCA = c.take<double>((size_t)p.T * p.T * p.NA * p.NBA);
+        const int64_t widest = std::max(std::max<int64_t>((int64_t)p.H * p.ndes, 3 * p.H + 1),
+                                        std::max<int64_t>((int64_t)p.NR * p.T * p.NBR, (int64_t)p.T * p.NA * p.NBA));
+        b.partials = c.take<double>((size_t)((N + 1023) / 1024) * p.T * widest);
+    }
     *bytes = (c.off + ALIGN - 1) / ALIGN * ALIGN;
     return QNEP_OK;
+}
+
+// the forward launch sequence shared by qnep_compute and qnep_backward
+hipError_t run_forward(Plan &p) {
+    hipError_t e;
+#define FW_TRY(x)                        \
+    do {                                 \
+        e = (x);                         \
+        if (e != hipSuccess) return e;   \
+    } while (0)
+    FW_TRY(fill_zero(p.flags, sizeof(int32_t) * 16, p.stream));
+    FW_TRY(fill_zero(p.scalars, sizeof(double) * 64, p.stream));
+    if (p.N == 0) return launch_zero_outputs(p);
+    FW_TRY(launch_neighbors(p));
+    FW_TRY(launch_descriptors(p));
+    stage_mark(p, ST_DESC);
+    FW_TRY(launch_mlp(p));
+    FW_TRY(launch_charges(p));
+    stage_mark(p, ST_MLP, 3);
+    FW_TRY(launch_real_space(p));
+    stage_mark(p, ST_REAL, 2);
+    if (p.method == 0) {
+        FW_TRY(launch_ewald(p));
+    } else {
+        FW_TRY(launch_pppm(p));
+    }
+    FW_TRY(launch_phi_mean(p));
+    stage_mark(p, ST_PHI, 3);
+    FW_TRY(launch_forces(p));
+    FW_TRY(launch_finalize(p));
+    stage_mark(p, ST_FINAL, 1);
+#undef FW_TRY
+    return hipSuccess;
 }
 
 qnep_status check_model(const qnep_hparams *hp, int prec) {
@@ -453,30 +508,42 @@ qnep_status qnep_compute(void *model, const float *theta, const qnep_es_params *
         p.timer = &mm.timer;
         HIP_TRY(mm.timer.begin(p.stream));
     }
-    HIP_TRY(fill_zero(p.flags, sizeof(int32_t) * 16, p.stream));
-    HIP_TRY(fill_zero(p.scalars, sizeof(double) * 64, p.stream));
-    if (p.N == 0) {
-        HIP_TRY(launch_zero_outputs(p));
-        return QNEP_OK;
-    }
-    HIP_TRY(launch_neighbors(p));
-    HIP_TRY(launch_descriptors(p));
-    stage_mark(p, ST_DESC);
-    HIP_TRY(launch_mlp(p));
-    HIP_TRY(launch_charges(p));
-    stage_mark(p, ST_MLP, 3);
-    HIP_TRY(launch_real_space(p));
-    stage_mark(p, ST_REAL, 2);
-    if (p.method == 0) {
-        HIP_TRY(launch_ewald(p));
-    } else {
-        HIP_TRY(launch_pppm(p));
-    }
-    HIP_TRY(launch_phi_mean(p));
-    stage_mark(p, ST_PHI, 3);
-    HIP_TRY(launch_forces(p));
-    HIP_TRY(launch_finalize(p));
-    stage_mark(p, ST_FINAL, 1);
+    HIP_TRY(run_forward(p));
+    return QNEP_OK;
+}
+
+qnep_status qnep_backward_workspace_size(const void *model, const qnep_es_params *es, const qnep_system *sys,
+                                         size_t *bytes) {
+    if (!model || !bytes) return fail(QNEP_E_INVALID_ARG, "null argument");
+    Plan p;
+    return make_plan(*static_cast<const Model *>(model), es, sys, nullptr, p, bytes, true);
+}
+
+qnep_status qnep_backward(void *model, const float *theta, const qnep_es_params *es, const qnep_system *sys,
+                          double gE, const double *gP, float *d_pos, double *d_cell, float *d_theta, void *ws,
+                          size_t ws_bytes, void *stream) {
+    if (!model || !theta || !ws) return fail(QNEP_E_INVALID_ARG, "null argument");
+    const Model &m = *static_cast<const Model *>(model);
+    Plan p;
+    size_t need = 0;
+    qnep_status s = make_plan(m, es, sys, static_cast<char *>(ws), p, &need, true);
+    if (s != QNEP_OK) return s;
+    if (ws_bytes < need) return fail(QNEP_E_WORKSPACE, "workspace smaller than qnep_backward_workspace_size()");
+    if (p.N == 0) return fail(QNEP_E_INVALID_ARG, "backward needs at least one atom");
+    if (!sys->pos || !sys->type) return fail(QNEP_E_INVALID_ARG, "null positions or types");
+    p.pos = sys->pos;
+    p.type = sys->type;
+    p.theta = theta;
+    p.stream = static_cast<hipStream_t>(stream);
+    Backward &b = p.bw;
+    b.gE = gE;
+    for (int a = 0; a < 3; ++a) b.gP[a] = gP ? gP[a] : 0.0;
+    b.dpos = d_pos;
+    b.dcell = d_cell;
+    b.dtheta = d_theta;
+    p.out = qnep_outputs{b.energy, b.Fout, b.virial, nullptr, nullptr, b.Zout, b.pol, b.terms};
+    HIP_TRY(run_forward(p));
+    HIP_TRY(launch_backward(p));
     return QNEP_OK;
 }
 

@@ -250,6 +250,11 @@ __global__ void k_reduce_partials(const double *__restrict__ partials, int nblk,
     if (threadIdx.x == 0) out[k] = accumulate ? out[k] + red[0] : red[0];
 }
 
+hipError_t reduce_partials_to(const Plan &p, int nblk, int nv, double *dst) {
+    hipLaunchKernelGGL(k_reduce_partials, dim3(nv), dim3(256), 0, p.stream, p.partials, nblk, nv, dst, 0);
+    return hipGetLastError();
+}
+
 hipError_t reduce_partials(const Plan &p, int nblk, int nv, int slot, bool accumulate) {
     hipLaunchKernelGGL(k_reduce_partials, dim3(nv), dim3(256), 0, p.stream, p.partials, nblk, nv, p.scalars + slot,
                        accumulate ? 1 : 0);

@@ -33,7 +33,7 @@ __global__ __launch_bounds__(256) void k_descriptors(int N, const float4 *__rest
                                                      const int *__restrict__ cntA, int capA,
                                                      const float *__restrict__ theta, int64_t off_cR,
                                                      int64_t off_cA, float *__restrict__ D,
-                                                     float *__restrict__ Amom) {
+                                                     float *__restrict__ Amom, float *__restrict__ Bsum) {
     __shared__ float cR[T * T * NR * NB];
     __shared__ float cA[T * T * NA * NB];
     for (int k = threadIdx.x; k < T * T * NR * NB; k += blockDim.x) cR[k] = theta[off_cR + k];
@@ -73,6 +73,12 @@ __global__ __launch_bounds__(256) void k_descriptors(int N, const float4 *__rest
 #pragma unroll
             for (int k = 0; k < NB; ++k) acc = fmaf(cR[((ti * T + t) * NR + n) * NB + k], B[t][k], acc);
         D[(size_t)n * N + i] = acc;
+    }
+    if (Bsum) {  // per-species radial basis sums B_{t,k} (used by the parameter gradient)
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+            for (int k = 0; k < NB; ++k) Bsum[(size_t)(t * NB + k) * N + i] = B[t][k];
     }
     // ---- angular
     float A[NA][LM];
@@ -482,7 +488,7 @@ static hipError_t run_descriptors(const Plan &p) {
     const int G = (p.N + 255) / 256;
     hipLaunchKernelGGL((k_descriptors<T, NR, NA, NB>), dim3(G), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell,
                        (float)p.rcR, (float)p.rcA, p.listR, p.cntR, p.capR, p.listA, p.cntA, p.capA, p.theta, p.off_cR,
-                       p.off_cA, p.D, p.Amom);
+                       p.off_cA, p.D, p.Amom, p.Bsum);
     return hipGetLastError();
 }
 

@@ -17,6 +17,18 @@ enum Stage : int {
 
 struct Timer;
 
+// reverse-mode state (qnep_backward)
+struct Backward {
+    double gE = 0.0, gP[3] = {0.0, 0.0, 0.0};
+    float *dpos = nullptr, *dtheta = nullptr;  // caller outputs (may be null)
+    double *dcell = nullptr;
+    float *Fout = nullptr, *Zout = nullptr;    // forward outputs kept in the workspace
+    double *energy = nullptr, *virial = nullptr, *pol = nullptr, *terms = nullptr;
+    float *Xvec = nullptr, *delta = nullptr, *Gam = nullptr, *Gc = nullptr;
+    double *sums = nullptr, *sW0 = nullptr, *sVec = nullptr, *sCR = nullptr, *sCA = nullptr;
+    double *partials = nullptr;
+};
+
 struct Plan {
     // ---- model
     int N = 0, T = 0, NR = 0, NA = 0, NBR = 0, NBA = 0, LMAX = 4, H = 0, ndes = 0;
@@ -52,6 +64,7 @@ struct Plan {
     uint32_t *listR = nullptr, *listA = nullptr;
     int *cntR = nullptr, *cntA = nullptr;
     float *D = nullptr, *Amom = nullptr;
+    float *Bsum = nullptr;  // per-species radial basis sums (backward only)
     float *U = nullptr, *qraw = nullptr, *gU = nullptr, *gq = nullptr;
     float *phi = nullptr, *Fst = nullptr, *hT = nullptr;
     float *pairF = nullptr, *pairA = nullptr;
@@ -71,6 +84,7 @@ struct Plan {
     qnep_outputs out{};
     hipStream_t stream = nullptr;
     Timer *timer = nullptr;
+    Backward bw;
 };
 
 // records the end of `stage` (work enqueued since the previous mark) when timing is on
@@ -88,8 +102,12 @@ hipError_t launch_forces(const Plan &p);
 hipError_t launch_finalize(const Plan &p);
 hipError_t launch_zero_outputs(const Plan &p);
 
+hipError_t launch_backward(const Plan &p);
+
 // fixed-order reduction of partials[nblk][nv] into scalars[slot..slot+nv)
 hipError_t reduce_partials(const Plan &p, int nblk, int nv, int slot, bool accumulate);
+// the same into an arbitrary FP64 destination
+hipError_t reduce_partials_to(const Plan &p, int nblk, int nv, double *dst);
 // fills n floats/ints with zero (a kernel, not a memset, so that the sequence can be captured)
 hipError_t fill_zero(void *ptr, size_t bytes, hipStream_t s);
 
