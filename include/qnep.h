@@ -173,6 +173,77 @@ qnep_status qnep_model_enable_timing(void *model, int32_t enable);
 qnep_status qnep_model_read_timing(void *model, double *ms, int64_t *launches, int32_t *calls);
 const char *qnep_stage_name(int32_t stage);
 
+/* ------------------------------------------------------------------------------
+ * Batched evaluation for training (Sec. 2.5): many small periodic structures, each
+ * under many candidate parameter vectors (a population, as evaluated by the
+ * evolution strategy the paper trains with), in one persistent launch.  Ewald
+ * electrostatics only (Sec. 2.2); the per-structure Ewald sum is set up once as a
+ * pair kernel (the parameters do not enter it) and contracted with the charges of
+ * every candidate.
+ *
+ * Sequence: qnep_batch_workspace_size -> allocate -> qnep_batch_prepare (builds the
+ * parameter-independent geometry into the workspace) -> any number of
+ * qnep_batch_compute calls with the same workspace.  The model handle keeps the
+ * host-side plan of the last prepared batch; a later prepare replaces it.
+ * qnep_batch_tune times tile choices on the prepared batch and keeps the fastest.
+ * Species must be in [0, n_types); all structures share the model's species set.
+ * Limits: at most 2048 atoms per structure; parameters per candidate at most 12288;
+ * l_max = 4, basis_R = basis_A = 8, (n_max_R, n_max_A) = (4, 4) or (8, 6).
+ * ------------------------------------------------------------------------------ */
+#define QNEP_BATCH_VIRIAL 1 /* also form the per-(structure, candidate) virial */
+
+typedef struct {
+    int32_t n_structures;   /* S >= 1 */
+    int32_t flags;          /* QNEP_BATCH_VIRIAL or 0 */
+    const int64_t *offsets; /* host, [S + 1], offsets[0] = 0; atoms of structure s are
+                               offsets[s] .. offsets[s+1]-1 of the packed arrays */
+    const double *cells;    /* host, [S][9], rows a, b, c (Angstrom), right-handed */
+    const float *pos;       /* device, SoA [3][n_total] (Angstrom), read by prepare only */
+    const int32_t *type;    /* device, [n_total], read by prepare only */
+} qnep_batch;
+
+typedef struct {
+    const double *energy;   /* device, [S] reference energies (eV) */
+    const float *forces;    /* device, SoA [3][n_total] reference forces (eV/Angstrom) */
+    double lambda_e, lambda_f, lambda_q; /* weights of the three RMSE terms */
+    double lambda_1, lambda_2;           /* weights of |theta|_1 and |theta|_2^2 */
+} qnep_batch_targets;
+
+typedef struct {
+    float *losses;   /* device, [S][C][3]: |E - E_ref|/N, RMS over the 3N force components
+                        of F - F_ref, |sum_i q~_i - Q| (scaled charges before the
+                        correction, Q = es.q_total); required */
+    double *loss;    /* device, [C]: lambda_e sqrt(mean_s (dE/N)^2) + lambda_f RMSE of all
+                        force components + lambda_q sqrt(mean_s dQ^2) + lambda_1 |theta|_1
+                        + lambda_2 |theta|_2^2; NULL = skip */
+    double *energy;  /* device, [S][C]; NULL = skip */
+    double *virial;  /* device, [S][C][9]; needs QNEP_BATCH_VIRIAL at prepare; NULL = skip */
+    float *forces;   /* device, [C][3][n_total]; NULL = skip */
+    float *charges;  /* device, [C][n_total], corrected scaled charges q~'; NULL = skip */
+} qnep_batch_outputs;
+
+/* bytes of device workspace for the batch and up to max_candidates candidates */
+qnep_status qnep_batch_workspace_size(const void *model, const qnep_es_params *es, const qnep_batch *batch,
+                                      int32_t max_candidates, size_t *bytes);
+/* enqueues the parameter-independent setup (lists, k-sets, Ewald pair matrices).
+   Raises QNEP_FLAG_RADIAL_OVERFLOW / QNEP_FLAG_BAD_SPECIES in the status word. */
+qnep_status qnep_batch_prepare(void *model, const qnep_es_params *es, const qnep_batch *batch,
+                               int32_t max_candidates, void *ws, size_t ws_bytes, void *stream);
+/* thetas: device, [C][n_theta] (layout of qnep_param_count), 1 <= C <= max_candidates.
+   Enqueues one persistent launch (plus one small launch for outputs->loss). */
+qnep_status qnep_batch_compute(void *model, const float *thetas, int32_t n_candidates,
+                               const qnep_batch_targets *targets, const qnep_batch_outputs *outputs, void *ws,
+                               size_t ws_bytes, void *stream);
+/* Autotuner: times the lanes-per-atom choice for each structure-size class (fewer
+   than 48, 48-127, 128-383, 384 or more atoms) over {1, 2, 4, 8, 16} and then the
+   number of resident workgroups per compute unit over {1, 2, 3, 4}, on the prepared
+   batch; keeps the fastest choice in the model.  Synchronizes the stream; the
+   outputs hold the result of the last timed run.  choice (may be NULL) receives
+   {lanes class 0..3, workgroups per compute unit}. */
+qnep_status qnep_batch_tune(void *model, const float *thetas, int32_t n_candidates,
+                            const qnep_batch_targets *targets, const qnep_batch_outputs *outputs, void *ws,
+                            size_t ws_bytes, void *stream, int32_t *choice);
+
 const char *qnep_status_string(qnep_status s);
 const char *qnep_last_error(void);
 

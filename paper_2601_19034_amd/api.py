@@ -8,6 +8,8 @@ from __future__ import annotations
 
 from typing import Dict, Optional
 
+import ctypes as C
+
 import numpy as np
 import torch
 
@@ -165,3 +167,78 @@ class QnepFunction(torch.autograd.Function):
         g = ctx.model.backward(pos.detach(), ctx.types, ctx.cell_np, theta.detach(), ctx.es, ge, gp)
         dcell = g["cell"].to("cpu") if ctx.needs_input_grad[2] else None
         return g["pos"], g["theta"], dcell, None, None, None
+
+
+class QNEPBatch:
+    """Many structures x many candidate parameter vectors (qnep_batch_*).
+
+        batch = QNEPBatch(model, systems, es, max_candidates=64)
+        out = batch.compute(thetas, E_ref, F_ref)          # dict of device tensors
+
+    ``systems`` carry ``pos`` (N, 3), ``types`` (N,) and ``cell`` (3, 3); the geometry
+    (lists and Ewald pair matrices) is built once here, on the device."""
+
+    def __init__(self, model: QNEP, systems, es, max_candidates: int, virial: bool = False, device="cuda"):
+        _require_gpu()
+        self.model = model
+        self.S = len(systems)
+        self.max_candidates = int(max_candidates)
+        sizes = [len(s.types) for s in systems]
+        self.offsets_np = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+        self.n_total = int(self.offsets_np[-1])
+        self.sizes = np.asarray(sizes)
+        self._offsets = (C.c_int64 * (self.S + 1))(*self.offsets_np.tolist())
+        cells = np.concatenate([np.asarray(s.cell, dtype=np.float64).reshape(9) for s in systems])
+        self._cells = (C.c_double * (9 * self.S))(*cells.tolist())
+        pos = np.concatenate([np.asarray(s.pos, dtype=np.float64) for s in systems]).astype(np.float32)
+        self.pos = torch.from_numpy(np.ascontiguousarray(pos.T)).to(device)
+        self.types = torch.from_numpy(np.concatenate([s.types for s in systems]).astype(np.int32)).to(device)
+        self.es = B.make_es(es)
+        self.flags = B.QNEP_BATCH_VIRIAL if virial else 0
+        self.cbatch = B.make_batch(self.S, self.flags, self._offsets, self._cells, self.pos.data_ptr(),
+                                   self.types.data_ptr())
+        nbytes = B.qnep_batch_workspace_size(model.handle, self.es, self.cbatch, self.max_candidates)
+        self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        self.device = self.pos.device
+        s = torch.cuda.current_stream(self.device)
+        B.qnep_batch_prepare(model.handle, self.es, self.cbatch, self.max_candidates, self.ws.data_ptr(),
+                             self.ws.numel(), s.cuda_stream)
+        self._stream = s
+
+    def _args(self, thetas, E_ref, F_ref, lambdas, outputs):
+        C_ = thetas.shape[0]
+        assert thetas.dtype == torch.float32 and thetas.is_contiguous() and thetas.shape[1] == self.model.n_theta
+        assert E_ref.dtype == torch.float64 and E_ref.numel() == self.S
+        assert F_ref.dtype == torch.float32 and F_ref.shape == (3, self.n_total) and F_ref.is_contiguous()
+        dev = self.device
+        shapes = {"losses": ((self.S, C_, 3), torch.float32), "loss": ((C_,), torch.float64),
+                  "energy": ((self.S, C_), torch.float64), "virial": ((self.S, C_, 9), torch.float64),
+                  "forces": ((C_, 3, self.n_total), torch.float32), "charges": ((C_, self.n_total), torch.float32)}
+        out = {k: torch.empty(shapes[k][0], dtype=shapes[k][1], device=dev) for k in ("losses",) + tuple(outputs)}
+        lam = list(lambdas) + [0.0] * (5 - len(lambdas))
+        tg = B.qnep_batch_targets(C.c_void_p(E_ref.data_ptr()), C.c_void_p(F_ref.data_ptr()), *[float(v) for v in lam])
+        ptr = lambda k: C.c_void_p(out[k].data_ptr()) if k in out else None
+        oc = B.qnep_batch_outputs(ptr("losses"), ptr("loss"), ptr("energy"), ptr("virial"), ptr("forces"),
+                                  ptr("charges"))
+        return C_, tg, oc, out
+
+    def compute(self, thetas: torch.Tensor, E_ref: torch.Tensor, F_ref: torch.Tensor,
+                lambdas=(1.0, 1.0, 1.0, 0.0, 0.0), outputs=("loss", "energy"),
+                stream: Optional[torch.cuda.Stream] = None) -> Dict[str, torch.Tensor]:
+        """thetas: float32 [C, n_theta]; E_ref float64 [S]; F_ref float32 [3, n_total]."""
+        C_, tg, oc, out = self._args(thetas, E_ref, F_ref, lambdas, outputs)
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        B.qnep_batch_compute(self.model.handle, thetas.data_ptr(), C_, tg, oc, self.ws.data_ptr(), self.ws.numel(),
+                             s.cuda_stream)
+        self._stream = s
+        return out
+
+    def tune(self, thetas, E_ref, F_ref, lambdas=(1.0, 1.0, 1.0, 0.0, 0.0)):
+        """Autotunes lanes per atom (per size class) and workgroups per CU; returns the choice."""
+        C_, tg, oc, out = self._args(thetas, E_ref, F_ref, lambdas, ("loss",))
+        s = torch.cuda.current_stream(self.device)
+        return B.qnep_batch_tune(self.model.handle, thetas.data_ptr(), C_, tg, oc, self.ws.data_ptr(),
+                                 self.ws.numel(), s.cuda_stream)
+
+    def check_status(self) -> int:
+        return B.qnep_check_status(self.ws.data_ptr(), self._stream.cuda_stream)

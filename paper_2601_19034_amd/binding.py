@@ -201,3 +201,85 @@ def qnep_backward(model: int, theta_ptr: int, es: qnep_es_params, sysm: qnep_sys
     _check(L.qnep_backward(C.c_void_p(model), C.c_void_p(theta_ptr), C.byref(es), C.byref(sysm), float(gE),
                            gp, C.c_void_p(dpos_ptr or None), C.c_void_p(dcell_ptr or None),
                            C.c_void_p(dtheta_ptr or None), C.c_void_p(ws_ptr), ws_bytes, C.c_void_p(stream)))
+
+
+# ---------------------------------------------------------------- batched evaluation
+QNEP_BATCH_VIRIAL = 1
+
+
+class qnep_batch(C.Structure):
+    _fields_ = [("n_structures", C.c_int32), ("flags", C.c_int32), ("offsets", C.c_void_p), ("cells", C.c_void_p),
+                ("pos", C.c_void_p), ("type", C.c_void_p)]
+
+
+class qnep_batch_targets(C.Structure):
+    _fields_ = [("energy", C.c_void_p), ("forces", C.c_void_p), ("lambda_e", C.c_double), ("lambda_f", C.c_double),
+                ("lambda_q", C.c_double), ("lambda_1", C.c_double), ("lambda_2", C.c_double)]
+
+
+class qnep_batch_outputs(C.Structure):
+    _fields_ = [("losses", C.c_void_p), ("loss", C.c_void_p), ("energy", C.c_void_p), ("virial", C.c_void_p),
+                ("forces", C.c_void_p), ("charges", C.c_void_p)]
+
+
+EXPORTED += ["qnep_batch_workspace_size", "qnep_batch_prepare", "qnep_batch_compute", "qnep_batch_tune"]
+
+
+def _bind_batch(L):
+    if getattr(L, "_batch_bound", False):
+        return
+    L.qnep_batch_workspace_size.restype = C.c_int
+    L.qnep_batch_workspace_size.argtypes = [C.c_void_p, C.POINTER(qnep_es_params), C.POINTER(qnep_batch), C.c_int32,
+                                            C.POINTER(C.c_size_t)]
+    L.qnep_batch_prepare.restype = C.c_int
+    L.qnep_batch_prepare.argtypes = [C.c_void_p, C.POINTER(qnep_es_params), C.POINTER(qnep_batch), C.c_int32,
+                                     C.c_void_p, C.c_size_t, C.c_void_p]
+    L.qnep_batch_compute.restype = C.c_int
+    L.qnep_batch_compute.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(qnep_batch_targets),
+                                     C.POINTER(qnep_batch_outputs), C.c_void_p, C.c_size_t, C.c_void_p]
+    L.qnep_batch_tune.restype = C.c_int
+    L.qnep_batch_tune.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(qnep_batch_targets),
+                                  C.POINTER(qnep_batch_outputs), C.c_void_p, C.c_size_t, C.c_void_p,
+                                  C.POINTER(C.c_int32)]
+    L._batch_bound = True
+
+
+def make_batch(n_structures: int, flags: int, offsets, cells, pos_ptr: int, type_ptr: int) -> qnep_batch:
+    """offsets: ctypes int64 array [S + 1]; cells: ctypes double array [S * 9] (both kept alive by the caller)."""
+    return qnep_batch(int(n_structures), int(flags), C.cast(offsets, C.c_void_p), C.cast(cells, C.c_void_p),
+                      C.c_void_p(pos_ptr), C.c_void_p(type_ptr))
+
+
+def qnep_batch_workspace_size(model: int, es: qnep_es_params, batch: qnep_batch, max_candidates: int) -> int:
+    L = load()
+    _bind_batch(L)
+    n = C.c_size_t()
+    _check(L.qnep_batch_workspace_size(C.c_void_p(model), C.byref(es), C.byref(batch), int(max_candidates),
+                                       C.byref(n)))
+    return int(n.value)
+
+
+def qnep_batch_prepare(model: int, es: qnep_es_params, batch: qnep_batch, max_candidates: int, ws_ptr: int,
+                       ws_bytes: int, stream: int):
+    L = load()
+    _bind_batch(L)
+    _check(L.qnep_batch_prepare(C.c_void_p(model), C.byref(es), C.byref(batch), int(max_candidates),
+                                C.c_void_p(ws_ptr), ws_bytes, C.c_void_p(stream)))
+
+
+def qnep_batch_compute(model: int, thetas_ptr: int, n_candidates: int, targets: qnep_batch_targets,
+                       outputs: qnep_batch_outputs, ws_ptr: int, ws_bytes: int, stream: int):
+    L = load()
+    _bind_batch(L)
+    _check(L.qnep_batch_compute(C.c_void_p(model), C.c_void_p(thetas_ptr), int(n_candidates), C.byref(targets),
+                                C.byref(outputs), C.c_void_p(ws_ptr), ws_bytes, C.c_void_p(stream)))
+
+
+def qnep_batch_tune(model: int, thetas_ptr: int, n_candidates: int, targets: qnep_batch_targets,
+                    outputs: qnep_batch_outputs, ws_ptr: int, ws_bytes: int, stream: int):
+    L = load()
+    _bind_batch(L)
+    choice = (C.c_int32 * 5)()
+    _check(L.qnep_batch_tune(C.c_void_p(model), C.c_void_p(thetas_ptr), int(n_candidates), C.byref(targets),
+                             C.byref(outputs), C.c_void_p(ws_ptr), ws_bytes, C.c_void_p(stream), choice))
+    return [int(v) for v in choice]

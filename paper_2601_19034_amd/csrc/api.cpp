@@ -8,6 +8,7 @@
 #include <cstring>
 #include <string>
 
+#include "batch.h"
 #include "plan.h"
 
 namespace qnep {
@@ -114,6 +115,7 @@ struct Model {
     int prec;
     double cap_factor;
     Timer timer;
+    BatchPlan batch;
 };
 
 constexpr size_t ALIGN = 256;
@@ -411,6 +413,103 @@ qnep_status check_model(const qnep_hparams *hp, int prec) {
     return QNEP_OK;
 }
 
+// Sizes, per-structure records and workspace layout of a batch (dry run when base is null).
+qnep_status batch_layout(const Model &m, const qnep_es_params *es, const qnep_batch *bt, int C_max, char *base,
+                         BatchPlan &bp, size_t *bytes) {
+    const qnep_hparams &hp = m.hp;
+    if (!es || !bt || !bytes) return fail(QNEP_E_INVALID_ARG, "null argument");
+    if (bt->n_structures < 1 || !bt->offsets || !bt->cells)
+        return fail(QNEP_E_INVALID_ARG, "batch needs n_structures >= 1, offsets and cells");
+    if (C_max < 1) return fail(QNEP_E_INVALID_ARG, "max_candidates must be >= 1");
+    const int T = hp.n_types, NR = hp.n_max_R + 1, NA = hp.n_max_A + 1, NB = hp.basis_R + 1;
+    if (hp.basis_A != hp.basis_R || hp.l_max != 4 || !batch_supported(T, NR, NA, NB))
+        return fail(QNEP_E_UNSUPPORTED, "batched path: l_max = 4, basis_R = basis_A = 8, (n_max_R, n_max_A) = (4, 4) or (8, 6)");
+    if (param_count(hp) > BATCH_MAX_THETA) return fail(QNEP_E_UNSUPPORTED, "batched path: more than 12288 parameters");
+    if (es->method != 0) return fail(QNEP_E_UNSUPPORTED, "batched path: Ewald only (method 0)");
+    if (es->mode != 1 && es->mode != 2) return fail(QNEP_E_INVALID_ARG, "mode must be 1 or 2");
+    if (!(es->alpha > 0) || !(es->kmax > 0)) return fail(QNEP_E_INVALID_ARG, "alpha and kmax must be positive");
+    if (es->mode == 1 && !(es->rc_coul > 0)) return fail(QNEP_E_INVALID_ARG, "rc_coul must be positive");
+    const int S = bt->n_structures;
+    if (bt->offsets[0] != 0) return fail(QNEP_E_INVALID_ARG, "offsets[0] must be 0");
+    bp = BatchPlan{};
+    bp.S = S;
+    bp.C_max = C_max;
+    bp.ncomp = (bt->flags & QNEP_BATCH_VIRIAL) ? BATCH_COMP_VIRIAL : BATCH_COMP_FORCE;
+    bp.qtot = es->q_total;
+    bp.st.resize(S);
+    double max_density = 0.0;
+    int64_t mat = 0, k0 = 0, ph0 = 0, tile0 = 0;
+    for (int s = 0; s < S; ++s) {
+        const int64_t n = bt->offsets[s + 1] - bt->offsets[s];
+        if (n < 1 || n > BATCH_MAX_ATOMS) return fail(QNEP_E_UNSUPPORTED, "batched path: 1..2048 atoms per structure");
+        BatchStruct &b = bp.st[s];
+        std::memcpy(b.h, bt->cells + 9 * s, sizeof(double) * 9);
+        if (!invert_cell(b.h, b.hinv, &b.vol)) return fail(QNEP_E_INVALID_ARG, "cell must be non-singular and right-handed");
+        double w[3];
+        cell_widths(b.h, b.vol, w);
+        b.atom0 = bt->offsets[s];
+        b.n = (int)n;
+        for (int a = 0; a < 3; ++a) {
+            b.mR[a] = (int)std::floor(std::max(hp.rc_R, hp.rc_A) / w[a] + 0.5) + 1;
+            b.mC[a] = es->mode == 1 ? (int)std::floor(es->rc_coul / w[a] + 0.5) + 1 : 0;
+            if (b.mR[a] > 8 || b.mC[a] > 8) return fail(QNEP_E_UNSUPPORTED, "batched path: cell thinner than an eighth of a cutoff");
+            const double *v = b.h + 3 * a;
+            b.kbox[a] = (int)std::floor(es->kmax * std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) / (2.0 * M_PI)) + 1;
+        }
+        b.kcap = (int)count_half_k(b.hinv, b.kbox[0], b.kbox[1], b.kbox[2], es->kmax, es->kmax_inclusive);
+        b.mat0 = mat;
+        b.k0 = k0;
+        b.ph0 = ph0;
+        b.tile0 = tile0;
+        b.group = batch_class(b.n);
+        mat += (int64_t)bp.ncomp * n * n;
+        k0 += b.kcap;
+        ph0 += (int64_t)b.kcap * n;
+        tile0 += (int64_t)((n + 15) / 16) * ((n + 15) / 16);
+        max_density = std::max(max_density, n / b.vol);
+        bp.max_atoms = std::max(bp.max_atoms, (int)n);
+    }
+    bp.n_total = bt->offsets[S];
+    bp.mat_total = mat;
+    bp.k_total = k0;
+    bp.ph_total = ph0;
+    bp.n_tiles = tile0;
+    bp.capR = capacity(max_density, hp.rc_R, m.cap_factor);
+    const int ndes = NR + 4 * NA;
+    bp.per_slot = (int64_t)(3 * ndes + LM * NA) * bp.max_atoms;
+    // queue order: size classes from large to small, larger structures first inside a class
+    bp.order.resize(S);
+    for (int s = 0; s < S; ++s) bp.order[s] = s;
+    std::stable_sort(bp.order.begin(), bp.order.end(), [&](int x, int y) { return bp.st[x].n > bp.st[y].n; });
+    for (int k = 0; k < BATCH_CLASSES; ++k) {
+        bp.cls_lo[k] = S;
+        bp.cls_hi[k] = 0;
+    }
+    for (int r = 0; r < S; ++r) {
+        const int k = bp.st[bp.order[r]].group;
+        bp.cls_lo[k] = std::min(bp.cls_lo[k], r);
+        bp.cls_hi[k] = std::max(bp.cls_hi[k], r + 1);
+    }
+    Carver c{base, 0, base == nullptr};
+    bp.flags = c.take<int32_t>(16);
+    bp.counter = c.take<int>(16);
+    bp.st_d = c.take<BatchStruct>(S);
+    bp.order_d = c.take<int>(S);
+    bp.ts = c.take<int>(bp.n_total);
+    bp.cntR = c.take<int>(bp.n_total);
+    bp.cntA = c.take<int>(bp.n_total);
+    bp.list = c.take<float4>((size_t)bp.n_total * bp.capR);
+    bp.kv = c.take<float4>(bp.k_total);
+    bp.kcount = c.take<int>(S);
+    bp.ph = c.take<float2>(bp.ph_total);
+    bp.mats = c.take<float>(bp.mat_total);
+    bp.stats = c.take<double>((size_t)S * C_max * 4);
+    bp.scratch = c.take<float>((size_t)BATCH_MAX_SLOTS * bp.per_slot);
+    bp.need = (c.off + ALIGN - 1) / ALIGN * ALIGN;
+    *bytes = bp.need;
+    return QNEP_OK;
+}
+
 #define HIP_TRY(x)                                                                         \
     do {                                                                                   \
         hipError_t e_ = (x);                                                               \
@@ -551,6 +650,211 @@ qnep_status qnep_check_status(const void *ws, void *stream, int32_t *flags) {
     if (!ws || !flags) return fail(QNEP_E_INVALID_ARG, "null argument");
     HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
     HIP_TRY(hipMemcpy(flags, ws, sizeof(int32_t), hipMemcpyDeviceToHost));
+    return QNEP_OK;
+}
+
+qnep_status qnep_batch_workspace_size(const void *model, const qnep_es_params *es, const qnep_batch *batch,
+                                      int32_t max_candidates, size_t *bytes) {
+    if (!model) return fail(QNEP_E_INVALID_ARG, "null model");
+    BatchPlan bp;
+    return batch_layout(*static_cast<const Model *>(model), es, batch, max_candidates, nullptr, bp, bytes);
+}
+
+qnep_status qnep_batch_prepare(void *model, const qnep_es_params *es, const qnep_batch *batch,
+                               int32_t max_candidates, void *ws, size_t ws_bytes, void *stream) {
+    if (!model || !ws) return fail(QNEP_E_INVALID_ARG, "null argument");
+    Model &m = *static_cast<Model *>(model);
+    BatchPlan bp;
+    size_t need = 0;
+    qnep_status s = batch_layout(m, es, batch, max_candidates, static_cast<char *>(ws), bp, &need);
+    if (s != QNEP_OK) return s;
+    if (ws_bytes < need) return fail(QNEP_E_WORKSPACE, "workspace smaller than qnep_batch_workspace_size()");
+    if (!batch->pos || !batch->type) return fail(QNEP_E_INVALID_ARG, "null positions or types");
+    int dev = 0, cus = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    bp.cus = cus > 0 ? cus : 256;
+    // keep the tuned choices of an earlier prepare
+    if (m.batch.ready) {
+        for (int k = 0; k < BATCH_CLASSES; ++k) bp.groups[k] = m.batch.groups[k];
+        bp.slots_per_cu = m.batch.slots_per_cu;
+    }
+    m.batch = std::move(bp);
+    BatchPlan &b = m.batch;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIP_TRY(fill_zero(b.flags, sizeof(int32_t) * 16, st));
+    HIP_TRY(hipMemcpyAsync(b.st_d, b.st.data(), sizeof(BatchStruct) * b.S, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(b.order_d, b.order.data(), sizeof(int) * b.S, hipMemcpyHostToDevice, st));
+    const qnep_hparams &hp = m.hp;
+    HIP_TRY(batch_setup(b.st_d, b.S, b.n_total, b.n_tiles, b.ph_total, batch->pos, batch->type, hp.n_types,
+                        hp.rc_R, hp.rc_A, b.list, b.cntR, b.cntA, b.capR, b.ts, b.flags, *es, b.kv, b.kcount, b.ph,
+                        b.ncomp, b.mats, st));
+    b.ws = ws;
+    b.ready = true;
+    return QNEP_OK;
+}
+
+namespace {
+qnep_status batch_args(const Model &m, const float *thetas, int C, const qnep_batch_targets *tg,
+                       const qnep_batch_outputs *out, const void *ws, size_t ws_bytes, BatchArgs &a) {
+    const BatchPlan &b = m.batch;
+    if (!b.ready || ws != b.ws) return fail(QNEP_E_INVALID_ARG, "workspace was not prepared by qnep_batch_prepare");
+    if (ws_bytes < b.need) return fail(QNEP_E_WORKSPACE, "workspace smaller than qnep_batch_workspace_size()");
+    if (!thetas || !tg || !out || !tg->energy || !tg->forces || !out->losses)
+        return fail(QNEP_E_INVALID_ARG, "null thetas, targets or losses");
+    if (C < 1 || C > b.C_max) return fail(QNEP_E_INVALID_ARG, "n_candidates must be in [1, max_candidates]");
+    if (out->virial && b.ncomp != BATCH_COMP_VIRIAL)
+        return fail(QNEP_E_INVALID_ARG, "virial output needs QNEP_BATCH_VIRIAL at prepare");
+    const qnep_hparams &hp = m.hp;
+    const int T = hp.n_types, NR = hp.n_max_R + 1, NA = hp.n_max_A + 1, NB = hp.basis_R + 1;
+    const int ndes = NR + 4 * NA;
+    a = BatchArgs{};
+    a.st = b.st_d;
+    a.order = b.order_d;
+    a.S = b.S;
+    a.C = C;
+    a.n_items = b.S * C;
+    a.counter = b.counter;
+    a.flags = b.flags;
+    a.list = b.list;
+    a.cntR = b.cntR;
+    a.cntA = b.cntA;
+    a.types = b.ts;
+    a.capR = b.capR;
+    a.mats = b.mats;
+    a.ncomp = b.ncomp;
+    a.thetas = thetas;
+    a.off_cA = (int64_t)T * T * NR * NB;
+    a.off_nn = a.off_cA + (int64_t)T * T * NA * NB;
+    a.per_species = (int64_t)hp.n_neu * ndes + 3 * hp.n_neu + 1;
+    a.off_b1E = a.off_nn + T * a.per_species;
+    a.off_s = a.off_b1E + 1;
+    a.n_theta = a.off_s + 1;
+    a.H = hp.n_neu;
+    a.ndes = ndes;
+    a.rcR = hp.rc_R;
+    a.rcA = hp.rc_A;
+    a.qtot = b.qtot;
+    a.E_ref = tg->energy;
+    a.F_ref = tg->forces;
+    a.n_total = b.n_total;
+    a.losses = out->losses;
+    a.energy = out->energy;
+    a.virial = out->virial;
+    a.forces = out->forces;
+    a.charges = out->charges;
+    a.stats = b.stats;
+    a.scratch = b.scratch;
+    a.max_atoms = b.max_atoms;
+    return QNEP_OK;
+}
+
+hipError_t batch_run(const Model &m, const BatchArgs &a, int item_begin, int item_end, const int *groups,
+                     int slots_per_cu, hipStream_t st) {
+    const BatchPlan &b = m.batch;
+    const qnep_hparams &hp = m.hp;
+    hipError_t e = fill_zero(b.counter, sizeof(int) * 16, st);
+    if (e != hipSuccess) return e;
+    int slots = std::min(b.cus * slots_per_cu, BATCH_MAX_SLOTS);
+    return batch_eval(a, hp.n_types, hp.n_max_R + 1, hp.n_max_A + 1, hp.basis_R + 1, slots, item_begin, item_end,
+                      make_int4(groups[0], groups[1], groups[2], groups[3]), st);
+}
+}  // namespace
+
+qnep_status qnep_batch_compute(void *model, const float *thetas, int32_t n_candidates,
+                               const qnep_batch_targets *targets, const qnep_batch_outputs *outputs, void *ws,
+                               size_t ws_bytes, void *stream) {
+    if (!model) return fail(QNEP_E_INVALID_ARG, "null model");
+    const Model &m = *static_cast<const Model *>(model);
+    BatchArgs a;
+    qnep_status s = batch_args(m, thetas, n_candidates, targets, outputs, ws, ws_bytes, a);
+    if (s != QNEP_OK) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIP_TRY(batch_run(m, a, 0, a.n_items, m.batch.groups, m.batch.slots_per_cu, st));
+    if (outputs->loss) {
+        const double lam[5] = {targets->lambda_e, targets->lambda_f, targets->lambda_q, targets->lambda_1,
+                               targets->lambda_2};
+        HIP_TRY(batch_loss(m.batch.stats, targets->energy, thetas, a.n_theta, a.S, a.C, a.qtot, lam, outputs->loss, st));
+    }
+    return QNEP_OK;
+}
+
+qnep_status qnep_batch_tune(void *model, const float *thetas, int32_t n_candidates,
+                            const qnep_batch_targets *targets, const qnep_batch_outputs *outputs, void *ws,
+                            size_t ws_bytes, void *stream, int32_t *choice) {
+    if (!model) return fail(QNEP_E_INVALID_ARG, "null model");
+    Model &m = *static_cast<Model *>(model);
+    BatchArgs a;
+    qnep_status s = batch_args(m, thetas, n_candidates, targets, outputs, ws, ws_bytes, a);
+    if (s != QNEP_OK) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    BatchPlan &b = m.batch;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    // best of three timed runs (after one untimed run) of items [lo, hi)
+    auto timed = [&](int lo, int hi, const int *groups, int spc, float *best) -> hipError_t {
+        hipError_t e = batch_run(m, a, lo, hi, groups, spc, st);
+        if (e != hipSuccess) return e;
+        *best = 1e30f;
+        for (int r = 0; r < 3; ++r) {
+            if ((e = hipEventRecord(e0, st)) != hipSuccess) return e;
+            if ((e = batch_run(m, a, lo, hi, groups, spc, st)) != hipSuccess) return e;
+            if ((e = hipEventRecord(e1, st)) != hipSuccess) return e;
+            if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
+            float ms = 0.f;
+            if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) return e;
+            *best = std::min(*best, ms);
+        }
+        return hipSuccess;
+    };
+    static const int lanes[] = {1, 2, 4, 8, 16};
+    hipError_t err = hipSuccess;
+    for (int k = 0; k < BATCH_CLASSES && err == hipSuccess; ++k) {
+        if (b.cls_lo[k] >= b.cls_hi[k]) continue;
+        float best = 1e30f;
+        int pick = b.groups[k];
+        for (int G : lanes) {
+            int g[BATCH_CLASSES];
+            for (int q = 0; q < BATCH_CLASSES; ++q) g[q] = b.groups[q];
+            g[k] = G;
+            float ms = 0.f;
+            err = timed(b.cls_lo[k] * a.C, b.cls_hi[k] * a.C, g, b.slots_per_cu, &ms);
+            if (err != hipSuccess) break;
+            if (ms < best) {
+                best = ms;
+                pick = G;
+            }
+        }
+        b.groups[k] = pick;
+    }
+    if (err == hipSuccess) {
+        float best = 1e30f;
+        int pick = b.slots_per_cu;
+        for (int spc = 1; spc <= 4 && err == hipSuccess; ++spc) {
+            float ms = 0.f;
+            err = timed(0, a.n_items, b.groups, spc, &ms);
+            if (err == hipSuccess && ms < best) {
+                best = ms;
+                pick = spc;
+            }
+        }
+        b.slots_per_cu = pick;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return fail(QNEP_E_DEVICE, std::string("batch tuning: ") + hipGetErrorString(err));
+    if (choice) {
+        for (int k = 0; k < BATCH_CLASSES; ++k) choice[k] = b.groups[k];
+        choice[BATCH_CLASSES] = b.slots_per_cu;
+    }
+    // leave the outputs of the chosen configuration
+    HIP_TRY(batch_run(m, a, 0, a.n_items, b.groups, b.slots_per_cu, st));
+    if (outputs->loss) {
+        const double lam[5] = {targets->lambda_e, targets->lambda_f, targets->lambda_q, targets->lambda_1,
+                               targets->lambda_2};
+        HIP_TRY(batch_loss(b.stats, targets->energy, thetas, a.n_theta, a.S, a.C, a.qtot, lam, outputs->loss, st));
+    }
     return QNEP_OK;
 }
 

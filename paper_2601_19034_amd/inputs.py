@@ -285,3 +285,30 @@ def _most_cubic(n):
             if best is None or score < best[0]:
                 best = (score, (a, b, c))
     return best[1]
+
+
+# one four-species model (O, H, A, B) with the hyper-parameters of the water workload
+BATCH_HP = HParams(n_types=4, n_max_R=4, n_max_A=4, basis_R=8, basis_A=8, l_max=4, n_neu=30)
+
+
+@dataclasses.dataclass
+class BatchWorkload:
+    systems: List[System]
+    hp: HParams
+    es: ESParams
+    theta0: np.ndarray
+    thetas: np.ndarray  # [C, n_theta] candidates theta0 + N(0, sigma_c^2)
+
+
+def batch_workload(n_struct: int = 512, n_cand: int = 64, sigma_c: float = 0.05) -> BatchWorkload:
+    """Uneven structures under a population of candidate parameter vectors: Ewald with
+    alpha = 0.3, rc = 9 A and kmax = 2 pi alpha; candidates perturb every component
+    of theta0 (including s) by N(0, sigma_c^2)."""
+    seed = SEED_BASE + 4
+    systems = batch_structures(n_struct, seed=seed)
+    th0 = theta0(BATCH_HP, seed)
+    rng = rng_for(seed + 1000)
+    thetas = th0[None, :] + rng.normal(0.0, sigma_c, (n_cand, th0.size))
+    thetas = thetas.astype(np.float32).astype(np.float64)
+    es = ESParams(mode=1, method=0, alpha=0.3, rc_coul=9.0, kmax=2 * math.pi * 0.3, kmax_inclusive=0)
+    return BatchWorkload(systems, BATCH_HP, es, th0, thetas)

@@ -98,3 +98,48 @@ def test_capacity_factor_validation(qlib):
         B.qnep_model_set_capacity_factor(h, 2.0)
     finally:
         B.qnep_model_destroy(h)
+
+
+def test_batch_workspace_and_validation(qlib):
+    """Sizing and argument checks of the batched entry points (host only)."""
+    import ctypes as C
+
+    from paper_2601_19034_amd import binding as B
+    wl = inputs.batch_workload(n_struct=16, n_cand=4)
+    h = B.qnep_model_create(wl.hp, 0)
+    try:
+        sizes = [len(s.types) for s in wl.systems]
+        off = (C.c_int64 * 17)(*np.concatenate([[0], np.cumsum(sizes)]).tolist())
+        cells = (C.c_double * (9 * 16))(*np.concatenate([s.cell.reshape(9) for s in wl.systems]).tolist())
+        es = B.make_es(wl.es)
+        b0 = B.make_batch(16, 0, off, cells, 0, 0)
+        b1 = B.make_batch(16, B.QNEP_BATCH_VIRIAL, off, cells, 0, 0)
+        n0 = B.qnep_batch_workspace_size(h, es, b0, 4)
+        n1 = B.qnep_batch_workspace_size(h, es, b1, 4)
+        # the virial adds six N x N matrices per structure
+        assert n1 - n0 >= 6 * 4 * sum(n * n for n in sizes) - 4096
+        assert B.qnep_batch_workspace_size(h, es, b0, 64) > n0
+        with pytest.raises(B.QnepError):
+            B.qnep_batch_workspace_size(h, es, b0, 0)
+        pppm = B.make_es(inputs.ESParams(method=1, mesh=(16, 16, 16)))
+        with pytest.raises(B.QnepError, match="unsupported"):
+            B.qnep_batch_workspace_size(h, pppm, b0, 4)
+        bad = (C.c_int64 * 17)(*([0] + [3000] * 16))
+        with pytest.raises(B.QnepError, match="unsupported"):
+            B.qnep_batch_workspace_size(h, es, B.make_batch(16, 0, bad, cells, 0, 0), 4)
+        empty = (C.c_int64 * 17)(*([0, 0] + [10] * 15))
+        with pytest.raises(B.QnepError):
+            B.qnep_batch_workspace_size(h, es, B.make_batch(16, 0, empty, cells, 0, 0), 4)
+        flat = (C.c_double * (9 * 16))(*([0.0] * 9 * 16))
+        with pytest.raises(B.QnepError, match="invalid"):
+            B.qnep_batch_workspace_size(h, es, B.make_batch(16, 0, off, flat, 0, 0), 4)
+    finally:
+        B.qnep_model_destroy(h)
+    # the garnet model (10310 parameters) fits the staged-parameter limit; a larger one does not
+    big = inputs.HParams(n_types=4, n_max_R=8, n_max_A=6, basis_R=8, basis_A=8, l_max=4, n_neu=64)
+    hb = B.qnep_model_create(big, 0)
+    try:
+        with pytest.raises(B.QnepError, match="unsupported"):
+            B.qnep_batch_workspace_size(hb, es, b0, 4)
+    finally:
+        B.qnep_model_destroy(hb)

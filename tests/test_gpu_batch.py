@@ -1,0 +1,194 @@
+"""Batched evaluation (qnep_batch_*) against the FP64 oracle.
+
+Every (structure, candidate) work item of the persistent launch is an independent
+qNEP evaluation with Ewald electrostatics; its E, F, W and corrected charges are
+compared with the oracle run on that structure with that candidate's parameters, at
+the FP32 bounds of the single-structure tests (|dE|/N <= 2e-6 eV, max |dF| <= 1e-4
+eV/A, max |dW|/N <= 2e-5 eV, max |dq~'| <= 4e-6 e).  The losses are checked against
+the same quantities formed from the oracle: Delta_e = |E - E_ref|/N, Delta_f = RMS of
+F - F_ref, Delta_Q = |s sum_i q_i - Q|, and the per-candidate total.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2601_19034_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = dict(e=2e-6, f=1e-4, w=2e-5, q=4e-6)
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def wl():
+    return inputs.batch_workload()
+
+
+def _pick(wl, idx):
+    return [wl.systems[i] for i in idx]
+
+
+def _oracle(orc, hp, es, sysm, theta):
+    return orc.compute(hp, es, sysm.pos, sysm.types, sysm.cell, theta, cells=False)
+
+
+def _targets(torch, systems, refs):
+    E = torch.tensor([r.energy for r in refs], dtype=torch.float64, device="cuda")
+    F = np.concatenate([r.forces for r in refs]).T.astype(np.float32)
+    return E, torch.from_numpy(np.ascontiguousarray(F)).cuda()
+
+
+def _run(torch, hp, es, systems, thetas, refs, virial=True, lambdas=(1.0, 2.0, 0.5, 1e-4, 1e-5),
+         precision="fp32"):
+    from paper_2601_19034_amd.api import QNEP, QNEPBatch
+
+    model = QNEP(hp, precision)
+    batch = QNEPBatch(model, systems, es, max_candidates=len(thetas), virial=virial)
+    th = torch.from_numpy(np.asarray(thetas, dtype=np.float32)).cuda()
+    E_ref, F_ref = _targets(torch, systems, refs)
+    outs = ("loss", "energy", "forces", "charges") + (("virial",) if virial else ())
+    out = batch.compute(th, E_ref, F_ref, lambdas=lambdas, outputs=outs)
+    flags = batch.check_status()
+    assert flags == 0, f"device status flags {flags}"
+    return batch, {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def _check_items(orc, hp, es, systems, thetas, refs, out, lambdas, tol=TOL, virial=True, label=""):
+    off = np.concatenate([[0], np.cumsum([len(s.types) for s in systems])])
+    S, C = len(systems), len(thetas)
+    se_e = np.zeros(C)
+    se_f = np.zeros(C)
+    se_q = np.zeros(C)
+    worst = dict(e=0.0, f=0.0, w=0.0, q=0.0)
+    for s, sysm in enumerate(systems):
+        n = len(sysm.types)
+        for c in range(C):
+            r = _oracle(orc, hp, es, sysm, thetas[c])
+            dE = abs(out["energy"][s, c] - r.energy) / n
+            F = out["forces"][c][:, off[s]:off[s + 1]].T.astype(np.float64)
+            dF = np.abs(F - r.forces).max()
+            dq = np.abs(out["charges"][c][off[s]:off[s + 1]] - r.q_naked).max()
+            worst["e"] = max(worst["e"], dE)
+            worst["f"] = max(worst["f"], dF)
+            worst["q"] = max(worst["q"], dq)
+            if virial:
+                dW = np.abs(out["virial"][s, c].reshape(3, 3) - r.virial).max() / n
+                worst["w"] = max(worst["w"], dW)
+            # losses of this item from the oracle values
+            le = abs(r.energy - refs[s].energy) / n
+            lf = math.sqrt(((r.forces - refs[s].forces) ** 2).sum() / (3 * n))
+            lq = abs(r.terms[6] * thetas[c][-1] - es.q_total)
+            got = out["losses"][s, c]
+            assert abs(got[0] - le) <= tol["e"] * 2 + 1e-6 * le, (s, c, got[0], le)
+            assert abs(got[1] - lf) <= tol["f"], (s, c, got[1], lf)
+            assert abs(got[2] - lq) <= 50 * tol["q"] * n ** 0.5, (s, c, got[2], lq)
+            se_e[c] += le ** 2
+            se_f[c] += lf ** 2 * 3 * n
+            se_q[c] += lq ** 2
+    _say(f"[{label}] S={S} C={C} worst dE/N={worst['e']:.2e} dF={worst['f']:.2e} dW/N={worst['w']:.2e} "
+         f"dq={worst['q']:.2e}")
+    assert worst["e"] <= tol["e"] and worst["f"] <= tol["f"] and worst["q"] <= tol["q"]
+    if virial:
+        assert worst["w"] <= tol["w"]
+    nf = 3 * off[-1]
+    th = np.asarray(thetas, dtype=np.float32).astype(np.float64)
+    want = (lambdas[0] * np.sqrt(se_e / S) + lambdas[1] * np.sqrt(se_f / nf) + lambdas[2] * np.sqrt(se_q / S)
+            + lambdas[3] * np.abs(th).sum(1) + lambdas[4] * (th ** 2).sum(1))
+    assert np.allclose(out["loss"], want, rtol=1e-4, atol=1e-6), (out["loss"], want)
+
+
+def test_batch_items_against_oracle(torch_dev, orc, wl):
+    """Water- and perovskite-like structures from the smallest (including a 4 x 4 x 20 A
+    cell thinner than both cutoffs) to the largest size class."""
+    sizes = np.array([len(s.types) for s in wl.systems])
+    idx = [int(np.argmin(sizes[:256])), int(256 + np.argmin(sizes[256:])), int(np.argmax(sizes[:256])),
+           int(256 + np.argmax(sizes[256:])), 7, 300, 100, 400]
+    systems = _pick(wl, idx)
+    thetas = wl.thetas[:3]
+    refs = [_oracle(orc, wl.hp, wl.es, s, wl.theta0) for s in systems]
+    lam = (1.0, 2.0, 0.5, 1e-4, 1e-5)
+    _say("case batch items: structures " + ", ".join(f"{s.name}({len(s.types)})" for s in systems))
+    _, out = _run(torch_dev, wl.hp, wl.es, systems, thetas, refs, lambdas=lam)
+    _check_items(orc, wl.hp, wl.es, systems, thetas, refs, out, lam, label="batch fp32")
+
+
+def test_batch_mode2_and_net_charge(torch_dev, orc, wl):
+    import copy
+
+    systems = _pick(wl, [3, 260, 50])
+    thetas = wl.thetas[5:7]
+    for mode, q in ((2, 0.0), (1, 0.6)):
+        es = copy.deepcopy(wl.es)
+        es.mode = mode
+        es.q_total = q
+        refs = [_oracle(orc, wl.hp, es, s, wl.theta0) for s in systems]
+        lam = (1.0, 1.0, 1.0, 0.0, 0.0)
+        _say(f"case batch mode {mode} Q={q}")
+        _, out = _run(torch_dev, wl.hp, es, systems, thetas, refs, lambdas=lam)
+        _check_items(orc, wl.hp, es, systems, thetas, refs, out, lam, label=f"batch mode{mode} Q={q}")
+
+
+def test_batch_without_virial_matches(torch_dev, orc, wl):
+    systems = _pick(wl, [10, 270])
+    thetas = wl.thetas[:2]
+    refs = [_oracle(orc, wl.hp, wl.es, s, wl.theta0) for s in systems]
+    _say("case batch without the virial matrices")
+    _, a = _run(torch_dev, wl.hp, wl.es, systems, thetas, refs, virial=True)
+    _, b = _run(torch_dev, wl.hp, wl.es, systems, thetas, refs, virial=False)
+    assert np.allclose(a["energy"], b["energy"], rtol=0, atol=1e-9 * np.abs(a["energy"]).max())
+    assert np.abs(a["forces"] - b["forces"]).max() < 1e-5
+
+
+def test_batch_full_population_and_tuner(torch_dev, orc, wl):
+    """All 512 structures x 64 candidates in one launch; sampled items against the
+    oracle; the autotuned configuration reproduces the default one."""
+    import torch
+
+    from paper_2601_19034_amd.api import QNEP, QNEPBatch
+
+    model = QNEP(wl.hp, "fp32")
+    _say("case batch 512 x 64: prepare")
+    batch = QNEPBatch(model, wl.systems, wl.es, max_candidates=64)
+    th = torch.from_numpy(wl.thetas.astype(np.float32)).cuda()
+    # targets: seeded synthetic values (the sampled checks below use the oracle directly)
+    rng = np.random.default_rng(7)
+    E_ref = torch.from_numpy(rng.normal(-5.0, 1.0, batch.S) * batch.sizes).cuda()
+    F_ref = torch.from_numpy(rng.normal(0, 1.0, (3, batch.n_total)).astype(np.float32)).cuda()
+    _say("case batch 512 x 64: compute")
+    out = batch.compute(th, E_ref, F_ref, outputs=("loss", "energy", "forces"))
+    torch.cuda.synchronize()
+    assert batch.check_status() == 0
+    res = {k: v.cpu().numpy() for k, v in out.items()}
+    assert np.isfinite(res["losses"]).all() and np.isfinite(res["loss"]).all()
+    off = batch.offsets_np
+    for s, c in ((0, 0), (137, 63), (300, 31), (511, 5), (int(np.argmax(batch.sizes)), 17)):
+        sysm = wl.systems[s]
+        r = _oracle(orc, wl.hp, wl.es, sysm, wl.thetas[c])
+        n = len(sysm.types)
+        dE = abs(res["energy"][s, c] - r.energy) / n
+        dF = np.abs(res["forces"][c][:, off[s]:off[s + 1]].T - r.forces).max()
+        _say(f"[batch 512x64 item ({s},{c}) n={n}] dE/N={dE:.2e} dF={dF:.2e}")
+        assert dE <= TOL["e"] and dF <= TOL["f"]
+    _say("case batch 512 x 64: tune")
+    choice = batch.tune(th, E_ref, F_ref)
+    _say(f"[tuner] lanes per class {choice[:4]}, workgroups per CU {choice[4]}")
+    assert all(g in (1, 2, 4, 8, 16) for g in choice[:4]) and 1 <= choice[4] <= 4
+    out2 = batch.compute(th, E_ref, F_ref, outputs=("loss", "energy", "forces"))
+    res2 = {k: v.cpu().numpy() for k, v in out2.items()}
+    assert np.abs(res2["energy"] - res["energy"]).max() <= 1e-6 * np.abs(res["energy"]).max()
+    assert np.abs(res2["forces"] - res["forces"]).max() <= 1e-5
