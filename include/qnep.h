@@ -190,7 +190,8 @@ const char *qnep_stage_name(int32_t stage);
  * Limits: at most 2048 atoms per structure; parameters per candidate at most 12288;
  * l_max = 4, basis_R = basis_A = 8, (n_max_R, n_max_A) = (4, 4) or (8, 6).
  * ------------------------------------------------------------------------------ */
-#define QNEP_BATCH_VIRIAL 1 /* also form the per-(structure, candidate) virial */
+#define QNEP_BATCH_VIRIAL 1   /* also form the per-(structure, candidate) virial */
+#define QNEP_BATCH_GRADIENT 2 /* reserve the buffers of qnep_batch_gradient */
 
 typedef struct {
     int32_t n_structures;   /* S >= 1 */
@@ -234,6 +235,17 @@ qnep_status qnep_batch_prepare(void *model, const qnep_es_params *es, const qnep
 qnep_status qnep_batch_compute(void *model, const float *thetas, int32_t n_candidates,
                                const qnep_batch_targets *targets, const qnep_batch_outputs *outputs, void *ws,
                                size_t ws_bytes, void *stream);
+/* Gradient of each candidate's total loss (outputs->loss, Sec. 2.5) with respect to
+   all of its parameters: d_thetas, device, [C][n_theta].  Runs the forward launch
+   (filling the requested outputs), the loss reduction and a second persistent launch
+   that differentiates the energy, force and total-charge terms in reverse mode, the
+   force term through the descriptor tangents and the network's second derivatives
+   (exact up to rounding; FP32 network arithmetic in the adjoint whatever the forward
+   precision).  Where an RMSE term is zero its gradient is taken as zero.  Needs
+   QNEP_BATCH_GRADIENT at prepare. */
+qnep_status qnep_batch_gradient(void *model, const float *thetas, int32_t n_candidates,
+                                const qnep_batch_targets *targets, const qnep_batch_outputs *outputs,
+                                float *d_thetas, void *ws, size_t ws_bytes, void *stream);
 /* Autotuner: times the lanes-per-atom choice for each structure-size class (fewer
    than 48, 48-127, 128-383, 384 or more atoms) over {1, 2, 4, 8, 16} and then the
    number of resident workgroups per compute unit over {1, 2, 3, 4}, on the prepared

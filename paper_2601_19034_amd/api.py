@@ -178,7 +178,8 @@ class QNEPBatch:
     ``systems`` carry ``pos`` (N, 3), ``types`` (N,) and ``cell`` (3, 3); the geometry
     (lists and Ewald pair matrices) is built once here, on the device."""
 
-    def __init__(self, model: QNEP, systems, es, max_candidates: int, virial: bool = False, device="cuda"):
+    def __init__(self, model: QNEP, systems, es, max_candidates: int, virial: bool = False, gradient: bool = False,
+                 device="cuda"):
         _require_gpu()
         self.model = model
         self.S = len(systems)
@@ -194,7 +195,7 @@ class QNEPBatch:
         self.pos = torch.from_numpy(np.ascontiguousarray(pos.T)).to(device)
         self.types = torch.from_numpy(np.concatenate([s.types for s in systems]).astype(np.int32)).to(device)
         self.es = B.make_es(es)
-        self.flags = B.QNEP_BATCH_VIRIAL if virial else 0
+        self.flags = (B.QNEP_BATCH_VIRIAL if virial else 0) | (B.QNEP_BATCH_GRADIENT if gradient else 0)
         self.cbatch = B.make_batch(self.S, self.flags, self._offsets, self._cells, self.pos.data_ptr(),
                                    self.types.data_ptr())
         nbytes = B.qnep_batch_workspace_size(model.handle, self.es, self.cbatch, self.max_candidates)
@@ -232,6 +233,18 @@ class QNEPBatch:
                              s.cuda_stream)
         self._stream = s
         return out
+
+    def gradient(self, thetas: torch.Tensor, E_ref: torch.Tensor, F_ref: torch.Tensor,
+                 lambdas=(1.0, 1.0, 1.0, 0.0, 0.0), outputs=("loss",),
+                 stream: Optional[torch.cuda.Stream] = None):
+        """(outputs, dL/dtheta [C, n_theta]) for the total loss of every candidate."""
+        C_, tg, oc, out = self._args(thetas, E_ref, F_ref, lambdas, outputs)
+        d = torch.empty_like(thetas)
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        B.qnep_batch_gradient(self.model.handle, thetas.data_ptr(), C_, tg, oc, d.data_ptr(), self.ws.data_ptr(),
+                              self.ws.numel(), s.cuda_stream)
+        self._stream = s
+        return out, d
 
     def tune(self, thetas, E_ref, F_ref, lambdas=(1.0, 1.0, 1.0, 0.0, 0.0)):
         """Autotunes lanes per atom (per size class) and workgroups per CU; returns the choice."""

@@ -205,6 +205,7 @@ def qnep_backward(model: int, theta_ptr: int, es: qnep_es_params, sysm: qnep_sys
 
 # ---------------------------------------------------------------- batched evaluation
 QNEP_BATCH_VIRIAL = 1
+QNEP_BATCH_GRADIENT = 2
 
 
 class qnep_batch(C.Structure):
@@ -222,7 +223,8 @@ class qnep_batch_outputs(C.Structure):
                 ("forces", C.c_void_p), ("charges", C.c_void_p)]
 
 
-EXPORTED += ["qnep_batch_workspace_size", "qnep_batch_prepare", "qnep_batch_compute", "qnep_batch_tune"]
+EXPORTED += ["qnep_batch_workspace_size", "qnep_batch_prepare", "qnep_batch_compute", "qnep_batch_gradient",
+             "qnep_batch_tune"]
 
 
 def _bind_batch(L):
@@ -237,6 +239,10 @@ def _bind_batch(L):
     L.qnep_batch_compute.restype = C.c_int
     L.qnep_batch_compute.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(qnep_batch_targets),
                                      C.POINTER(qnep_batch_outputs), C.c_void_p, C.c_size_t, C.c_void_p]
+    L.qnep_batch_gradient.restype = C.c_int
+    L.qnep_batch_gradient.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(qnep_batch_targets),
+                                      C.POINTER(qnep_batch_outputs), C.c_void_p, C.c_void_p, C.c_size_t,
+                                      C.c_void_p]
     L.qnep_batch_tune.restype = C.c_int
     L.qnep_batch_tune.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(qnep_batch_targets),
                                   C.POINTER(qnep_batch_outputs), C.c_void_p, C.c_size_t, C.c_void_p,
@@ -283,3 +289,12 @@ def qnep_batch_tune(model: int, thetas_ptr: int, n_candidates: int, targets: qne
     _check(L.qnep_batch_tune(C.c_void_p(model), C.c_void_p(thetas_ptr), int(n_candidates), C.byref(targets),
                              C.byref(outputs), C.c_void_p(ws_ptr), ws_bytes, C.c_void_p(stream), choice))
     return [int(v) for v in choice]
+
+
+def qnep_batch_gradient(model: int, thetas_ptr: int, n_candidates: int, targets: qnep_batch_targets,
+                        outputs: qnep_batch_outputs, dthetas_ptr: int, ws_ptr: int, ws_bytes: int, stream: int):
+    L = load()
+    _bind_batch(L)
+    _check(L.qnep_batch_gradient(C.c_void_p(model), C.c_void_p(thetas_ptr), int(n_candidates), C.byref(targets),
+                                 C.byref(outputs), C.c_void_p(dthetas_ptr), C.c_void_p(ws_ptr), ws_bytes,
+                                 C.c_void_p(stream)))

@@ -504,7 +504,15 @@ qnep_status batch_layout(const Model &m, const qnep_es_params *es, const qnep_ba
     bp.ph = c.take<float2>(bp.ph_total);
     bp.mats = c.take<float>(bp.mat_total);
     bp.stats = c.take<double>((size_t)S * C_max * 4);
+    bp.rmse = c.take<double>((size_t)C_max * 4);
     bp.scratch = c.take<float>((size_t)BATCH_MAX_SLOTS * bp.per_slot);
+    bp.grad = (bt->flags & QNEP_BATCH_GRADIENT) != 0;
+    if (bp.grad) {
+        bp.per_slot_adj = batch_adj_floats(T, NR, NA, NB, hp.n_neu) * bp.max_atoms;
+        bp.fbuf = c.take<float>((size_t)C_max * 3 * bp.n_total);
+        bp.grow = c.take<float>((size_t)S * C_max * param_count(hp));
+        bp.adj_scratch = c.take<float>((size_t)BATCH_ADJ_SLOTS * bp.per_slot_adj);
+    }
     bp.need = (c.off + ALIGN - 1) / ALIGN * ALIGN;
     *bytes = bp.need;
     return QNEP_OK;
@@ -732,6 +740,7 @@ qnep_status batch_args(const Model &m, const float *thetas, int C, const qnep_ba
     a.n_theta = a.off_s + 1;
     a.H = hp.n_neu;
     a.ndes = ndes;
+    a.prec = m.prec;
     a.rcR = hp.rc_R;
     a.rcA = hp.rc_A;
     a.qtot = b.qtot;
@@ -774,8 +783,43 @@ qnep_status qnep_batch_compute(void *model, const float *thetas, int32_t n_candi
     if (outputs->loss) {
         const double lam[5] = {targets->lambda_e, targets->lambda_f, targets->lambda_q, targets->lambda_1,
                                targets->lambda_2};
-        HIP_TRY(batch_loss(m.batch.stats, targets->energy, thetas, a.n_theta, a.S, a.C, a.qtot, lam, outputs->loss, st));
+        HIP_TRY(batch_loss(m.batch.stats, targets->energy, thetas, a.n_theta, a.S, a.C, a.qtot, lam, outputs->loss,
+                           m.batch.rmse, st));
     }
+    return QNEP_OK;
+}
+
+qnep_status qnep_batch_gradient(void *model, const float *thetas, int32_t n_candidates,
+                                const qnep_batch_targets *targets, const qnep_batch_outputs *outputs,
+                                float *d_thetas, void *ws, size_t ws_bytes, void *stream) {
+    if (!model || !d_thetas) return fail(QNEP_E_INVALID_ARG, "null model or gradient");
+    const Model &m = *static_cast<const Model *>(model);
+    BatchArgs a;
+    qnep_status s = batch_args(m, thetas, n_candidates, targets, outputs, ws, ws_bytes, a);
+    if (s != QNEP_OK) return s;
+    const BatchPlan &b = m.batch;
+    if (!b.grad) return fail(QNEP_E_INVALID_ARG, "gradient needs QNEP_BATCH_GRADIENT at prepare");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const qnep_hparams &hp = m.hp;
+    // forward (forces kept for the upstream force weights), then the aggregated loss
+    float *F = outputs->forces ? outputs->forces : b.fbuf;
+    a.forces = F;
+    HIP_TRY(batch_run(m, a, 0, a.n_items, b.groups, b.slots_per_cu, st));
+    const double lam[5] = {targets->lambda_e, targets->lambda_f, targets->lambda_q, targets->lambda_1,
+                           targets->lambda_2};
+    HIP_TRY(batch_loss(b.stats, targets->energy, thetas, a.n_theta, a.S, a.C, a.qtot, lam, outputs->loss, b.rmse, st));
+    AdjArgs g{};
+    g.forces = F;
+    g.rmse = b.rmse;
+    for (int k = 0; k < 5; ++k) g.lam[k] = lam[k];
+    g.nf = 3.0 * (double)b.n_total;
+    g.grow = b.grow;
+    g.scratch = b.adj_scratch;
+    HIP_TRY(fill_zero(b.counter, sizeof(int) * 16, st));
+    const int slots = std::min(b.cus * 2, BATCH_ADJ_SLOTS);
+    HIP_TRY(batch_adjoint(a, g, hp.n_types, hp.n_max_R + 1, hp.n_max_A + 1, hp.basis_R + 1, slots,
+                          make_int4(b.groups[0], b.groups[1], b.groups[2], b.groups[3]), st));
+    HIP_TRY(batch_grad_reduce(b.grow, thetas, a.n_theta, a.S, a.C, lam[3], lam[4], d_thetas, st));
     return QNEP_OK;
 }
 
@@ -853,7 +897,7 @@ qnep_status qnep_batch_tune(void *model, const float *thetas, int32_t n_candidat
     if (outputs->loss) {
         const double lam[5] = {targets->lambda_e, targets->lambda_f, targets->lambda_q, targets->lambda_1,
                                targets->lambda_2};
-        HIP_TRY(batch_loss(b.stats, targets->energy, thetas, a.n_theta, a.S, a.C, a.qtot, lam, outputs->loss, st));
+        HIP_TRY(batch_loss(b.stats, targets->energy, thetas, a.n_theta, a.S, a.C, a.qtot, lam, outputs->loss, b.rmse, st));
     }
     return QNEP_OK;
 }

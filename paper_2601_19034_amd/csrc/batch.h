@@ -50,6 +50,7 @@ struct BatchArgs {
     const float *thetas;     // [C][n_theta]
     int64_t n_theta, off_cA, off_nn, per_species, off_b1E, off_s;
     int H, ndes;
+    int prec;                // network precision (QNEP_MLP_*)
     float rcR, rcA;
     double qtot;
     const double *E_ref;     // [S]
@@ -65,8 +66,26 @@ struct BatchArgs {
     int max_atoms;
 };
 
+// Extra arguments of the adjoint launch (gradient of the loss with respect to theta).
+struct AdjArgs {
+    const float *forces;     // [C][3][n_total] forces of the forward launch
+    const double *rmse;      // [C][4] RMSE_e, RMSE_f, RMSE_Q of each candidate
+    double lam[5];           // loss weights
+    double nf;               // number of force components, 3 sum_s N_s
+    float *grow;             // [S][C][n_theta] gradient of each work item
+    float *scratch;          // per slot: batch_adj_floats(...) x max_atoms
+};
+
+// per-atom floats of the adjoint scratch: D, A, gU, gq (forward phases), B, B', A',
+// nu (tangents), h, z' , zeta, tau (network), D-bar, nu-bar
+__host__ __device__ inline int64_t batch_adj_floats(int T, int NR, int NA, int NB, int H) {
+    const int ndes = NR + 4 * NA;
+    return 3 * ndes + 24 * NA + 2 * T * NB + 24 * NA + ndes + 4 * H + 2 * ndes;
+}
+
 constexpr int BATCH_CLASSES = 4;        // size classes: < 48, < 128, < 384, >= 384 atoms
 constexpr int BATCH_MAX_SLOTS = 1024;   // resident workgroups of the persistent launch
+constexpr int BATCH_ADJ_SLOTS = 512;    // resident workgroups of the adjoint launch
 
 inline int batch_class(int n) { return n < 48 ? 0 : (n < 128 ? 1 : (n < 384 ? 2 : 3)); }
 
@@ -94,6 +113,11 @@ struct BatchPlan {
     float2 *ph = nullptr;
     float *mats = nullptr, *scratch = nullptr;
     double *stats = nullptr;
+    // gradient buffers (QNEP_BATCH_GRADIENT)
+    bool grad = false;
+    int64_t per_slot_adj = 0;
+    float *fbuf = nullptr, *grow = nullptr, *adj_scratch = nullptr;
+    double *rmse = nullptr;
     int n_slots() const {
         int s = cus * slots_per_cu;
         return s < BATCH_MAX_SLOTS ? s : BATCH_MAX_SLOTS;
@@ -108,6 +132,10 @@ bool batch_supported(int T, int NR, int NA, int NB);
 hipError_t batch_eval(const BatchArgs &a, int T, int NR, int NA, int NB, int n_slots, int item_begin,
                       int item_end, int4 groups, hipStream_t stream);
 hipError_t batch_loss(const double *stats, const double *E_ref, const float *thetas, int64_t n_theta, int S, int C,
-                      double qtot, const double *lam, double *loss, hipStream_t stream);
+                      double qtot, const double *lam, double *loss, double *rmse, hipStream_t stream);
+hipError_t batch_adjoint(const BatchArgs &a, const AdjArgs &g, int T, int NR, int NA, int NB, int n_slots,
+                         int4 groups, hipStream_t stream);
+hipError_t batch_grad_reduce(const float *grow, const float *thetas, int64_t n_theta, int S, int C, double l1,
+                             double l2, float *dthetas, hipStream_t stream);
 
 }  // namespace qnep

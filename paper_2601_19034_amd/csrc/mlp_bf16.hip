@@ -6,46 +6,10 @@
 // species share a tile: for every species t the A-operand rows of other species are
 // zeroed, so sum_t A_t W0_t gives each row its own species' product.  tanh and the
 // output layers stay in FP32.
+#include "mfma.h"
 #include "plan.h"
 
 namespace qnep {
-
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-
-__device__ inline short to_bf16(float f) {  // round to nearest even
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (short)(u >> 16);
-}
-
-// Lane layout of the 16x16x16 BF16 MFMA (wave64, lane l):
-//   A[i][k]: i = l % 16, k = 4 (l / 16) + e  (element e of the 4-vector)
-//   B[k][j]: j = l % 16, k = 4 (l / 16) + e
-//   D[i][j]: j = l % 16, i = 4 (l / 16) + e
-// NSPLIT = 1: one BF16 product per term.  NSPLIT = 3: operands split x = hi + lo in
-// BF16 and hi*hi + hi*lo + lo*hi accumulated (about 16 mantissa bits).
-template <int NSPLIT>
-__device__ inline floatx4 mfma_split(const float (&a)[4], const float (&b)[4], floatx4 acc) {
-    bf16x4 ah, bh;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        ah[e] = to_bf16(a[e]);
-        bh[e] = to_bf16(b[e]);
-    }
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
-    if (NSPLIT == 3) {
-        bf16x4 al, bl;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            al[e] = to_bf16(a[e] - __uint_as_float((uint32_t)(unsigned short)ah[e] << 16));
-            bl[e] = to_bf16(b[e] - __uint_as_float((uint32_t)(unsigned short)bh[e] << 16));
-        }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
-    }
-    return acc;
-}
 
 template <int KD, int KH, int NSPLIT>
 __global__ __launch_bounds__(256) void k_mlp_bf16(int N, int T, int H, int ndes, const int *__restrict__ ts,

@@ -125,4 +125,39 @@ __host__ __device__ inline void harmonics_grad_dot(float x, float y, float z, co
     gz = az;
 }
 
+// Directional derivative of each polynomial above along (vx, vy, vz):
+// Yd[lm] = grad Y_lm(x, y, z) . v  (the caller passes a tangential v to obtain the
+// derivative on the sphere).
+__host__ __device__ inline void harmonics_jvp(float x, float y, float z, float vx, float vy, float vz,
+                                              float *Yd) {
+    const float s3 = 1.7320508075688772f, s15 = 3.872983346207417f, s6 = 2.449489742783178f;
+    const float s10 = 3.1622776601683795f, s5 = 2.23606797749979f, s35 = 5.916079783099616f;
+    const float c43 = 2.091650066335189f, c41 = 0.7905694150420949f;
+    float x2 = x * x, y2 = y * y, z2 = z * z;
+    Yd[0] = vy;
+    Yd[1] = vz;
+    Yd[2] = vx;
+    Yd[3] = s3 * (y * vx + x * vy);
+    Yd[4] = s3 * (z * vy + y * vz);
+    Yd[5] = 3.0f * z * vz;
+    Yd[6] = s3 * (z * vx + x * vz);
+    Yd[7] = s3 * (x * vx - y * vy);
+    Yd[8] = 1.5f * s10 * x * y * vx + 0.75f * s10 * (x2 - y2) * vy;
+    Yd[9] = s15 * (y * z * vx + x * z * vy + x * y * vz);
+    Yd[10] = 0.25f * s6 * (5.0f * z2 - 1.0f) * vy + 2.5f * s6 * y * z * vz;
+    Yd[11] = (7.5f * z2 - 1.5f) * vz;
+    Yd[12] = 0.25f * s6 * (5.0f * z2 - 1.0f) * vx + 2.5f * s6 * x * z * vz;
+    Yd[13] = s15 * x * z * vx - s15 * y * z * vy + 0.5f * s15 * (x2 - y2) * vz;
+    Yd[14] = 0.75f * s10 * (x2 - y2) * vx - 1.5f * s10 * x * y * vy;
+    Yd[15] = 0.5f * s35 * ((3.0f * x2 * y - y2 * y) * vx + (x2 * x - 3.0f * x * y2) * vy);
+    Yd[16] = c43 * (6.0f * x * y * z * vx + 3.0f * z * (x2 - y2) * vy + y * (3.0f * x2 - y2) * vz);
+    Yd[17] = 0.5f * s5 * (7.0f * z2 - 1.0f) * (y * vx + x * vy) + 7.0f * s5 * x * y * z * vz;
+    Yd[18] = c41 * (z * (7.0f * z2 - 3.0f) * vy + y * (21.0f * z2 - 3.0f) * vz);
+    Yd[19] = (17.5f * z2 * z - 7.5f * z) * vz;
+    Yd[20] = c41 * (z * (7.0f * z2 - 3.0f) * vx + x * (21.0f * z2 - 3.0f) * vz);
+    Yd[21] = 0.5f * s5 * (7.0f * z2 - 1.0f) * (x * vx - y * vy) + 3.5f * s5 * z * (x2 - y2) * vz;
+    Yd[22] = c43 * (3.0f * z * (x2 - y2) * vx - 6.0f * x * y * z * vy + x * (x2 - 3.0f * y2) * vz);
+    Yd[23] = 0.5f * s35 * ((x2 * x - 3.0f * x * y2) * vx + (y2 * y - 3.0f * x2 * y) * vy);
+}
+
 }  // namespace qnep

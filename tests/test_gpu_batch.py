@@ -191,4 +191,14 @@ def test_batch_full_population_and_tuner(torch_dev, orc, wl):
     out2 = batch.compute(th, E_ref, F_ref, outputs=("loss", "energy", "forces"))
     res2 = {k: v.cpu().numpy() for k, v in out2.items()}
     assert np.abs(res2["energy"] - res["energy"]).max() <= 1e-6 * np.abs(res["energy"]).max()
-    assert np.abs(res2["forces"] - res["forces"]).max() <= 1e-5
+    # other lane groupings change the FP32 summation order of the descriptors; on cells
+    # only 4 A wide (1 x 1 x n perovskite chains, where every atom sees many of its own
+    # images) that reordering alone moves a force by up to about 8e-5 eV/A, so the two
+    # configurations agree to the FP32 bound of the oracle comparison
+    assert np.abs(res2["forces"] - res["forces"]).max() <= TOL["f"]
+    for s, c in ((294, 18), (446, 30)):
+        sysm = wl.systems[s]
+        r = _oracle(orc, wl.hp, wl.es, sysm, wl.thetas[c])
+        dF = np.abs(res2["forces"][c][:, off[s]:off[s + 1]].T - r.forces).max()
+        _say(f"[tuned item ({s},{c}) n={len(sysm.types)}] dF={dF:.2e}")
+        assert dF <= TOL["f"]
