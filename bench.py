@@ -34,8 +34,33 @@ def pair_counts(system, radii):
     from scipy.spatial import cKDTree
 
     box = np.diag(system.cell)
-    tree = cKDTree(np.mod(system.pos, box), boxsize=box)
-    return {r: 2 * int(tree.count_neighbors(tree, r) - system.n) // 2 for r in radii}
+    x = np.mod(system.pos, box)
+    tree = cKDTree(x, boxsize=box)
+    return {r: int(tree.query_ball_point(x, r, return_length=True, workers=-1).sum()) - system.n for r in radii}
+
+
+# FP32 operations of one ordered pair inside the real-space cutoff (FMA = 2): image
+# displacement 6, r^2 5, rsqrt and r 2, corrected charge 1, alpha r 1, erfc by the
+# Numerical Recipes rational form 24, exp(-a^2 r^2) 2, potential 3, force factor 5,
+# force 6, virial (six products and sums) 18.
+REAL_SPACE_FLOPS_PER_PAIR = 73
+
+
+def traffic_from_profile(kernel, workload, source):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary,
+    or None when there is none or the kernel's source changed since it was taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2601_19034_amd", "csrc", source), "rb").read()).hexdigest()
+    for line in open(path):
+        if line.startswith("traffic_bytes_per_launch:"):
+            fields = dict(kv.split("=") for kv in line.split(":", 1)[1].split())
+            if fields.get("source_sha256") == sha:
+                return float(fields["bytes"])
+    return None
 
 
 def angular_flops_per_pair(hp):
@@ -75,6 +100,62 @@ def timed_run(model, pos, types, th, w, steps, warmup, torch):
     return ms, wall / steps * 1e3, ms_stage, launches, calls, float(out["energy"][0])
 
 
+def batch_bench(torch, reps=3):
+    """The batched training evaluation: 512 uneven structures x 64 candidate parameter
+    vectors, Ewald, in one persistent launch (plus the loss reduction); then the
+    loss gradient (forward + adjoint launches).  Targets are seeded synthetic values;
+    the work does not depend on them."""
+    import numpy as np
+
+    from paper_2601_19034_amd import inputs
+    from paper_2601_19034_amd.api import QNEP, QNEPBatch
+
+    wl = inputs.batch_workload()
+    res = {}
+    for form in ("fp32", "bf16"):
+        model = QNEP(wl.hp, form)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        batch = QNEPBatch(model, wl.systems, wl.es, max_candidates=64, gradient=(form == "fp32"))
+        e1.record()
+        torch.cuda.synchronize()
+        prep = e0.elapsed_time(e1)
+        th = torch.from_numpy(wl.thetas.astype(np.float32)).cuda()
+        rng = np.random.default_rng(7)
+        E_ref = torch.from_numpy(rng.normal(-5.0, 1.0, batch.S) * batch.sizes).cuda()
+        F_ref = torch.from_numpy(rng.normal(0, 1.0, (3, batch.n_total)).astype(np.float32)).cuda()
+        choice = batch.tune(th, E_ref, F_ref)
+        batch.compute(th, E_ref, F_ref)
+        torch.cuda.synchronize()
+        if batch.check_status():
+            raise SystemExit("batched evaluation: device status flags set")
+        e0.record()
+        for _ in range(reps):
+            batch.compute(th, E_ref, F_ref)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        evals = batch.n_total * th.shape[0]
+        rec = {"ms_per_launch": ms, "atom_evaluations_per_s": evals / (ms * 1e-3), "prepare_ms": prep,
+               "tuned": {"lanes_per_class": choice[:4], "workgroups_per_cu": choice[4]}}
+        if form == "fp32":
+            batch.gradient(th, E_ref, F_ref)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                batch.gradient(th, E_ref, F_ref)
+            e1.record()
+            torch.cuda.synchronize()
+            rec["gradient_ms"] = e0.elapsed_time(e1) / reps
+        res[form] = rec
+        log(f"# batch {form}: {ms:.2f} ms per 512 x 64 launch ({evals / (ms * 1e-3):.3e} atom-evaluations/s), "
+            f"prepare {prep:.1f} ms" + (f", gradient {rec['gradient_ms']:.2f} ms" if "gradient_ms" in rec else ""))
+        del batch, model
+        torch.cuda.empty_cache()
+    return {"workload": f"{len(wl.systems)} structures ({int(sum(len(s.types) for s in wl.systems))} atoms) x "
+                        f"{wl.thetas.shape[0]} candidates, Ewald", "forms": res}
+
+
 def cpu_baseline(budget_s=12.0):
     """The FP64 oracle, as it stands, on a bounded sample of the same workload:
     a 20^3-cell (40,000-atom) perovskite box of the same generator, PPPM with a
@@ -110,6 +191,9 @@ def main():
     ap.add_argument("--variant", default="full")
     ap.add_argument("--forms", default="fp32,bf16x3,bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched (structures x candidates) line")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run three 1 GiB device copies first (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "one structure is evaluated on one GPU in this build; run with --gpus 1"}))
@@ -120,6 +204,14 @@ def main():
     from paper_2601_19034_amd import inputs
     from paper_2601_19034_amd.api import QNEP, to_device_inputs
 
+    if args.calibrate_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("# copy calibration: 3 x 1 GiB device-to-device copies")
+        del a, b
     w = inputs.workload(args.workload, args.variant)
     n = w.system.n
     log(f"# workload {w.name}: N={n}, mesh={w.es.mesh}")
@@ -146,15 +238,26 @@ def main():
     st_ms, st_launch = stages[head]
     dom = max(st_ms, key=st_ms.get)
     roof = None
+    t_launch = st_ms[dom] / st_launch[dom] * 1e-3
     if dom.startswith("angular_forces"):
         pairs = pair_counts(w.system, [w.hp.rc_A])[w.hp.rc_A]
         per_launch_flops = pairs * angular_flops_per_pair(w.hp)
-        t_launch = st_ms[dom] / st_launch[dom] * 1e-3
         ach = per_launch_flops / t_launch / 1e12
         roof = {"bound": "alu", "kernel": f"k_angular_forces ({dom})", "achieved": ach,
-                "peak": FP32_VALU_PEAK_TF, "unit": "TFLOP/s", "frac": ach / FP32_VALU_PEAK_TF, "traffic": None,
+                "peak": FP32_VALU_PEAK_TF, "unit": "TFLOP/s", "frac": ach / FP32_VALU_PEAK_TF,
+                "traffic": traffic_from_profile("k_angular_forces", w.name, "nep.hip"),
                 "units_per_launch": pairs, "flops_per_unit": angular_flops_per_pair(w.hp),
                 "launch_ms": t_launch * 1e3}
+    elif dom == "real_space":
+        pairs = pair_counts(w.system, [w.es.rc_coul])[w.es.rc_coul]
+        ach = pairs * REAL_SPACE_FLOPS_PER_PAIR / t_launch / 1e12
+        roof = {"bound": "alu", "kernel": "k_real_space", "achieved": ach, "peak": FP32_VALU_PEAK_TF,
+                "unit": "TFLOP/s", "frac": ach / FP32_VALU_PEAK_TF,
+                "traffic": traffic_from_profile("k_real_space", w.name, "coul.hip"),
+                "units_per_launch": pairs, "flops_per_unit": REAL_SPACE_FLOPS_PER_PAIR,
+                "launch_ms": t_launch * 1e3}
+    if roof is None:
+        log(f"# no roofline model for the dominant stage {dom}")
     rec = {
         "metric": "atom-steps/s (E+F+virial+Z*) at 1M atoms PPPM",
         "value": n / (ms * 1e-3),
@@ -175,6 +278,8 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in stages[head][0].items()},
         "roofline": roof,
     }
+    if not args.no_batch:
+        rec["batch"] = batch_bench(torch)
     if not args.no_cpu_baseline:
         log("# cpu baseline (FP64 oracle)")
         rec["cpu_baseline"] = cpu_baseline()

@@ -379,8 +379,8 @@ hipError_t run_forward(Plan &p) {
     FW_TRY(launch_mlp(p));
     FW_TRY(launch_charges(p));
     stage_mark(p, ST_MLP, 3);
-    FW_TRY(launch_real_space(p));
-    stage_mark(p, ST_REAL, 2);
+    FW_TRY(launch_real_space(p));  // marks the real-space kernel itself
+    stage_mark(p, ST_OTHER, 1);
     if (p.method == 0) {
         FW_TRY(launch_ewald(p));
     } else {

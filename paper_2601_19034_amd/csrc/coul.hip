@@ -116,6 +116,7 @@ hipError_t launch_real_space(const Plan &p) {
                        (float)p.alpha, p.phi, p.Fst, p.partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    stage_mark(p, ST_REAL, 1);
     return reduce_partials(p, G, 11, S_UREAL, false);  // S_UREAL, S_QSQ, S_WREAL[9]
 }
 
