@@ -192,6 +192,7 @@ def main():
     ap.add_argument("--forms", default="fp32,bf16x3,bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched (structures x candidates) line")
+    ap.add_argument("--batch-only", action="store_true", help="only the batched line")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run three 1 GiB device copies first (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -204,6 +205,9 @@ def main():
     from paper_2601_19034_amd import inputs
     from paper_2601_19034_amd.api import QNEP, to_device_inputs
 
+    if args.batch_only:  # the batched line alone (for profiling its kernels)
+        print(json.dumps({"batch": batch_bench(torch)}), flush=True)
+        return
     if args.calibrate_copy:
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
         b = torch.empty_like(a)

@@ -110,6 +110,17 @@ __device__ inline float erfc_nr(float x) {
 
 __device__ inline int species_of(float4 p) { return __float_as_int(p.w); }
 
+// Workgroup b of a 1D grid runs on XCD b % 8 (round-robin placement), and each XCD has
+// its own L2.  Kernels that read their neighbours' data use the logical block below,
+// which gives every XCD one contiguous range of blocks, i.e. spatially close atoms in
+// the bin-sorted order, so that neighbour rows are re-read from that XCD's L2.
+constexpr int N_XCD = 8;
+__device__ inline int xcd_block() {
+    const int b = blockIdx.x, nb = gridDim.x;
+    const int x = b % N_XCD, k = b / N_XCD, q = nb / N_XCD, r = nb % N_XCD;
+    return x * q + (x < r ? x : r) + k;
+}
+
 // ---------------------------------------------------------------- reductions
 __device__ inline double wave_sum(double v) {
 #pragma unroll

@@ -25,7 +25,7 @@ __global__ __launch_bounds__(256) void k_real_space(int N, const float4 *__restr
                                                     const double *__restrict__ scalars, float alpha,
                                                     float *__restrict__ phi, float *__restrict__ Fst,
                                                     double *__restrict__ partials) {
-    const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int gtid = xcd_block() * blockDim.x + threadIdx.x;
     const int i = gtid / RS_LANES, sub = gtid % RS_LANES;
     float acc[10];  // phi, B r (3), B r r (xx yy zz xy xz yz)
 #pragma unroll

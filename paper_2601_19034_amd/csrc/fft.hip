@@ -2,13 +2,18 @@
 // work-group loading a batch of lines into LDS, transforming them with Stockham
 // radix-2/3/4/5/8 stages and writing them back in place.  Unnormalized in both
 // directions: sign -1 gives sum_m x_m e^{-2 pi i n m / L}, sign +1 the inverse sum.
+//
+// The twiddles e^{sign 2 pi i m / L} of the line length are tabulated once per
+// work-group in LDS; the roots of the small DFTs are compile-time constants.  Lines
+// are stored in LDS with a stride of L + 1 elements so that the transposing loads and
+// stores of the strided axes (consecutive lanes = consecutive lines) hit distinct banks.
 #include "plan.h"
 
 namespace qnep {
 
 constexpr int FFT_THREADS = 256;
 constexpr int FFT_MAX_STAGES = 12;
-constexpr int FFT_ELEMS = 4096;  // line elements held per work-group
+constexpr int FFT_ELEMS = 2048;  // line elements held per work-group (8 lines of 256: 34 KB of LDS)
 
 struct FftPlan1D {
     int L;
@@ -39,12 +44,43 @@ static bool make_plan(int L, FftPlan1D &p) {
 
 bool fft_length_supported(int n) {
     FftPlan1D p;
-    return n >= 1 && n <= FFT_ELEMS / 4 && make_plan(n, p);
+    return n >= 1 && n <= 1024 && make_plan(n, p);
 }
 
 __device__ inline float2 cmul(float2 a, float2 b) { return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
 
-// small DFT of length R (R in 2, 3, 4, 5, 8): out_m = sum_r a_r w^{r m}, w = e^{sign 2 pi i / R}
+// cos and sin of 2 pi k / R for the small radices
+template <int R>
+struct Roots;
+template <>
+struct Roots<2> {
+    static constexpr float c[2] = {1.0f, -1.0f}, s[2] = {0.0f, 0.0f};
+};
+template <>
+struct Roots<3> {
+    static constexpr float c[3] = {1.0f, -0.5f, -0.5f};
+    static constexpr float s[3] = {0.0f, 0.86602540378443865f, -0.86602540378443865f};
+};
+template <>
+struct Roots<4> {
+    static constexpr float c[4] = {1.0f, 0.0f, -1.0f, 0.0f}, s[4] = {0.0f, 1.0f, 0.0f, -1.0f};
+};
+template <>
+struct Roots<5> {
+    static constexpr float c[5] = {1.0f, 0.30901699437494742f, -0.80901699437494742f, -0.80901699437494742f,
+                                   0.30901699437494742f};
+    static constexpr float s[5] = {0.0f, 0.95105651629515357f, 0.58778525229247313f, -0.58778525229247313f,
+                                   -0.95105651629515357f};
+};
+template <>
+struct Roots<8> {
+    static constexpr float c[8] = {1.0f, 0.70710678118654752f, 0.0f, -0.70710678118654752f,
+                                   -1.0f, -0.70710678118654752f, 0.0f, 0.70710678118654752f};
+    static constexpr float s[8] = {0.0f, 0.70710678118654752f, 1.0f, 0.70710678118654752f,
+                                   0.0f, -0.70710678118654752f, -1.0f, -0.70710678118654752f};
+};
+
+// small DFT of length R: out_m = sum_r a_r w^{r m}, w = e^{sign 2 pi i / R}
 template <int R>
 __device__ inline void dft_small(float2 (&a)[R], float sign) {
     float2 o[R];
@@ -54,10 +90,8 @@ __device__ inline void dft_small(float2 (&a)[R], float sign) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
             const int idx = (r * m) % R;
-            float sn, cs;
-            sincospif(2.0f * (float)idx / (float)R, &sn, &cs);
-            float2 w = make_float2(cs, sign * sn);
-            float2 t = cmul(a[r], w);
+            const float2 w = make_float2(Roots<R>::c[idx], sign * Roots<R>::s[idx]);
+            const float2 t = cmul(a[r], w);
             acc.x += t.x;
             acc.y += t.y;
         }
@@ -67,28 +101,28 @@ __device__ inline void dft_small(float2 (&a)[R], float sign) {
     for (int m = 0; m < R; ++m) a[m] = o[m];
 }
 
+// one Stockham stage over `nlines` lines of stride Lp; tw[m] = e^{sign 2 pi i m / L}
+// nbs, nss: log2 of L / R and of Ns when L is a power of two (shifts replace the
+// integer divisions), else -1
 template <int R>
-__device__ inline void stage(const float2 *__restrict__ src, float2 *__restrict__ dst, int L, int nlines, int Ns,
-                             float sign) {
+__device__ inline void stage(const float2 *__restrict__ src, float2 *__restrict__ dst, const float2 *__restrict__ tw,
+                             int L, int Lp, int nlines, int Ns, float sign, int nbs, int nss) {
     const int nb = L / R;
+    const int tstep = L / (Ns * R);  // twiddle index step: e^{2 pi i r k / (Ns R)} = tw[r k tstep]
     for (int bf = threadIdx.x; bf < nlines * nb; bf += FFT_THREADS) {
-        const int line = bf / nb, j = bf - line * nb;
-        const int k = j % Ns;
-        const float2 *s = src + line * L;
-        float2 *d = dst + line * L;
+        const int line = nbs >= 0 ? bf >> nbs : bf / nb, j = bf - line * nb;
+        const int k = nss >= 0 ? (j & (Ns - 1)) : j % Ns;
+        const float2 *s = src + line * Lp;
+        float2 *d = dst + line * Lp;
         float2 a[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) a[r] = s[j + r * nb];
         if (Ns > 1) {
 #pragma unroll
-            for (int r = 1; r < R; ++r) {
-                float sn, cs;
-                sincospif(2.0f * (float)(r * k) / (float)(Ns * R), &sn, &cs);
-                a[r] = cmul(a[r], make_float2(cs, sign * sn));
-            }
+            for (int r = 1; r < R; ++r) a[r] = cmul(a[r], tw[r * k * tstep]);
         }
         dft_small<R>(a, sign);
-        const int base = (j / Ns) * Ns * R + k;
+        const int base = (j - k) * R + k;  // (j / Ns) Ns R + k
 #pragma unroll
         for (int r = 0; r < R; ++r) d[base + r * Ns] = a[r];
     }
@@ -97,11 +131,18 @@ __device__ inline void stage(const float2 *__restrict__ src, float2 *__restrict_
 // Lines of length L along an axis with element stride S.  Line (o, in): element p at
 // o * L * S + p * S + in.  S > 1: a block holds B consecutive `in` of one `o`;
 // S == 1: B consecutive `o`.
+// ls, bs: log2 L and log2 B when they are powers of two, else -1
 __global__ __launch_bounds__(FFT_THREADS) void k_fft_axis(float2 *__restrict__ data, FftPlan1D plan, int S,
-                                                           int nouter, int B, float sign) {
+                                                           int nouter, int B, float sign, int ls, int bs) {
     extern __shared__ float2 lds[];
-    const int L = plan.L;
-    float2 *buf0 = lds, *buf1 = lds + L * B;
+    const int L = plan.L, Lp = L + 1;
+    float2 *tw = lds;
+    float2 *buf0 = lds + L, *buf1 = buf0 + Lp * B;
+    for (int m = threadIdx.x; m < L; m += FFT_THREADS) {
+        float sn, cs;
+        sincospif(2.0f * (float)m / (float)L, &sn, &cs);
+        tw[m] = make_float2(cs, sign * sn);
+    }
     int o0, in0, nl;
     if (S > 1) {
         const int groups = (S + B - 1) / B;
@@ -113,34 +154,37 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_axis(float2 *__restrict__ d
         in0 = 0;
         nl = min(B, nouter - o0);
     }
-    // load
+    // load (consecutive lanes read consecutive addresses in both cases)
     for (int idx = threadIdx.x; idx < L * B; idx += FFT_THREADS) {
         int p, cl;
         if (S > 1) {
-            p = idx / B;
+            p = bs >= 0 ? idx >> bs : idx / B;
             cl = idx - p * B;
         } else {
-            cl = idx / L;
+            cl = ls >= 0 ? idx >> ls : idx / L;
             p = idx - cl * L;
         }
         if (cl < nl) {
-            size_t g = S > 1 ? ((size_t)o0 * L * S + (size_t)p * S + in0 + cl) : ((size_t)(o0 + cl) * L + p);
-            buf0[cl * L + p] = data[g];
+            const size_t g = S > 1 ? ((size_t)o0 * L * S + (size_t)p * S + in0 + cl) : ((size_t)(o0 + cl) * L + p);
+            buf0[cl * Lp + p] = data[g];
         }
     }
     __syncthreads();
     float2 *src = buf0, *dst = buf1;
-    int Ns = 1;
+    int Ns = 1, nsl = 0;
     for (int st = 0; st < plan.nst; ++st) {
         const int R = plan.radix[st];
+        const int rl = R == 8 ? 3 : (R == 4 ? 2 : 1);  // log2 R (used only when L is a power of two)
+        const int nbs = ls >= 0 ? ls - rl : -1, nss = ls >= 0 ? nsl : -1;
         switch (R) {
-            case 8: stage<8>(src, dst, L, nl, Ns, sign); break;
-            case 4: stage<4>(src, dst, L, nl, Ns, sign); break;
-            case 2: stage<2>(src, dst, L, nl, Ns, sign); break;
-            case 5: stage<5>(src, dst, L, nl, Ns, sign); break;
-            default: stage<3>(src, dst, L, nl, Ns, sign); break;
+            case 8: stage<8>(src, dst, tw, L, Lp, nl, Ns, sign, nbs, nss); break;
+            case 4: stage<4>(src, dst, tw, L, Lp, nl, Ns, sign, nbs, nss); break;
+            case 2: stage<2>(src, dst, tw, L, Lp, nl, Ns, sign, nbs, nss); break;
+            case 5: stage<5>(src, dst, tw, L, Lp, nl, Ns, sign, -1, -1); break;
+            default: stage<3>(src, dst, tw, L, Lp, nl, Ns, sign, -1, -1); break;
         }
         Ns *= R;
+        nsl += rl;
         __syncthreads();
         float2 *t = src;
         src = dst;
@@ -150,20 +194,21 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_axis(float2 *__restrict__ d
     for (int idx = threadIdx.x; idx < L * B; idx += FFT_THREADS) {
         int p, cl;
         if (S > 1) {
-            p = idx / B;
+            p = bs >= 0 ? idx >> bs : idx / B;
             cl = idx - p * B;
         } else {
-            cl = idx / L;
+            cl = ls >= 0 ? idx >> ls : idx / L;
             p = idx - cl * L;
         }
         if (cl < nl) {
-            size_t g = S > 1 ? ((size_t)o0 * L * S + (size_t)p * S + in0 + cl) : ((size_t)(o0 + cl) * L + p);
-            data[g] = src[cl * L + p];
+            const size_t g = S > 1 ? ((size_t)o0 * L * S + (size_t)p * S + in0 + cl) : ((size_t)(o0 + cl) * L + p);
+            data[g] = src[cl * Lp + p];
         }
     }
 }
 
 hipError_t fft3d(float2 *data, float2 * /*tmp*/, const int *mesh, int sign, hipStream_t s) {
+    static size_t lds_allowed = 65536;  // the default limit of dynamic LDS per work-group
     const int64_t M = (int64_t)mesh[0] * mesh[1] * mesh[2];
     for (int axis = 2; axis >= 0; --axis) {
         FftPlan1D plan;
@@ -180,9 +225,18 @@ hipError_t fft3d(float2 *data, float2 * /*tmp*/, const int *mesh, int sign, hipS
         } else {
             blocks = (nouter + B - 1) / B;
         }
-        const size_t lds = sizeof(float2) * 2 * (size_t)L * B;
+        // twiddle table plus two buffers of B lines of L + 1 elements (at most 139 KB)
+        const size_t lds = sizeof(float2) * ((size_t)L + 2 * (size_t)(L + 1) * B);
+        if (lds > lds_allowed) {
+            hipError_t e = hipFuncSetAttribute((const void *)k_fft_axis, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)lds);
+            if (e != hipSuccess) return e;
+            lds_allowed = lds;
+        }
+        const int ls = (L & (L - 1)) == 0 ? __builtin_ctz(L) : -1;
+        const int bs = (B & (B - 1)) == 0 ? __builtin_ctz(B) : -1;
         hipLaunchKernelGGL(k_fft_axis, dim3(blocks), dim3(FFT_THREADS), lds, s, data, plan, S, nouter, B,
-                           (float)sign);
+                           (float)sign, ls, bs);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

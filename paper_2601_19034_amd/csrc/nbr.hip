@@ -139,7 +139,7 @@ __global__ __launch_bounds__(256) void k_lists(int N, const float4 *__restrict__
                                                int *__restrict__ cnt, double rs2, int cap_sub,
                                                uint32_t *__restrict__ sub, int *__restrict__ cnt_sub,
                                                int32_t *__restrict__ flags) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = xcd_block() * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const float4 pi = xyzt[i];
     int ci[3];

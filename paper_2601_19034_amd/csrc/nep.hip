@@ -39,7 +39,7 @@ __global__ __launch_bounds__(256) void k_descriptors(int N, const float4 *__rest
     for (int k = threadIdx.x; k < T * T * NR * NB; k += blockDim.x) cR[k] = theta[off_cR + k];
     for (int k = threadIdx.x; k < T * T * NA * NB; k += blockDim.x) cA[k] = theta[off_cA + k];
     __syncthreads();
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = xcd_block() * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const float4 pi = xyzt[i];
     const int ti = species_of(pi);
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(256) void k_radial_tables(int N, const int *__restr
     __shared__ float cR[T * T * NR * NB];
     for (int k = threadIdx.x; k < T * T * NR * NB; k += blockDim.x) cR[k] = theta[off_cR + k];
     __syncthreads();
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = xcd_block() * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const float s = theta[off_s];
     const float chi = (float)((double)phi[i] - scalars[S_PHIBAR]);
@@ -193,7 +193,7 @@ __global__ __launch_bounds__(256) void k_radial_forces(int N, const float4 *__re
                                                        const float *__restrict__ hT, float *__restrict__ Fnep,
                                                        float *__restrict__ Znep, double *__restrict__ partials) {
     constexpr int NBP = Pad4<NB>::v;
-    const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int gtid = xcd_block() * blockDim.x + threadIdx.x;
     const int i = gtid / RF_LANES, sub = gtid % RF_LANES;
     float acc[15];  // F (3), Z (xx yy zz xy xz yz), W (same order)
 #pragma unroll
@@ -292,7 +292,7 @@ __global__ __launch_bounds__(256) void k_angular_forces(
     __shared__ float cA[T * T * NA * NB];
     for (int k = threadIdx.x; k < T * T * NA * NB; k += blockDim.x) cA[k] = theta[off_cA + k];
     __syncthreads();
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = xcd_block() * blockDim.x + threadIdx.x;
     double w[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (i < N) {
         const float4 pi = xyzt[i];
@@ -422,7 +422,7 @@ __global__ __launch_bounds__(256) void k_assemble(
     int64_t off_s, const int *__restrict__ perm, const float *__restrict__ pos, float *__restrict__ forces,
     float *__restrict__ bec, float *__restrict__ charges, float *__restrict__ charges_naked,
     double *__restrict__ partials) {
-    const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int gtid = xcd_block() * blockDim.x + threadIdx.x;
     const int i = gtid / AS_LANES, sub = gtid % AS_LANES;
     float acc[12];  // F (3), Z (9)
 #pragma unroll

@@ -178,7 +178,7 @@ __global__ __launch_bounds__(256) void k_spread_tiles(const float4 *__restrict__
 __global__ __launch_bounds__(256) void k_tile_gather(MeshGeom g, int nc0, int nc1, int nc2, TileGeom tg,
                                                      const float *__restrict__ tiles, float2 *__restrict__ out) {
     const int64_t M = (int64_t)g.n[0] * g.n[1] * g.n[2];
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t idx = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
     if (idx >= M) return;
     const int nc[3] = {nc0, nc1, nc2};
     const int m[3] = {(int)(idx / ((int64_t)g.n[1] * g.n[2])), (int)((idx / g.n[2]) % g.n[1]), (int)(idx % g.n[2])};
@@ -288,7 +288,7 @@ __global__ __launch_bounds__(256) void k_gather(int N, const float4 *__restrict_
                                                 const float *__restrict__ qraw, const double *__restrict__ scalars,
                                                 const float2 *__restrict__ A, const float2 *__restrict__ Bm,
                                                 float *__restrict__ phi, float *__restrict__ Fst) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = xcd_block() * blockDim.x + threadIdx.x;
     if (i >= N) return;
     int m0[3];
     float w[3][5];
