@@ -42,6 +42,26 @@ __device__ inline floatx4 mfma_split(const float (&a)[4], const float (&b)[4], f
     return acc;
 }
 
+// x = hi + lo with hi, lo in BF16 (lo = 0 when only hi is used)
+__device__ inline void split_bf16(const float (&x)[4], bf16x4 &hi, bf16x4 &lo) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        hi[e] = to_bf16(x[e]);
+        lo[e] = to_bf16(x[e] - __uint_as_float((uint32_t)(unsigned short)hi[e] << 16));
+    }
+}
+
+// products of operands already split into BF16 parts: hi*hi (+ hi*lo + lo*hi)
+template <int NSPLIT>
+__device__ inline floatx4 mfma_parts(bf16x4 ah, bf16x4 al, bf16x4 bh, bf16x4 bl, floatx4 acc) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
+    if (NSPLIT == 3) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
 // the same with the split chosen at run time (1 or 3 products)
 __device__ inline floatx4 mfma_split_rt(const float (&a)[4], const float (&b)[4], floatx4 acc, int nsplit) {
     return nsplit == 3 ? mfma_split<3>(a, b, acc) : mfma_split<1>(a, b, acc);

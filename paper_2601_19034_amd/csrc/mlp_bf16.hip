@@ -2,14 +2,22 @@
 //   Z = D W0_t^T, h = tanh(Z - b0_t), U = w1E_t . h - b1E, q = w1q_t . h - b1q_t,
 //   dU/dD = [(1 - h^2) w1E_t] W0_t, dq/dD = [(1 - h^2) w1q_t] W0_t.
 // One wave computes a tile of 16 consecutive (spatially sorted) atoms with
-// v_mfma_f32_16x16x16_bf16 (BF16 inputs, FP32 accumulation).  Atoms of different
-// species share a tile: for every species t the A-operand rows of other species are
-// zeroed, so sum_t A_t W0_t gives each row its own species' product.  tanh and the
-// output layers stay in FP32.
+// v_mfma_f32_16x16x16_bf16 (BF16 inputs, FP32 accumulation), in transposed form:
+//   Z^T = sum_t W0_t D_t^T   (columns = atoms; atoms of other species zeroed in B),
+//   gU^T = sum_t W0_t^T G_t^T with G = (1 - h^2) w1E (and likewise for q).
+// After the first product the lane that holds column `row` holds the hidden units
+// 16 jt + 4 lg + e of that atom, which are exactly the B-operand elements of G^T the
+// second product needs, so no activation goes through LDS.  The weights of all
+// species are split into BF16 parts once per work-group and kept in LDS in the two
+// layouts the products read (rows of W0 and rows of W0^T, four consecutive elements
+// per lane); every activation operand is split once and reused across the tiles of
+// the other dimension.  tanh and the output layers stay in FP32.
 #include "mfma.h"
 #include "plan.h"
 
 namespace qnep {
+
+constexpr int MLPB_BLOCKS_MAX = 2048;
 
 template <int KD, int KH, int NSPLIT>
 __global__ __launch_bounds__(256) void k_mlp_bf16(int N, int T, int H, int ndes, const int *__restrict__ ts,
@@ -18,143 +26,136 @@ __global__ __launch_bounds__(256) void k_mlp_bf16(int N, int T, int H, int ndes,
                                                   float *__restrict__ U, float *__restrict__ qraw,
                                                   float *__restrict__ gU, float *__restrict__ gq,
                                                   double *__restrict__ partials) {
-    __shared__ float sW0[KH][KD];  // W0_t[j][k] of the species being processed, zero padded
+    constexpr int RF = KD + 4, RB = KH + 4;  // padded row lengths (elements)
+    extern __shared__ short wlds[];
+    // [t][j][k] rows of W0 (forward) and [t][v][j] rows of W0^T (backward), hi then lo parts
+    short *fh = wlds, *bh = fh + MAX_T * KH * RF;
+    short *fl = bh + MAX_T * KD * RB, *bl = fl + MAX_T * KH * RF;
     __shared__ float sb0[MAX_T][KH], sw1E[MAX_T][KH], sw1q[MAX_T][KH], sb1q[MAX_T];
-    __shared__ float sG[4][2][16][KH];  // per wave: (1-h^2) w1E and (1-h^2) w1q, rows = atoms
+    for (int idx = threadIdx.x; idx < T * KH * KD; idx += blockDim.x) {
+        const int t = idx / (KH * KD), r = idx - t * KH * KD, j = r / KD, k = r - j * KD;
+        const float w = (j < H && k < ndes) ? theta[off_nn + t * per_species + (int64_t)j * ndes + k] : 0.0f;
+        const short h = to_bf16(w);
+        fh[(t * KH + j) * RF + k] = h;
+        bh[(t * KD + k) * RB + j] = h;
+        if (NSPLIT == 3) {
+            const short l = to_bf16(w - __uint_as_float((uint32_t)(unsigned short)h << 16));
+            fl[(t * KH + j) * RF + k] = l;
+            bl[(t * KD + k) * RB + j] = l;
+        }
+    }
     for (int idx = threadIdx.x; idx < T * KH; idx += blockDim.x) {
-        int t = idx / KH, j = idx % KH;
+        const int t = idx / KH, j = idx % KH;
         const float *base = theta + off_nn + t * per_species + (int64_t)H * ndes;
         sb0[t][j] = j < H ? base[j] : 0.0f;
         sw1E[t][j] = j < H ? base[H + j] : 0.0f;
         sw1q[t][j] = j < H ? base[2 * H + j] : 0.0f;
         if (j == 0) sb1q[t] = base[3 * H];
     }
+    __syncthreads();
+    const float b1E = theta[off_b1E];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int base = (blockIdx.x * 4 + wave) * 16;
     const int li = lane & 15, lg = lane >> 4;
-    const int arow = base + li;  // this lane's A-operand row
-    const int at = arow < N ? ts[arow] : -1;
-    float dv[KD / 16][4];
-#pragma unroll
-    for (int kk = 0; kk < KD / 16; ++kk)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            int k = 16 * kk + 4 * lg + e;
-            dv[kk][e] = (arow < N && k < ndes) ? D[(size_t)k * N + arow] : 0.0f;
-        }
-    // ---- forward: Z = sum_t A_t W0_t^T
-    floatx4 acc[KH / 16];
-#pragma unroll
-    for (int nt = 0; nt < KH / 16; ++nt) acc[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int t = 0; t < T; ++t) {
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < KH * KD; idx += blockDim.x) {
-            int j = idx / KD, k = idx % KD;
-            sW0[j][k] = (j < H && k < ndes) ? theta[off_nn + t * per_species + (int64_t)j * ndes + k] : 0.0f;
-        }
-        __syncthreads();
+    const int ntiles = (N + 15) / 16;
+    const bf16x4 zero4 = {0, 0, 0, 0};
+    double red[2] = {0.0, 0.0};
+    for (int tile = blockIdx.x * 4 + wave; tile < ntiles; tile += gridDim.x * 4) {
+        const int row = 16 * tile + li;  // this lane's atom (column of the transposed products)
+        const bool rok = row < N;
+        const int tr = rok ? ts[row] : -1;
+        bf16x4 dh[KD / 16], dl[KD / 16];
 #pragma unroll
         for (int kk = 0; kk < KD / 16; ++kk) {
-            float a[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) a[e] = (at == t) ? dv[kk][e] : 0.0f;
-#pragma unroll
-            for (int nt = 0; nt < KH / 16; ++nt) {
-                float b[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) b[e] = sW0[16 * nt + li][16 * kk + 4 * lg + e];
-                acc[nt] = mfma_split<NSPLIT>(a, b, acc[nt]);
-            }
-        }
-    }
-    // ---- activation and output layers (FP32); D layout: row 4 lg + e, column 16 nt + li
-    float up[4] = {0.f, 0.f, 0.f, 0.f}, qp[4] = {0.f, 0.f, 0.f, 0.f};
-    int rt[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        int row = base + 4 * lg + e;
-        rt[e] = row < N ? ts[row] : 0;
-    }
-#pragma unroll
-    for (int nt = 0; nt < KH / 16; ++nt) {
-        const int j = 16 * nt + li;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int t = rt[e];
-            float h = tanhf(acc[nt][e] - sb0[t][j]);
-            float wE = sw1E[t][j], wQ = sw1q[t][j];  // zero for padded j
-            up[e] = fmaf(wE, h, up[e]);
-            qp[e] = fmaf(wQ, h, qp[e]);
-            float dh = 1.0f - h * h;
-            sG[wave][0][4 * lg + e][j] = wE * dh;
-            sG[wave][1][4 * lg + e][j] = wQ * dh;
-        }
-    }
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-#pragma unroll
-        for (int o = 8; o > 0; o >>= 1) {
-            up[e] += __shfl_xor(up[e], o, 64);
-            qp[e] += __shfl_xor(qp[e], o, 64);
-        }
-    double red[2] = {0.0, 0.0};
-    if (li == 0) {
-        const float b1E = theta[off_b1E];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            int row = base + 4 * lg + e;
-            if (row < N) {
-                float u = up[e] - b1E, q = qp[e] - sb1q[rt[e]];
-                U[row] = u;
-                qraw[row] = q;
-                red[0] += u;
-                red[1] += q;
-            }
-        }
-    }
-    // ---- backward: gU = sum_t G_t W0_t (rows of other species zeroed)
-    floatx4 aE[KD / 16], aQ[KD / 16];
-#pragma unroll
-    for (int vt = 0; vt < KD / 16; ++vt) {
-        aE[vt] = floatx4{0.f, 0.f, 0.f, 0.f};
-        aQ[vt] = floatx4{0.f, 0.f, 0.f, 0.f};
-    }
-    for (int t = 0; t < T; ++t) {
-        __syncthreads();  // also orders the sG writes above before their reads
-        for (int idx = threadIdx.x; idx < KH * KD; idx += blockDim.x) {
-            int j = idx / KD, k = idx % KD;
-            sW0[j][k] = (j < H && k < ndes) ? theta[off_nn + t * per_species + (int64_t)j * ndes + k] : 0.0f;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int jj = 0; jj < KH / 16; ++jj) {
-            float ge[4], gqv[4];
+            float dv[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                int j = 16 * jj + 4 * lg + e;
-                ge[e] = (at == t) ? sG[wave][0][li][j] : 0.0f;
-                gqv[e] = (at == t) ? sG[wave][1][li][j] : 0.0f;
+                const int k = 16 * kk + 4 * lg + e;
+                dv[e] = (rok && k < ndes) ? D[(size_t)k * N + row] : 0.0f;
             }
+            split_bf16(dv, dh[kk], dl[kk]);
+        }
+        // ---- forward: Z^T (lane holds Z[row][16 jt + 4 lg + e])
+        floatx4 acc[KH / 16];
 #pragma unroll
-            for (int vt = 0; vt < KD / 16; ++vt) {
-                float b[4];
+        for (int jt = 0; jt < KH / 16; ++jt) acc[jt] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < T; ++t) {
+            if (__ballot(tr == t) == 0) continue;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) b[e] = sW0[16 * jj + 4 * lg + e][16 * vt + li];
-                aE[vt] = mfma_split<NSPLIT>(ge, b, aE[vt]);
-                aQ[vt] = mfma_split<NSPLIT>(gqv, b, aQ[vt]);
+            for (int kk = 0; kk < KD / 16; ++kk) {
+                const bf16x4 b_h = tr == t ? dh[kk] : zero4, b_l = tr == t ? dl[kk] : zero4;
+#pragma unroll
+                for (int jt = 0; jt < KH / 16; ++jt) {
+                    const int o = (t * KH + 16 * jt + li) * RF + 16 * kk + 4 * lg;
+                    const bf16x4 a_h = *reinterpret_cast<const bf16x4 *>(fh + o);
+                    const bf16x4 a_l = NSPLIT == 3 ? *reinterpret_cast<const bf16x4 *>(fl + o) : zero4;
+                    acc[jt] = mfma_parts<NSPLIT>(a_h, a_l, b_h, b_l, acc[jt]);
+                }
             }
         }
-    }
+        // ---- activation and output layers (FP32)
+        const int tl = tr < 0 ? 0 : tr;
+        float up = 0.f, qp = 0.f;
+        bf16x4 geh[KH / 16], gel[KH / 16], gqh[KH / 16], gql[KH / 16];
 #pragma unroll
-    for (int vt = 0; vt < KD / 16; ++vt) {
-        const int v = 16 * vt + li;
+        for (int jt = 0; jt < KH / 16; ++jt) {
+            float ge[4], gqq[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            int row = base + 4 * lg + e;
-            if (row < N && v < ndes) {
-                gU[(size_t)v * N + row] = aE[vt][e];
-                gq[(size_t)v * N + row] = aQ[vt][e];
+            for (int e = 0; e < 4; ++e) {
+                const int j = 16 * jt + 4 * lg + e;
+                const float hh = tanhf(acc[jt][e] - sb0[tl][j]);
+                const float wE = sw1E[tl][j], wQ = sw1q[tl][j];  // zero for padded j
+                up = fmaf(wE, hh, up);
+                qp = fmaf(wQ, hh, qp);
+                const float dd = 1.0f - hh * hh;
+                ge[e] = tr >= 0 ? dd * wE : 0.0f;
+                gqq[e] = tr >= 0 ? dd * wQ : 0.0f;
             }
+            split_bf16(ge, geh[jt], gel[jt]);
+            split_bf16(gqq, gqh[jt], gql[jt]);
+        }
+        up += __shfl_xor(up, 16, 64);
+        up += __shfl_xor(up, 32, 64);
+        qp += __shfl_xor(qp, 16, 64);
+        qp += __shfl_xor(qp, 32, 64);
+        if (rok && lg == 0) {
+            const float u = up - b1E, q = qp - sb1q[tl];
+            U[row] = u;
+            qraw[row] = q;
+            red[0] += u;
+            red[1] += q;
+        }
+        // ---- backward: gU^T = sum_t W0_t^T G_t^T (lane holds gU[row][16 vt + 4 lg + e])
+        floatx4 gA[KD / 16], gB[KD / 16];
+#pragma unroll
+        for (int vt = 0; vt < KD / 16; ++vt) gA[vt] = gB[vt] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < T; ++t) {
+            if (__ballot(tr == t) == 0) continue;
+            const bool mine = tr == t;
+#pragma unroll
+            for (int jj = 0; jj < KH / 16; ++jj) {
+                const bf16x4 beh = mine ? geh[jj] : zero4, bel = mine ? gel[jj] : zero4;
+                const bf16x4 bqh = mine ? gqh[jj] : zero4, bql = mine ? gql[jj] : zero4;
+#pragma unroll
+                for (int vt = 0; vt < KD / 16; ++vt) {
+                    const int o = (t * KD + 16 * vt + li) * RB + 16 * jj + 4 * lg;
+                    const bf16x4 a_h = *reinterpret_cast<const bf16x4 *>(bh + o);
+                    const bf16x4 a_l = NSPLIT == 3 ? *reinterpret_cast<const bf16x4 *>(bl + o) : zero4;
+                    gA[vt] = mfma_parts<NSPLIT>(a_h, a_l, beh, bel, gA[vt]);
+                    gB[vt] = mfma_parts<NSPLIT>(a_h, a_l, bqh, bql, gB[vt]);
+                }
+            }
+        }
+        if (rok) {
+#pragma unroll
+            for (int vt = 0; vt < KD / 16; ++vt)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int v = 16 * vt + 4 * lg + e;
+                    if (v < ndes) {
+                        gU[(size_t)v * N + row] = gA[vt][e];
+                        gq[(size_t)v * N + row] = gB[vt][e];
+                    }
+                }
         }
     }
     block_partials<2>(red, partials);
@@ -167,17 +168,29 @@ bool mlp_bf16_supported(int ndes, int H) {
     return (kd == 32 || kd == 48) && (kh == 32 || kh == 48 || kh == 64);
 }
 
+template <int KD, int KH, int NSPLIT>
+static hipError_t run_bf16_split(const Plan &p, int G) {
+    // BF16 weights: forward and backward layouts, hi (and lo) parts, MAX_T species
+    const size_t lds = sizeof(short) * (size_t)MAX_T * (KH * (KD + 4) + KD * (KH + 4)) * (NSPLIT == 3 ? 2 : 1);
+    static bool raised = false;
+    if (!raised && lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_mlp_bf16<KD, KH, NSPLIT>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        raised = true;
+    }
+    hipLaunchKernelGGL((k_mlp_bf16<KD, KH, NSPLIT>), dim3(G), dim3(256), lds, p.stream, p.N, p.T, p.H, p.ndes, p.ts,
+                       p.D, p.theta, p.off_nn, p.per_species, p.off_b1E, p.U, p.qraw, p.gU, p.gq, p.partials);
+    return hipGetLastError();
+}
+
 template <int KD, int KH>
 static hipError_t run_bf16(const Plan &p) {
     const int tiles = (p.N + 15) / 16;
-    const int G = (tiles + 3) / 4;
-    if (p.mlp_prec == QNEP_MLP_BF16X3)
-        hipLaunchKernelGGL((k_mlp_bf16<KD, KH, 3>), dim3(G), dim3(256), 0, p.stream, p.N, p.T, p.H, p.ndes, p.ts,
-                           p.D, p.theta, p.off_nn, p.per_species, p.off_b1E, p.U, p.qraw, p.gU, p.gq, p.partials);
-    else
-        hipLaunchKernelGGL((k_mlp_bf16<KD, KH, 1>), dim3(G), dim3(256), 0, p.stream, p.N, p.T, p.H, p.ndes, p.ts, p.D,
-                       p.theta, p.off_nn, p.per_species, p.off_b1E, p.U, p.qraw, p.gU, p.gq, p.partials);
-    hipError_t e = hipGetLastError();
+    int G = (tiles + 3) / 4;
+    if (G > MLPB_BLOCKS_MAX) G = MLPB_BLOCKS_MAX;
+    if (G < 1) G = 1;
+    hipError_t e = p.mlp_prec == QNEP_MLP_BF16X3 ? run_bf16_split<KD, KH, 3>(p, G) : run_bf16_split<KD, KH, 1>(p, G);
     if (e != hipSuccess) return e;
     return reduce_partials(p, G, 2, S_UNEP, false);
 }
