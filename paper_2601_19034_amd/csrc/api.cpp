@@ -303,6 +303,7 @@ qnep_status make_plan(const Model &m, const qnep_es_params *es, const qnep_syste
     p.scan_tmp = c.take<int>((p.ncell + 1023) / 1024 + 1);
     p.perm = c.take<int>(N);
     p.xyzt = c.take<float4>(N);
+    p.xyzq = c.take<float4>(N);
     p.ts = c.take<int>(N);
     p.listR = c.take<uint32_t>((size_t)p.capR * N);
     p.cntR = c.take<int>(N);

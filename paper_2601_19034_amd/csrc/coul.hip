@@ -18,7 +18,16 @@ namespace qnep {
 // pair virial (each unordered pair is seen from both atoms with weight 1/2).
 constexpr int RS_LANES = 16;
 
-__global__ __launch_bounds__(256) void k_real_space(int N, const float4 *__restrict__ xyzt, Cell c, int nc0,
+// positions with the corrected charge q' in w: one 16-byte load per candidate
+__global__ void k_pack_charges(int N, const float4 *__restrict__ xyzt, const float *__restrict__ qraw,
+                               const double *__restrict__ scalars, float4 *__restrict__ xyzq) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const float4 p = xyzt[i];
+    xyzq[i] = make_float4(p.x, p.y, p.z, qraw[i] + (float)scalars[S_DELTA]);
+}
+
+__global__ __launch_bounds__(256) void k_real_space(int N, const float4 *__restrict__ xyzq, Cell c, int nc0,
                                                     int nc1, int nc2, int m0, int m1, int m2,
                                                     const int *__restrict__ start, double rc2,
                                                     const float *__restrict__ qraw,
@@ -32,7 +41,7 @@ __global__ __launch_bounds__(256) void k_real_space(int N, const float4 *__restr
     for (int k = 0; k < 10; ++k) acc[k] = 0.f;
     const float delta = (float)scalars[S_DELTA];
     if (i < N) {
-        const float4 pi = xyzt[i];
+        const float4 pi = xyzq[i];
         int ci[3];
         bin_of(pi, c, nc0, nc1, nc2, ci);
         const float rc2f = (float)rc2;
@@ -54,7 +63,7 @@ __global__ __launch_bounds__(256) void k_real_space(int N, const float4 *__restr
             const int jb0 = start[rowbase + za], je0 = start[rowbase + zb + 1];
             // the four lanes of a row take every fourth atom of it
             for (int j = jb0 + part; j < je0; j += 4) {
-                const float4 pj = xyzt[j];
+                const float4 pj = xyzq[j];
                 // FP32 displacement: exactly antisymmetric in (i, j); across the seam its
                 // error (~ulp of the box length) is negligible for this soft pair term
                 const float3 d = make_float3((pj.x - pi.x) + sh.fx, (pj.y - pi.y) + sh.fy, (pj.z - pi.z) + sh.fz);
@@ -63,7 +72,7 @@ __global__ __launch_bounds__(256) void k_real_space(int N, const float4 *__restr
                 if (self_img && j == i) continue;
                 const float ir = rsqrtf(r2);
                 const float r = r2 * ir;
-                const float qj = qraw[j] + delta;
+                const float qj = pj.w;
                 const float ar = alpha * r;
                 const float ec = erfc_nr(ar);
                 const float ex = __expf(-ar * ar);
@@ -110,8 +119,11 @@ hipError_t launch_real_space(const Plan &p) {
         if (e != hipSuccess) return e;
         return fill_zero(p.Fst, sizeof(float) * 3 * (size_t)p.N, p.stream);
     }
+    hipLaunchKernelGGL(k_pack_charges, dim3((p.N + 255) / 256), dim3(256), 0, p.stream, p.N, p.xyzt, p.qraw,
+                       p.scalars, p.xyzq);
+    stage_mark(p, ST_OTHER, 1);
     const int G = (int)(((int64_t)p.N * RS_LANES + 255) / 256);
-    hipLaunchKernelGGL(k_real_space, dim3(G), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, p.nc[0], p.nc[1],
+    hipLaunchKernelGGL(k_real_space, dim3(G), dim3(256), 0, p.stream, p.N, p.xyzq, p.cell, p.nc[0], p.nc[1],
                        p.nc[2], p.mC[0], p.mC[1], p.mC[2], p.cell_start, p.rc_coul * p.rc_coul, p.qraw, p.scalars,
                        (float)p.alpha, p.phi, p.Fst, p.partials);
     hipError_t e = hipGetLastError();

@@ -60,6 +60,7 @@ struct Plan {
     int *cid = nullptr, *cell_count = nullptr, *cell_start = nullptr, *cell_cursor = nullptr, *perm = nullptr;
     int *scan_tmp = nullptr;
     float4 *xyzt = nullptr;  // sorted positions (x, y, z) with the species in w (as int bits)
+    float4 *xyzq = nullptr;  // sorted positions with the corrected charge q' in w (real-space sum)
     int *ts = nullptr;       // sorted species
     uint32_t *listR = nullptr, *listA = nullptr;
     int *cntR = nullptr, *cntA = nullptr;
