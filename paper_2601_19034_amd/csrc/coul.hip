@@ -11,12 +11,25 @@
 namespace qnep {
 
 // ---------------------------------------------------------------- real space
-// RS_LANES lanes share one sorted atom and split the (2m+1)^3 bins of its stencil
-// (no stored list): candidates are screened in FP32, decided with the FP64
-// displacement rounded to FP32, and contribute phi^r_i, the static pair force
-// F_i = -k_e q'_i sum_j q'_j [erfc(a r)/r + 2a e^{-a^2 r^2}/sqrt(pi)] r_ij / r^2 and the
-// pair virial (each unordered pair is seen from both atoms with weight 1/2).
+// RS_LANES lanes share one sorted atom i.  Its stencil of (2m+1)^3 bins is cut into
+// segments: a row of bins along c is one contiguous range of sorted atoms per
+// periodic image along c.  In an orthorhombic cell each row is first trimmed to the
+// bins that can hold an atom within the cutoff of i (a row whose gap to i in the ab
+// plane exceeds the cutoff is dropped, the others are cut to the chord of the cutoff
+// sphere along c).  The lanes build the segment table of their atom in LDS and then
+// walk the concatenated segments with stride RS_LANES, so that all lanes get the
+// same number of candidates whatever the row lengths.  A candidate is decided by its
+// FP32 displacement; the pair terms are evaluated without a branch (a candidate
+// outside the cutoff, or i itself, gets weight zero) and give phi^r_i, the static
+// pair force F_i = -k_e q'_i sum_j q'_j [erfc(a r)/r + 2a e^{-a^2 r^2}/sqrt(pi)] r_ij / r^2
+// and the pair virial (each unordered pair is seen from both atoms with weight 1/2).
 constexpr int RS_LANES = 16;
+constexpr int RS_APB = 256 / RS_LANES;  // atoms per work-group
+constexpr int RS_SEG = 128;             // segments of one atom held in LDS at a time
+constexpr int RS_RMAX = 3;              // periodic images |n_a| <= RS_RMAX
+constexpr int RS_IMG = (2 * RS_RMAX + 1) * (2 * RS_RMAX + 1) * (2 * RS_RMAX + 1);
+constexpr int RS_LEN_BITS = 23;  // a segment is {first atom, length | image << RS_LEN_BITS}
+constexpr uint32_t RS_LEN_MASK = (1u << RS_LEN_BITS) - 1u;
 
 // positions with the corrected charge q' in w: one 16-byte load per candidate
 __global__ void k_pack_charges(int N, const float4 *__restrict__ xyzt, const float *__restrict__ qraw,
@@ -27,68 +40,147 @@ __global__ void k_pack_charges(int N, const float4 *__restrict__ xyzt, const flo
     xyzq[i] = make_float4(p.x, p.y, p.z, qraw[i] + (float)scalars[S_DELTA]);
 }
 
+// one candidate j (image shift sh) of atom i; w = 0 discards it
+__device__ __forceinline__ void rs_pair(const float4 &pi, const float4 &pj, const float4 &sh, float w, float rc2f,
+                                        float alpha, float c2, float (&acc)[10]) {
+    // FP32 displacement: exactly antisymmetric in (i, j); across the seam its error
+    // (~ulp of the box length) is negligible for this soft pair term
+    const float dx = (pj.x - pi.x) + sh.x, dy = (pj.y - pi.y) + sh.y, dz = (pj.z - pi.z) + sh.z;
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    const bool in = r2 < rc2f && r2 > 0.0f;  // r2 = 0 only for i itself
+    const float qj = in ? pj.w * w : 0.0f;
+    const float rr = in ? r2 : 1.0f;
+    const float ir = __builtin_amdgcn_rsqf(rr);
+    const float ar = alpha * (rr * ir);
+    const float ec = erfc_nr(ar);
+    const float ex = __expf(-ar * ar);
+    const float eir = ec * ir;
+    acc[0] = fmaf(qj, eir, acc[0]);
+    const float B = qj * fmaf(c2, ex, eir) * ir * ir;
+    const float bx = B * dx, by = B * dy, bz = B * dz;
+    acc[1] += bx;
+    acc[2] += by;
+    acc[3] += bz;
+    acc[4] = fmaf(bx, dx, acc[4]);
+    acc[5] = fmaf(by, dy, acc[5]);
+    acc[6] = fmaf(bz, dz, acc[6]);
+    acc[7] = fmaf(bx, dy, acc[7]);
+    acc[8] = fmaf(bx, dz, acc[8]);
+    acc[9] = fmaf(by, dz, acc[9]);
+}
+
 __global__ __launch_bounds__(256) void k_real_space(int N, const float4 *__restrict__ xyzq, Cell c, int nc0,
-                                                    int nc1, int nc2, int m0, int m1, int m2,
+                                                    int nc1, int nc2, int m0, int m1, int m2, int R,
+                                                    int rows_chunk, int trim, double rtrim,
                                                     const int *__restrict__ start, double rc2,
                                                     const float *__restrict__ qraw,
                                                     const double *__restrict__ scalars, float alpha,
                                                     float *__restrict__ phi, float *__restrict__ Fst,
                                                     double *__restrict__ partials) {
-    const int gtid = xcd_block() * blockDim.x + threadIdx.x;
-    const int i = gtid / RS_LANES, sub = gtid % RS_LANES;
+    __shared__ int2 seg[RS_APB][RS_SEG];
+    __shared__ float4 shift_tab[RS_IMG];
+    __shared__ int seg_n[RS_APB];
+    const int nimg = 2 * R + 1;
+    for (int k = threadIdx.x; k < nimg * nimg * nimg; k += blockDim.x) {
+        const ImageShift sh(c, k / (nimg * nimg) - R, (k / nimg) % nimg - R, k % nimg - R);
+        shift_tab[k] = make_float4(sh.fx, sh.fy, sh.fz, 0.0f);
+    }
+    const int a = threadIdx.x / RS_LANES, sub = threadIdx.x % RS_LANES;
+    const int i = xcd_block() * RS_APB + a;
+    const bool live = i < N;
+    const float4 pi = xyzq[live ? i : 0];
+    // bin of i (as in the binning) and its position in bin units
+    const int nc[3] = {nc0, nc1, nc2};
+    double u[3];
+    int ci[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double s = (double)pi.x * c.hinv[d] + (double)pi.y * c.hinv[3 + d] + (double)pi.z * c.hinv[6 + d];
+        u[d] = s * nc[d];
+        const int k = (int)floor(u[d]);
+        ci[d] = k < 0 ? 0 : (k >= nc[d] ? nc[d] - 1 : k);
+    }
+    const double bw0 = c.h[0] / nc0, bw1 = c.h[4] / nc1, bw2 = c.h[8] / nc2;  // orthorhombic bin widths
+    const int w1n = 2 * m1 + 1, nrows = (2 * m0 + 1) * w1n;
+    // bins [zl, zh] along c (unwrapped) of stencil row r that can hold a neighbour of i
+    auto row_z = [&](int r, int &zl, int &zh) -> bool {
+        zl = ci[2] - m2;
+        zh = ci[2] + m2;
+        if (!trim) return true;
+        const double l0 = ci[0] + (r / w1n - m0), l1 = ci[1] + (r % w1n - m1);
+        const double g0 = fmax(0.0, fmax(l0 - u[0], u[0] - l0 - 1.0)) * bw0;
+        const double g1 = fmax(0.0, fmax(l1 - u[1], u[1] - l1 - 1.0)) * bw1;
+        const double h2 = rtrim * rtrim - g0 * g0 - g1 * g1;
+        if (h2 <= 0.0) return false;
+        const double hz = sqrt(h2) / bw2;
+        zl = max(zl, (int)floor(u[2] - hz));
+        zh = min(zh, (int)floor(u[2] + hz));
+        return zl <= zh;
+    };
+    const float rc2f = (float)rc2;
+    const float c2 = 2.0f * alpha * 0.5641895835477563f;  // 2 alpha / sqrt(pi)
     float acc[10];  // phi, B r (3), B r r (xx yy zz xy xz yz)
 #pragma unroll
     for (int k = 0; k < 10; ++k) acc[k] = 0.f;
-    const float delta = (float)scalars[S_DELTA];
-    if (i < N) {
-        const float4 pi = xyzq[i];
-        int ci[3];
-        bin_of(pi, c, nc0, nc1, nc2, ci);
-        const float rc2f = (float)rc2;
-        const float c2 = 2.0f * alpha * 0.5641895835477563f;  // 2 alpha / sqrt(pi)
-        const int w1n = 2 * m1 + 1;
-        const int nrows = (2 * m0 + 1) * w1n;
-        const int zlo = ci[2] - m2, zhi = ci[2] + m2;
-        // a row of bins along c is one contiguous atom range per image along c
-        for (int ri = sub; ri < nrows * 4; ri += RS_LANES) {
-            const int row = ri >> 2, part = ri & 3;
-            const int d0 = row / w1n - m0, d1 = row % w1n - m1;
-            const int u0 = ci[0] + d0, i0 = floor_div(u0, nc0), b0 = u0 - i0 * nc0;
-            const int u1 = ci[1] + d1, i1 = floor_div(u1, nc1), b1 = u1 - i1 * nc1;
+    for (int r0 = 0; r0 < nrows; r0 += rows_chunk) {  // the same trip count in every lane
+        // rows [rb, re) of this chunk belong to this lane; count their segments
+        const int rn = min(rows_chunk, nrows - r0), rpl = (rn + RS_LANES - 1) / RS_LANES;
+        const int rb = r0 + sub * rpl, re = min(rb + rpl, r0 + rn);
+        int cnt = 0;
+        for (int r = rb; live && r < re; ++r) {
+            int zl, zh;
+            if (row_z(r, zl, zh)) cnt += floor_div(zh, nc2) - floor_div(zl, nc2) + 1;
+        }
+        int incl = cnt;  // inclusive scan over the lanes of this atom
+#pragma unroll
+        for (int o = 1; o < RS_LANES; o <<= 1) {
+            const int v = __shfl_up(incl, o, RS_LANES);
+            if (sub >= o) incl += v;
+        }
+        int pos = incl - cnt;
+        __syncthreads();  // the previous chunk's walk is done with the table
+        for (int r = rb; live && r < re; ++r) {
+            int zl, zh;
+            if (!row_z(r, zl, zh)) continue;
+            const int u0 = ci[0] + r / w1n - m0, i0 = floor_div(u0, nc0), b0 = u0 - i0 * nc0;
+            const int u1 = ci[1] + r % w1n - m1, i1 = floor_div(u1, nc1), b1 = u1 - i1 * nc1;
             const int rowbase = (b0 * nc1 + b1) * nc2;
-            for (int i2 = floor_div(zlo, nc2); i2 <= floor_div(zhi, nc2); ++i2) {
-            const int za = max(zlo, i2 * nc2) - i2 * nc2, zb = min(zhi, i2 * nc2 + nc2 - 1) - i2 * nc2;
-            ImageShift sh(c, i0, i1, i2);
-            const bool self_img = (i0 == 0 && i1 == 0 && i2 == 0);
-            const int jb0 = start[rowbase + za], je0 = start[rowbase + zb + 1];
-            // the four lanes of a row take every fourth atom of it
-            for (int j = jb0 + part; j < je0; j += 4) {
-                const float4 pj = xyzq[j];
-                // FP32 displacement: exactly antisymmetric in (i, j); across the seam its
-                // error (~ulp of the box length) is negligible for this soft pair term
-                const float3 d = make_float3((pj.x - pi.x) + sh.fx, (pj.y - pi.y) + sh.fy, (pj.z - pi.z) + sh.fz);
-                const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
-                if (r2 >= rc2f) continue;
-                if (self_img && j == i) continue;
-                const float ir = rsqrtf(r2);
-                const float r = r2 * ir;
-                const float qj = pj.w;
-                const float ar = alpha * r;
-                const float ec = erfc_nr(ar);
-                const float ex = __expf(-ar * ar);
-                acc[0] = fmaf(qj, ec * ir, acc[0]);
-                const float B = qj * (ec * ir + c2 * ex) * ir * ir;
-                acc[1] = fmaf(B, d.x, acc[1]);
-                acc[2] = fmaf(B, d.y, acc[2]);
-                acc[3] = fmaf(B, d.z, acc[3]);
-                acc[4] = fmaf(B, d.x * d.x, acc[4]);
-                acc[5] = fmaf(B, d.y * d.y, acc[5]);
-                acc[6] = fmaf(B, d.z * d.z, acc[6]);
-                acc[7] = fmaf(B, d.x * d.y, acc[7]);
-                acc[8] = fmaf(B, d.x * d.z, acc[8]);
-                acc[9] = fmaf(B, d.y * d.z, acc[9]);
+            for (int i2 = floor_div(zl, nc2); i2 <= floor_div(zh, nc2); ++i2) {
+                const int za = max(zl, i2 * nc2) - i2 * nc2, zb = min(zh, i2 * nc2 + nc2 - 1) - i2 * nc2;
+                const int jb = start[rowbase + za], je = start[rowbase + zb + 1];
+                const uint32_t img = (uint32_t)(((i0 + R) * nimg + (i1 + R)) * nimg + (i2 + R));
+                seg[a][pos++] = make_int2(jb, (int)((uint32_t)(je - jb) | (img << RS_LEN_BITS)));
             }
+        }
+        if (sub == RS_LANES - 1) seg_n[a] = live ? incl : 0;
+        __syncthreads();
+        // walk: this lane takes candidates sub, sub + RS_LANES, ... of the concatenation
+        const int ns = seg_n[a];
+        int s = 0, off = sub;
+        int2 e = ns > 0 ? seg[a][0] : make_int2(0, 0);
+        auto settle = [&]() {  // move (s, off) into the segment that holds offset off
+            while (s < ns) {
+                const int len = (int)((uint32_t)e.y & RS_LEN_MASK);
+                if (off < len) break;
+                off -= len;
+                if (++s < ns) e = seg[a][s];
             }
+        };
+        settle();
+        while (s < ns) {  // two candidates per pass, both loads issued before either is used
+            const int jA = e.x + off, gA = (int)((uint32_t)e.y >> RS_LEN_BITS);
+            off += RS_LANES;
+            settle();
+            const bool hasB = s < ns;
+            const int jB = hasB ? e.x + off : jA, gB = hasB ? (int)((uint32_t)e.y >> RS_LEN_BITS) : gA;
+            if (hasB) {
+                off += RS_LANES;
+                settle();
+            }
+            const float4 pa = xyzq[jA], pb = xyzq[jB];
+            const float4 sa = shift_tab[gA], sb = shift_tab[gB];
+            rs_pair(pi, pa, sa, 1.0f, rc2f, alpha, c2, acc);
+            rs_pair(pi, pb, sb, hasB ? 1.0f : 0.0f, rc2f, alpha, c2, acc);
         }
     }
 #pragma unroll
@@ -96,8 +188,8 @@ __global__ __launch_bounds__(256) void k_real_space(int N, const float4 *__restr
 #pragma unroll
         for (int o = RS_LANES / 2; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o, 64);
     double red[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    if (i < N && sub == 0) {
-        const float qi = qraw[i] + delta;
+    if (live && sub == 0) {
+        const float qi = qraw[i] + (float)scalars[S_DELTA];
         const float ke = (float)KE;
         phi[i] = ke * acc[0];
         Fst[i] = -ke * qi * acc[1];
@@ -122,10 +214,21 @@ hipError_t launch_real_space(const Plan &p) {
     hipLaunchKernelGGL(k_pack_charges, dim3((p.N + 255) / 256), dim3(256), 0, p.stream, p.N, p.xyzt, p.qraw,
                        p.scalars, p.xyzq);
     stage_mark(p, ST_OTHER, 1);
-    const int G = (int)(((int64_t)p.N * RS_LANES + 255) / 256);
+    // periodic images reached by the stencil, and rows per LDS chunk of segments
+    int R = 0;
+    for (int d = 0; d < 3; ++d) R = max(R, (p.mC[d] + p.nc[d] - 1) / p.nc[d]);
+    if (R > RS_RMAX) return hipErrorInvalidValue;
+    const int nz = 2 * p.mC[2] / p.nc[2] + 2;  // most images along c one row spans
+    const int rows_chunk = max(1, RS_SEG / nz);
+    const double *h = p.cell.h;
+    const int trim = (h[1] == 0.0 && h[2] == 0.0 && h[3] == 0.0 && h[5] == 0.0 && h[6] == 0.0 && h[7] == 0.0 &&
+                      h[0] > 0.0 && h[4] > 0.0 && h[8] > 0.0) ? 1 : 0;
+    // trimming radius: the cutoff plus a margin far above the FP32 error of positions
+    const double rtrim = p.rc_coul * (1.0 + 1e-4) + 1e-3;
+    const int G = (p.N + RS_APB - 1) / RS_APB;
     hipLaunchKernelGGL(k_real_space, dim3(G), dim3(256), 0, p.stream, p.N, p.xyzq, p.cell, p.nc[0], p.nc[1],
-                       p.nc[2], p.mC[0], p.mC[1], p.mC[2], p.cell_start, p.rc_coul * p.rc_coul, p.qraw, p.scalars,
-                       (float)p.alpha, p.phi, p.Fst, p.partials);
+                       p.nc[2], p.mC[0], p.mC[1], p.mC[2], R, rows_chunk, trim, rtrim, p.cell_start,
+                       p.rc_coul * p.rc_coul, p.qraw, p.scalars, (float)p.alpha, p.phi, p.Fst, p.partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     stage_mark(p, ST_REAL, 1);
