@@ -168,7 +168,7 @@ qnep_status qnep_check_status(const void *ws, void *stream, int32_t *flags);
    synchronizes the recorded events and returns, for each stage, the total
    milliseconds and the number of kernel launches since the previous read
    (arrays of length QNEP_N_STAGES), then resets the totals. */
-#define QNEP_N_STAGES 20
+#define QNEP_N_STAGES 19
 qnep_status qnep_model_enable_timing(void *model, int32_t enable);
 qnep_status qnep_model_read_timing(void *model, double *ms, int64_t *launches, int32_t *calls);
 const char *qnep_stage_name(int32_t stage);

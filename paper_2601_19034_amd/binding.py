@@ -15,7 +15,7 @@ QNEP_OK = 0
 QNEP_MLP_FP32 = 0
 QNEP_MLP_BF16 = 1
 QNEP_MLP_BF16X3 = 2
-N_STAGES = 20
+N_STAGES = 19
 FLAG_RADIAL_OVERFLOW = 1
 FLAG_ANGULAR_OVERFLOW = 2
 FLAG_COULOMB_OVERFLOW = 4

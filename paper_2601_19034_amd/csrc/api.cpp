@@ -32,7 +32,7 @@ qnep_status fail(qnep_status s, const std::string &msg) {
 const char *const kStageNames[QNEP_N_STAGES] = {
     "sort", "lists", "lists_coulomb", "descriptors", "mlp", "real_space", "ewald_structure_factor",
     "ewald_atoms", "pppm_spread", "fft_forward", "pppm_influence", "fft_inverse", "pppm_gather", "phi_mean",
-    "radial_forces", "angular_forces_energy", "angular_forces_charge", "assemble", "finalize", "other"};
+    "radial_forces", "angular_forces", "assemble", "finalize", "other"};
 
 }  // namespace
 
@@ -268,26 +268,11 @@ qnep_status make_plan(const Model &m, const qnep_es_params *es, const qnep_syste
                 return fail(QNEP_E_UNSUPPORTED, "mesh sizes must be products of 2, 3, 5 up to 1024");
         p.mesh_pts = (int64_t)p.mesh[0] * p.mesh[1] * p.mesh[2];
         red_blocks = std::max<int64_t>(red_blocks, (p.mesh_pts + 255) / 256);
-        // bricks of bins for the atomic-free spread: the first shape whose LDS tile
-        // (B N / nc + 8 points per axis) fits 12288 floats
-        static const int shapes[][3] = {{4, 4, 8}, {4, 4, 6}, {4, 4, 4}, {3, 3, 4}, {2, 2, 4}, {2, 2, 2}, {1, 1, 2},
-                                        {1, 1, 1}};
-        for (const auto &sh : shapes) {
-            int T[3], B[3];
-            int64_t vol = 1;
-            for (int a = 0; a < 3; ++a) {
-                B[a] = std::min(sh[a], p.nc[a]);
-                T[a] = (int)(((int64_t)B[a] * p.mesh[a] + p.nc[a] - 1) / p.nc[a]) + 8;
-                vol *= T[a];
-            }
-            if (vol <= 12288) {
-                for (int a = 0; a < 3; ++a) {
-                    p.tileB[a] = B[a];
-                    p.tileT[a] = T[a];
-                    p.tileNb[a] = (p.nc[a] + B[a] - 1) / B[a];
-                }
-                break;
-            }
+        BrickGeom bg;
+        p.bricks = spread_bricks(p.mesh, p.nc, &bg);
+        for (int a = 0; a < 3; ++a) {
+            p.brickP[a] = p.bricks ? bg.P[a] : 0;
+            p.brickNb[a] = p.bricks ? bg.nb[a] : 0;
         }
     }
     p.partials_cap = red_blocks * 11;
@@ -328,12 +313,7 @@ qnep_status make_plan(const Model &m, const qnep_es_params *es, const qnep_syste
         p.Spart = c.take<float2>((size_t)p.s_chunks * p.nk_cap);
         p.Sk = c.take<float2>(p.nk_cap);
     } else {
-        if (p.tileB[0] > 0) {
-            const size_t nbricks = (size_t)p.tileNb[0] * p.tileNb[1] * p.tileNb[2];
-            p.tiles = c.take<float>(nbricks * p.tileT[0] * p.tileT[1] * p.tileT[2]);
-        } else {
-            p.rho = c.take<float>(p.mesh_pts);
-        }
+        if (!p.bricks) p.rho = c.take<float>(p.mesh_pts);
         p.meshA = c.take<float2>(p.mesh_pts);
         p.meshB = c.take<float2>(p.mesh_pts);
     }

@@ -277,48 +277,80 @@ __global__ __launch_bounds__(256) void k_radial_forces(int N, const float4 *__re
 }
 
 // ---------------------------------------------------------------- angular forces
-// Atilde_nlm = 2 G_nl A_nlm with G the upstream gradient (energy: dU/dD + chi dq/dD;
-// charge: s dq/dD).  Per pair: P_n = sum_lm Atilde_nlm Y_lm, Q_lm = sum_n Atilde_nlm g_n,
+// Atilde_nlm = 2 G_nl A_nlm with G the upstream gradient, for two gradients at once:
+// energy G = dU/dD + chi dq/dD and charge G = s dq/dD.  Per pair and gradient:
+// P_n = sum_lm Atilde_nlm Y_lm, Q_lm = sum_n Atilde_nlm g_n,
 // F_ij = u sum_n g_n' P_n + (I - u u^T) (sum_lm Q_lm grad Y_lm) / r.
-// WHICH = 0: energy pass (pair buffer pairF, own forces and virial);
-// WHICH = 1: charge pass (pair buffer pairA, own Z contribution).
-template <int T, int NR, int NA, int NB, int WHICH>
+// AF_LANES lanes share one atom and split its angular neighbours; the two Atilde
+// tables of the atom are built once in LDS (the lanes split their entries) and read
+// by every lane, so the pair geometry (basis, radial functions, harmonics) is
+// evaluated once for both gradients.  Writes the pair buffers pairF (energy) and
+// pairA (charge), adds the own force and Z contributions, and the virial partials.
+constexpr int AF_LANES = 8;
+constexpr int AF_APB = 256 / AF_LANES;  // atoms per work-group
+
+template <int NA>
+__device__ __forceinline__ float3 angular_pair(const float *__restrict__ At, const float (&g)[NA],
+                                               const float (&dg)[NA], const float (&Y)[LM], float ux, float uy,
+                                               float uz, float ir) {
+    float radial = 0.f;
+    float Qv[LM];
+#pragma unroll
+    for (int q = 0; q < LM; ++q) Qv[q] = 0.f;
+#pragma unroll
+    for (int n = 0; n < NA; ++n) {
+        float Pn = 0.f;
+#pragma unroll
+        for (int q = 0; q < LM; ++q) {
+            const float a = At[n * LM + q];
+            Pn = fmaf(a, Y[q], Pn);
+            Qv[q] = fmaf(a, g[n], Qv[q]);
+        }
+        radial = fmaf(dg[n], Pn, radial);
+    }
+    float gx, gy, gz;
+    harmonics_grad_dot(ux, uy, uz, Qv, gx, gy, gz);
+    const float ug = ux * gx + uy * gy + uz * gz;
+    return make_float3(radial * ux + (gx - ug * ux) * ir, radial * uy + (gy - ug * uy) * ir,
+                       radial * uz + (gz - ug * uz) * ir);
+}
+
+template <int T, int NR, int NA, int NB>
 __global__ __launch_bounds__(256) void k_angular_forces(
     int N, const float4 *__restrict__ xyzt, Cell c, float rcA, const uint32_t *__restrict__ listA,
     const int *__restrict__ cntA, int capA, const float *__restrict__ Amom, const float *__restrict__ gU,
     const float *__restrict__ gq, const float *__restrict__ phi, const double *__restrict__ scalars,
-    const float *__restrict__ theta, int64_t off_cA, int64_t off_s, float4 *__restrict__ pair,
-    float *__restrict__ Fnep, float *__restrict__ Znep, double *__restrict__ partials) {
+    const float *__restrict__ theta, int64_t off_cA, int64_t off_s, float4 *__restrict__ pairF,
+    float4 *__restrict__ pairA, float *__restrict__ Fnep, float *__restrict__ Znep, double *__restrict__ partials) {
+    constexpr int NAL = NA * LM;
     __shared__ float cA[T * T * NA * NB];
+    __shared__ __align__(16) float AtE[AF_APB][NAL];
+    __shared__ __align__(16) float AtQ[AF_APB][NAL];
     for (int k = threadIdx.x; k < T * T * NA * NB; k += blockDim.x) cA[k] = theta[off_cA + k];
-    __syncthreads();
-    const int i = xcd_block() * blockDim.x + threadIdx.x;
-    double w[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    if (i < N) {
-        const float4 pi = xyzt[i];
-        const int ti = species_of(pi);
+    const int a = threadIdx.x / AF_LANES, sub = threadIdx.x % AF_LANES;
+    const int i = xcd_block() * AF_APB + a;
+    const bool live = i < N;
+    if (live) {
         const float s = theta[off_s];
         const float chi = (float)((double)phi[i] - scalars[S_PHIBAR]);
-        float At[NA][LM];
-#pragma unroll
-        for (int n = 0; n < NA; ++n) {
-            float G[4];
-#pragma unroll
-            for (int l = 0; l < 4; ++l) {
-                size_t row = (size_t)(NR + l * NA + n) * N + i;
-                float b = gq[row];
-                G[l] = 2.0f * (WHICH == 0 ? fmaf(chi, b, gU[row]) : s * b);
-            }
-#pragma unroll
-            for (int q = 0; q < LM; ++q) {
-                const int l = q < 3 ? 0 : (q < 8 ? 1 : (q < 15 ? 2 : 3));
-                At[n][q] = G[l] * Amom[(size_t)(n * LM + q) * N + i];
-            }
+        for (int k = sub; k < NAL; k += AF_LANES) {
+            const int n = k / LM, q = k - n * LM;
+            const int l = q < 3 ? 0 : (q < 8 ? 1 : (q < 15 ? 2 : 3));
+            const size_t row = (size_t)(NR + l * NA + n) * N + i;
+            const float b = gq[row], am = Amom[(size_t)k * N + i];
+            AtE[a][k] = 2.0f * fmaf(chi, b, gU[row]) * am;
+            AtQ[a][k] = 2.0f * s * b * am;
         }
-        float ox = 0.f, oy = 0.f, oz = 0.f;
-        float m9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    }
+    __syncthreads();
+    float acc[21];  // own force (3), virial W_ab -= F_a r_b (9), Z_ab += 1/2 r_a a_b (9)
+#pragma unroll
+    for (int k = 0; k < 21; ++k) acc[k] = 0.f;
+    if (live) {
+        const float4 pi = xyzt[i];
+        const int ti = species_of(pi);
         const int nA = cntA[i];
-        for (int sl = 0; sl < nA; ++sl) {
+        for (int sl = sub; sl < nA; sl += AF_LANES) {
             const uint32_t e = listA[(size_t)i * capA + sl];
             const float4 pj = xyzt[nb_index(e)];
             const float3 d = pair_displacement(pi, pj, e, c);
@@ -331,65 +363,53 @@ __global__ __launch_bounds__(256) void k_angular_forces(
             float g[NA], dg[NA];
 #pragma unroll
             for (int n = 0; n < NA; ++n) {
-                float a = 0.f, b = 0.f;
+                float x = 0.f, y = 0.f;
 #pragma unroll
                 for (int k = 0; k < NB; ++k) {
-                    a = fmaf(cp[n * NB + k], f[k], a);
-                    b = fmaf(cp[n * NB + k], df[k], b);
+                    x = fmaf(cp[n * NB + k], f[k], x);
+                    y = fmaf(cp[n * NB + k], df[k], y);
                 }
-                g[n] = a;
-                dg[n] = b;
+                g[n] = x;
+                dg[n] = y;
             }
             float Y[LM];
             harmonics(ux, uy, uz, Y);
-            float radial = 0.f;
-            float Qv[LM];
+            // an offset the compiler cannot prove loop-invariant, so that the tables are
+            // read from LDS per pair instead of being hoisted into registers
+            int row = a * NAL;
+            asm volatile("" : "+v"(row));
+            const float3 F = angular_pair<NA>(&AtE[0][0] + row, g, dg, Y, ux, uy, uz, ir);
+            const float3 A = angular_pair<NA>(&AtQ[0][0] + row, g, dg, Y, ux, uy, uz, ir);
+            pairF[(size_t)i * capA + sl] = make_float4(F.x, F.y, F.z, 0.f);
+            pairA[(size_t)i * capA + sl] = make_float4(A.x, A.y, A.z, 0.f);
+            const float fv[3] = {F.x, F.y, F.z}, av[3] = {A.x, A.y, A.z}, dv[3] = {d.x, d.y, d.z};
 #pragma unroll
-            for (int q = 0; q < LM; ++q) Qv[q] = 0.f;
+            for (int x = 0; x < 3; ++x) {
+                acc[x] += fv[x];
 #pragma unroll
-            for (int n = 0; n < NA; ++n) {
-                float Pn = 0.f;
-#pragma unroll
-                for (int q = 0; q < LM; ++q) {
-                    Pn = fmaf(At[n][q], Y[q], Pn);
-                    Qv[q] = fmaf(At[n][q], g[n], Qv[q]);
+                for (int y = 0; y < 3; ++y) {
+                    acc[3 + 3 * x + y] = fmaf(-fv[x], dv[y], acc[3 + 3 * x + y]);
+                    acc[12 + 3 * x + y] = fmaf(0.5f * dv[x], av[y], acc[12 + 3 * x + y]);
                 }
-                radial = fmaf(dg[n], Pn, radial);
             }
-            float gx, gy, gz;
-            harmonics_grad_dot(ux, uy, uz, Qv, gx, gy, gz);
-            const float ug = ux * gx + uy * gy + uz * gz;
-            const float Fx = radial * ux + (gx - ug * ux) * ir;
-            const float Fy = radial * uy + (gy - ug * uy) * ir;
-            const float Fz = radial * uz + (gz - ug * uz) * ir;
-            pair[(size_t)i * capA + sl] = make_float4(Fx, Fy, Fz, 0.f);
-            if (WHICH == 0) {
-                ox += Fx;
-                oy += Fy;
-                oz += Fz;
-                // W_ab -= F_a r_b
-                m9[0] -= Fx * d.x; m9[1] -= Fx * d.y; m9[2] -= Fx * d.z;
-                m9[3] -= Fy * d.x; m9[4] -= Fy * d.y; m9[5] -= Fy * d.z;
-                m9[6] -= Fz * d.x; m9[7] -= Fz * d.y; m9[8] -= Fz * d.z;
-            } else {
-                // Z_ab += 1/2 r_a a_b
-                m9[0] += 0.5f * d.x * Fx; m9[1] += 0.5f * d.x * Fy; m9[2] += 0.5f * d.x * Fz;
-                m9[3] += 0.5f * d.y * Fx; m9[4] += 0.5f * d.y * Fy; m9[5] += 0.5f * d.y * Fz;
-                m9[6] += 0.5f * d.z * Fx; m9[7] += 0.5f * d.z * Fy; m9[8] += 0.5f * d.z * Fz;
-            }
-        }
-        if (WHICH == 0) {
-            Fnep[i] += ox;
-            Fnep[(size_t)N + i] += oy;
-            Fnep[(size_t)2 * N + i] += oz;
-#pragma unroll
-            for (int k = 0; k < 9; ++k) w[k] = m9[k];
-        } else {
-#pragma unroll
-            for (int k = 0; k < 9; ++k) Znep[(size_t)k * N + i] += m9[k];
         }
     }
-    if (WHICH == 0) block_partials<9>(w, partials);
+#pragma unroll
+    for (int k = 0; k < 21; ++k)
+#pragma unroll
+        for (int o = AF_LANES / 2; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o, 64);
+    double w[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (live && sub == 0) {
+        Fnep[i] += acc[0];
+        Fnep[(size_t)N + i] += acc[1];
+        Fnep[(size_t)2 * N + i] += acc[2];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            w[k] = acc[3 + k];
+            Znep[(size_t)k * N + i] += acc[12 + k];
+        }
+    }
+    block_partials<9>(w, partials);
 }
 
 // slot of `want` in atom j's angular list (-1 if absent); rows are 16-byte aligned
@@ -503,17 +523,14 @@ static hipError_t run_forces(const Plan &p) {
     hipError_t e = reduce_partials(p, GR, 9, S_WNEP, false);
     if (e != hipSuccess) return e;
     stage_mark(p, ST_RADIAL, 3);
-    hipLaunchKernelGGL((k_angular_forces<T, NR, NA, NB, 0>), dim3(G), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell,
+    const int GF = (p.N + AF_APB - 1) / AF_APB;
+    hipLaunchKernelGGL((k_angular_forces<T, NR, NA, NB>), dim3(GF), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell,
                        (float)p.rcA, p.listA, p.cntA, p.capA, p.Amom, p.gU, p.gq, p.phi, p.scalars, p.theta,
-                       p.off_cA, p.off_s, (float4 *)p.pairF, p.Fnep, p.Znep, p.partials);
-    stage_mark(p, ST_ANG_E);
-    e = reduce_partials(p, G, 9, S_WNEP, true);
+                       p.off_cA, p.off_s, (float4 *)p.pairF, (float4 *)p.pairA, p.Fnep, p.Znep, p.partials);
+    stage_mark(p, ST_ANG);
+    e = reduce_partials(p, GF, 9, S_WNEP, true);
     if (e != hipSuccess) return e;
     stage_mark(p, ST_OTHER);
-    hipLaunchKernelGGL((k_angular_forces<T, NR, NA, NB, 1>), dim3(G), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell,
-                       (float)p.rcA, p.listA, p.cntA, p.capA, p.Amom, p.gU, p.gq, p.phi, p.scalars, p.theta,
-                       p.off_cA, p.off_s, (float4 *)p.pairA, p.Fnep, p.Znep, p.partials);
-    stage_mark(p, ST_ANG_Q);
     const int GA = (int)(((int64_t)p.N * AS_LANES + 255) / 256);
     hipLaunchKernelGGL(k_assemble, dim3(GA), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, p.listA, p.cntA, p.capA,
                        (const float4 *)p.pairF, (const float4 *)p.pairA, p.Fnep, p.Znep, p.Fst, p.qraw, p.scalars,

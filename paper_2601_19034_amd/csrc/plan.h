@@ -11,7 +11,7 @@ namespace qnep {
 // pipeline stages timed by qnep_model_enable_timing (names in api.cpp)
 enum Stage : int {
     ST_SORT = 0, ST_LISTS, ST_LISTS_C, ST_DESC, ST_MLP, ST_REAL, ST_EWALD_SK, ST_EWALD_ATOMS, ST_SPREAD,
-    ST_FFT_FWD, ST_INFLUENCE, ST_FFT_INV, ST_GATHER, ST_PHI, ST_RADIAL, ST_ANG_E, ST_ANG_Q, ST_ASSEMBLE,
+    ST_FFT_FWD, ST_INFLUENCE, ST_FFT_INV, ST_GATHER, ST_PHI, ST_RADIAL, ST_ANG, ST_ASSEMBLE,
     ST_FINAL, ST_OTHER
 };
 
@@ -74,8 +74,8 @@ struct Plan {
     int *kcount = nullptr;
     float2 *Spart = nullptr;  // [s_chunks][nk_cap]
     float2 *Sk = nullptr;     // [nk_cap]
-    int tileB[3] = {0, 0, 0}, tileNb[3] = {0, 0, 0}, tileT[3] = {0, 0, 0};
-    float *tiles = nullptr;   // per-brick charge tiles of the atomic-free spread
+    bool bricks = false;      // charge assignment by mesh bricks (else global atomics into rho)
+    int brickP[3] = {0, 0, 0}, brickNb[3] = {0, 0, 0};
     float *rho = nullptr;
     float2 *meshA = nullptr, *meshB = nullptr;
     // ---- call arguments
@@ -99,6 +99,11 @@ hipError_t launch_charges(const Plan &p);
 hipError_t launch_real_space(const Plan &p);
 hipError_t launch_ewald(const Plan &p);
 hipError_t launch_pppm(const Plan &p);
+// mesh bricks of the charge assignment: edge P (points) and count nb per axis
+struct BrickGeom {
+    int P[3], nb[3];
+};
+bool spread_bricks(const int *mesh, const int *nc, BrickGeom *bg);
 hipError_t launch_forces(const Plan &p);
 hipError_t launch_finalize(const Plan &p);
 hipError_t launch_zero_outputs(const Plan &p);

@@ -81,139 +81,171 @@ __global__ void k_real_to_complex(int64_t M, const float *__restrict__ rho, floa
     if (i < M) out[i] = make_float2(rho[i], 0.0f);
 }
 
-// ---------------------------------------------------------------- tiled spread
-// Atomic-free charge assignment.  A brick of B0 x B1 x B2 bins accumulates the
-// order-5 stencils of its atoms in an LDS tile (LDS atomics) that spans the mesh
-// points those atoms can reach, and stores the tile in its own slot; k_tile_gather
-// then forms each mesh point as the sum over the few tiles that cover it.  The
-// result is deterministic.  Tile origin along axis a: floor(b B_a N_a / nc_a) - 3.
-struct TileGeom {
-    int B[3], nb[3], T[3];
-};
+// ---------------------------------------------------------------- brick spread
+// Charge assignment without global atomics.  A work-group owns a brick of mesh
+// points and collects from the cell list every atom copy whose order-5 stencil can
+// reach the brick: the bins (unwrapped, so periodic images are explicit) whose atoms
+// have u in [M0 - 5/2, M0 + P + 3/2) in mesh units, read as rows along c split per
+// image.  Each copy adds the part of its stencil inside the brick to an LDS tile,
+// and the brick is stored once as the complex FFT input (rho, 0): every mesh point
+// is written by exactly one work-group.  Positions are taken unwrapped (the sorted
+// copies lie in the cell up to rounding), so a copy sits next to the bin it is
+// listed in.
+constexpr int SB_P = 16;      // largest brick edge (mesh points)
+constexpr int SB_ROWS = 256;  // rows of bins per brick (one per thread)
+constexpr int SB_SEGS = 512;  // segments (row x image along c) per brick
 
-__device__ inline int tile_origin(int b, int B, int N, int nc) { return (int)(((int64_t)b * B * N) / nc) - 3; }
+__device__ inline int sb_code(int k0, int k1, int k2) { return (k0 + 128) | (k1 + 128) << 8 | (k2 + 128) << 16; }
 
-__global__ __launch_bounds__(256) void k_spread_tiles(const float4 *__restrict__ xyzt, Cell c, MeshGeom g,
-                                                      int nc0, int nc1, int nc2, TileGeom tg,
-                                                      const int *__restrict__ start, const float *__restrict__ qraw,
-                                                      const double *__restrict__ scalars, float *__restrict__ tiles,
-                                                      int32_t *__restrict__ flags) {
-    extern __shared__ float tile[];
-    __shared__ int rowoff[65], rowbeg[64];
-    const int nc[3] = {nc0, nc1, nc2};
-    const int brick = blockIdx.x;
-    const int bi[3] = {brick / (tg.nb[1] * tg.nb[2]), (brick / tg.nb[2]) % tg.nb[1], brick % tg.nb[2]};
-    int lo[3], blo[3], bhi[3];
+// exclusive scan of (x, y) over the 256 threads of a work-group; totals in tx, ty
+__device__ inline void sb_exscan2(int &x, int &y, int &tx, int &ty) {
+    __shared__ int ws[2][4];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int ix = x, iy = y;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        blo[a] = bi[a] * tg.B[a];
-        bhi[a] = min(blo[a] + tg.B[a], nc[a]);
-        lo[a] = tile_origin(bi[a], tg.B[a], g.n[a], nc[a]);
-    }
-    const int TV = tg.T[0] * tg.T[1] * tg.T[2];
-    for (int p = threadIdx.x; p < TV; p += blockDim.x) tile[p] = 0.0f;
-    const int ny = bhi[1] - blo[1];
-    const int nrows = (bhi[0] - blo[0]) * ny;
-    if (threadIdx.x == 0) {
-        int acc = 0;
-        for (int r = 0; r < nrows; ++r) {
-            const int x = blo[0] + r / ny, y = blo[1] + r % ny;
-            const int base = (x * nc1 + y) * nc2;
-            rowbeg[r] = start[base + blo[2]];
-            rowoff[r] = acc;
-            acc += start[base + bhi[2]] - rowbeg[r];
+    for (int o = 1; o < 64; o <<= 1) {
+        const int vx = __shfl_up(ix, o, 64), vy = __shfl_up(iy, o, 64);
+        if (lane >= o) {
+            ix += vx;
+            iy += vy;
         }
-        rowoff[nrows] = acc;
+    }
+    if (lane == 63) {
+        ws[0][wid] = ix;
+        ws[1][wid] = iy;
     }
     __syncthreads();
-    const int total = rowoff[nrows];
+    int bx = 0, by = 0;
+    for (int w = 0; w < wid; ++w) {
+        bx += ws[0][w];
+        by += ws[1][w];
+    }
+    tx = ws[0][0] + ws[0][1] + ws[0][2] + ws[0][3];
+    ty = ws[1][0] + ws[1][1] + ws[1][2] + ws[1][3];
+    x = bx + ix - x;
+    y = by + iy - y;
+}
+
+__global__ __launch_bounds__(256) void k_spread_bricks(const float4 *__restrict__ xyzt, Cell c, MeshGeom g,
+                                                       int nc0, int nc1, int nc2, BrickGeom bg,
+                                                       const int *__restrict__ start, const float *__restrict__ qraw,
+                                                       const double *__restrict__ scalars, float2 *__restrict__ out) {
+    __shared__ float tile[SB_P * SB_P * SB_P];
+    __shared__ int sbeg[SB_SEGS], spre[SB_SEGS + 1], scode[SB_SEGS];
+    const int nc[3] = {nc0, nc1, nc2};
+    const int br = xcd_block();
+    const int bi[3] = {br / (bg.nb[1] * bg.nb[2]), (br / bg.nb[2]) % bg.nb[1], br % bg.nb[2]};
+    int M0[3], Pa[3], blo[3], bhi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        M0[a] = bi[a] * bg.P[a];
+        Pa[a] = min(bg.P[a], g.n[a] - M0[a]);
+        blo[a] = (int)floor((M0[a] - 2.51) * nc[a] / g.n[a]);
+        bhi[a] = (int)floor((M0[a] + Pa[a] + 1.51) * nc[a] / g.n[a]);
+    }
+    const int TP = bg.P[0] * bg.P[1] * bg.P[2];
+    for (int p = threadIdx.x; p < TP; p += blockDim.x) tile[p] = 0.0f;
+    // one row of bins (x, y fixed) per thread: count its segments and atoms
+    const int ny = bhi[1] - blo[1] + 1, nrows = (bhi[0] - blo[0] + 1) * ny;
+    const int r = threadIdx.x;
+    const bool has_row = r < nrows;
+    int i0 = 0, i1 = 0, rowbase = 0;
+    if (has_row) {
+        const int u0 = blo[0] + r / ny, u1 = blo[1] + r % ny;
+        i0 = floor_div(u0, nc0);
+        i1 = floor_div(u1, nc1);
+        rowbase = ((u0 - i0 * nc0) * nc1 + (u1 - i1 * nc1)) * nc2;
+    }
+    const int z0 = floor_div(blo[2], nc2), z1 = floor_div(bhi[2], nc2);
+    int nseg = 0, nat = 0;
+    for (int i2 = z0; has_row && i2 <= z1; ++i2) {
+        const int za = max(blo[2], i2 * nc2) - i2 * nc2, zb = min(bhi[2], i2 * nc2 + nc2 - 1) - i2 * nc2;
+        ++nseg;
+        nat += start[rowbase + zb + 1] - start[rowbase + za];
+    }
+    int tseg, tat;
+    sb_exscan2(nseg, nat, tseg, tat);  // nseg, nat become this row's offsets
+    for (int i2 = z0; has_row && i2 <= z1; ++i2) {
+        const int za = max(blo[2], i2 * nc2) - i2 * nc2, zb = min(bhi[2], i2 * nc2 + nc2 - 1) - i2 * nc2;
+        const int jb = start[rowbase + za];
+        sbeg[nseg] = jb;
+        spre[nseg] = nat;
+        scode[nseg] = sb_code(i0, i1, i2);
+        ++nseg;
+        nat += start[rowbase + zb + 1] - jb;
+    }
+    if (threadIdx.x == 0) spre[tseg] = tat;
+    __syncthreads();
     const float delta = (float)scalars[S_DELTA];
-    for (int t = threadIdx.x; t < total; t += blockDim.x) {
-        int r = 0;
-        while (rowoff[r + 1] <= t) ++r;
-        const int j = rowbeg[r] + (t - rowoff[r]);
+    // the 64 lanes of a wave take atoms tcol apart in the list (different rows of
+    // bins), so that their stencils rarely add to the same LDS word at once
+    const int tcol = (tat + 63) / 64;
+    for (int v = threadIdx.x; v < 64 * tcol; v += blockDim.x) {
+        const int t = (v & 63) * tcol + (v >> 6);
+        if (t >= tat) continue;
+        int lo = 0, hi = tseg - 1;  // the last segment whose prefix is <= t (non-empty)
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (spre[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const int j = sbeg[lo] + (t - spre[lo]);
+        const int code = scode[lo];
+        const int k[3] = {(code & 0xFF) - 128, ((code >> 8) & 0xFF) - 128, ((code >> 16) & 0xFF) - 128};
         const float4 p = xyzt[j];
         const float q = qraw[j] + delta;
-        const double s[3] = {(double)p.x * c.hinv[0] + (double)p.y * c.hinv[3] + (double)p.z * c.hinv[6],
-                             (double)p.x * c.hinv[1] + (double)p.y * c.hinv[4] + (double)p.z * c.hinv[7],
-                             (double)p.x * c.hinv[2] + (double)p.y * c.hinv[5] + (double)p.z * c.hinv[8]};
         int l[3];
         float w[3][5];
-        bool ok = true;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            double sa = s[a] - floor(s[a]);
-            // keep the atom next to its bin across the periodic seam (rounding at s = 1)
-            if (sa < (double)blo[a] / nc[a] - 0.5) sa += 1.0;
-            if (sa > (double)bhi[a] / nc[a] + 0.5) sa -= 1.0;
-            const double u = sa * g.n[a];
+            const double s = (double)p.x * c.hinv[a] + (double)p.y * c.hinv[3 + a] + (double)p.z * c.hinv[6 + a];
+            const double u = (s + k[a]) * g.n[a];
             const double m = floor(u + 0.5);
             bspline5((float)(u - m), w[a]);
-            l[a] = (int)m - 2 - lo[a];
-            ok = ok && l[a] >= 0 && l[a] + 4 < tg.T[a];
-        }
-        if (!ok) {
-            atomicOr(flags, QNEP_FLAG_INTERNAL);
-            continue;
+            l[a] = (int)m - 2 - M0[a];
         }
 #pragma unroll
         for (int a = 0; a < 5; ++a) {
+            const int x = l[0] + a;
+            if (x < 0 || x >= Pa[0]) continue;
             const float qa = q * w[0][a];
 #pragma unroll
             for (int b = 0; b < 5; ++b) {
+                const int y = l[1] + b;
+                if (y < 0 || y >= Pa[1]) continue;
                 const float qab = qa * w[1][b];
-                float *row = tile + ((l[0] + a) * tg.T[1] + (l[1] + b)) * tg.T[2] + l[2];
+                float *row = tile + (x * bg.P[1] + y) * bg.P[2];
 #pragma unroll
-                for (int e = 0; e < 5; ++e) atomicAdd(row + e, qab * w[2][e]);
-            }
-        }
-    }
-    __syncthreads();
-    float *out = tiles + (size_t)brick * TV;
-    for (int p = threadIdx.x; p < TV; p += blockDim.x) out[p] = tile[p];
-}
-
-// mesh point m <- sum of the tile entries that map to m (periodically); writes the
-// complex FFT input (rho, 0)
-__global__ __launch_bounds__(256) void k_tile_gather(MeshGeom g, int nc0, int nc1, int nc2, TileGeom tg,
-                                                     const float *__restrict__ tiles, float2 *__restrict__ out) {
-    const int64_t M = (int64_t)g.n[0] * g.n[1] * g.n[2];
-    const int64_t idx = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
-    if (idx >= M) return;
-    const int nc[3] = {nc0, nc1, nc2};
-    const int m[3] = {(int)(idx / ((int64_t)g.n[1] * g.n[2])), (int)((idx / g.n[2]) % g.n[1]), (int)(idx % g.n[2])};
-    int cb[3][8], cl[3][8], cn[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        cn[a] = 0;
-        const int N = g.n[a];
-        const int kr = tg.T[a] / N + 1;
-        for (int k = -kr; k <= kr; ++k) {
-            const int mm = m[a] + k * N;  // unwrapped mesh index
-            // tile(b) = [origin(b), origin(b) + T) holds mm only for b in [bmin, bmax]
-            const double scale = (double)nc[a] / ((double)tg.B[a] * N);
-            const int bmin = (int)floor((double)(mm - tg.T[a] + 5) * scale) - 1;
-            const int bmax = (int)floor((double)(mm + 3) * scale) + 1;
-            for (int b = bmin; b <= bmax; ++b) {
-                if (b < 0 || b >= tg.nb[a]) continue;
-                const int l = mm - tile_origin(b, tg.B[a], N, nc[a]);
-                if (l >= 0 && l < tg.T[a] && cn[a] < 8) {
-                    cb[a][cn[a]] = b;
-                    cl[a][cn[a]] = l;
-                    ++cn[a];
+                for (int e = 0; e < 5; ++e) {
+                    const int z = l[2] + e;
+                    if (z >= 0 && z < Pa[2]) atomicAdd(row + z, qab * w[2][e]);
                 }
             }
         }
     }
-    const int TV = tg.T[0] * tg.T[1] * tg.T[2];
-    float sum = 0.0f;
-    for (int x = 0; x < cn[0]; ++x)
-        for (int y = 0; y < cn[1]; ++y)
-            for (int z = 0; z < cn[2]; ++z) {
-                const int brick = (cb[0][x] * tg.nb[1] + cb[1][y]) * tg.nb[2] + cb[2][z];
-                sum += tiles[(size_t)brick * TV + ((size_t)cl[0][x] * tg.T[1] + cl[1][y]) * tg.T[2] + cl[2][z]];
-            }
-    out[idx] = make_float2(sum, 0.0f);
+    __syncthreads();
+    for (int p = threadIdx.x; p < TP; p += blockDim.x) {
+        const int x = p / (bg.P[1] * bg.P[2]), y = (p / bg.P[2]) % bg.P[1], z = p % bg.P[2];
+        if (x < Pa[0] && y < Pa[1] && z < Pa[2])
+            out[((size_t)(M0[0] + x) * g.n[1] + (M0[1] + y)) * g.n[2] + (M0[2] + z)] = make_float2(tile[p], 0.0f);
+    }
+}
+
+// Brick shape for the spread, or false when the rows or segments of a brick would
+// exceed the per-work-group tables (the caller then uses the atomic spread).
+bool spread_bricks(const int *mesh, const int *nc, BrickGeom *bg) {
+    for (int P = SB_P; P >= 4; P /= 2) {
+        int cnt[3];
+        for (int a = 0; a < 3; ++a) {
+            bg->P[a] = std::min(P, mesh[a]);
+            bg->nb[a] = (mesh[a] + bg->P[a] - 1) / bg->P[a];
+            cnt[a] = (int)std::floor((bg->P[a] + 4.02) * nc[a] / mesh[a]) + 2;  // bins spanned, upper bound
+        }
+        const int rows = cnt[0] * cnt[1];
+        const int segs = rows * ((cnt[2] - 1) / nc[2] + 2);
+        if (rows <= SB_ROWS && segs <= SB_SEGS) return true;
+    }
+    return false;
 }
 
 __device__ inline float alias_poly5(float z) {
@@ -333,22 +365,18 @@ hipError_t launch_pppm(const Plan &p) {
     const int G = (p.N + 255) / 256;
     const int GM = (int)((M + 255) / 256);
     hipError_t e;
-    if (p.tiles) {
-        TileGeom tg;
+    if (p.bricks) {
+        BrickGeom bg;
         for (int a = 0; a < 3; ++a) {
-            tg.B[a] = p.tileB[a];
-            tg.nb[a] = p.tileNb[a];
-            tg.T[a] = p.tileT[a];
+            bg.P[a] = p.brickP[a];
+            bg.nb[a] = p.brickNb[a];
         }
-        const int nbricks = tg.nb[0] * tg.nb[1] * tg.nb[2];
-        const size_t lds = sizeof(float) * (size_t)tg.T[0] * tg.T[1] * tg.T[2];
-        hipLaunchKernelGGL(k_spread_tiles, dim3(nbricks), dim3(256), lds, p.stream, p.xyzt, p.cell, g, p.nc[0],
-                           p.nc[1], p.nc[2], tg, p.cell_start, p.qraw, p.scalars, p.tiles, p.flags);
-        hipLaunchKernelGGL(k_tile_gather, dim3(GM), dim3(256), 0, p.stream, g, p.nc[0], p.nc[1], p.nc[2], tg,
-                           p.tiles, p.meshA);
+        const int nbricks = bg.nb[0] * bg.nb[1] * bg.nb[2];
+        hipLaunchKernelGGL(k_spread_bricks, dim3(nbricks), dim3(256), 0, p.stream, p.xyzt, p.cell, g, p.nc[0],
+                           p.nc[1], p.nc[2], bg, p.cell_start, p.qraw, p.scalars, p.meshA);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
-        stage_mark(p, ST_SPREAD, 2);
+        stage_mark(p, ST_SPREAD, 1);
     } else {
         e = fill_zero(p.rho, sizeof(float) * (size_t)M, p.stream);
         if (e != hipSuccess) return e;
