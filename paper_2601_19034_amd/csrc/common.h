@@ -72,6 +72,164 @@ struct ImageShift {
     }
 };
 
+// ---------------------------------------------------------------- stencil segments
+// The bins within m_a of an atom's bin, read as rows along c: a row is one contiguous
+// range of sorted atoms per periodic image along c.  A group of lanes that share one
+// atom builds the list of these ranges ("segments") in LDS and then walks their
+// concatenation with a stride of the group size, so that every lane of the group gets
+// the same number of candidates whatever the row lengths.  In an orthorhombic cell a
+// row is first trimmed to the bins that can hold an atom within rtrim (a row whose
+// gap to the atom in the ab plane exceeds rtrim is dropped, the others are cut to the
+// chord of that sphere along c).  A segment is {first atom, length | image index <<
+// SEG_LEN_BITS}; the image index addresses the (2R+1)^3 lattice shifts |n_a| <= R.
+constexpr int SEG_LEN_BITS = 23;  // N < 2^23
+constexpr uint32_t SEG_LEN_MASK = (1u << SEG_LEN_BITS) - 1u;
+constexpr int SEG_RMAX = 3;
+constexpr int SEG_NIMG = (2 * SEG_RMAX + 1) * (2 * SEG_RMAX + 1) * (2 * SEG_RMAX + 1);
+
+struct Stencil {
+    int nc[3], m[3];
+    int R;           // images reached: |n_a| <= R
+    int nrows;       // (2 m0 + 1)(2 m1 + 1)
+    int rows_chunk;  // rows whose segments always fit one table of `cap` entries
+    int trim;        // orthorhombic cell: rows trimmed to the sphere of radius rtrim
+    float rtrim2;    // rtrim^2
+    float bw0, bw1;  // bin widths along a and b (orthorhombic cell)
+    float ibw2;      // bins per unit length along c
+};
+
+// Host set-up for a stencil of half-widths m over nc bins, trimmed to the cutoff rc
+// (plus a margin far above the FP32 error of positions).  False when the stencil
+// reaches images beyond SEG_RMAX.
+inline bool stencil_setup(Stencil &st, const int *nc, const int *m, const double *h, double rc, int cap) {
+    st.R = 0;
+    for (int a = 0; a < 3; ++a) {
+        st.nc[a] = nc[a];
+        st.m[a] = m[a];
+        const int r = (m[a] + nc[a] - 1) / nc[a];
+        st.R = r > st.R ? r : st.R;
+    }
+    if (st.R > SEG_RMAX) return false;
+    st.nrows = (2 * m[0] + 1) * (2 * m[1] + 1);
+    const int nz = 2 * m[2] / nc[2] + 2;  // most images along c that one row spans
+    st.rows_chunk = cap / nz > 1 ? cap / nz : 1;
+    st.trim = (h[1] == 0.0 && h[2] == 0.0 && h[3] == 0.0 && h[5] == 0.0 && h[6] == 0.0 && h[7] == 0.0 &&
+               h[0] > 0.0 && h[4] > 0.0 && h[8] > 0.0) ? 1 : 0;
+    const double rt = rc * (1.0 + 1e-4) + 1e-3;
+    st.rtrim2 = (float)(rt * rt);
+    st.bw0 = (float)(h[0] / nc[0]);
+    st.bw1 = (float)(h[4] / nc[1]);
+    st.ibw2 = (float)(nc[2] / h[8]);
+    return true;
+}
+
+// bin of a position (as bin_of) and the position in bin units (the FP32 rounding of u
+// is far inside the trimming margin)
+struct AtomBin {
+    int ci[3];
+    float u[3];
+};
+__device__ inline AtomBin atom_bin(float4 p, const Cell &c, const Stencil &st) {
+    AtomBin b;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double s = (double)p.x * c.hinv[a] + (double)p.y * c.hinv[3 + a] + (double)p.z * c.hinv[6 + a];
+        const double u = s * st.nc[a];
+        b.u[a] = (float)u;
+        const int k = (int)floor(u);
+        b.ci[a] = k < 0 ? 0 : (k >= st.nc[a] ? st.nc[a] - 1 : k);
+    }
+    return b;
+}
+
+// bins [zl, zh] along c (unwrapped) of stencil row r that can hold a neighbour
+__device__ inline bool stencil_row(const Stencil &st, const Cell &c, const AtomBin &b, int r, int &zl, int &zh) {
+    const int w1n = 2 * st.m[1] + 1;
+    zl = b.ci[2] - st.m[2];
+    zh = b.ci[2] + st.m[2];
+    if (!st.trim) return true;
+    const float l0 = (float)(b.ci[0] + (r / w1n - st.m[0])), l1 = (float)(b.ci[1] + (r % w1n - st.m[1]));
+    const float g0 = fmaxf(0.0f, fmaxf(l0 - b.u[0], b.u[0] - l0 - 1.0f)) * st.bw0;
+    const float g1 = fmaxf(0.0f, fmaxf(l1 - b.u[1], b.u[1] - l1 - 1.0f)) * st.bw1;
+    const float h2 = st.rtrim2 - g0 * g0 - g1 * g1;
+    if (h2 <= 0.0f) return false;
+    const float hz = sqrtf(h2) * st.ibw2;
+    zl = max(zl, (int)floorf(b.u[2] - hz));
+    zh = min(zh, (int)floorf(b.u[2] + hz));
+    return zl <= zh;
+}
+
+// Segments of stencil rows [r0, r0 + rn) of one atom into seg[]: every lane of the
+// LANES-lane group calls it (lanes without a live atom pass live = false) and gets
+// the segment count.  The caller synchronizes before the table is read.
+template <int LANES>
+__device__ inline int stencil_segments(const Stencil &st, const Cell &c, const AtomBin &b, bool live, int sub,
+                                       int r0, int rn, const int *__restrict__ start, int2 *seg) {
+    const int nc0 = st.nc[0], nc1 = st.nc[1], nc2 = st.nc[2], w1n = 2 * st.m[1] + 1;
+    const int nimg = 2 * st.R + 1;
+    const int rpl = (rn + LANES - 1) / LANES;  // rows per lane, contiguous: the table keeps row order
+    const int rb = r0 + sub * rpl, re = min(rb + rpl, r0 + rn);
+    int cnt = 0;
+    for (int r = rb; live && r < re; ++r) {
+        int zl, zh;
+        if (stencil_row(st, c, b, r, zl, zh)) cnt += floor_div(zh, nc2) - floor_div(zl, nc2) + 1;
+    }
+    int incl = cnt;
+#pragma unroll
+    for (int o = 1; o < LANES; o <<= 1) {
+        const int v = __shfl_up(incl, o, LANES);
+        if (sub >= o) incl += v;
+    }
+    int pos = incl - cnt;
+    for (int r = rb; live && r < re; ++r) {
+        int zl, zh;
+        if (!stencil_row(st, c, b, r, zl, zh)) continue;
+        const int u0 = b.ci[0] + r / w1n - st.m[0], i0 = floor_div(u0, nc0), b0 = u0 - i0 * nc0;
+        const int u1 = b.ci[1] + r % w1n - st.m[1], i1 = floor_div(u1, nc1), b1 = u1 - i1 * nc1;
+        const int rowbase = (b0 * nc1 + b1) * nc2;
+        for (int i2 = floor_div(zl, nc2); i2 <= floor_div(zh, nc2); ++i2) {
+            const int za = max(zl, i2 * nc2) - i2 * nc2, zb = min(zh, i2 * nc2 + nc2 - 1) - i2 * nc2;
+            const int jb = start[rowbase + za], je = start[rowbase + zb + 1];
+            const uint32_t img = (uint32_t)(((i0 + st.R) * nimg + (i1 + st.R)) * nimg + (i2 + st.R));
+            seg[pos++] = make_int2(jb, (int)((uint32_t)(je - jb) | (img << SEG_LEN_BITS)));
+        }
+    }
+    return live ? __shfl(incl, LANES - 1, LANES) : 0;
+}
+
+// lattice shift n of image index k in [0, (2R+1)^3)
+__device__ inline void image_of(int k, int R, int &n0, int &n1, int &n2) {
+    const int nimg = 2 * R + 1;
+    n0 = k / (nimg * nimg) - R;
+    n1 = (k / nimg) % nimg - R;
+    n2 = k % nimg - R;
+}
+
+// position of one lane in the concatenated segments of its atom: segment s, offset off
+struct SegWalk {
+    int s, off, ns;
+    int2 e;
+    __device__ SegWalk(const int2 *seg, int ns_, int start_off) : s(0), off(start_off), ns(ns_) {
+        e = ns > 0 ? seg[0] : make_int2(0, 0);
+        settle(seg);
+    }
+    __device__ bool valid() const { return s < ns; }
+    __device__ int atom() const { return e.x + off; }
+    __device__ int image() const { return (int)((uint32_t)e.y >> SEG_LEN_BITS); }
+    __device__ void settle(const int2 *seg) {  // move into the segment that holds offset off
+        while (s < ns) {
+            const int len = (int)((uint32_t)e.y & SEG_LEN_MASK);
+            if (off < len) break;
+            off -= len;
+            if (++s < ns) e = seg[s];
+        }
+    }
+    __device__ void advance(const int2 *seg, int stride) {
+        off += stride;
+        settle(seg);
+    }
+};
+
 // image bits of n = (0, 0, 0)
 constexpr uint32_t IMAGE_ZERO = 3u | (3u << 3) | (3u << 6);
 

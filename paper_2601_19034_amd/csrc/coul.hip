@@ -11,25 +11,16 @@
 namespace qnep {
 
 // ---------------------------------------------------------------- real space
-// RS_LANES lanes share one sorted atom i.  Its stencil of (2m+1)^3 bins is cut into
-// segments: a row of bins along c is one contiguous range of sorted atoms per
-// periodic image along c.  In an orthorhombic cell each row is first trimmed to the
-// bins that can hold an atom within the cutoff of i (a row whose gap to i in the ab
-// plane exceeds the cutoff is dropped, the others are cut to the chord of the cutoff
-// sphere along c).  The lanes build the segment table of their atom in LDS and then
-// walk the concatenated segments with stride RS_LANES, so that all lanes get the
-// same number of candidates whatever the row lengths.  A candidate is decided by its
-// FP32 displacement; the pair terms are evaluated without a branch (a candidate
-// outside the cutoff, or i itself, gets weight zero) and give phi^r_i, the static
-// pair force F_i = -k_e q'_i sum_j q'_j [erfc(a r)/r + 2a e^{-a^2 r^2}/sqrt(pi)] r_ij / r^2
+// RS_LANES lanes share one sorted atom i and walk the segments of its bin stencil
+// (trimmed to the cutoff sphere in orthorhombic cells) with stride RS_LANES.  A
+// candidate is decided by its FP32 displacement; the pair terms are evaluated without
+// a branch (a candidate outside the cutoff, or i itself, gets weight zero) and give
+// phi^r_i, the static pair force
+// F_i = -k_e q'_i sum_j q'_j [erfc(a r)/r + 2a e^{-a^2 r^2}/sqrt(pi)] r_ij / r^2
 // and the pair virial (each unordered pair is seen from both atoms with weight 1/2).
 constexpr int RS_LANES = 16;
 constexpr int RS_APB = 256 / RS_LANES;  // atoms per work-group
 constexpr int RS_SEG = 128;             // segments of one atom held in LDS at a time
-constexpr int RS_RMAX = 3;              // periodic images |n_a| <= RS_RMAX
-constexpr int RS_IMG = (2 * RS_RMAX + 1) * (2 * RS_RMAX + 1) * (2 * RS_RMAX + 1);
-constexpr int RS_LEN_BITS = 23;  // a segment is {first atom, length | image << RS_LEN_BITS}
-constexpr uint32_t RS_LEN_MASK = (1u << RS_LEN_BITS) - 1u;
 
 // positions with the corrected charge q' in w: one 16-byte load per candidate
 __global__ void k_pack_charges(int N, const float4 *__restrict__ xyzt, const float *__restrict__ qraw,
@@ -69,114 +60,45 @@ __device__ __forceinline__ void rs_pair(const float4 &pi, const float4 &pj, cons
     acc[9] = fmaf(by, dz, acc[9]);
 }
 
-__global__ __launch_bounds__(256) void k_real_space(int N, const float4 *__restrict__ xyzq, Cell c, int nc0,
-                                                    int nc1, int nc2, int m0, int m1, int m2, int R,
-                                                    int rows_chunk, int trim, double rtrim,
+__global__ __launch_bounds__(256) void k_real_space(int N, const float4 *__restrict__ xyzq, Cell c, Stencil st,
                                                     const int *__restrict__ start, double rc2,
                                                     const float *__restrict__ qraw,
                                                     const double *__restrict__ scalars, float alpha,
                                                     float *__restrict__ phi, float *__restrict__ Fst,
                                                     double *__restrict__ partials) {
     __shared__ int2 seg[RS_APB][RS_SEG];
-    __shared__ float4 shift_tab[RS_IMG];
-    __shared__ int seg_n[RS_APB];
-    const int nimg = 2 * R + 1;
+    __shared__ float4 shift_tab[SEG_NIMG];
+    const int nimg = 2 * st.R + 1;
     for (int k = threadIdx.x; k < nimg * nimg * nimg; k += blockDim.x) {
-        const ImageShift sh(c, k / (nimg * nimg) - R, (k / nimg) % nimg - R, k % nimg - R);
+        int n0, n1, n2;
+        image_of(k, st.R, n0, n1, n2);
+        const ImageShift sh(c, n0, n1, n2);
         shift_tab[k] = make_float4(sh.fx, sh.fy, sh.fz, 0.0f);
     }
     const int a = threadIdx.x / RS_LANES, sub = threadIdx.x % RS_LANES;
     const int i = xcd_block() * RS_APB + a;
     const bool live = i < N;
     const float4 pi = xyzq[live ? i : 0];
-    // bin of i (as in the binning) and its position in bin units
-    const int nc[3] = {nc0, nc1, nc2};
-    double u[3];
-    int ci[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const double s = (double)pi.x * c.hinv[d] + (double)pi.y * c.hinv[3 + d] + (double)pi.z * c.hinv[6 + d];
-        u[d] = s * nc[d];
-        const int k = (int)floor(u[d]);
-        ci[d] = k < 0 ? 0 : (k >= nc[d] ? nc[d] - 1 : k);
-    }
-    const double bw0 = c.h[0] / nc0, bw1 = c.h[4] / nc1, bw2 = c.h[8] / nc2;  // orthorhombic bin widths
-    const int w1n = 2 * m1 + 1, nrows = (2 * m0 + 1) * w1n;
-    // bins [zl, zh] along c (unwrapped) of stencil row r that can hold a neighbour of i
-    auto row_z = [&](int r, int &zl, int &zh) -> bool {
-        zl = ci[2] - m2;
-        zh = ci[2] + m2;
-        if (!trim) return true;
-        const double l0 = ci[0] + (r / w1n - m0), l1 = ci[1] + (r % w1n - m1);
-        const double g0 = fmax(0.0, fmax(l0 - u[0], u[0] - l0 - 1.0)) * bw0;
-        const double g1 = fmax(0.0, fmax(l1 - u[1], u[1] - l1 - 1.0)) * bw1;
-        const double h2 = rtrim * rtrim - g0 * g0 - g1 * g1;
-        if (h2 <= 0.0) return false;
-        const double hz = sqrt(h2) / bw2;
-        zl = max(zl, (int)floor(u[2] - hz));
-        zh = min(zh, (int)floor(u[2] + hz));
-        return zl <= zh;
-    };
+    const AtomBin ab = atom_bin(pi, c, st);
     const float rc2f = (float)rc2;
     const float c2 = 2.0f * alpha * 0.5641895835477563f;  // 2 alpha / sqrt(pi)
     float acc[10];  // phi, B r (3), B r r (xx yy zz xy xz yz)
 #pragma unroll
     for (int k = 0; k < 10; ++k) acc[k] = 0.f;
-    for (int r0 = 0; r0 < nrows; r0 += rows_chunk) {  // the same trip count in every lane
-        // rows [rb, re) of this chunk belong to this lane; count their segments
-        const int rn = min(rows_chunk, nrows - r0), rpl = (rn + RS_LANES - 1) / RS_LANES;
-        const int rb = r0 + sub * rpl, re = min(rb + rpl, r0 + rn);
-        int cnt = 0;
-        for (int r = rb; live && r < re; ++r) {
-            int zl, zh;
-            if (row_z(r, zl, zh)) cnt += floor_div(zh, nc2) - floor_div(zl, nc2) + 1;
-        }
-        int incl = cnt;  // inclusive scan over the lanes of this atom
-#pragma unroll
-        for (int o = 1; o < RS_LANES; o <<= 1) {
-            const int v = __shfl_up(incl, o, RS_LANES);
-            if (sub >= o) incl += v;
-        }
-        int pos = incl - cnt;
+    for (int r0 = 0; r0 < st.nrows; r0 += st.rows_chunk) {  // the same trip count in every lane
         __syncthreads();  // the previous chunk's walk is done with the table
-        for (int r = rb; live && r < re; ++r) {
-            int zl, zh;
-            if (!row_z(r, zl, zh)) continue;
-            const int u0 = ci[0] + r / w1n - m0, i0 = floor_div(u0, nc0), b0 = u0 - i0 * nc0;
-            const int u1 = ci[1] + r % w1n - m1, i1 = floor_div(u1, nc1), b1 = u1 - i1 * nc1;
-            const int rowbase = (b0 * nc1 + b1) * nc2;
-            for (int i2 = floor_div(zl, nc2); i2 <= floor_div(zh, nc2); ++i2) {
-                const int za = max(zl, i2 * nc2) - i2 * nc2, zb = min(zh, i2 * nc2 + nc2 - 1) - i2 * nc2;
-                const int jb = start[rowbase + za], je = start[rowbase + zb + 1];
-                const uint32_t img = (uint32_t)(((i0 + R) * nimg + (i1 + R)) * nimg + (i2 + R));
-                seg[a][pos++] = make_int2(jb, (int)((uint32_t)(je - jb) | (img << RS_LEN_BITS)));
-            }
-        }
-        if (sub == RS_LANES - 1) seg_n[a] = live ? incl : 0;
+        const int ns = stencil_segments<RS_LANES>(st, c, ab, live, sub, r0, min(st.rows_chunk, st.nrows - r0),
+                                                  start, seg[a]);
         __syncthreads();
-        // walk: this lane takes candidates sub, sub + RS_LANES, ... of the concatenation
-        const int ns = seg_n[a];
-        int s = 0, off = sub;
-        int2 e = ns > 0 ? seg[a][0] : make_int2(0, 0);
-        auto settle = [&]() {  // move (s, off) into the segment that holds offset off
-            while (s < ns) {
-                const int len = (int)((uint32_t)e.y & RS_LEN_MASK);
-                if (off < len) break;
-                off -= len;
-                if (++s < ns) e = seg[a][s];
-            }
-        };
-        settle();
-        while (s < ns) {  // two candidates per pass, both loads issued before either is used
-            const int jA = e.x + off, gA = (int)((uint32_t)e.y >> RS_LEN_BITS);
-            off += RS_LANES;
-            settle();
-            const bool hasB = s < ns;
-            const int jB = hasB ? e.x + off : jA, gB = hasB ? (int)((uint32_t)e.y >> RS_LEN_BITS) : gA;
-            if (hasB) {
-                off += RS_LANES;
-                settle();
-            }
+        // this lane takes candidates sub, sub + RS_LANES, ... of the concatenation, two
+        // per pass with both loads issued before either is used
+        SegWalk wk(seg[a], ns, sub);
+        while (wk.valid()) {
+            const int jA = wk.atom(), gA = wk.image();
+            wk.advance(seg[a], RS_LANES);
+            const bool hasB = wk.valid();
+            const int jB = hasB ? wk.atom() : jA, gB = hasB ? wk.image() : gA;
+            if (hasB) wk.advance(seg[a], RS_LANES);
             const float4 pa = xyzq[jA], pb = xyzq[jB];
             const float4 sa = shift_tab[gA], sb = shift_tab[gB];
             rs_pair(pi, pa, sa, 1.0f, rc2f, alpha, c2, acc);
@@ -214,20 +136,10 @@ hipError_t launch_real_space(const Plan &p) {
     hipLaunchKernelGGL(k_pack_charges, dim3((p.N + 255) / 256), dim3(256), 0, p.stream, p.N, p.xyzt, p.qraw,
                        p.scalars, p.xyzq);
     stage_mark(p, ST_OTHER, 1);
-    // periodic images reached by the stencil, and rows per LDS chunk of segments
-    int R = 0;
-    for (int d = 0; d < 3; ++d) R = max(R, (p.mC[d] + p.nc[d] - 1) / p.nc[d]);
-    if (R > RS_RMAX) return hipErrorInvalidValue;
-    const int nz = 2 * p.mC[2] / p.nc[2] + 2;  // most images along c one row spans
-    const int rows_chunk = max(1, RS_SEG / nz);
-    const double *h = p.cell.h;
-    const int trim = (h[1] == 0.0 && h[2] == 0.0 && h[3] == 0.0 && h[5] == 0.0 && h[6] == 0.0 && h[7] == 0.0 &&
-                      h[0] > 0.0 && h[4] > 0.0 && h[8] > 0.0) ? 1 : 0;
-    // trimming radius: the cutoff plus a margin far above the FP32 error of positions
-    const double rtrim = p.rc_coul * (1.0 + 1e-4) + 1e-3;
+    Stencil st;
+    if (!stencil_setup(st, p.nc, p.mC, p.cell.h, p.rc_coul, RS_SEG)) return hipErrorInvalidValue;
     const int G = (p.N + RS_APB - 1) / RS_APB;
-    hipLaunchKernelGGL(k_real_space, dim3(G), dim3(256), 0, p.stream, p.N, p.xyzq, p.cell, p.nc[0], p.nc[1],
-                       p.nc[2], p.mC[0], p.mC[1], p.mC[2], R, rows_chunk, trim, rtrim, p.cell_start,
+    hipLaunchKernelGGL(k_real_space, dim3(G), dim3(256), 0, p.stream, p.N, p.xyzq, p.cell, st, p.cell_start,
                        p.rc_coul * p.rc_coul, p.qraw, p.scalars, (float)p.alpha, p.phi, p.Fst, p.partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

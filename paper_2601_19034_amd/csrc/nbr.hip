@@ -131,63 +131,97 @@ __global__ void k_gather_sorted(int N, const float *__restrict__ pos, const int3
 }
 
 // ---------------------------------------------------------------- lists
-// One thread per sorted atom.  Both lists are atom-major: list[i * cap + k] and,
-// for r < rc_sub, sub[i * cap_sub + k].
-__global__ __launch_bounds__(256) void k_lists(int N, const float4 *__restrict__ xyzt, Cell c, int nc0, int nc1,
-                                               int nc2, int m0, int m1, int m2, const int *__restrict__ start,
-                                               double rc2, int cap, uint32_t *__restrict__ list,
-                                               int *__restrict__ cnt, double rs2, int cap_sub,
-                                               uint32_t *__restrict__ sub, int *__restrict__ cnt_sub,
-                                               int32_t *__restrict__ flags) {
-    int i = xcd_block() * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const float4 pi = xyzt[i];
-    int ci[3];
-    bin_of(pi, c, nc0, nc1, nc2, ci);
+// LS_LANES lanes share one sorted atom and walk the segments of its bin stencil
+// (trimmed to the list cutoff in orthorhombic cells) with stride LS_LANES.  A
+// candidate is screened in FP32 and decided with the FP64-formed displacement
+// (ImageShift::exact): r^2 < rc^2 puts it in the main list, r^2 < rs^2 also in the
+// sub-list.  The hits of one pass of the lane group are compacted with a ballot in
+// lane order, so both lists come out in the fixed walk order.  Lists are atom-major:
+// list[i * cap + k] and sub[i * cap_sub + k].
+constexpr int LS_LANES = 16;
+constexpr int LS_APB = 256 / LS_LANES;  // atoms per work-group
+constexpr int LS_SEG = 64;              // segments of one atom held in LDS at a time
+
+__global__ __launch_bounds__(256) void k_lists(int N, const float4 *__restrict__ xyzt, Cell c, Stencil st,
+                                               const int *__restrict__ start, double rc2, int cap,
+                                               uint32_t *__restrict__ list, int *__restrict__ cnt, double rs2,
+                                               int cap_sub, uint32_t *__restrict__ sub,
+                                               int *__restrict__ cnt_sub, int32_t *__restrict__ flags) {
+    __shared__ int2 seg[LS_APB][LS_SEG];
+    __shared__ double shx[SEG_NIMG], shy[SEG_NIMG], shz[SEG_NIMG];
+    const int nimg = 2 * st.R + 1;
+    for (int k = threadIdx.x; k < nimg * nimg * nimg; k += blockDim.x) {
+        int n0, n1, n2;
+        image_of(k, st.R, n0, n1, n2);
+        const ImageShift sh(c, n0, n1, n2);
+        shx[k] = sh.sx;
+        shy[k] = sh.sy;
+        shz[k] = sh.sz;
+    }
+    const int a = threadIdx.x / LS_LANES, ln = threadIdx.x % LS_LANES;
+    const int i = xcd_block() * LS_APB + a;
+    const bool live = i < N;
+    const float4 pi = xyzt[live ? i : 0];
+    const AtomBin ab = atom_bin(pi, c, st);
     const float rc2_hi = (float)(rc2 * (1.0 + 1e-4));
-    int n_main = 0, n_sub = 0;
-    const int zlo = ci[2] - m2, zhi = ci[2] + m2;
-    for (int d0 = -m0; d0 <= m0; ++d0) {
-        int u0 = ci[0] + d0, i0 = floor_div(u0, nc0), w0 = u0 - i0 * nc0;
-        for (int d1 = -m1; d1 <= m1; ++d1) {
-            int u1 = ci[1] + d1, i1 = floor_div(u1, nc1), w1 = u1 - i1 * nc1;
-            const int rowbase = (w0 * nc1 + w1) * nc2;
-            // bins along c are consecutive in the sort: one atom range per image along c
-            for (int i2 = floor_div(zlo, nc2); i2 <= floor_div(zhi, nc2); ++i2) {
-                const int za = max(zlo, i2 * nc2) - i2 * nc2, zb = min(zhi, i2 * nc2 + nc2 - 1) - i2 * nc2;
-                ImageShift sh(c, i0, i1, i2);
-                const bool self_img = (i0 == 0 && i1 == 0 && i2 == 0);
-                const int b = start[rowbase + za], e = start[rowbase + zb + 1];
-                for (int j = b; j < e; ++j) {
-                    const float4 pj = xyzt[j];
-                    float fx = (pj.x - pi.x) + sh.fx, fy = (pj.y - pi.y) + sh.fy, fz = (pj.z - pi.z) + sh.fz;
-                    if (fx * fx + fy * fy + fz * fz >= rc2_hi) continue;
-                    if (self_img && j == i) continue;
-                    float3 d = sh.exact(pi, pj);
-                    double r2 = (double)d.x * d.x + (double)d.y * d.y + (double)d.z * d.z;
-                    if (r2 < rc2) {
-                        uint32_t code = nb_encode(j, i0, i1, i2);
-                        if (n_main < cap) list[(size_t)i * cap + n_main] = code;
-                        ++n_main;
-                        if (r2 < rs2) {
-                            if (n_sub < cap_sub) sub[(size_t)i * cap_sub + n_sub] = code;
-                            ++n_sub;
-                        }
-                    }
+    const int self_img = (st.R * nimg + st.R) * nimg + st.R;
+    const int gshift = (threadIdx.x & 63) & ~(LS_LANES - 1);  // first lane of this group in the wave
+    const uint32_t below = (1u << ln) - 1u;
+    int n_main = 0, n_sub = 0;  // exact in lane 0, which has the most candidates of every chunk
+    for (int r0 = 0; r0 < st.nrows; r0 += st.rows_chunk) {
+        __syncthreads();
+        const int ns = stencil_segments<LS_LANES>(st, c, ab, live, ln, r0, min(st.rows_chunk, st.nrows - r0),
+                                                  start, seg[a]);
+        __syncthreads();
+        SegWalk wk(seg[a], ns, ln);
+        while (wk.valid()) {
+            const int j = wk.atom(), g = wk.image();
+            wk.advance(seg[a], LS_LANES);
+            const float4 pj = xyzt[j];
+            const double sx = shx[g], sy = shy[g], sz = shz[g];
+            const float fx = (pj.x - pi.x) + (float)sx, fy = (pj.y - pi.y) + (float)sy,
+                        fz = (pj.z - pi.z) + (float)sz;
+            bool hit = false, hs = false;
+            if (fx * fx + fy * fy + fz * fz < rc2_hi && !(g == self_img && j == i)) {
+                const float dx = (float)(((double)pj.x - (double)pi.x) + sx);
+                const float dy = (float)(((double)pj.y - (double)pi.y) + sy);
+                const float dz = (float)(((double)pj.z - (double)pi.z) + sz);
+                const double r2 = (double)dx * dx + (double)dy * dy + (double)dz * dz;
+                hit = r2 < rc2;
+                hs = r2 < rs2;
+            }
+            const uint32_t gm = (uint32_t)(__ballot(hit) >> gshift) & 0xFFFFu;
+            const uint32_t gs = (uint32_t)(__ballot(hs) >> gshift) & 0xFFFFu;
+            if (hit) {
+                int n0, n1, n2;
+                image_of(g, st.R, n0, n1, n2);
+                const uint32_t code = nb_encode(j, n0, n1, n2);
+                const int k = n_main + __popc(gm & below);
+                if (k < cap) list[(size_t)i * cap + k] = code;
+                if (hs) {
+                    const int ks = n_sub + __popc(gs & below);
+                    if (ks < cap_sub) sub[(size_t)i * cap_sub + ks] = code;
                 }
             }
+            n_main += __popc(gm);
+            n_sub += __popc(gs);
         }
+        // lanes that ran out of candidates early missed the last passes' counts
+        n_main = __shfl(n_main, 0, LS_LANES);
+        n_sub = __shfl(n_sub, 0, LS_LANES);
     }
-    if (n_main > cap) {
-        atomicOr(flags, QNEP_FLAG_RADIAL_OVERFLOW);
-        n_main = cap;
+    if (live && ln == 0) {
+        if (n_main > cap) {
+            atomicOr(flags, QNEP_FLAG_RADIAL_OVERFLOW);
+            n_main = cap;
+        }
+        if (n_sub > cap_sub) {
+            atomicOr(flags, QNEP_FLAG_ANGULAR_OVERFLOW);
+            n_sub = cap_sub;
+        }
+        cnt[i] = n_main;
+        cnt_sub[i] = n_sub;
     }
-    if (n_sub > cap_sub) {
-        atomicOr(flags, QNEP_FLAG_ANGULAR_OVERFLOW);
-        n_sub = cap_sub;
-    }
-    cnt[i] = n_main;
-    cnt_sub[i] = n_sub;
 }
 
 hipError_t launch_neighbors(const Plan &p) {
@@ -211,9 +245,11 @@ hipError_t launch_neighbors(const Plan &p) {
                        p.xyzt, p.ts);
     stage_mark(p, ST_SORT, 8);
     double rcR2 = p.rcR * p.rcR, rcA2 = p.rcA * p.rcA;
-    hipLaunchKernelGGL(k_lists, dim3(G), dim3(B), 0, p.stream, N, p.xyzt, p.cell, p.nc[0], p.nc[1], p.nc[2],
-                       p.mR[0], p.mR[1], p.mR[2], p.cell_start, rcR2, p.capR, p.listR, p.cntR, rcA2, p.capA,
-                       p.listA, p.cntA, p.flags);
+    Stencil st;
+    if (!stencil_setup(st, p.nc, p.mR, p.cell.h, p.rcR > p.rcA ? p.rcR : p.rcA, LS_SEG)) return hipErrorInvalidValue;
+    const int GL = (N + LS_APB - 1) / LS_APB;
+    hipLaunchKernelGGL(k_lists, dim3(GL), dim3(B), 0, p.stream, N, p.xyzt, p.cell, st, p.cell_start, rcR2, p.capR,
+                       p.listR, p.cntR, rcA2, p.capA, p.listA, p.cntA, p.flags);
     stage_mark(p, ST_LISTS);
     return hipGetLastError();
 }
