@@ -46,6 +46,9 @@ def pair_counts(system, radii):
 REAL_SPACE_FLOPS_PER_PAIR = 73
 
 
+KERNEL_HEADERS = ("common.h", "plan.h", "nep_math.h")
+
+
 def traffic_from_profile(kernel, workload, source):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary,
     or None when there is none or the kernel's source changed since it was taken."""
@@ -54,7 +57,10 @@ def traffic_from_profile(kernel, workload, source):
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.md")
     if not os.path.exists(path):
         return None
-    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2601_19034_amd", "csrc", source), "rb").read()).hexdigest()
+    h = hashlib.sha256()
+    for f in (source,) + KERNEL_HEADERS:  # the kernel's source and the headers it includes
+        h.update(open(os.path.join(ROOT, "paper_2601_19034_amd", "csrc", f), "rb").read())
+    sha = h.hexdigest()
     for line in open(path):
         if line.startswith("traffic_bytes_per_launch:"):
             fields = dict(kv.split("=") for kv in line.split(":", 1)[1].split())
