@@ -289,10 +289,11 @@ __global__ __launch_bounds__(256) void k_radial_forces(int N, const float4 *__re
 constexpr int AF_LANES = 8;
 constexpr int AF_APB = 256 / AF_LANES;  // atoms per work-group
 
+// one gradient's pair force from its Atilde table (rows of LM = 24 floats, 16-byte aligned)
 template <int NA>
-__device__ __forceinline__ float3 angular_pair(const float *__restrict__ At, const float (&g)[NA],
-                                               const float (&dg)[NA], const float (&Y)[LM], float ux, float uy,
-                                               float uz, float ir) {
+__device__ __forceinline__ float3 angular_pair(const float4 *__restrict__ At4, const float (&g)[8],
+                                               const float (&dg)[8], const float (&Y)[LM],
+                                               const HarmonicsGrad &hg, float ux, float uy, float uz, float ir) {
     float radial = 0.f;
     float Qv[LM];
 #pragma unroll
@@ -301,15 +302,19 @@ __device__ __forceinline__ float3 angular_pair(const float *__restrict__ At, con
     for (int n = 0; n < NA; ++n) {
         float Pn = 0.f;
 #pragma unroll
-        for (int q = 0; q < LM; ++q) {
-            const float a = At[n * LM + q];
-            Pn = fmaf(a, Y[q], Pn);
-            Qv[q] = fmaf(a, g[n], Qv[q]);
+        for (int q4 = 0; q4 < LM / 4; ++q4) {
+            const float4 a4 = At4[n * (LM / 4) + q4];
+            const float a[4] = {a4.x, a4.y, a4.z, a4.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                Pn = fmaf(a[e], Y[4 * q4 + e], Pn);
+                Qv[4 * q4 + e] = fmaf(a[e], g[n], Qv[4 * q4 + e]);
+            }
         }
         radial = fmaf(dg[n], Pn, radial);
     }
     float gx, gy, gz;
-    harmonics_grad_dot(ux, uy, uz, Qv, gx, gy, gz);
+    harmonics_grad_apply(hg, Qv, gx, gy, gz);
     const float ug = ux * gx + uy * gy + uz * gz;
     return make_float3(radial * ux + (gx - ug * ux) * ir, radial * uy + (gy - ug * uy) * ir,
                        radial * uz + (gz - ug * uz) * ir);
@@ -323,10 +328,15 @@ __global__ __launch_bounds__(256) void k_angular_forces(
     const float *__restrict__ theta, int64_t off_cA, int64_t off_s, float4 *__restrict__ pairF,
     float4 *__restrict__ pairA, float *__restrict__ Fnep, float *__restrict__ Znep, double *__restrict__ partials) {
     constexpr int NAL = NA * LM;
-    __shared__ float cA[T * T * NA * NB];
+    static_assert(NA <= 8 && LM % 4 == 0, "angular table layout");
+    // cA8[ti tj][k][n], n padded to 8: the two float4 of one k serve all g_n
+    __shared__ __align__(16) float cA8[T * T * NB * 8];
     __shared__ __align__(16) float AtE[AF_APB][NAL];
     __shared__ __align__(16) float AtQ[AF_APB][NAL];
-    for (int k = threadIdx.x; k < T * T * NA * NB; k += blockDim.x) cA[k] = theta[off_cA + k];
+    for (int k = threadIdx.x; k < T * T * NB * 8; k += blockDim.x) {
+        const int tp = k / (NB * 8), kb = (k / 8) % NB, n = k % 8;
+        cA8[k] = n < NA ? theta[off_cA + (int64_t)(tp * NA + n) * NB + kb] : 0.0f;
+    }
     const int a = threadIdx.x / AF_LANES, sub = threadIdx.x % AF_LANES;
     const int i = xcd_block() * AF_APB + a;
     const bool live = i < N;
@@ -354,32 +364,37 @@ __global__ __launch_bounds__(256) void k_angular_forces(
             const uint32_t e = listA[(size_t)i * capA + sl];
             const float4 pj = xyzt[nb_index(e)];
             const float3 d = pair_displacement(pi, pj, e, c);
-            const float r = sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
-            const float ir = 1.0f / r;
+            const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
+            const float ir = __builtin_amdgcn_rsqf(r2);  // v_rsq_f32, 1 ulp
+            const float r = r2 * ir;
             const float ux = d.x * ir, uy = d.y * ir, uz = d.z * ir;
             float f[NB], df[NB];
             cheb_basis<NB>(r, rcA, f, df);
-            const float *cp = &cA[(ti * T + species_of(pj)) * NA * NB];
-            float g[NA], dg[NA];
+            const float4 *cp = reinterpret_cast<const float4 *>(&cA8[(ti * T + species_of(pj)) * NB * 8]);
+            float g[8], dg[8];
 #pragma unroll
-            for (int n = 0; n < NA; ++n) {
-                float x = 0.f, y = 0.f;
+            for (int n = 0; n < 8; ++n) g[n] = dg[n] = 0.f;
 #pragma unroll
-                for (int k = 0; k < NB; ++k) {
-                    x = fmaf(cp[n * NB + k], f[k], x);
-                    y = fmaf(cp[n * NB + k], df[k], y);
+            for (int k = 0; k < NB; ++k) {
+                const float4 c0 = cp[2 * k], c1 = cp[2 * k + 1];
+                const float cv[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+#pragma unroll
+                for (int n = 0; n < NA; ++n) {
+                    g[n] = fmaf(cv[n], f[k], g[n]);
+                    dg[n] = fmaf(cv[n], df[k], dg[n]);
                 }
-                g[n] = x;
-                dg[n] = y;
             }
             float Y[LM];
             harmonics(ux, uy, uz, Y);
             // an offset the compiler cannot prove loop-invariant, so that the tables are
             // read from LDS per pair instead of being hoisted into registers
-            int row = a * NAL;
+            int row = a * (NAL / 4);
             asm volatile("" : "+v"(row));
-            const float3 F = angular_pair<NA>(&AtE[0][0] + row, g, dg, Y, ux, uy, uz, ir);
-            const float3 A = angular_pair<NA>(&AtQ[0][0] + row, g, dg, Y, ux, uy, uz, ir);
+            const HarmonicsGrad hg = harmonics_grad(ux, uy, uz);
+            const float3 F =
+                angular_pair<NA>(reinterpret_cast<const float4 *>(&AtE[0][0]) + row, g, dg, Y, hg, ux, uy, uz, ir);
+            const float3 A =
+                angular_pair<NA>(reinterpret_cast<const float4 *>(&AtQ[0][0]) + row, g, dg, Y, hg, ux, uy, uz, ir);
             pairF[(size_t)i * capA + sl] = make_float4(F.x, F.y, F.z, 0.f);
             pairA[(size_t)i * capA + sl] = make_float4(A.x, A.y, A.z, 0.f);
             const float fv[3] = {F.x, F.y, F.z}, av[3] = {A.x, A.y, A.z}, dv[3] = {d.x, d.y, d.z};

@@ -1,5 +1,4 @@
-// Radial basis and angular harmonics of the NEP descriptors (FP32), written for
-// both host (unit tests) and device.
+// Radial basis and angular harmonics of the NEP descriptors (FP32).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -9,12 +8,13 @@ namespace qnep {
 // f_k(r) = (T_k(x) + 1)/2 * f_c(r), x = 2 (r/rc - 1)^2 - 1, f_c = (1 + cos(pi r/rc))/2,
 // k = 0..NB-1, and df_k/dr, with T_k' = k U_{k-1}.
 template <int NB>
-__host__ __device__ inline void cheb_basis(float r, float rc, float *f, float *df) {
-    const float pr = 3.14159265358979f / rc;
-    float sn = sinf(pr * r), cs = cosf(pr * r);
+__device__ inline void cheb_basis(float r, float rc, float *f, float *df) {
+    const float irc = __builtin_amdgcn_rcpf(rc);  // v_rcp_f32, 1 ulp
+    const float pr = 3.14159265358979f * irc;
+    const float sn = sinf(pr * r), cs = cosf(pr * r);
     float fc = 0.5f * (1.0f + cs), dfc = -0.5f * pr * sn;
-    float t = r / rc - 1.0f;
-    float x = 2.0f * t * t - 1.0f, dx = 4.0f * t / rc;
+    float t = r * irc - 1.0f;
+    float x = 2.0f * t * t - 1.0f, dx = 4.0f * t * irc;
     float Tm2 = 1.0f, Tm1 = x;       // T_0, T_1
     float Um2 = 1.0f, Um1 = 2.0f * x; // U_0, U_1
     f[0] = fc;
@@ -120,6 +120,91 @@ __host__ __device__ inline void harmonics_grad_dot(float x, float y, float z, co
     az += Q[22] * c43 * x * (x2 - 3.0f * y2);
     ax += Q[23] * 0.5f * s35 * (x2 * x - 3.0f * x * y2);
     ay += Q[23] * 0.5f * s35 * (y2 * y - 3.0f * x2 * y);
+    gx = ax;
+    gy = ay;
+    gz = az;
+}
+
+// The same gradient split in two steps, for several Q at one direction: the nonzero
+// partial derivatives dY_lm/dx, /dy, /dz (16 each; lm indices in HG_X, HG_Y, HG_Z),
+// then 48 FMAs per Q.
+constexpr int HG_X[16] = {2, 3, 6, 7, 8, 9, 12, 13, 14, 15, 16, 17, 20, 21, 22, 23};
+constexpr int HG_Y[16] = {0, 3, 4, 7, 8, 9, 10, 13, 14, 15, 16, 17, 18, 21, 22, 23};
+constexpr int HG_Z[16] = {1, 4, 5, 6, 9, 10, 11, 12, 13, 16, 17, 18, 19, 20, 21, 22};
+struct HarmonicsGrad {
+    float cx[16], cy[16], cz[16];
+};
+__device__ inline HarmonicsGrad harmonics_grad(float x, float y, float z) {
+    const float s3 = 1.7320508075688772f, s15 = 3.872983346207417f, s6 = 2.449489742783178f;
+    const float s10 = 3.1622776601683795f, s5 = 2.23606797749979f, s35 = 5.916079783099616f;
+    const float c43 = 2.091650066335189f, c41 = 0.7905694150420949f;
+    const float x2 = x * x, y2 = y * y, z2 = z * z;
+    const float xy = x * y, xz = x * z, yz = y * z, xyz = xy * z;
+    const float dxy = x2 - y2, z5 = 5.0f * z2 - 1.0f, z7 = 7.0f * z2 - 1.0f, z73 = 7.0f * z2 - 3.0f;
+    const float z21 = 21.0f * z2 - 3.0f;
+    HarmonicsGrad h;
+    // d/dx for lm = 2 3 6 7 8 9 12 13 14 15 16 17 20 21 22 23
+    h.cx[0] = 1.0f;
+    h.cx[1] = s3 * y;
+    h.cx[2] = s3 * z;
+    h.cx[3] = s3 * x;
+    h.cx[4] = 1.5f * s10 * xy;
+    h.cx[5] = s15 * yz;
+    h.cx[6] = 0.25f * s6 * z5;
+    h.cx[7] = s15 * xz;
+    h.cx[8] = 0.75f * s10 * dxy;
+    h.cx[9] = 0.5f * s35 * (3.0f * x2 * y - y2 * y);
+    h.cx[10] = c43 * 6.0f * xyz;
+    h.cx[11] = 0.5f * s5 * y * z7;
+    h.cx[12] = c41 * z * z73;
+    h.cx[13] = 0.5f * s5 * x * z7;
+    h.cx[14] = c43 * 3.0f * z * dxy;
+    h.cx[15] = 0.5f * s35 * (x2 * x - 3.0f * x * y2);
+    // d/dy for lm = 0 3 4 7 8 9 10 13 14 15 16 17 18 21 22 23
+    h.cy[0] = 1.0f;
+    h.cy[1] = s3 * x;
+    h.cy[2] = s3 * z;
+    h.cy[3] = -s3 * y;
+    h.cy[4] = 0.75f * s10 * dxy;
+    h.cy[5] = s15 * xz;
+    h.cy[6] = 0.25f * s6 * z5;
+    h.cy[7] = -s15 * yz;
+    h.cy[8] = -1.5f * s10 * xy;
+    h.cy[9] = 0.5f * s35 * (x2 * x - 3.0f * x * y2);
+    h.cy[10] = c43 * 3.0f * z * dxy;
+    h.cy[11] = 0.5f * s5 * x * z7;
+    h.cy[12] = c41 * z * z73;
+    h.cy[13] = -0.5f * s5 * y * z7;
+    h.cy[14] = -c43 * 6.0f * xyz;
+    h.cy[15] = 0.5f * s35 * (y2 * y - 3.0f * x2 * y);
+    // d/dz for lm = 1 4 5 6 9 10 11 12 13 16 17 18 19 20 21 22
+    h.cz[0] = 1.0f;
+    h.cz[1] = s3 * y;
+    h.cz[2] = 3.0f * z;
+    h.cz[3] = s3 * x;
+    h.cz[4] = s15 * xy;
+    h.cz[5] = 2.5f * s6 * yz;
+    h.cz[6] = 7.5f * z2 - 1.5f;
+    h.cz[7] = 2.5f * s6 * xz;
+    h.cz[8] = 0.5f * s15 * dxy;
+    h.cz[9] = c43 * y * (3.0f * x2 - y2);
+    h.cz[10] = 7.0f * s5 * xyz;
+    h.cz[11] = c41 * y * z21;
+    h.cz[12] = 17.5f * z2 * z - 7.5f * z;
+    h.cz[13] = c41 * x * z21;
+    h.cz[14] = 3.5f * s5 * z * dxy;
+    h.cz[15] = c43 * x * (x2 - 3.0f * y2);
+    return h;
+}
+__device__ inline void harmonics_grad_apply(const HarmonicsGrad &h, const float *Q, float &gx, float &gy,
+                                            float &gz) {
+    float ax = 0.f, ay = 0.f, az = 0.f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        ax = fmaf(h.cx[i], Q[HG_X[i]], ax);
+        ay = fmaf(h.cy[i], Q[HG_Y[i]], ay);
+        az = fmaf(h.cz[i], Q[HG_Z[i]], az);
+    }
     gx = ax;
     gy = ay;
     gz = az;
