@@ -80,33 +80,89 @@ struct Roots<8> {
                                    0.0f, -0.70710678118654752f, -1.0f, -0.70710678118654752f};
 };
 
-// small DFT of length R: out_m = sum_r a_r w^{r m}, w = e^{sign 2 pi i / R}
-template <int R>
-__device__ inline void dft_small(float2 (&a)[R], float sign) {
-    float2 o[R];
-#pragma unroll
-    for (int m = 0; m < R; ++m) {
-        float2 acc = a[0];
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-            const int idx = (r * m) % R;
-            const float2 w = make_float2(Roots<R>::c[idx], sign * Roots<R>::s[idx]);
-            const float2 t = cmul(a[r], w);
-            acc.x += t.x;
-            acc.y += t.y;
-        }
-        o[m] = acc;
-    }
-#pragma unroll
-    for (int m = 0; m < R; ++m) a[m] = o[m];
+// small DFT of length R: out_m = sum_r a_r w^{r m}, w = e^{SG 2 pi i / R}, SG = +-1.
+// Radices 3 and 5 by the definition with constant roots; 2, 4 and 8 as butterflies
+// (8 = two radix-4 transforms of the even and odd inputs joined by w^m).
+__device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+template <int SG>
+__device__ inline float2 mul_i(float2 a) {  // (SG i) a
+    return make_float2(-(float)SG * a.y, (float)SG * a.x);
 }
 
-// one Stockham stage over `nlines` lines of stride Lp; tw[m] = e^{sign 2 pi i m / L}
+template <int R, int SG>
+struct SmallDft {
+    __device__ static void run(float2 (&a)[R]) {
+        float2 o[R];
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            float2 acc = a[0];
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                const int idx = (r * m) % R;
+                const float2 t = cmul(a[r], make_float2(Roots<R>::c[idx], (float)SG * Roots<R>::s[idx]));
+                acc.x += t.x;
+                acc.y += t.y;
+            }
+            o[m] = acc;
+        }
+#pragma unroll
+        for (int m = 0; m < R; ++m) a[m] = o[m];
+    }
+};
+template <int SG>
+struct SmallDft<2, SG> {
+    __device__ static void run(float2 (&a)[2]) {
+        const float2 t = a[0];
+        a[0] = cadd(t, a[1]);
+        a[1] = csub(t, a[1]);
+    }
+};
+template <int SG>
+__device__ inline void dft4(float2 a0, float2 a1, float2 a2, float2 a3, float2 (&o)[4]) {
+    const float2 t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3), t3 = mul_i<SG>(csub(a1, a3));
+    o[0] = cadd(t0, t2);
+    o[1] = cadd(t1, t3);
+    o[2] = csub(t0, t2);
+    o[3] = csub(t1, t3);
+}
+template <int SG>
+struct SmallDft<4, SG> {
+    __device__ static void run(float2 (&a)[4]) {
+        float2 o[4];
+        dft4<SG>(a[0], a[1], a[2], a[3], o);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) a[m] = o[m];
+    }
+};
+template <int SG>
+struct SmallDft<8, SG> {
+    __device__ static void run(float2 (&a)[8]) {
+        constexpr float h = 0.70710678118654752f;
+        float2 e[4], d[4];
+        dft4<SG>(a[0], a[2], a[4], a[6], e);
+        dft4<SG>(a[1], a[3], a[5], a[7], d);
+        // w^1 d1 = h (x - SG y, SG x + y), w^2 d2 = (SG i) d2, w^3 d3 = h (-x - SG y, SG x - y)
+        const float2 w1 = make_float2(h * (d[1].x - (float)SG * d[1].y), h * ((float)SG * d[1].x + d[1].y));
+        const float2 w2 = mul_i<SG>(d[2]);
+        const float2 w3 = make_float2(h * (-d[3].x - (float)SG * d[3].y), h * ((float)SG * d[3].x - d[3].y));
+        a[0] = cadd(e[0], d[0]);
+        a[4] = csub(e[0], d[0]);
+        a[1] = cadd(e[1], w1);
+        a[5] = csub(e[1], w1);
+        a[2] = cadd(e[2], w2);
+        a[6] = csub(e[2], w2);
+        a[3] = cadd(e[3], w3);
+        a[7] = csub(e[3], w3);
+    }
+};
+
+// one Stockham stage over `nlines` lines of stride Lp; tw[m] = e^{SG 2 pi i m / L}
 // nbs, nss: log2 of L / R and of Ns when L is a power of two (shifts replace the
 // integer divisions), else -1
-template <int R>
+template <int R, int SG>
 __device__ inline void stage(const float2 *__restrict__ src, float2 *__restrict__ dst, const float2 *__restrict__ tw,
-                             int L, int Lp, int nlines, int Ns, float sign, int nbs, int nss) {
+                             int L, int Lp, int nlines, int Ns, int nbs, int nss) {
     const int nb = L / R;
     const int tstep = L / (Ns * R);  // twiddle index step: e^{2 pi i r k / (Ns R)} = tw[r k tstep]
     for (int bf = threadIdx.x; bf < nlines * nb; bf += FFT_THREADS) {
@@ -121,7 +177,7 @@ __device__ inline void stage(const float2 *__restrict__ src, float2 *__restrict_
 #pragma unroll
             for (int r = 1; r < R; ++r) a[r] = cmul(a[r], tw[r * k * tstep]);
         }
-        dft_small<R>(a, sign);
+        SmallDft<R, SG>::run(a);
         const int base = (j - k) * R + k;  // (j / Ns) Ns R + k
 #pragma unroll
         for (int r = 0; r < R; ++r) d[base + r * Ns] = a[r];
@@ -132,8 +188,9 @@ __device__ inline void stage(const float2 *__restrict__ src, float2 *__restrict_
 // o * L * S + p * S + in.  S > 1: a block holds B consecutive `in` of one `o`;
 // S == 1: B consecutive `o`.
 // ls, bs: log2 L and log2 B when they are powers of two, else -1
+template <int SG>
 __global__ __launch_bounds__(FFT_THREADS) void k_fft_axis(float2 *__restrict__ data, FftPlan1D plan, int S,
-                                                           int nouter, int B, float sign, int ls, int bs) {
+                                                           int nouter, int B, int ls, int bs) {
     extern __shared__ float2 lds[];
     const int L = plan.L, Lp = L + 1;
     float2 *tw = lds;
@@ -141,7 +198,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_axis(float2 *__restrict__ d
     for (int m = threadIdx.x; m < L; m += FFT_THREADS) {
         float sn, cs;
         sincospif(2.0f * (float)m / (float)L, &sn, &cs);
-        tw[m] = make_float2(cs, sign * sn);
+        tw[m] = make_float2(cs, (float)SG * sn);
     }
     int o0, in0, nl;
     if (S > 1) {
@@ -177,11 +234,11 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_axis(float2 *__restrict__ d
         const int rl = R == 8 ? 3 : (R == 4 ? 2 : 1);  // log2 R (used only when L is a power of two)
         const int nbs = ls >= 0 ? ls - rl : -1, nss = ls >= 0 ? nsl : -1;
         switch (R) {
-            case 8: stage<8>(src, dst, tw, L, Lp, nl, Ns, sign, nbs, nss); break;
-            case 4: stage<4>(src, dst, tw, L, Lp, nl, Ns, sign, nbs, nss); break;
-            case 2: stage<2>(src, dst, tw, L, Lp, nl, Ns, sign, nbs, nss); break;
-            case 5: stage<5>(src, dst, tw, L, Lp, nl, Ns, sign, -1, -1); break;
-            default: stage<3>(src, dst, tw, L, Lp, nl, Ns, sign, -1, -1); break;
+            case 8: stage<8, SG>(src, dst, tw, L, Lp, nl, Ns, nbs, nss); break;
+            case 4: stage<4, SG>(src, dst, tw, L, Lp, nl, Ns, nbs, nss); break;
+            case 2: stage<2, SG>(src, dst, tw, L, Lp, nl, Ns, nbs, nss); break;
+            case 5: stage<5, SG>(src, dst, tw, L, Lp, nl, Ns, -1, -1); break;
+            default: stage<3, SG>(src, dst, tw, L, Lp, nl, Ns, -1, -1); break;
         }
         Ns *= R;
         nsl += rl;
@@ -228,15 +285,22 @@ hipError_t fft3d(float2 *data, float2 * /*tmp*/, const int *mesh, int sign, hipS
         // twiddle table plus two buffers of B lines of L + 1 elements (at most 139 KB)
         const size_t lds = sizeof(float2) * ((size_t)L + 2 * (size_t)(L + 1) * B);
         if (lds > lds_allowed) {
-            hipError_t e = hipFuncSetAttribute((const void *)k_fft_axis, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               (int)lds);
+            hipError_t e = hipFuncSetAttribute((const void *)k_fft_axis<-1>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e == hipSuccess)
+                e = hipFuncSetAttribute((const void *)k_fft_axis<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)lds);
             if (e != hipSuccess) return e;
             lds_allowed = lds;
         }
         const int ls = (L & (L - 1)) == 0 ? __builtin_ctz(L) : -1;
         const int bs = (B & (B - 1)) == 0 ? __builtin_ctz(B) : -1;
-        hipLaunchKernelGGL(k_fft_axis, dim3(blocks), dim3(FFT_THREADS), lds, s, data, plan, S, nouter, B,
-                           (float)sign, ls, bs);
+        if (sign < 0)
+            hipLaunchKernelGGL(k_fft_axis<-1>, dim3(blocks), dim3(FFT_THREADS), lds, s, data, plan, S, nouter, B, ls,
+                               bs);
+        else
+            hipLaunchKernelGGL(k_fft_axis<1>, dim3(blocks), dim3(FFT_THREADS), lds, s, data, plan, S, nouter, B, ls,
+                               bs);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
