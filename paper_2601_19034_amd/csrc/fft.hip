@@ -200,14 +200,17 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_axis(float2 *__restrict__ d
         sincospif(2.0f * (float)m / (float)L, &sn, &cs);
         tw[m] = make_float2(cs, (float)SG * sn);
     }
+    // XCD-aware order: neighbouring batches (which share 128-byte lines on the strided
+    // axes) run on the same XCD and meet in its L2
+    const int blk = xcd_block();
     int o0, in0, nl;
     if (S > 1) {
         const int groups = (S + B - 1) / B;
-        o0 = blockIdx.x / groups;
-        in0 = (blockIdx.x % groups) * B;
+        o0 = blk / groups;
+        in0 = (blk % groups) * B;
         nl = min(B, S - in0);
     } else {
-        o0 = blockIdx.x * B;
+        o0 = blk * B;
         in0 = 0;
         nl = min(B, nouter - o0);
     }
