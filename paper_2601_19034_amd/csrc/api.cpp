@@ -250,6 +250,7 @@ qnep_status make_plan(const Model &m, const qnep_es_params *es, const qnep_syste
     p.capA = capacity(density, p.rcA, m.cap_factor);
     p.nblk = (p.N + RED_THREADS - 1) / RED_THREADS;
     int64_t red_blocks = std::max(p.nblk, 1);
+    red_blocks = std::max<int64_t>(red_blocks, ((int64_t)p.N * PARTIALS_LANES_MAX + RED_THREADS - 1) / RED_THREADS);
     if (p.method == 0) {
         if (!(p.kmax > 0)) return fail(QNEP_E_INVALID_ARG, "kmax must be positive for Ewald");
         for (int a = 0; a < 3; ++a) {
@@ -268,6 +269,8 @@ qnep_status make_plan(const Model &m, const qnep_es_params *es, const qnep_syste
                 return fail(QNEP_E_UNSUPPORTED, "mesh sizes must be products of 2, 3, 5 up to 1024");
         p.mesh_pts = (int64_t)p.mesh[0] * p.mesh[1] * p.mesh[2];
         red_blocks = std::max<int64_t>(red_blocks, (p.mesh_pts + 255) / 256);
+        // the influence kernel: one work-group per row along c, at most 4096
+        red_blocks = std::max<int64_t>(red_blocks, std::min<int64_t>((int64_t)p.mesh[0] * p.mesh[1], 4096));
         BrickGeom bg;
         p.bricks = spread_bricks(p.mesh, p.nc, &bg);
         for (int a = 0; a < 3; ++a) {

@@ -11,6 +11,9 @@ constexpr int LM = 24;                // real harmonics (l, m) for l = 1..4
 constexpr int MAX_T = 4;              // species compiled in
 constexpr int MAX_NEU = 64;           // hidden units
 constexpr int RED_THREADS = 256;      // threads of every block that writes FP64 partials
+// most lanes per atom among the kernels that write FP64 partials (real space, radial
+// forces); the partials buffer holds one row per work-group of the largest grid
+constexpr int PARTIALS_LANES_MAX = 16;
 
 // Cell passed by value to kernels: rows of h are the cell vectors a, b, c.
 struct Cell {

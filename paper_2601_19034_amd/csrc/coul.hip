@@ -21,6 +21,7 @@ namespace qnep {
 constexpr int RS_LANES = 16;
 constexpr int RS_APB = 256 / RS_LANES;  // atoms per work-group
 constexpr int RS_SEG = 128;             // segments of one atom held in LDS at a time
+static_assert(RS_LANES <= PARTIALS_LANES_MAX, "partials buffer sized for PARTIALS_LANES_MAX lanes per atom");
 
 // positions with the corrected charge q' in w: one 16-byte load per candidate
 __global__ void k_pack_charges(int N, const float4 *__restrict__ xyzt, const float *__restrict__ qraw,

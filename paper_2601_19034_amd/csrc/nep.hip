@@ -185,6 +185,7 @@ __global__ __launch_bounds__(256) void k_radial_tables(int N, const int *__restr
 // RF_LANES lanes share one atom and split its neighbours; the sums are combined
 // across the lane group with butterfly shuffles.
 constexpr int RF_LANES = 16;
+static_assert(RF_LANES <= PARTIALS_LANES_MAX, "partials buffer sized for PARTIALS_LANES_MAX lanes per atom");
 
 template <int T, int NB>
 __global__ __launch_bounds__(256) void k_radial_forces(int N, const float4 *__restrict__ xyzt, Cell c, float rcR,
@@ -288,6 +289,7 @@ __global__ __launch_bounds__(256) void k_radial_forces(int N, const float4 *__re
 // pairA (charge), adds the own force and Z contributions, and the virial partials.
 constexpr int AF_LANES = 8;
 constexpr int AF_APB = 256 / AF_LANES;  // atoms per work-group
+static_assert(AF_LANES <= PARTIALS_LANES_MAX, "partials buffer sized for PARTIALS_LANES_MAX lanes per atom");
 
 // one gradient's pair force from its Atilde table (rows of LM = 24 floats, 16-byte aligned)
 template <int NA>
@@ -448,6 +450,7 @@ __device__ inline int find_slot(const uint32_t *__restrict__ listA, int j, int c
 // writes F, Z*, q', q~' in input order and FP64 partials of P = sum_i q~'_i r_i.
 // AS_LANES lanes share one atom and split its angular neighbours.
 constexpr int AS_LANES = 8;
+static_assert(AS_LANES <= PARTIALS_LANES_MAX, "partials buffer sized for PARTIALS_LANES_MAX lanes per atom");
 
 __global__ __launch_bounds__(256) void k_assemble(
     int N, const float4 *__restrict__ xyzt, Cell c, const uint32_t *__restrict__ listA,

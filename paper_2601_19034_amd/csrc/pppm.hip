@@ -253,64 +253,78 @@ __device__ inline float alias_poly5(float z) {
     return 1.0f + z2 * (-5.0f / 3.0f + z2 * (7.0f / 9.0f + z2 * (-17.0f / 189.0f + z2 * (2.0f / 2835.0f))));
 }
 
-__device__ inline float sinc_pi(float x) {  // sin(pi x)/(pi x)
-    if (x == 0.0f) return 1.0f;
-    return sinpif(x) / (3.14159265358979f * x);
+// per-axis factors of G_opt at x = n / N: sinc^{10}(x) and alias_poly5(sin^2(pi x))^2
+__device__ inline void gopt_axis(float x, float &num, float &den) {
+    const float sn = sinpif(x);
+    const float sc = x == 0.0f ? 1.0f : sn / (3.14159265358979f * x);
+    const float sc2 = sc * sc, sc5 = sc2 * sc2 * sc;
+    const float d = alias_poly5(sn);
+    num = sc5 * sc5;
+    den = d * d;
 }
 
 // Pointwise in k: energy and virial partials, then the two packed spectra
 //   A <- i X (k~_z + 1)  (inverse: E_z + i phi'),  B <- i X k~_x - X k~_y  (inverse: E_x + i E_y)
 // with X = S G_opt and k~ the derivative wave vector (zero index at a Nyquist plane).
+// A work-group takes whole rows along c (the row's a and b factors once per row).
 __global__ __launch_bounds__(256) void k_influence(MeshGeom g, Cell c, float alpha, double vol,
                                                    float2 *__restrict__ A, float2 *__restrict__ Bm,
                                                    double *__restrict__ partials) {
-    const int64_t M = (int64_t)g.n[0] * g.n[1] * g.n[2];
-    double red[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < M;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        const int j2 = (int)(idx % g.n[2]);
-        const int j1 = (int)((idx / g.n[2]) % g.n[1]);
-        const int j0 = (int)(idx / ((int64_t)g.n[2] * g.n[1]));
-        int nv[3] = {2 * j0 < g.n[0] ? j0 : j0 - g.n[0], 2 * j1 < g.n[1] ? j1 : j1 - g.n[1],
-                     2 * j2 < g.n[2] ? j2 : j2 - g.n[2]};
-        const float2 S = A[idx];
-        if (nv[0] == 0 && nv[1] == 0 && nv[2] == 0) {
-            A[idx] = make_float2(0.f, 0.f);
-            Bm[idx] = make_float2(0.f, 0.f);
-            continue;
-        }
-        int nt[3];
+    const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
+    const float gk = (float)(2.0 * PI_D / vol), ia2 = 1.0f / (4.0f * alpha * alpha), cB0 = 2.0f * ia2;
+    const float in2 = 1.0f / (float)n2;
+    float kz[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) nt[a] = ((g.n[a] & 1) == 0 && 2 * nv[a] == -g.n[a]) ? 0 : nv[a];
-        float k[3], kt[3];
+    for (int b = 0; b < 3; ++b) kz[b] = (float)(2.0 * PI_D * c.hinv[3 * b + 2]);
+    double red[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int row = blockIdx.x; row < n0 * n1; row += gridDim.x) {
+        const int j0 = row / n1, j1 = row - j0 * n1;
+        const int nv0 = 2 * j0 < n0 ? j0 : j0 - n0, nv1 = 2 * j1 < n1 ? j1 : j1 - n1;
+        const int nt0 = ((n0 & 1) == 0 && 2 * nv0 == -n0) ? 0 : nv0;
+        const int nt1 = ((n1 & 1) == 0 && 2 * nv1 == -n1) ? 0 : nv1;
+        float kr[3], ktr[3];
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
-            k[b] = (float)(2.0 * PI_D * (c.hinv[3 * b] * nv[0] + c.hinv[3 * b + 1] * nv[1] + c.hinv[3 * b + 2] * nv[2]));
-            kt[b] = (float)(2.0 * PI_D * (c.hinv[3 * b] * nt[0] + c.hinv[3 * b + 1] * nt[1] + c.hinv[3 * b + 2] * nt[2]));
+            kr[b] = (float)(2.0 * PI_D * (c.hinv[3 * b] * nv0 + c.hinv[3 * b + 1] * nv1));
+            ktr[b] = (float)(2.0 * PI_D * (c.hinv[3 * b] * nt0 + c.hinv[3 * b + 1] * nt1));
         }
-        const float k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
-        const float G = (float)(2.0 * PI_D / vol) * __expf(-k2 / (4.0f * alpha * alpha)) / k2;
-        float num = 1.0f, den = 1.0f;
+        float num0, den0, num1, den1;
+        gopt_axis((float)nv0 / (float)n0, num0, den0);
+        gopt_axis((float)nv1 / (float)n1, num1, den1);
+        const float num01 = num0 * num1, den01 = den0 * den1;
+        for (int j2 = threadIdx.x; j2 < n2; j2 += blockDim.x) {
+            const size_t idx = (size_t)row * n2 + j2;
+            const int nv2 = 2 * j2 < n2 ? j2 : j2 - n2;
+            const float2 S = A[idx];
+            if (nv0 == 0 && nv1 == 0 && nv2 == 0) {
+                A[idx] = make_float2(0.f, 0.f);
+                Bm[idx] = make_float2(0.f, 0.f);
+                continue;
+            }
+            const int nt2 = ((n2 & 1) == 0 && 2 * nv2 == -n2) ? 0 : nv2;
+            float k[3], kt[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const float x = (float)nv[a] / (float)g.n[a];
-            const float sc = sinc_pi(x);
-            const float sc2 = sc * sc;
-            num *= sc2 * sc2 * sc;
-            den *= alias_poly5(sinpif(x));
+            for (int b = 0; b < 3; ++b) {
+                k[b] = fmaf(kz[b], (float)nv2, kr[b]);
+                kt[b] = fmaf(kz[b], (float)nt2, ktr[b]);
+            }
+            const float k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+            const float ik2 = 1.0f / k2;
+            float num2, den2;
+            gopt_axis((float)nv2 * in2, num2, den2);
+            const float Gopt = gk * __expf(-k2 * ia2) * ik2 * (num01 * num2) / (den01 * den2);
+            const float e = (float)KE * Gopt * (S.x * S.x + S.y * S.y);
+            const float cB = cB0 + 2.0f * ik2;
+            red[0] += e;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) red[1 + 3 * a + b] += e * ((a == b ? 1.0f : 0.0f) - cB * k[a] * k[b]);
+            const float2 X = make_float2(S.x * Gopt, S.y * Gopt);
+            const float2 iX = make_float2(-X.y, X.x);
+            A[idx] = make_float2(iX.x * (kt[2] + 1.0f), iX.y * (kt[2] + 1.0f));
+            Bm[idx] = make_float2(iX.x * kt[0] - X.x * kt[1], iX.y * kt[0] - X.y * kt[1]);
         }
-        const float Gopt = G * (num * num) / (den * den);
-        const float e = (float)KE * Gopt * (S.x * S.x + S.y * S.y);
-        const float cB = 2.0f / (4.0f * alpha * alpha) + 2.0f / k2;
-        red[0] += e;
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) red[1 + 3 * a + b] += e * ((a == b ? 1.0f : 0.0f) - cB * k[a] * k[b]);
-        const float2 X = make_float2(S.x * Gopt, S.y * Gopt);
-        const float2 iX = make_float2(-X.y, X.x);
-        A[idx] = make_float2(iX.x * (kt[2] + 1.0f), iX.y * (kt[2] + 1.0f));
-        Bm[idx] = make_float2(iX.x * kt[0] - X.x * kt[1], iX.y * kt[0] - X.y * kt[1]);
     }
     block_partials<10>(red, partials);
 }
@@ -390,7 +404,8 @@ hipError_t launch_pppm(const Plan &p) {
     e = fft3d(p.meshA, nullptr, p.mesh, -1, p.stream);
     if (e != hipSuccess) return e;
     stage_mark(p, ST_FFT_FWD, 3);
-    const int GI = GM < 2048 ? GM : 2048;
+    const int rows = p.mesh[0] * p.mesh[1];
+    const int GI = rows < 4096 ? rows : 4096;
     hipLaunchKernelGGL(k_influence, dim3(GI), dim3(256), 0, p.stream, g, p.cell, (float)p.alpha, p.vol, p.meshA,
                        p.meshB, p.partials);
     e = hipGetLastError();
