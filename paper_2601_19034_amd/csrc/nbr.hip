@@ -270,16 +270,26 @@ hipError_t fill_zero(void *ptr, size_t bytes, hipStream_t s) {
     return hipGetLastError();
 }
 
-// one block per reduced value; fixed-order tree, so the result is deterministic
-__global__ void k_reduce_partials(const double *__restrict__ partials, int nblk, int nv, double *__restrict__ out,
-                                  int accumulate) {
-    __shared__ double red[256];
+// one block of RP_THREADS per reduced value; every thread keeps four independent
+// sums over a fixed stride, then a fixed-order tree: the result is deterministic
+constexpr int RP_THREADS = 1024;
+
+__global__ __launch_bounds__(RP_THREADS) void k_reduce_partials(const double *__restrict__ partials, int nblk,
+                                                                 int nv, double *__restrict__ out, int accumulate) {
+    __shared__ double red[RP_THREADS];
     const int k = blockIdx.x;
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += 256) s += partials[(size_t)b * nv + k];
-    red[threadIdx.x] = s;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int b = threadIdx.x;
+    for (; b + 3 * RP_THREADS < nblk; b += 4 * RP_THREADS) {
+        s0 += partials[(size_t)b * nv + k];
+        s1 += partials[(size_t)(b + RP_THREADS) * nv + k];
+        s2 += partials[(size_t)(b + 2 * RP_THREADS) * nv + k];
+        s3 += partials[(size_t)(b + 3 * RP_THREADS) * nv + k];
+    }
+    for (; b < nblk; b += RP_THREADS) s0 += partials[(size_t)b * nv + k];
+    red[threadIdx.x] = (s0 + s1) + (s2 + s3);
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
+    for (int o = RP_THREADS / 2; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
@@ -287,12 +297,12 @@ __global__ void k_reduce_partials(const double *__restrict__ partials, int nblk,
 }
 
 hipError_t reduce_partials_to(const Plan &p, int nblk, int nv, double *dst) {
-    hipLaunchKernelGGL(k_reduce_partials, dim3(nv), dim3(256), 0, p.stream, p.partials, nblk, nv, dst, 0);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(nv), dim3(RP_THREADS), 0, p.stream, p.partials, nblk, nv, dst, 0);
     return hipGetLastError();
 }
 
 hipError_t reduce_partials(const Plan &p, int nblk, int nv, int slot, bool accumulate) {
-    hipLaunchKernelGGL(k_reduce_partials, dim3(nv), dim3(256), 0, p.stream, p.partials, nblk, nv, p.scalars + slot,
+    hipLaunchKernelGGL(k_reduce_partials, dim3(nv), dim3(RP_THREADS), 0, p.stream, p.partials, nblk, nv, p.scalars + slot,
                        accumulate ? 1 : 0);
     return hipGetLastError();
 }

@@ -362,8 +362,11 @@ __global__ __launch_bounds__(256) void k_angular_forces(
         const float4 pi = xyzt[i];
         const int ti = species_of(pi);
         const int nA = cntA[i];
+        const uint32_t *lrow = listA + (size_t)i * capA;
+        uint32_t e_next = sub < nA ? lrow[sub] : 0u;  // the next entry is loaded one pass ahead
         for (int sl = sub; sl < nA; sl += AF_LANES) {
-            const uint32_t e = listA[(size_t)i * capA + sl];
+            const uint32_t e = e_next;
+            if (sl + AF_LANES < nA) e_next = lrow[sl + AF_LANES];
             const float4 pj = xyzt[nb_index(e)];
             const float3 d = pair_displacement(pi, pj, e, c);
             const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
@@ -429,17 +432,37 @@ __global__ __launch_bounds__(256) void k_angular_forces(
     block_partials<9>(w, partials);
 }
 
-// slot of `want` in atom j's angular list (-1 if absent); rows are 16-byte aligned
-__device__ inline int find_slot(const uint32_t *__restrict__ listA, int j, int capA, int nj, uint32_t want) {
+// slot of `want` in atom j's angular list (-1 if absent); rows are 16-byte aligned.
+// The first FS_AHEAD 16-byte groups of the row are loaded together with nj (one
+// round trip covers lists of up to 4 FS_AHEAD entries); longer rows continue in order.
+constexpr int FS_AHEAD = 6;
+
+__device__ inline int find_slot(const uint32_t *__restrict__ listA, const int *__restrict__ cntA, int j, int capA,
+                                uint32_t want) {
     const uint4 *row = reinterpret_cast<const uint4 *>(listA + (size_t)j * capA);
-    for (int t4 = 0; 4 * t4 < nj; ++t4) {
-        // entries at or past nj are stale and must not match
-        const uint4 v = row[t4];
+    const int ng = capA / 4 < FS_AHEAD ? capA / 4 : FS_AHEAD;
+    uint4 v[FS_AHEAD];
+#pragma unroll
+    for (int t = 0; t < FS_AHEAD; ++t) v[t] = t < ng ? row[t] : make_uint4(0u, 0u, 0u, 0u);
+    const int nj = cntA[j];
+    // entries at or past nj are stale and must not match
+#pragma unroll
+    for (int t = 0; t < FS_AHEAD; ++t) {
+        const int b = 4 * t;
+        if (t < ng) {
+            if (v[t].x == want && b < nj) return b;
+            if (v[t].y == want && b + 1 < nj) return b + 1;
+            if (v[t].z == want && b + 2 < nj) return b + 2;
+            if (v[t].w == want && b + 3 < nj) return b + 3;
+        }
+    }
+    for (int t4 = ng; 4 * t4 < nj; ++t4) {
+        const uint4 u = row[t4];
         const int b = 4 * t4;
-        if (v.x == want) return b;
-        if (v.y == want && b + 1 < nj) return b + 1;
-        if (v.z == want && b + 2 < nj) return b + 2;
-        if (v.w == want && b + 3 < nj) return b + 3;
+        if (u.x == want) return b;
+        if (u.y == want && b + 1 < nj) return b + 1;
+        if (u.z == want && b + 2 < nj) return b + 2;
+        if (u.w == want && b + 3 < nj) return b + 3;
     }
     return -1;
 }
@@ -468,10 +491,13 @@ __global__ __launch_bounds__(256) void k_assemble(
     if (i < N) {
         const float4 pi = xyzt[i];
         const int nA = cntA[i];
+        const uint32_t *lrow = listA + (size_t)i * capA;
+        uint32_t e_next = sub < nA ? lrow[sub] : 0u;  // the next entry is loaded one pass ahead
         for (int sl = sub; sl < nA; sl += AS_LANES) {
-            const uint32_t e = listA[(size_t)i * capA + sl];
+            const uint32_t e = e_next;
+            if (sl + AS_LANES < nA) e_next = lrow[sl + AS_LANES];
             const int j = nb_index(e);
-            const int found = find_slot(listA, j, capA, cntA[j], nb_reverse(e, i));
+            const int found = find_slot(listA, cntA, j, capA, nb_reverse(e, i));
             if (found < 0) continue;  // pair at the cutoff on one side only: contributes zero
             const float4 fji = pairF[(size_t)j * capA + found];
             const float4 aji = pairA[(size_t)j * capA + found];
