@@ -207,21 +207,35 @@ __global__ __launch_bounds__(256) void k_radial_forces(int N, const float4 *__re
         for (int s = sub; s < nR; s += RF_LANES) {
             const uint32_t e = listR[(size_t)i * capR + s];
             const int j = nb_index(e);
+            // every load of the pair is issued before any of them is used: the
+            // neighbour's rows for this atom's species (16-byte aligned), its position,
+            // then this atom's rows for the neighbour's species
+            const float4 *ne = reinterpret_cast<const float4 *>(hT + (size_t)j * (2 * T * NBP) + ti * NBP);
+            const float4 *nq = reinterpret_cast<const float4 *>(hT + (size_t)j * (2 * T * NBP) + T * NBP + ti * NBP);
+            float4 xr[NBP / 4], yr[NBP / 4];
+#pragma unroll
+            for (int k4 = 0; k4 < NBP / 4; ++k4) {
+                xr[k4] = ne[k4];
+                yr[k4] = nq[k4];
+            }
             const float4 pj = xyzt[j];
+            const int tj = species_of(pj);
+            const float4 *oe = reinterpret_cast<const float4 *>(own + tj * NBP);
+            const float4 *oq = reinterpret_cast<const float4 *>(own + T * NBP + tj * NBP);
+            float4 ar[NBP / 4], br[NBP / 4];
+#pragma unroll
+            for (int k4 = 0; k4 < NBP / 4; ++k4) {
+                ar[k4] = oe[k4];
+                br[k4] = oq[k4];
+            }
             const float3 d = pair_displacement(pi, pj, e, c);
             const float r = sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
             float f[NB], df[NB];
             cheb_basis<NB>(r, rcR, f, df);
-            const int tj = species_of(pj);
-            // own tables for the neighbour's species (rows are 16-byte aligned)
-            const float4 *oe = reinterpret_cast<const float4 *>(own + tj * NBP);
-            const float4 *oq = reinterpret_cast<const float4 *>(own + T * NBP + tj * NBP);
-            const float4 *ne = reinterpret_cast<const float4 *>(hT + (size_t)j * (2 * T * NBP) + ti * NBP);
-            const float4 *nq = reinterpret_cast<const float4 *>(hT + (size_t)j * (2 * T * NBP) + T * NBP + ti * NBP);
             float sij = 0.f, rij = 0.f, sji = 0.f, rji = 0.f;
 #pragma unroll
             for (int k4 = 0; k4 < NBP / 4; ++k4) {
-                const float4 a = oe[k4], b = oq[k4], x = ne[k4], y = nq[k4];
+                const float4 a = ar[k4], b = br[k4], x = xr[k4], y = yr[k4];
                 const float av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
                 const float xv[4] = {x.x, x.y, x.z, x.w}, yv[4] = {y.x, y.y, y.z, y.w};
 #pragma unroll

@@ -5,14 +5,36 @@
 
 namespace qnep {
 
+// sin and cos of x = (pi/2) u for u in [0, 1] by their Taylor series through x^13 and
+// x^14 (truncation below 1e-9 on [0, pi/2])
+__device__ inline void sincos_half_pi(float u, float &sn, float &cs) {
+    const float x = 1.5707963267948966f * u, x2 = x * x;
+    float ps = fmaf(-x2, 1.0f / 156.0f, 1.0f);
+    ps = fmaf(-x2 * (1.0f / 110.0f), ps, 1.0f);
+    ps = fmaf(-x2 * (1.0f / 72.0f), ps, 1.0f);
+    ps = fmaf(-x2 * (1.0f / 42.0f), ps, 1.0f);
+    ps = fmaf(-x2 * (1.0f / 20.0f), ps, 1.0f);
+    ps = fmaf(-x2 * (1.0f / 6.0f), ps, 1.0f);
+    sn = x * ps;
+    float pc = fmaf(-x2, 1.0f / 182.0f, 1.0f);
+    pc = fmaf(-x2 * (1.0f / 132.0f), pc, 1.0f);
+    pc = fmaf(-x2 * (1.0f / 90.0f), pc, 1.0f);
+    pc = fmaf(-x2 * (1.0f / 56.0f), pc, 1.0f);
+    pc = fmaf(-x2 * (1.0f / 30.0f), pc, 1.0f);
+    pc = fmaf(-x2 * (1.0f / 12.0f), pc, 1.0f);
+    cs = fmaf(-x2 * 0.5f, pc, 1.0f);
+}
+
 // f_k(r) = (T_k(x) + 1)/2 * f_c(r), x = 2 (r/rc - 1)^2 - 1, f_c = (1 + cos(pi r/rc))/2,
 // k = 0..NB-1, and df_k/dr, with T_k' = k U_{k-1}.
 template <int NB>
 __device__ inline void cheb_basis(float r, float rc, float *f, float *df) {
     const float irc = __builtin_amdgcn_rcpf(rc);  // v_rcp_f32, 1 ulp
     const float pr = 3.14159265358979f * irc;
-    const float sn = sinf(pr * r), cs = cosf(pr * r);
-    float fc = 0.5f * (1.0f + cs), dfc = -0.5f * pr * sn;
+    // f_c = cos^2(theta), theta = pi r / (2 rc): no cancellation near the cutoff
+    float sh, ch;
+    sincos_half_pi(r * irc, sh, ch);
+    float fc = ch * ch, dfc = -pr * sh * ch;
     float t = r * irc - 1.0f;
     float x = 2.0f * t * t - 1.0f, dx = 4.0f * t * irc;
     float Tm2 = 1.0f, Tm1 = x;       // T_0, T_1
