@@ -234,9 +234,11 @@ qnep_status make_plan(const Model &m, const qnep_es_params *es, const qnep_syste
         return fail(QNEP_E_INVALID_ARG, "cell must be non-singular and right-handed");
     double w[3];
     cell_widths(p.cell.h, p.vol, w);
+    // bins of about rc_R / 2 across rows and rc_R / 4 along c: a stencil row (one atom
+    // range per image) is trimmed to the cutoff sphere in steps of a quarter cutoff
     const double rbin = 0.5 * std::max(p.rcR, p.rcA);
     for (int a = 0; a < 3; ++a) {
-        p.nc[a] = std::max(1, (int)std::floor(w[a] / rbin));
+        p.nc[a] = std::max(1, (int)std::floor(w[a] / (a == 2 ? 0.5 * rbin : rbin)));
         p.mR[a] = (int)std::ceil(std::max(p.rcR, p.rcA) * p.nc[a] / w[a] - 1e-12);
         p.mC[a] = (int)std::ceil(p.rc_coul * p.nc[a] / w[a] - 1e-12);
         if (p.mR[a] < 1) p.mR[a] = 1;
