@@ -94,6 +94,10 @@ __global__ void k_real_to_complex(int64_t M, const float *__restrict__ rho, floa
 constexpr int SB_P = 16;      // largest brick edge (mesh points)
 constexpr int SB_ROWS = 256;  // rows of bins per brick (one per thread)
 constexpr int SB_SEGS = 512;  // segments (row x image along c) per brick
+// Contributions are added to the LDS tile as 64-bit fixed point (units of 2^-40 e):
+// integer additions are exact and associative, so the mesh does not depend on the
+// order of the additions, and LDS integer atomics are faster than float ones.
+constexpr double SB_SCALE = 1099511627776.0;  // 2^40
 
 __device__ inline int sb_code(int k0, int k1, int k2) { return (k0 + 128) | (k1 + 128) << 8 | (k2 + 128) << 16; }
 
@@ -130,7 +134,7 @@ __global__ __launch_bounds__(256) void k_spread_bricks(const float4 *__restrict_
                                                        int nc0, int nc1, int nc2, BrickGeom bg,
                                                        const int *__restrict__ start, const float *__restrict__ qraw,
                                                        const double *__restrict__ scalars, float2 *__restrict__ out) {
-    __shared__ float tile[SB_P * SB_P * SB_P];
+    __shared__ unsigned long long tile[SB_P * SB_P * SB_P];  // fixed point, SB_SCALE units
     __shared__ int sbeg[SB_SEGS], spre[SB_SEGS + 1], scode[SB_SEGS];
     const int nc[3] = {nc0, nc1, nc2};
     const int br = xcd_block();
@@ -144,7 +148,7 @@ __global__ __launch_bounds__(256) void k_spread_bricks(const float4 *__restrict_
         bhi[a] = (int)floor((M0[a] + Pa[a] + 1.51) * nc[a] / g.n[a]);
     }
     const int TP = bg.P[0] * bg.P[1] * bg.P[2];
-    for (int p = threadIdx.x; p < TP; p += blockDim.x) tile[p] = 0.0f;
+    for (int p = threadIdx.x; p < TP; p += blockDim.x) tile[p] = 0ull;
     // one row of bins (x, y fixed) per thread: count its segments and atoms
     const int ny = bhi[1] - blo[1] + 1, nrows = (bhi[0] - blo[0] + 1) * ny;
     const int r = threadIdx.x;
@@ -214,11 +218,12 @@ __global__ __launch_bounds__(256) void k_spread_bricks(const float4 *__restrict_
                 const int y = l[1] + b;
                 if (y < 0 || y >= Pa[1]) continue;
                 const float qab = qa * w[1][b];
-                float *row = tile + (x * bg.P[1] + y) * bg.P[2];
+                unsigned long long *row = tile + (x * bg.P[1] + y) * bg.P[2];
 #pragma unroll
                 for (int e = 0; e < 5; ++e) {
                     const int z = l[2] + e;
-                    if (z >= 0 && z < Pa[2]) atomicAdd(row + z, qab * w[2][e]);
+                    if (z >= 0 && z < Pa[2])
+                        atomicAdd(row + z, (unsigned long long)__double2ll_rn((double)(qab * w[2][e]) * SB_SCALE));
                 }
             }
         }
@@ -227,7 +232,7 @@ __global__ __launch_bounds__(256) void k_spread_bricks(const float4 *__restrict_
     for (int p = threadIdx.x; p < TP; p += blockDim.x) {
         const int x = p / (bg.P[1] * bg.P[2]), y = (p / bg.P[2]) % bg.P[1], z = p % bg.P[2];
         if (x < Pa[0] && y < Pa[1] && z < Pa[2])
-            out[((size_t)(M0[0] + x) * g.n[1] + (M0[1] + y)) * g.n[2] + (M0[2] + z)] = make_float2(tile[p], 0.0f);
+            out[((size_t)(M0[0] + x) * g.n[1] + (M0[1] + y)) * g.n[2] + (M0[2] + z)] = make_float2((float)((double)(long long)tile[p] * (1.0 / SB_SCALE)), 0.0f);
     }
 }
 
