@@ -369,9 +369,10 @@ __global__ __launch_bounds__(BATCH_THREADS) void k_batch_eval(BatchArgs a, int i
     __shared__ double red[4 * 16];
     __shared__ int s_item;
     const int M = a.max_atoms;
-    // forces accumulate in FP64 so that the sum does not depend on the order of the
-    // LDS atomics (pair terms can be much larger than their sum)
-    double *fx = lds, *fy = fx + M, *fz = fy + M;
+    // forces accumulate in 64-bit fixed point (to_fixed) so that the sum does not
+    // depend on the order of the LDS atomics (pair terms can be much larger than
+    // their sum)
+    unsigned long long *fx = reinterpret_cast<unsigned long long *>(lds), *fy = fx + M, *fz = fy + M;
     float *th = reinterpret_cast<float *>(fz + M);  // parameters of the candidate
     float *qv = th + a.n_theta;                      // q' per atom
     float *phi = qv + M;                             // potential, then chi
@@ -429,11 +430,11 @@ __global__ __launch_bounds__(BATCH_THREADS) void k_batch_eval(BatchArgs a, int i
                     accP += (double)y;
                     accE += 0.5 * (double)qi * (double)y;
                 } else if (comp == 1) {
-                    fx[i] = (double)qi * y;
+                    fx[i] = to_fixed((double)qi * y);
                 } else if (comp == 2) {
-                    fy[i] = (double)qi * y;
+                    fy[i] = to_fixed((double)qi * y);
                 } else if (comp == 3) {
-                    fz[i] = (double)qi * y;
+                    fz[i] = to_fixed((double)qi * y);
                 } else {
                     const double v = 0.5 * (double)qi * (double)y;
                     wes[0] += comp == 4 ? v : 0.0;
@@ -498,9 +499,9 @@ __global__ __launch_bounds__(BATCH_THREADS) void k_batch_eval(BatchArgs a, int i
                     ox += Fx;
                     oy += Fy;
                     oz += Fz;
-                    atomicAdd(&fx[j], -(double)Fx);
-                    atomicAdd(&fy[j], -(double)Fy);
-                    atomicAdd(&fz[j], -(double)Fz);
+                    atomicAdd(&fx[j], to_fixed(-(double)Fx));
+                    atomicAdd(&fy[j], to_fixed(-(double)Fy));
+                    atomicAdd(&fz[j], to_fixed(-(double)Fz));
                     m9[0] -= Fx * e.x; m9[1] -= Fx * e.y; m9[2] -= Fx * e.z;
                     m9[3] -= Fy * e.x; m9[4] -= Fy * e.y; m9[5] -= Fy * e.z;
                     m9[6] -= Fz * e.x; m9[7] -= Fz * e.y; m9[8] -= Fz * e.z;
@@ -566,9 +567,9 @@ __global__ __launch_bounds__(BATCH_THREADS) void k_batch_eval(BatchArgs a, int i
                     ox += Fx;
                     oy += Fy;
                     oz += Fz;
-                    atomicAdd(&fx[j], -(double)Fx);
-                    atomicAdd(&fy[j], -(double)Fy);
-                    atomicAdd(&fz[j], -(double)Fz);
+                    atomicAdd(&fx[j], to_fixed(-(double)Fx));
+                    atomicAdd(&fy[j], to_fixed(-(double)Fy));
+                    atomicAdd(&fz[j], to_fixed(-(double)Fz));
                     m9[0] -= Fx * e.x; m9[1] -= Fx * e.y; m9[2] -= Fx * e.z;
                     m9[3] -= Fy * e.x; m9[4] -= Fy * e.y; m9[5] -= Fy * e.z;
                     m9[6] -= Fz * e.x; m9[7] -= Fz * e.y; m9[8] -= Fz * e.z;
@@ -578,9 +579,9 @@ __global__ __launch_bounds__(BATCH_THREADS) void k_batch_eval(BatchArgs a, int i
             oy = group_sum_d(oy, G);
             oz = group_sum_d(oz, G);
             if (act && lig == 0) {
-                atomicAdd(&fx[i], ox);
-                atomicAdd(&fy[i], oy);
-                atomicAdd(&fz[i], oz);
+                atomicAdd(&fx[i], to_fixed(ox));
+                atomicAdd(&fy[i], to_fixed(oy));
+                atomicAdd(&fz[i], to_fixed(oz));
             }
         }
         __syncthreads();
@@ -589,7 +590,7 @@ __global__ __launch_bounds__(BATCH_THREADS) void k_batch_eval(BatchArgs a, int i
         double accF = 0.0;
         for (int i = tid; i < n; i += BATCH_THREADS) {
             const int64_t g = it.atom0 + i;
-            const float Fx = (float)fx[i], Fy = (float)fy[i], Fz = (float)fz[i];
+            const float Fx = (float)from_fixed(fx[i]), Fy = (float)from_fixed(fy[i]), Fz = (float)from_fixed(fz[i]);
             const double ex = (double)Fx - a.F_ref[g], ey = (double)Fy - a.F_ref[a.n_total + g],
                          ez = (double)Fz - a.F_ref[2 * a.n_total + g];
             accF += ex * ex + ey * ey + ez * ez;

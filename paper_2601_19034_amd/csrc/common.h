@@ -75,6 +75,16 @@ struct ImageShift {
     }
 };
 
+// ---------------------------------------------------------------- fixed point
+// 64-bit fixed point in units of 2^-40 for sums accumulated by LDS atomics: integer
+// additions are exact and associative (the sum does not depend on their order) and
+// LDS integer atomics are faster than floating-point ones.  Range +-8.4e6.
+constexpr double FIX_SCALE = 1099511627776.0;  // 2^40
+__device__ inline unsigned long long to_fixed(double x) {
+    return (unsigned long long)__double2ll_rn(x * FIX_SCALE);
+}
+__device__ inline double from_fixed(unsigned long long v) { return (double)(long long)v * (1.0 / FIX_SCALE); }
+
 // ---------------------------------------------------------------- stencil segments
 // The bins within m_a of an atom's bin, read as rows along c: a row is one contiguous
 // range of sorted atoms per periodic image along c.  A group of lanes that share one

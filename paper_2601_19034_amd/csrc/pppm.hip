@@ -94,10 +94,8 @@ __global__ void k_real_to_complex(int64_t M, const float *__restrict__ rho, floa
 constexpr int SB_P = 16;      // largest brick edge (mesh points)
 constexpr int SB_ROWS = 256;  // rows of bins per brick (one per thread)
 constexpr int SB_SEGS = 512;  // segments (row x image along c) per brick
-// Contributions are added to the LDS tile as 64-bit fixed point (units of 2^-40 e):
-// integer additions are exact and associative, so the mesh does not depend on the
-// order of the additions, and LDS integer atomics are faster than float ones.
-constexpr double SB_SCALE = 1099511627776.0;  // 2^40
+// Contributions are added to the LDS tile in 64-bit fixed point (to_fixed): the mesh
+// does not depend on the order of the additions.
 
 __device__ inline int sb_code(int k0, int k1, int k2) { return (k0 + 128) | (k1 + 128) << 8 | (k2 + 128) << 16; }
 
@@ -134,7 +132,7 @@ __global__ __launch_bounds__(256) void k_spread_bricks(const float4 *__restrict_
                                                        int nc0, int nc1, int nc2, BrickGeom bg,
                                                        const int *__restrict__ start, const float *__restrict__ qraw,
                                                        const double *__restrict__ scalars, float2 *__restrict__ out) {
-    __shared__ unsigned long long tile[SB_P * SB_P * SB_P];  // fixed point, SB_SCALE units
+    __shared__ unsigned long long tile[SB_P * SB_P * SB_P];  // fixed point
     __shared__ int sbeg[SB_SEGS], spre[SB_SEGS + 1], scode[SB_SEGS];
     const int nc[3] = {nc0, nc1, nc2};
     const int br = xcd_block();
@@ -223,7 +221,7 @@ __global__ __launch_bounds__(256) void k_spread_bricks(const float4 *__restrict_
                 for (int e = 0; e < 5; ++e) {
                     const int z = l[2] + e;
                     if (z >= 0 && z < Pa[2])
-                        atomicAdd(row + z, (unsigned long long)__double2ll_rn((double)(qab * w[2][e]) * SB_SCALE));
+                        atomicAdd(row + z, to_fixed((double)(qab * w[2][e])));
                 }
             }
         }
@@ -232,7 +230,7 @@ __global__ __launch_bounds__(256) void k_spread_bricks(const float4 *__restrict_
     for (int p = threadIdx.x; p < TP; p += blockDim.x) {
         const int x = p / (bg.P[1] * bg.P[2]), y = (p / bg.P[2]) % bg.P[1], z = p % bg.P[2];
         if (x < Pa[0] && y < Pa[1] && z < Pa[2])
-            out[((size_t)(M0[0] + x) * g.n[1] + (M0[1] + y)) * g.n[2] + (M0[2] + z)] = make_float2((float)((double)(long long)tile[p] * (1.0 / SB_SCALE)), 0.0f);
+            out[((size_t)(M0[0] + x) * g.n[1] + (M0[1] + y)) * g.n[2] + (M0[2] + z)] = make_float2((float)from_fixed(tile[p]), 0.0f);
     }
 }
 
