@@ -320,7 +320,7 @@ qnep_status make_plan(const Model &m, const qnep_es_params *es, const qnep_syste
     } else {
         if (!p.bricks) p.rho = c.take<float>(p.mesh_pts);
         p.meshA = c.take<float2>(p.mesh_pts);
-        p.meshB = c.take<float2>(p.mesh_pts);
+        p.meshAB = c.take<float2>(2 * p.mesh_pts);
     }
     if (backward) {
         Backward &b = p.bw;

@@ -267,14 +267,16 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_axis(float2 *__restrict__ d
     }
 }
 
-hipError_t fft3d(float2 *data, float2 * /*tmp*/, const int *mesh, int sign, hipStream_t s) {
+// `inner` interleaved transforms: element (m0, m1, m2, t) of transform t at
+// ((m0 n1 + m1) n2 + m2) inner + t; they go through the same launches
+hipError_t fft3d(float2 *data, float2 * /*tmp*/, const int *mesh, int sign, hipStream_t s, int inner) {
     static size_t lds_allowed = 65536;  // the default limit of dynamic LDS per work-group
-    const int64_t M = (int64_t)mesh[0] * mesh[1] * mesh[2];
+    const int64_t M = (int64_t)mesh[0] * mesh[1] * mesh[2] * inner;
     for (int axis = 2; axis >= 0; --axis) {
         FftPlan1D plan;
         if (!make_plan(mesh[axis], plan)) return hipErrorInvalidValue;
         const int L = mesh[axis];
-        const int S = axis == 2 ? 1 : (axis == 1 ? mesh[2] : mesh[1] * mesh[2]);
+        const int S = inner * (axis == 2 ? 1 : (axis == 1 ? mesh[2] : mesh[1] * mesh[2]));
         const int nouter = (int)(M / ((int64_t)L * S));
         int B = FFT_ELEMS / L;
         if (B < 1) B = 1;

@@ -77,7 +77,8 @@ struct Plan {
     bool bricks = false;      // charge assignment by mesh bricks (else global atomics into rho)
     int brickP[3] = {0, 0, 0}, brickNb[3] = {0, 0, 0};
     float *rho = nullptr;
-    float2 *meshA = nullptr, *meshB = nullptr;
+    float2 *meshA = nullptr;   // rho, then its transform S
+    float2 *meshAB = nullptr;  // the two packed spectra / fields, interleaved [point][2]
     // ---- call arguments
     const float *pos = nullptr;
     const int32_t *type = nullptr;
@@ -118,7 +119,7 @@ hipError_t reduce_partials_to(const Plan &p, int nblk, int nv, double *dst);
 hipError_t fill_zero(void *ptr, size_t bytes, hipStream_t s);
 
 // in-house 3D FFT (complex, in place on `data` using `tmp` as scratch); sign -1 forward, +1 inverse
-hipError_t fft3d(float2 *data, float2 *tmp, const int *mesh, int sign, hipStream_t s);
+hipError_t fft3d(float2 *data, float2 *tmp, const int *mesh, int sign, hipStream_t s, int inner = 1);
 bool fft_length_supported(int n);
 
 }  // namespace qnep

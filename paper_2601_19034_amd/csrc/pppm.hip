@@ -5,7 +5,8 @@
 //   P = 5 alias sum), energy k_e sum G_opt |S|^2 (Eq. 34) and virial k_e sum G_opt |S|^2 B
 //   (B as in Eq. 21), ik differentiation for the static force (Eq. 37) and the
 //   potential mesh for the dynamic-charge force (Eq. 38), gathered with the same W.
-// Two packed complex inverse transforms give (E_x + i E_y) and (E_z + i phi).
+// Two packed complex inverse transforms, interleaved per mesh point and run through
+// the same launches, give (E_z + i phi) and (E_x + i E_y).
 #include "plan.h"
 
 namespace qnep {
@@ -269,9 +270,10 @@ __device__ inline void gopt_axis(float x, float &num, float &den) {
 // Pointwise in k: energy and virial partials, then the two packed spectra
 //   A <- i X (k~_z + 1)  (inverse: E_z + i phi'),  B <- i X k~_x - X k~_y  (inverse: E_x + i E_y)
 // with X = S G_opt and k~ the derivative wave vector (zero index at a Nyquist plane).
-// A work-group takes whole rows along c (the row's a and b factors once per row).
+// A work-group takes whole rows along c (the row's a and b factors once per row).  S is
+// read from Sk; A and B are written interleaved, AB[point] = (A, B).
 __global__ __launch_bounds__(256) void k_influence(MeshGeom g, Cell c, float alpha, double vol,
-                                                   float2 *__restrict__ A, float2 *__restrict__ Bm,
+                                                   const float2 *__restrict__ Sk, float4 *__restrict__ AB,
                                                    double *__restrict__ partials) {
     const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
     const float gk = (float)(2.0 * PI_D / vol), ia2 = 1.0f / (4.0f * alpha * alpha), cB0 = 2.0f * ia2;
@@ -298,10 +300,9 @@ __global__ __launch_bounds__(256) void k_influence(MeshGeom g, Cell c, float alp
         for (int j2 = threadIdx.x; j2 < n2; j2 += blockDim.x) {
             const size_t idx = (size_t)row * n2 + j2;
             const int nv2 = 2 * j2 < n2 ? j2 : j2 - n2;
-            const float2 S = A[idx];
+            const float2 S = Sk[idx];
             if (nv0 == 0 && nv1 == 0 && nv2 == 0) {
-                A[idx] = make_float2(0.f, 0.f);
-                Bm[idx] = make_float2(0.f, 0.f);
+                AB[idx] = make_float4(0.f, 0.f, 0.f, 0.f);
                 continue;
             }
             const int nt2 = ((n2 & 1) == 0 && 2 * nv2 == -n2) ? 0 : nv2;
@@ -325,8 +326,8 @@ __global__ __launch_bounds__(256) void k_influence(MeshGeom g, Cell c, float alp
                 for (int b = 0; b < 3; ++b) red[1 + 3 * a + b] += e * ((a == b ? 1.0f : 0.0f) - cB * k[a] * k[b]);
             const float2 X = make_float2(S.x * Gopt, S.y * Gopt);
             const float2 iX = make_float2(-X.y, X.x);
-            A[idx] = make_float2(iX.x * (kt[2] + 1.0f), iX.y * (kt[2] + 1.0f));
-            Bm[idx] = make_float2(iX.x * kt[0] - X.x * kt[1], iX.y * kt[0] - X.y * kt[1]);
+            AB[idx] = make_float4(iX.x * (kt[2] + 1.0f), iX.y * (kt[2] + 1.0f), iX.x * kt[0] - X.x * kt[1],
+                                  iX.y * kt[0] - X.y * kt[1]);
         }
     }
     block_partials<10>(red, partials);
@@ -335,8 +336,8 @@ __global__ __launch_bounds__(256) void k_influence(MeshGeom g, Cell c, float alp
 // phi^k_i += 2 k_e sum_s W phi'_s,  F^k_i += -2 k_e q'_i sum_s W E_s
 __global__ __launch_bounds__(256) void k_gather(int N, const float4 *__restrict__ xyzt, Cell c, MeshGeom g,
                                                 const float *__restrict__ qraw, const double *__restrict__ scalars,
-                                                const float2 *__restrict__ A, const float2 *__restrict__ Bm,
-                                                float *__restrict__ phi, float *__restrict__ Fst) {
+                                                const float4 *__restrict__ AB, float *__restrict__ phi,
+                                                float *__restrict__ Fst) {
     const int i = xcd_block() * blockDim.x + threadIdx.x;
     if (i >= N) return;
     int m0[3];
@@ -360,11 +361,11 @@ __global__ __launch_bounds__(256) void k_gather(int N, const float4 *__restrict_
 #pragma unroll
             for (int e = 0; e < 5; ++e) {
                 const float ww = wab * w[2][e];
-                const float2 va = A[row + j2[e]], vb = Bm[row + j2[e]];
-                ez = fmaf(ww, va.x, ez);
-                ph = fmaf(ww, va.y, ph);
-                ex = fmaf(ww, vb.x, ex);
-                ey = fmaf(ww, vb.y, ey);
+                const float4 v = AB[row + j2[e]];  // (E_z, phi', E_x, E_y)
+                ez = fmaf(ww, v.x, ez);
+                ph = fmaf(ww, v.y, ph);
+                ex = fmaf(ww, v.z, ex);
+                ey = fmaf(ww, v.w, ey);
             }
         }
     }
@@ -410,19 +411,17 @@ hipError_t launch_pppm(const Plan &p) {
     const int rows = p.mesh[0] * p.mesh[1];
     const int GI = rows < 4096 ? rows : 4096;
     hipLaunchKernelGGL(k_influence, dim3(GI), dim3(256), 0, p.stream, g, p.cell, (float)p.alpha, p.vol, p.meshA,
-                       p.meshB, p.partials);
+                       (float4 *)p.meshAB, p.partials);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = reduce_partials(p, GI, 10, S_UK, false);  // S_UK, S_WK[9]
     if (e != hipSuccess) return e;
     stage_mark(p, ST_INFLUENCE, 2);
-    e = fft3d(p.meshA, nullptr, p.mesh, +1, p.stream);
+    e = fft3d(p.meshAB, nullptr, p.mesh, +1, p.stream, 2);  // both spectra in the same launches
     if (e != hipSuccess) return e;
-    e = fft3d(p.meshB, nullptr, p.mesh, +1, p.stream);
-    if (e != hipSuccess) return e;
-    stage_mark(p, ST_FFT_INV, 6);
+    stage_mark(p, ST_FFT_INV, 3);
     hipLaunchKernelGGL(k_gather, dim3(G), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, g, p.qraw,
-                       p.scalars, p.meshA, p.meshB, p.phi, p.Fst);
+                       p.scalars, (const float4 *)p.meshAB, p.phi, p.Fst);
     stage_mark(p, ST_GATHER);
     return hipGetLastError();
 }
