@@ -50,9 +50,16 @@ __global__ __launch_bounds__(256) void k_descriptors(int N, const float4 *__rest
 #pragma unroll
         for (int k = 0; k < NB; ++k) B[t][k] = 0.0f;
     const int nR = cntR[i];
+    // software pipeline: list entries two pairs ahead, neighbour positions one ahead
+    const uint32_t *lr = listR + (size_t)i * capR;
+    uint32_t e_a = nR > 0 ? lr[0] : 0u, e_b = nR > 1 ? lr[1] : 0u;
+    float4 p_a = nR > 0 ? xyzt[nb_index(e_a)] : pi;
     for (int s = 0; s < nR; ++s) {
-        const uint32_t e = listR[(size_t)i * capR + s];
-        const float4 pj = xyzt[nb_index(e)];
+        const uint32_t e = e_a;
+        const float4 pj = p_a;
+        e_a = e_b;
+        if (s + 1 < nR) p_a = xyzt[nb_index(e_b)];
+        if (s + 2 < nR) e_b = lr[s + 2];
         const float3 d = pair_displacement(pi, pj, e, c);
         const float r = sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
         float f[NB], df[NB];
@@ -87,9 +94,15 @@ __global__ __launch_bounds__(256) void k_descriptors(int N, const float4 *__rest
 #pragma unroll
         for (int q = 0; q < LM; ++q) A[n][q] = 0.0f;
     const int nA = cntA[i];
+    const uint32_t *la = listA + (size_t)i * capA;
+    uint32_t a_a = nA > 0 ? la[0] : 0u, a_b = nA > 1 ? la[1] : 0u;
+    float4 q_a = nA > 0 ? xyzt[nb_index(a_a)] : pi;
     for (int s = 0; s < nA; ++s) {
-        const uint32_t e = listA[(size_t)i * capA + s];
-        const float4 pj = xyzt[nb_index(e)];
+        const uint32_t e = a_a;
+        const float4 pj = q_a;
+        a_a = a_b;
+        if (s + 1 < nA) q_a = xyzt[nb_index(a_b)];
+        if (s + 2 < nA) a_b = la[s + 2];
         const float3 d = pair_displacement(pi, pj, e, c);
         const float r = sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
         float f[NB], df[NB];
