@@ -217,21 +217,36 @@ __global__ __launch_bounds__(256) void k_radial_forces(int N, const float4 *__re
         const int ti = species_of(pi);
         const float *own = hT + (size_t)i * (2 * T * NBP);
         const int nR = cntR[i];
+        // software pipeline: list entries two passes ahead; the neighbour's position and
+        // its rows for this atom's species (16-byte aligned) one pass ahead
+        const uint32_t *lr = listR + (size_t)i * capR;
+        uint32_t e_a = sub < nR ? lr[sub] : 0u, e_b = sub + RF_LANES < nR ? lr[sub + RF_LANES] : 0u;
+        float4 pj_n = pi, xr_n[NBP / 4], yr_n[NBP / 4];
+        auto fetch = [&](uint32_t en) {
+            const float *nrow = hT + (size_t)nb_index(en) * (2 * T * NBP);
+            const float4 *ne = reinterpret_cast<const float4 *>(nrow + ti * NBP);
+            const float4 *nq = reinterpret_cast<const float4 *>(nrow + T * NBP + ti * NBP);
+#pragma unroll
+            for (int k4 = 0; k4 < NBP / 4; ++k4) {
+                xr_n[k4] = ne[k4];
+                yr_n[k4] = nq[k4];
+            }
+            pj_n = xyzt[nb_index(en)];
+        };
+        if (sub < nR) fetch(e_a);
         for (int s = sub; s < nR; s += RF_LANES) {
-            const uint32_t e = listR[(size_t)i * capR + s];
-            const int j = nb_index(e);
-            // every load of the pair is issued before any of them is used: the
-            // neighbour's rows for this atom's species (16-byte aligned), its position,
-            // then this atom's rows for the neighbour's species
-            const float4 *ne = reinterpret_cast<const float4 *>(hT + (size_t)j * (2 * T * NBP) + ti * NBP);
-            const float4 *nq = reinterpret_cast<const float4 *>(hT + (size_t)j * (2 * T * NBP) + T * NBP + ti * NBP);
+            const uint32_t e = e_a;
+            const float4 pj = pj_n;
             float4 xr[NBP / 4], yr[NBP / 4];
 #pragma unroll
             for (int k4 = 0; k4 < NBP / 4; ++k4) {
-                xr[k4] = ne[k4];
-                yr[k4] = nq[k4];
+                xr[k4] = xr_n[k4];
+                yr[k4] = yr_n[k4];
             }
-            const float4 pj = xyzt[j];
+            e_a = e_b;
+            if (s + RF_LANES < nR) fetch(e_a);
+            if (s + 2 * RF_LANES < nR) e_b = lr[s + 2 * RF_LANES];
+            // this atom's rows for the neighbour's species
             const int tj = species_of(pj);
             const float4 *oe = reinterpret_cast<const float4 *>(own + tj * NBP);
             const float4 *oq = reinterpret_cast<const float4 *>(own + T * NBP + tj * NBP);
