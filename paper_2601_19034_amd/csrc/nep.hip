@@ -405,11 +405,15 @@ __global__ __launch_bounds__(256) void k_angular_forces(
         const int ti = species_of(pi);
         const int nA = cntA[i];
         const uint32_t *lrow = listA + (size_t)i * capA;
-        uint32_t e_next = sub < nA ? lrow[sub] : 0u;  // the next entry is loaded one pass ahead
+        // list entries two passes ahead, neighbour positions one pass ahead
+        uint32_t e_a = sub < nA ? lrow[sub] : 0u, e_b = sub + AF_LANES < nA ? lrow[sub + AF_LANES] : 0u;
+        float4 pj_n = sub < nA ? xyzt[nb_index(e_a)] : pi;
         for (int sl = sub; sl < nA; sl += AF_LANES) {
-            const uint32_t e = e_next;
-            if (sl + AF_LANES < nA) e_next = lrow[sl + AF_LANES];
-            const float4 pj = xyzt[nb_index(e)];
+            const uint32_t e = e_a;
+            const float4 pj = pj_n;
+            e_a = e_b;
+            if (sl + AF_LANES < nA) pj_n = xyzt[nb_index(e_a)];
+            if (sl + 2 * AF_LANES < nA) e_b = lrow[sl + 2 * AF_LANES];
             const float3 d = pair_displacement(pi, pj, e, c);
             const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
             const float ir = __builtin_amdgcn_rsqf(r2);  // v_rsq_f32, 1 ulp
