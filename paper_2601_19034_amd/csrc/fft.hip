@@ -267,6 +267,102 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_axis(float2 *__restrict__ d
     }
 }
 
+// ---------------------------------------------------------------- length 256
+// Four-step transform of lines of 256 = 16 x 16 held in registers: thread t of a line
+// holds x[t + 16 m], m < 16, and transforms over m (16-point DFT, radix 4 x 4); the
+// results are multiplied by w_256^{t k1}, exchanged through LDS (thread k1 gathers
+// the values of all t) and transformed again, giving X[k1 + 16 k2] in thread k1 at
+// register k2 -- the load pattern, so loads and stores match.  One LDS exchange
+// replaces the three staged passes of the general kernel.  A work-group holds 16
+// lines; consecutive lanes read consecutive addresses in every layout:
+//   mode 0 (S == 1): lane = 16 line + t;  mode 1 (S a multiple of 16): lane = 16 t + line
+//   (16 consecutive `in`);  mode 2 (S = 2, 4, 8): lane = S (t + 16 o) + in (16 / S
+//   consecutive `o` with all their `in`).
+constexpr int F256_LS = 16 * 17 + 1;  // LDS stride of one line (padded rows of 17)
+
+template <int SG>
+__device__ inline float2 w16(int e) {  // e^{SG 2 pi i e / 16}, e < 16
+    constexpr float c[16] = {1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f,
+                             0.0f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f,
+                             -1.0f, -0.92387953251128674f, -0.70710678118654752f, -0.38268343236508977f,
+                             0.0f, 0.38268343236508977f, 0.70710678118654752f, 0.92387953251128674f};
+    return make_float2(c[e], (float)SG * c[(e + 12) & 15]);  // sin(x) = cos(x - pi/2)
+}
+
+template <int SG>
+__device__ inline void dft16(float2 (&a)[16]) {
+    float2 y[4][4];  // y[n1][k1] = sum_n2 a[n1 + 4 n2] w4^{n2 k1}
+#pragma unroll
+    for (int n1 = 0; n1 < 4; ++n1) dft4<SG>(a[n1], a[n1 + 4], a[n1 + 8], a[n1 + 12], y[n1]);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        float2 z[4], o[4];
+#pragma unroll
+        for (int n1 = 0; n1 < 4; ++n1) z[n1] = (n1 * k1 == 0) ? y[n1][k1] : cmul(y[n1][k1], w16<SG>(n1 * k1));
+        dft4<SG>(z[0], z[1], z[2], z[3], o);
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) a[k1 + 4 * k2] = o[k2];
+    }
+}
+
+template <int SG>
+__global__ __launch_bounds__(256) void k_fft256(float2 *__restrict__ data, int S, int nouter, int mode) {
+    __shared__ float2 tw[256];
+    __shared__ float2 xch[16 * F256_LS];
+    for (int m = threadIdx.x; m < 256; m += blockDim.x) {
+        float sn, cs;
+        sincospif((float)m / 128.0f, &sn, &cs);
+        tw[m] = make_float2(cs, (float)SG * sn);
+    }
+    const int lane = threadIdx.x, blk = xcd_block();
+    int cl, t;        // line in the work-group and position in the line
+    size_t base;      // address of element 0 of the line
+    int stride;       // element stride along the line
+    bool ok;
+    if (mode == 0) {
+        cl = lane >> 4;
+        t = lane & 15;
+        const int o = blk * 16 + cl;
+        ok = o < nouter;
+        base = (size_t)o * 256;
+        stride = 1;
+    } else if (mode == 1) {
+        cl = lane & 15;
+        t = lane >> 4;
+        const int groups = S / 16;
+        const int o = blk / groups, in = (blk - o * groups) * 16 + cl;
+        ok = true;
+        base = (size_t)o * 256 * S + in;
+        stride = S;
+    } else {
+        const int in = lane % S, r = lane / S;
+        t = r & 15;
+        const int ol = r >> 4, o = blk * (16 / S) + ol;
+        cl = ol * S + in;
+        ok = o < nouter;
+        base = (size_t)o * 256 * S + in;
+        stride = S;
+    }
+    float2 a[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) a[m] = ok ? data[base + (size_t)(t + 16 * m) * stride] : make_float2(0.f, 0.f);
+    dft16<SG>(a);
+    __syncthreads();  // twiddle table ready
+#pragma unroll
+    for (int k1 = 1; k1 < 16; ++k1) a[k1] = cmul(a[k1], tw[t * k1]);
+    float2 *row = xch + cl * F256_LS;
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) row[k1 * 17 + t] = a[k1];
+    __syncthreads();
+#pragma unroll
+    for (int n1 = 0; n1 < 16; ++n1) a[n1] = row[t * 17 + n1];
+    dft16<SG>(a);
+    if (ok) {
+#pragma unroll
+        for (int k2 = 0; k2 < 16; ++k2) data[base + (size_t)(t + 16 * k2) * stride] = a[k2];
+    }
+}
+
 // `inner` interleaved transforms: element (m0, m1, m2, t) of transform t at
 // ((m0 n1 + m1) n2 + m2) inner + t; they go through the same launches
 hipError_t fft3d(float2 *data, float2 * /*tmp*/, const int *mesh, int sign, hipStream_t s, int inner) {
@@ -278,6 +374,18 @@ hipError_t fft3d(float2 *data, float2 * /*tmp*/, const int *mesh, int sign, hipS
         const int L = mesh[axis];
         const int S = inner * (axis == 2 ? 1 : (axis == 1 ? mesh[2] : mesh[1] * mesh[2]));
         const int nouter = (int)(M / ((int64_t)L * S));
+        if (L == 256 && (S == 1 || S % 16 == 0 || S == 2 || S == 4 || S == 8)) {
+            const int mode = S == 1 ? 0 : (S % 16 == 0 ? 1 : 2);
+            const int blocks = mode == 0 ? (nouter + 15) / 16
+                                         : (mode == 1 ? nouter * (S / 16) : (nouter + 16 / S - 1) / (16 / S));
+            if (sign < 0)
+                hipLaunchKernelGGL(k_fft256<-1>, dim3(blocks), dim3(256), 0, s, data, S, nouter, mode);
+            else
+                hipLaunchKernelGGL(k_fft256<1>, dim3(blocks), dim3(256), 0, s, data, S, nouter, mode);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            continue;
+        }
         int B = FFT_ELEMS / L;
         if (B < 1) B = 1;
         int blocks;
