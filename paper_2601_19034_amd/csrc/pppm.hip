@@ -281,7 +281,15 @@ __global__ __launch_bounds__(256) void k_influence(MeshGeom g, Cell c, float alp
     float kz[3];
 #pragma unroll
     for (int b = 0; b < 3; ++b) kz[b] = (float)(2.0 * PI_D * c.hinv[3 * b + 2]);
-    double red[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    __shared__ float fc[1024];  // the c factor num / den of G_opt per index along c (n2 <= 1024)
+    for (int j2 = threadIdx.x; j2 < n2; j2 += blockDim.x) {
+        const int nv2 = 2 * j2 < n2 ? j2 : j2 - n2;
+        float num2, den2;
+        gopt_axis((float)nv2 * in2, num2, den2);
+        fc[j2] = num2 / den2;
+    }
+    __syncthreads();
+    float acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};  // over this thread's few points, then FP64
     for (int row = blockIdx.x; row < n0 * n1; row += gridDim.x) {
         const int j0 = row / n1, j1 = row - j0 * n1;
         const int nv0 = 2 * j0 < n0 ? j0 : j0 - n0, nv1 = 2 * j1 < n1 ? j1 : j1 - n1;
@@ -296,7 +304,7 @@ __global__ __launch_bounds__(256) void k_influence(MeshGeom g, Cell c, float alp
         float num0, den0, num1, den1;
         gopt_axis((float)nv0 / (float)n0, num0, den0);
         gopt_axis((float)nv1 / (float)n1, num1, den1);
-        const float num01 = num0 * num1, den01 = den0 * den1;
+        const float f01 = (num0 * num1) / (den0 * den1);
         for (int j2 = threadIdx.x; j2 < n2; j2 += blockDim.x) {
             const size_t idx = (size_t)row * n2 + j2;
             const int nv2 = 2 * j2 < n2 ? j2 : j2 - n2;
@@ -314,22 +322,23 @@ __global__ __launch_bounds__(256) void k_influence(MeshGeom g, Cell c, float alp
             }
             const float k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
             const float ik2 = 1.0f / k2;
-            float num2, den2;
-            gopt_axis((float)nv2 * in2, num2, den2);
-            const float Gopt = gk * __expf(-k2 * ia2) * ik2 * (num01 * num2) / (den01 * den2);
+            const float Gopt = gk * __expf(-k2 * ia2) * ik2 * (f01 * fc[j2]);
             const float e = (float)KE * Gopt * (S.x * S.x + S.y * S.y);
             const float cB = cB0 + 2.0f * ik2;
-            red[0] += e;
+            acc[0] += e;
 #pragma unroll
             for (int a = 0; a < 3; ++a)
 #pragma unroll
-                for (int b = 0; b < 3; ++b) red[1 + 3 * a + b] += e * ((a == b ? 1.0f : 0.0f) - cB * k[a] * k[b]);
+                for (int b = 0; b < 3; ++b) acc[1 + 3 * a + b] += e * ((a == b ? 1.0f : 0.0f) - cB * k[a] * k[b]);
             const float2 X = make_float2(S.x * Gopt, S.y * Gopt);
             const float2 iX = make_float2(-X.y, X.x);
             AB[idx] = make_float4(iX.x * (kt[2] + 1.0f), iX.y * (kt[2] + 1.0f), iX.x * kt[0] - X.x * kt[1],
                                   iX.y * kt[0] - X.y * kt[1]);
         }
     }
+    double red[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) red[k] = acc[k];
     block_partials<10>(red, partials);
 }
 
