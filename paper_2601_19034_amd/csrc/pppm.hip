@@ -342,31 +342,37 @@ __global__ __launch_bounds__(256) void k_influence(MeshGeom g, Cell c, float alp
     block_partials<10>(red, partials);
 }
 
-// phi^k_i += 2 k_e sum_s W phi'_s,  F^k_i += -2 k_e q'_i sum_s W E_s
+// phi^k_i += 2 k_e sum_s W phi'_s,  F^k_i += -2 k_e q'_i sum_s W E_s.
+// GA_LANES lanes share one atom: lane a < 5 reads the 25 points of stencil plane a, so
+// five shorter chains of loads are in flight per atom instead of one long one
+constexpr int GA_LANES = 8;
+
 __global__ __launch_bounds__(256) void k_gather(int N, const float4 *__restrict__ xyzt, Cell c, MeshGeom g,
                                                 const float *__restrict__ qraw, const double *__restrict__ scalars,
                                                 const float4 *__restrict__ AB, float *__restrict__ phi,
                                                 float *__restrict__ Fst) {
-    const int i = xcd_block() * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    int m0[3];
-    float w[3][5];
-    const float4 pa = xyzt[i];
-    mesh_stencil(pa.x, pa.y, pa.z, c, g, m0, w);
-    int j0[5], j1[5], j2[5];
-#pragma unroll
-    for (int t = 0; t < 5; ++t) {
-        j0[t] = wrap_index(m0[0] + t - 2, g.n[0]);
-        j1[t] = wrap_index(m0[1] + t - 2, g.n[1]);
-        j2[t] = wrap_index(m0[2] + t - 2, g.n[2]);
-    }
+    const int gtid = xcd_block() * blockDim.x + threadIdx.x;
+    const int i = gtid / GA_LANES, pa_ = gtid % GA_LANES;
     float ph = 0.f, ex = 0.f, ey = 0.f, ez = 0.f;
+    if (i < N && pa_ < 5) {
+        int m0[3];
+        float w[3][5];
+        const float4 pa = xyzt[i];
+        mesh_stencil(pa.x, pa.y, pa.z, c, g, m0, w);
+        float wa = 0.f;  // w[0][pa_] without a dynamic register index
 #pragma unroll
-    for (int a = 0; a < 5; ++a) {
+        for (int t = 0; t < 5; ++t) wa = pa_ == t ? w[0][t] : wa;
+        const int j0 = wrap_index(m0[0] + pa_ - 2, g.n[0]);
+        int j1[5], j2[5];
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+            j1[t] = wrap_index(m0[1] + t - 2, g.n[1]);
+            j2[t] = wrap_index(m0[2] + t - 2, g.n[2]);
+        }
 #pragma unroll
         for (int b = 0; b < 5; ++b) {
-            const float wab = w[0][a] * w[1][b];
-            const size_t row = ((size_t)j0[a] * g.n[1] + j1[b]) * g.n[2];
+            const float wab = wa * w[1][b];
+            const size_t row = ((size_t)j0 * g.n[1] + j1[b]) * g.n[2];
 #pragma unroll
             for (int e = 0; e < 5; ++e) {
                 const float ww = wab * w[2][e];
@@ -378,12 +384,21 @@ __global__ __launch_bounds__(256) void k_gather(int N, const float4 *__restrict_
             }
         }
     }
-    const float q = qraw[i] + (float)scalars[S_DELTA];
-    const float k2 = 2.0f * (float)KE;
-    phi[i] += k2 * ph;
-    Fst[i] += -k2 * q * ex;
-    Fst[(size_t)N + i] += -k2 * q * ey;
-    Fst[(size_t)2 * N + i] += -k2 * q * ez;
+#pragma unroll
+    for (int o = GA_LANES / 2; o > 0; o >>= 1) {
+        ph += __shfl_xor(ph, o, 64);
+        ex += __shfl_xor(ex, o, 64);
+        ey += __shfl_xor(ey, o, 64);
+        ez += __shfl_xor(ez, o, 64);
+    }
+    if (i < N && pa_ == 0) {
+        const float q = qraw[i] + (float)scalars[S_DELTA];
+        const float k2 = 2.0f * (float)KE;
+        phi[i] += k2 * ph;
+        Fst[i] += -k2 * q * ex;
+        Fst[(size_t)N + i] += -k2 * q * ey;
+        Fst[(size_t)2 * N + i] += -k2 * q * ez;
+    }
 }
 
 hipError_t launch_pppm(const Plan &p) {
@@ -429,7 +444,8 @@ hipError_t launch_pppm(const Plan &p) {
     e = fft3d(p.meshAB, nullptr, p.mesh, +1, p.stream, 2);  // both spectra in the same launches
     if (e != hipSuccess) return e;
     stage_mark(p, ST_FFT_INV, 3);
-    hipLaunchKernelGGL(k_gather, dim3(G), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, g, p.qraw,
+    const int GG = (int)(((int64_t)p.N * GA_LANES + 255) / 256);
+    hipLaunchKernelGGL(k_gather, dim3(GG), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, g, p.qraw,
                        p.scalars, (const float4 *)p.meshAB, p.phi, p.Fst);
     stage_mark(p, ST_GATHER);
     return hipGetLastError();
