@@ -308,8 +308,7 @@ qnep_status make_plan(const Model &m, const qnep_es_params *es, const qnep_syste
     p.phi = c.take<float>(N);
     p.Fst = c.take<float>(3 * (size_t)N);
     p.hT = c.take<float>((size_t)2 * p.T * radial_table_row(p.NBR) * N);
-    p.pairF = c.take<float>((size_t)4 * p.capA * N);
-    p.pairA = c.take<float>((size_t)4 * p.capA * N);
+    p.pairFA = c.take<float>((size_t)8 * p.capA * N);
     p.Fnep = c.take<float>(3 * (size_t)N);
     p.Znep = c.take<float>(9 * (size_t)N);
     if (p.method == 0) {

@@ -327,8 +327,9 @@ __global__ __launch_bounds__(256) void k_radial_forces(int N, const float4 *__re
 // AF_LANES lanes share one atom and split its angular neighbours; the two Atilde
 // tables of the atom are built once in LDS (the lanes split their entries) and read
 // by every lane, so the pair geometry (basis, radial functions, harmonics) is
-// evaluated once for both gradients.  Writes the pair buffers pairF (energy) and
-// pairA (charge), adds the own force and Z contributions, and the virial partials.
+// evaluated once for both gradients.  Writes the pair buffer (F_ij of the energy and
+// a_ij of the charge gradient side by side, one 32-byte slot per pair), adds the own
+// force and Z contributions, and the virial partials.
 constexpr int AF_LANES = 8;
 constexpr int AF_APB = 256 / AF_LANES;  // atoms per work-group
 static_assert(AF_LANES <= PARTIALS_LANES_MAX, "partials buffer sized for PARTIALS_LANES_MAX lanes per atom");
@@ -369,8 +370,8 @@ __global__ __launch_bounds__(256) void k_angular_forces(
     int N, const float4 *__restrict__ xyzt, Cell c, float rcA, const uint32_t *__restrict__ listA,
     const int *__restrict__ cntA, int capA, const float *__restrict__ Amom, const float *__restrict__ gU,
     const float *__restrict__ gq, const float *__restrict__ phi, const double *__restrict__ scalars,
-    const float *__restrict__ theta, int64_t off_cA, int64_t off_s, float4 *__restrict__ pairF,
-    float4 *__restrict__ pairA, float *__restrict__ Fnep, float *__restrict__ Znep, double *__restrict__ partials) {
+    const float *__restrict__ theta, int64_t off_cA, int64_t off_s, float4 *__restrict__ pairFA,
+    float *__restrict__ Fnep, float *__restrict__ Znep, double *__restrict__ partials) {
     constexpr int NAL = NA * LM;
     static_assert(NA <= 8 && LM % 4 == 0, "angular table layout");
     // cA8[ti tj][k][n], n padded to 8: the two float4 of one k serve all g_n
@@ -446,8 +447,8 @@ __global__ __launch_bounds__(256) void k_angular_forces(
                 angular_pair<NA>(reinterpret_cast<const float4 *>(&AtE[0][0]) + row, g, dg, Y, hg, ux, uy, uz, ir);
             const float3 A =
                 angular_pair<NA>(reinterpret_cast<const float4 *>(&AtQ[0][0]) + row, g, dg, Y, hg, ux, uy, uz, ir);
-            pairF[(size_t)i * capA + sl] = make_float4(F.x, F.y, F.z, 0.f);
-            pairA[(size_t)i * capA + sl] = make_float4(A.x, A.y, A.z, 0.f);
+            pairFA[((size_t)i * capA + sl) * 2] = make_float4(F.x, F.y, F.z, 0.f);
+            pairFA[((size_t)i * capA + sl) * 2 + 1] = make_float4(A.x, A.y, A.z, 0.f);
             const float fv[3] = {F.x, F.y, F.z}, av[3] = {A.x, A.y, A.z}, dv[3] = {d.x, d.y, d.z};
 #pragma unroll
             for (int x = 0; x < 3; ++x) {
@@ -523,7 +524,7 @@ static_assert(AS_LANES <= PARTIALS_LANES_MAX, "partials buffer sized for PARTIAL
 
 __global__ __launch_bounds__(256) void k_assemble(
     int N, const float4 *__restrict__ xyzt, Cell c, const uint32_t *__restrict__ listA,
-    const int *__restrict__ cntA, int capA, const float4 *__restrict__ pairF, const float4 *__restrict__ pairA,
+    const int *__restrict__ cntA, int capA, const float4 *__restrict__ pairFA,
     const float *__restrict__ Fnep, const float *__restrict__ Znep, const float *__restrict__ Fst,
     const float *__restrict__ qraw, const double *__restrict__ scalars, const float *__restrict__ theta,
     int64_t off_s, const int *__restrict__ perm, const float *__restrict__ pos, float *__restrict__ forces,
@@ -545,8 +546,8 @@ __global__ __launch_bounds__(256) void k_assemble(
             const int j = nb_index(e);
             const int found = find_slot(listA, cntA, j, capA, nb_reverse(e, i));
             if (found < 0) continue;  // pair at the cutoff on one side only: contributes zero
-            const float4 fji = pairF[(size_t)j * capA + found];
-            const float4 aji = pairA[(size_t)j * capA + found];
+            const float4 fji = pairFA[((size_t)j * capA + found) * 2];
+            const float4 aji = pairFA[((size_t)j * capA + found) * 2 + 1];
             acc[0] -= fji.x;
             acc[1] -= fji.y;
             acc[2] -= fji.z;
@@ -616,14 +617,14 @@ static hipError_t run_forces(const Plan &p) {
     const int GF = (p.N + AF_APB - 1) / AF_APB;
     hipLaunchKernelGGL((k_angular_forces<T, NR, NA, NB>), dim3(GF), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell,
                        (float)p.rcA, p.listA, p.cntA, p.capA, p.Amom, p.gU, p.gq, p.phi, p.scalars, p.theta,
-                       p.off_cA, p.off_s, (float4 *)p.pairF, (float4 *)p.pairA, p.Fnep, p.Znep, p.partials);
+                       p.off_cA, p.off_s, (float4 *)p.pairFA, p.Fnep, p.Znep, p.partials);
     stage_mark(p, ST_ANG);
     e = reduce_partials(p, GF, 9, S_WNEP, true);
     if (e != hipSuccess) return e;
     stage_mark(p, ST_OTHER);
     const int GA = (int)(((int64_t)p.N * AS_LANES + 255) / 256);
     hipLaunchKernelGGL(k_assemble, dim3(GA), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, p.listA, p.cntA, p.capA,
-                       (const float4 *)p.pairF, (const float4 *)p.pairA, p.Fnep, p.Znep, p.Fst, p.qraw, p.scalars,
+                       (const float4 *)p.pairFA, p.Fnep, p.Znep, p.Fst, p.qraw, p.scalars,
                        p.theta, p.off_s, p.perm, p.pos, p.out.forces, p.out.bec, p.out.charges,
                        p.out.charges_naked, p.partials);
     e = reduce_partials(p, GA, 3, S_POL, false);

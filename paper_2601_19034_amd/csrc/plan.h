@@ -68,7 +68,7 @@ struct Plan {
     float *Bsum = nullptr;  // per-species radial basis sums (backward only)
     float *U = nullptr, *qraw = nullptr, *gU = nullptr, *gq = nullptr;
     float *phi = nullptr, *Fst = nullptr, *hT = nullptr;
-    float *pairF = nullptr, *pairA = nullptr;
+    float *pairFA = nullptr;  // angular pair buffer [i][capA][2] float4: F_ij, then a_ij
     float *Fnep = nullptr, *Znep = nullptr;
     float4 *kvec = nullptr;   // (kx, ky, kz, G) of the half set
     int *kcount = nullptr;
