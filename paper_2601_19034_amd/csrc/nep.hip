@@ -147,7 +147,7 @@ __global__ __launch_bounds__(256) void k_descriptors(int N, const float4 *__rest
 // ---------------------------------------------------------------- gradient tables
 // Per atom: chi_i = phi_i - mean(phi); radial coefficient tables
 //   hE[t][k] = sum_n (gU_n + chi gq_n) cR[ti][t][n][k],  hq[t][k] = s sum_n gq_n cR[ti][t][n][k]
-// stored atom-major hT[i][2][T][NBP] (rows padded to 16 bytes) so that a neighbour's
+// stored atom-major hT[i][T][2][NBP] (rows padded to 16 bytes) so that a neighbour's
 // row for one species is a few aligned vector loads.
 template <int T, int NR, int NB>
 __global__ __launch_bounds__(256) void k_radial_tables(int N, const int *__restrict__ ts,
@@ -186,8 +186,8 @@ __global__ __launch_bounds__(256) void k_radial_tables(int N, const int *__restr
                     q = fmaf(GQ[n], cv, q);
                 }
             }
-            out[t * NBP + k] = e;
-            out[T * NBP + t * NBP + k] = q;
+            out[(2 * t) * NBP + k] = e;
+            out[(2 * t + 1) * NBP + k] = q;
         }
 }
 
@@ -224,8 +224,8 @@ __global__ __launch_bounds__(256) void k_radial_forces(int N, const float4 *__re
         float4 pj_n = pi, xr_n[NBP / 4], yr_n[NBP / 4];
         auto fetch = [&](uint32_t en) {
             const float *nrow = hT + (size_t)nb_index(en) * (2 * T * NBP);
-            const float4 *ne = reinterpret_cast<const float4 *>(nrow + ti * NBP);
-            const float4 *nq = reinterpret_cast<const float4 *>(nrow + T * NBP + ti * NBP);
+            const float4 *ne = reinterpret_cast<const float4 *>(nrow + (2 * ti) * NBP);
+            const float4 *nq = reinterpret_cast<const float4 *>(nrow + (2 * ti + 1) * NBP);
 #pragma unroll
             for (int k4 = 0; k4 < NBP / 4; ++k4) {
                 xr_n[k4] = ne[k4];
@@ -248,8 +248,8 @@ __global__ __launch_bounds__(256) void k_radial_forces(int N, const float4 *__re
             if (s + 2 * RF_LANES < nR) e_b = lr[s + 2 * RF_LANES];
             // this atom's rows for the neighbour's species
             const int tj = species_of(pj);
-            const float4 *oe = reinterpret_cast<const float4 *>(own + tj * NBP);
-            const float4 *oq = reinterpret_cast<const float4 *>(own + T * NBP + tj * NBP);
+            const float4 *oe = reinterpret_cast<const float4 *>(own + (2 * tj) * NBP);
+            const float4 *oq = reinterpret_cast<const float4 *>(own + (2 * tj + 1) * NBP);
             float4 ar[NBP / 4], br[NBP / 4];
 #pragma unroll
             for (int k4 = 0; k4 < NBP / 4; ++k4) {
