@@ -43,6 +43,17 @@ __device__ inline uint32_t nb_reverse(uint32_t e, int i) {
 
 __device__ inline int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 
+// Storage rank of the row of bins (a, b) (a row runs along c).  Rows are kept in
+// strips ROW_STRIP rows wide along b: strip by strip, then a, then b within the
+// strip.  A sweep over the sorted atoms then meets a row's neighbours across a
+// (which a neighbour search reaches) a few hundred atoms apart rather than a
+// whole a-plane apart, so the data of neighbouring atoms is still cached.
+constexpr int ROW_STRIP = 8;
+__device__ inline int row_rank(int a, int b, int nc0, int nc1) {
+    const int b0 = b / ROW_STRIP * ROW_STRIP, w = min(ROW_STRIP, nc1 - b0);
+    return b0 * nc0 + a * w + (b - b0);
+}
+
 // bin of a (wrapped) position: floor(s_a n_a) with s = r h^{-1} in FP64, clamped
 __device__ inline void bin_of(float4 p, const Cell &c, int nc0, int nc1, int nc2, int *ci) {
     const int nc[3] = {nc0, nc1, nc2};
@@ -199,7 +210,7 @@ __device__ inline int stencil_segments(const Stencil &st, const Cell &c, const A
         if (!stencil_row(st, c, b, r, zl, zh)) continue;
         const int u0 = b.ci[0] + r / w1n - st.m[0], i0 = floor_div(u0, nc0), b0 = u0 - i0 * nc0;
         const int u1 = b.ci[1] + r % w1n - st.m[1], i1 = floor_div(u1, nc1), b1 = u1 - i1 * nc1;
-        const int rowbase = (b0 * nc1 + b1) * nc2;
+        const int rowbase = row_rank(b0, b1, nc0, nc1) * nc2;
         for (int i2 = floor_div(zl, nc2); i2 <= floor_div(zh, nc2); ++i2) {
             const int za = max(zl, i2 * nc2) - i2 * nc2, zb = min(zh, i2 * nc2 + nc2 - 1) - i2 * nc2;
             const int jb = start[rowbase + za], je = start[rowbase + zb + 1];
@@ -277,6 +288,20 @@ __device__ inline float erfc_nr(float x) {
     p = fmaf(p, t, 1.00002368f);
     p = fmaf(p, t, -1.26551223f);
     return t * __expf(-x * x + p);
+}
+
+// erfc(x) for x >= 0 given e = exp(-x^2), by the five-term formula of Abramowitz and
+// Stegun (Handbook of Mathematical Functions, 7.1.26), absolute error at most 1.5e-7:
+// erfc(x) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) e, t = 1 / (1 + p x).  Where the
+// caller needs exp(-x^2) anyway this costs one reciprocal and five FMAs.
+__device__ inline float erfc_as(float x, float e) {
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));  // v_rcp_f32, 1 ulp
+    float p = 1.061405429f;
+    p = fmaf(p, t, -1.453152027f);
+    p = fmaf(p, t, 1.421413741f);
+    p = fmaf(p, t, -0.284496736f);
+    p = fmaf(p, t, 0.254829592f);
+    return t * p * e;
 }
 
 __device__ inline int species_of(float4 p) { return __float_as_int(p.w); }

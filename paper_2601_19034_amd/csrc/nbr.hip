@@ -26,7 +26,7 @@ __global__ void k_bin(int N, const float *__restrict__ pos, const int32_t *__res
         int k = (int)(s * nc[a]);
         cc[a] = k < 0 ? 0 : (k >= nc[a] ? nc[a] - 1 : k);
     }
-    int lin = (cc[0] * nc1 + cc[1]) * nc2 + cc[2];
+    int lin = row_rank(cc[0], cc[1], nc0, nc1) * nc2 + cc[2];
     cid[i] = lin;
     atomicAdd(&count[lin], 1);
     int t = type[i];

@@ -157,7 +157,7 @@ __global__ __launch_bounds__(256) void k_spread_bricks(const float4 *__restrict_
         const int u0 = blo[0] + r / ny, u1 = blo[1] + r % ny;
         i0 = floor_div(u0, nc0);
         i1 = floor_div(u1, nc1);
-        rowbase = ((u0 - i0 * nc0) * nc1 + (u1 - i1 * nc1)) * nc2;
+        rowbase = row_rank(u0 - i0 * nc0, u1 - i1 * nc1, nc0, nc1) * nc2;
     }
     const int z0 = floor_div(blo[2], nc2), z1 = floor_div(bhi[2], nc2);
     int nseg = 0, nat = 0;
