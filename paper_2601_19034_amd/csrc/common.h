@@ -272,24 +272,6 @@ __device__ inline float3 displacement(float4 pi, const float4 *__restrict__ xyzt
     return pair_displacement(pi, xyzt[nb_index(e)], e, c);
 }
 
-// erfc(x) for x >= 0 by the Chebyshev-fitted formula of Numerical Recipes
-// (Press et al., 2nd ed., Sec. 6.2, "erfcc"), fractional error below 1.2e-7:
-// erfc(x) = t exp(-x^2 + P(t)), t = 1 / (1 + x/2).
-__device__ inline float erfc_nr(float x) {
-    const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, x, 1.0f));  // v_rcp_f32, 1 ulp
-    float p = 0.17087277f;
-    p = fmaf(p, t, -0.82215223f);
-    p = fmaf(p, t, 1.48851587f);
-    p = fmaf(p, t, -1.13520398f);
-    p = fmaf(p, t, 0.27886807f);
-    p = fmaf(p, t, -0.18628806f);
-    p = fmaf(p, t, 0.09678418f);
-    p = fmaf(p, t, 0.37409196f);
-    p = fmaf(p, t, 1.00002368f);
-    p = fmaf(p, t, -1.26551223f);
-    return t * __expf(-x * x + p);
-}
-
 // erfc(x) for x >= 0 given e = exp(-x^2), by the five-term formula of Abramowitz and
 // Stegun (Handbook of Mathematical Functions, 7.1.26), absolute error at most 1.5e-7:
 // erfc(x) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) e, t = 1 / (1 + p x).  Where the

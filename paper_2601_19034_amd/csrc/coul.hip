@@ -44,8 +44,8 @@ __device__ __forceinline__ void rs_pair(const float4 &pi, const float4 &pj, cons
     const float rr = in ? r2 : 1.0f;
     const float ir = __builtin_amdgcn_rsqf(rr);
     const float ar = alpha * (rr * ir);
-    const float ec = erfc_nr(ar);
     const float ex = __expf(-ar * ar);
+    const float ec = erfc_as(ar, ex);
     const float eir = ec * ir;
     acc[0] = fmaf(qj, eir, acc[0]);
     const float B = qj * fmaf(c2, ex, eir) * ir * ir;
