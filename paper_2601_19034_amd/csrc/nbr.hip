@@ -148,22 +148,23 @@ __global__ __launch_bounds__(256) void k_lists(int N, const float4 *__restrict__
                                                int cap_sub, uint32_t *__restrict__ sub,
                                                int *__restrict__ cnt_sub, int32_t *__restrict__ flags) {
     __shared__ int2 seg[LS_APB][LS_SEG];
-    __shared__ double shx[SEG_NIMG], shy[SEG_NIMG], shz[SEG_NIMG];
+    __shared__ float4 shf[SEG_NIMG];  // (shift rounded to FP32, the image part of a list entry)
     const int nimg = 2 * st.R + 1;
     for (int k = threadIdx.x; k < nimg * nimg * nimg; k += blockDim.x) {
         int n0, n1, n2;
         image_of(k, st.R, n0, n1, n2);
         const ImageShift sh(c, n0, n1, n2);
-        shx[k] = sh.sx;
-        shy[k] = sh.sy;
-        shz[k] = sh.sz;
+        shf[k] = make_float4(sh.fx, sh.fy, sh.fz, __uint_as_float(nb_encode(0, n0, n1, n2)));
     }
     const int a = threadIdx.x / LS_LANES, ln = threadIdx.x % LS_LANES;
     const int i = xcd_block() * LS_APB + a;
     const bool live = i < N;
     const float4 pi = xyzt[live ? i : 0];
     const AtomBin ab = atom_bin(pi, c, st);
-    const float rc2_hi = (float)(rc2 * (1.0 + 1e-4));
+    // FP32 distances decide every candidate outside thin shells around the two cutoffs
+    // (their error is ~1e-5 relative); inside a shell the FP64 test decides
+    const float rc2_hi = (float)(rc2 * (1.0 + 1e-4)), rc2_lo = (float)(rc2 * (1.0 - 1e-4));
+    const float rs2_hi = (float)(rs2 * (1.0 + 1e-4)), rs2_lo = (float)(rs2 * (1.0 - 1e-4));
     const int self_img = (st.R * nimg + st.R) * nimg + st.R;
     const int gshift = (threadIdx.x & 63) & ~(LS_LANES - 1);  // first lane of this group in the wave
     const uint32_t below = (1u << ln) - 1u;
@@ -178,11 +179,16 @@ __global__ __launch_bounds__(256) void k_lists(int N, const float4 *__restrict__
             const int j = wk.atom(), g = wk.image();
             wk.advance(seg[a], LS_LANES);
             const float4 pj = xyzt[j];
-            const double sx = shx[g], sy = shy[g], sz = shz[g];
-            const float fx = (pj.x - pi.x) + (float)sx, fy = (pj.y - pi.y) + (float)sy,
-                        fz = (pj.z - pi.z) + (float)sz;
-            bool hit = false, hs = false;
-            if (fx * fx + fy * fy + fz * fz < rc2_hi && !(g == self_img && j == i)) {
+            const float4 sf = shf[g];
+            const float fx = (pj.x - pi.x) + sf.x, fy = (pj.y - pi.y) + sf.y, fz = (pj.z - pi.z) + sf.z;
+            const float r2f = fx * fx + fy * fy + fz * fz;
+            const bool cand = r2f < rc2_hi && !(g == self_img && j == i);
+            bool hit = cand && r2f < rc2_lo, hs = cand && r2f < rs2_lo;
+            if (cand && ((r2f >= rc2_lo) || (r2f >= rs2_lo && r2f < rs2_hi))) {
+                int n0, n1, n2;
+                image_of(g, st.R, n0, n1, n2);
+                const ImageShift sh(c, n0, n1, n2);
+                const double sx = sh.sx, sy = sh.sy, sz = sh.sz;
                 const float dx = (float)(((double)pj.x - (double)pi.x) + sx);
                 const float dy = (float)(((double)pj.y - (double)pi.y) + sy);
                 const float dz = (float)(((double)pj.z - (double)pi.z) + sz);
@@ -193,9 +199,7 @@ __global__ __launch_bounds__(256) void k_lists(int N, const float4 *__restrict__
             const uint32_t gm = (uint32_t)(__ballot(hit) >> gshift) & 0xFFFFu;
             const uint32_t gs = (uint32_t)(__ballot(hs) >> gshift) & 0xFFFFu;
             if (hit) {
-                int n0, n1, n2;
-                image_of(g, st.R, n0, n1, n2);
-                const uint32_t code = nb_encode(j, n0, n1, n2);
+                const uint32_t code = (uint32_t)j | __float_as_uint(sf.w);
                 const int k = n_main + __popc(gm & below);
                 if (k < cap) list[(size_t)i * cap + k] = code;
                 if (hs) {
