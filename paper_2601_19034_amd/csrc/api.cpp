@@ -16,6 +16,7 @@ bool nep_supported(int T, int NR, int NA, int NBR, int NBA, int LMAX);
 hipError_t launch_phi_mean(const Plan &p);
 bool mlp_bf16_supported(int ndes, int H);
 int radial_table_row(int NB);
+int reduce_tmp_doubles();
 }  // namespace qnep
 
 using namespace qnep;
@@ -286,6 +287,7 @@ qnep_status make_plan(const Model &m, const qnep_es_params *es, const qnep_syste
     p.flags = c.take<int32_t>(16);
     p.scalars = c.take<double>(64);
     p.partials = c.take<double>(p.partials_cap);
+    p.red_tmp = c.take<double>(reduce_tmp_doubles());
     p.cid = c.take<int>(N);
     p.cell_count = c.take<int>(p.ncell);
     p.cell_start = c.take<int>(p.ncell + 1);

@@ -274,41 +274,59 @@ hipError_t fill_zero(void *ptr, size_t bytes, hipStream_t s) {
     return hipGetLastError();
 }
 
-// one block of RP_THREADS per reduced value; every thread keeps four independent
-// sums over a fixed stride, then a fixed-order tree: the result is deterministic
-constexpr int RP_THREADS = 1024;
+// Sum over the nblk rows of partials[nblk][nv] (nv <= RP_MAX_NV), in two launches:
+// RP_SLICES blocks each sum one contiguous slice of rows, every thread one value of
+// rows read coalesced, then a fixed-order tree; one block adds the slice sums in
+// slice order.  The result depends only on (nblk, nv): deterministic.
+constexpr int RP_THREADS = 1024, RP_SLICES = 64, RP_MAX_NV = 16;
 
-__global__ __launch_bounds__(RP_THREADS) void k_reduce_partials(const double *__restrict__ partials, int nblk,
-                                                                 int nv, double *__restrict__ out, int accumulate) {
+int reduce_tmp_doubles() { return RP_SLICES * RP_MAX_NV; }
+
+__global__ __launch_bounds__(RP_THREADS) void k_reduce_slices(const double *__restrict__ partials, int nblk,
+                                                               int nv, double *__restrict__ tmp) {
     __shared__ double red[RP_THREADS];
-    const int k = blockIdx.x;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int b = threadIdx.x;
-    for (; b + 3 * RP_THREADS < nblk; b += 4 * RP_THREADS) {
-        s0 += partials[(size_t)b * nv + k];
-        s1 += partials[(size_t)(b + RP_THREADS) * nv + k];
-        s2 += partials[(size_t)(b + 2 * RP_THREADS) * nv + k];
-        s3 += partials[(size_t)(b + 3 * RP_THREADS) * nv + k];
-    }
-    for (; b < nblk; b += RP_THREADS) s0 += partials[(size_t)b * nv + k];
-    red[threadIdx.x] = (s0 + s1) + (s2 + s3);
-    __syncthreads();
-    for (int o = RP_THREADS / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    const int rows = RP_THREADS / nv;  // rows read per pass; at most 128 for nv >= 8
+    const int tb = threadIdx.x / nv, k = threadIdx.x - tb * nv;
+    const int per = (nblk + gridDim.x - 1) / gridDim.x;
+    const int b0 = blockIdx.x * per, b1 = min(nblk, b0 + per);
+    double s = 0.0;
+    if (tb < rows)
+        for (int b = b0 + tb; b < b1; b += rows) s += partials[(size_t)b * nv + k];
+    red[threadIdx.x] = s;
+    int o = 1;
+    while (2 * o < rows) o <<= 1;  // largest power of two below rows (rows <= 2 o)
+    for (; o > 0; o >>= 1) {
         __syncthreads();
+        if (tb < o && tb + o < rows) red[threadIdx.x] += red[threadIdx.x + o * nv];
     }
-    if (threadIdx.x == 0) out[k] = accumulate ? out[k] + red[0] : red[0];
+    if (threadIdx.x < nv) tmp[blockIdx.x * nv + threadIdx.x] = red[threadIdx.x];
+}
+
+__global__ void k_reduce_final(const double *__restrict__ tmp, int nslice, int nv, double *__restrict__ out,
+                               int accumulate) {
+    const int k = threadIdx.x;
+    if (k >= nv) return;
+    double s = 0.0;
+    for (int b = 0; b < nslice; ++b) s += tmp[b * nv + k];
+    out[k] = accumulate ? out[k] + s : s;
+}
+
+static hipError_t reduce_into(const Plan &p, int nblk, int nv, double *dst, bool accumulate) {
+    if (nv < 1 || nv > RP_MAX_NV) return hipErrorInvalidValue;
+    const int nslice = std::max(1, std::min(RP_SLICES, nblk / 64));
+    hipLaunchKernelGGL(k_reduce_slices, dim3(nslice), dim3(RP_THREADS), 0, p.stream, p.partials, nblk, nv,
+                       p.red_tmp);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, p.stream, p.red_tmp, nslice, nv, dst,
+                       accumulate ? 1 : 0);
+    return hipGetLastError();
 }
 
 hipError_t reduce_partials_to(const Plan &p, int nblk, int nv, double *dst) {
-    hipLaunchKernelGGL(k_reduce_partials, dim3(nv), dim3(RP_THREADS), 0, p.stream, p.partials, nblk, nv, dst, 0);
-    return hipGetLastError();
+    return reduce_into(p, nblk, nv, dst, false);
 }
 
 hipError_t reduce_partials(const Plan &p, int nblk, int nv, int slot, bool accumulate) {
-    hipLaunchKernelGGL(k_reduce_partials, dim3(nv), dim3(RP_THREADS), 0, p.stream, p.partials, nblk, nv, p.scalars + slot,
-                       accumulate ? 1 : 0);
-    return hipGetLastError();
+    return reduce_into(p, nblk, nv, p.scalars + slot, accumulate);
 }
 
 }  // namespace qnep

@@ -57,6 +57,7 @@ struct Plan {
     double *scalars = nullptr;
     double *partials = nullptr;
     int64_t partials_cap = 0;
+    double *red_tmp = nullptr;  // per-slice sums of one partials reduction
     int *cid = nullptr, *cell_count = nullptr, *cell_start = nullptr, *cell_cursor = nullptr, *perm = nullptr;
     int *scan_tmp = nullptr;
     float4 *xyzt = nullptr;  // sorted positions (x, y, z) with the species in w (as int bits)
