@@ -274,32 +274,46 @@ hipError_t fill_zero(void *ptr, size_t bytes, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Sum over the nblk rows of partials[nblk][nv] (nv <= RP_MAX_NV), in two launches:
-// RP_SLICES blocks each sum one contiguous slice of rows, every thread one value of
-// rows read coalesced, then a fixed-order tree; one block adds the slice sums in
-// slice order.  The result depends only on (nblk, nv): deterministic.
+// Sum over the nblk rows of partials[nblk][nv] (nv <= RP_MAX_NV): up to RP_SLICES
+// blocks each sum one contiguous slice of rows, every thread one value of rows read
+// coalesced, then a fixed-order tree; with several slices one more block adds the
+// slice sums in slice order.  The result depends only on (nblk, nv): deterministic.
 constexpr int RP_THREADS = 1024, RP_SLICES = 64, RP_MAX_NV = 16;
 
 int reduce_tmp_doubles() { return RP_SLICES * RP_MAX_NV; }
 
 __global__ __launch_bounds__(RP_THREADS) void k_reduce_slices(const double *__restrict__ partials, int nblk,
-                                                               int nv, double *__restrict__ tmp) {
+                                                               int nv, double *__restrict__ tmp,
+                                                               double *__restrict__ out, int accumulate) {
     __shared__ double red[RP_THREADS];
     const int rows = RP_THREADS / nv;  // rows read per pass; at most 128 for nv >= 8
     const int tb = threadIdx.x / nv, k = threadIdx.x - tb * nv;
     const int per = (nblk + gridDim.x - 1) / gridDim.x;
     const int b0 = blockIdx.x * per, b1 = min(nblk, b0 + per);
-    double s = 0.0;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};  // four loads in flight per thread
     if (tb < rows)
-        for (int b = b0 + tb; b < b1; b += rows) s += partials[(size_t)b * nv + k];
-    red[threadIdx.x] = s;
+        for (int b = b0 + tb; b < b1; b += 4 * rows) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int bu = b + u * rows;
+                s[u] += bu < b1 ? partials[(size_t)bu * nv + k] : 0.0;
+            }
+        }
+    red[threadIdx.x] = (s[0] + s[1]) + (s[2] + s[3]);
     int o = 1;
     while (2 * o < rows) o <<= 1;  // largest power of two below rows (rows <= 2 o)
     for (; o > 0; o >>= 1) {
         __syncthreads();
         if (tb < o && tb + o < rows) red[threadIdx.x] += red[threadIdx.x + o * nv];
     }
-    if (threadIdx.x < nv) tmp[blockIdx.x * nv + threadIdx.x] = red[threadIdx.x];
+    if (threadIdx.x < nv) {
+        if (gridDim.x > 1) {
+            tmp[blockIdx.x * nv + threadIdx.x] = red[threadIdx.x];
+        } else {  // one slice: this is the sum
+            const double v = red[threadIdx.x];
+            out[threadIdx.x] = accumulate ? out[threadIdx.x] + v : v;
+        }
+    }
 }
 
 __global__ void k_reduce_final(const double *__restrict__ tmp, int nslice, int nv, double *__restrict__ out,
@@ -313,11 +327,13 @@ __global__ void k_reduce_final(const double *__restrict__ tmp, int nslice, int n
 
 static hipError_t reduce_into(const Plan &p, int nblk, int nv, double *dst, bool accumulate) {
     if (nv < 1 || nv > RP_MAX_NV) return hipErrorInvalidValue;
-    const int nslice = std::max(1, std::min(RP_SLICES, nblk / 64));
+    // up to 8192 rows one block suffices and saves the second launch
+    const int nslice = nblk <= 8192 ? 1 : std::min(RP_SLICES, nblk / 256);
     hipLaunchKernelGGL(k_reduce_slices, dim3(nslice), dim3(RP_THREADS), 0, p.stream, p.partials, nblk, nv,
-                       p.red_tmp);
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, p.stream, p.red_tmp, nslice, nv, dst,
-                       accumulate ? 1 : 0);
+                       p.red_tmp, dst, accumulate ? 1 : 0);
+    if (nslice > 1)
+        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, p.stream, p.red_tmp, nslice, nv, dst,
+                           accumulate ? 1 : 0);
     return hipGetLastError();
 }
 
