@@ -15,7 +15,7 @@ namespace qnep {
 bool nep_supported(int T, int NR, int NA, int NBR, int NBA, int LMAX);
 hipError_t launch_phi_mean(const Plan &p);
 bool mlp_bf16_supported(int ndes, int H);
-int radial_table_row(int NB);
+int radial_record_floats(int NB);
 int reduce_tmp_doubles();
 }  // namespace qnep
 
@@ -309,7 +309,7 @@ qnep_status make_plan(const Model &m, const qnep_es_params *es, const qnep_syste
     p.gq = c.take<float>((size_t)p.ndes * N);
     p.phi = c.take<float>(N);
     p.Fst = c.take<float>(3 * (size_t)N);
-    p.hT = c.take<float>((size_t)2 * p.T * radial_table_row(p.NBR) * N);
+    p.hT = c.take<float>((size_t)p.T * radial_record_floats(p.NBR) * N);
     p.pairFA = c.take<float>((size_t)8 * p.capA * N);
     p.Fnep = c.take<float>(3 * (size_t)N);
     p.Znep = c.take<float>(9 * (size_t)N);

@@ -147,8 +147,14 @@ __global__ __launch_bounds__(256) void k_descriptors(int N, const float4 *__rest
 // ---------------------------------------------------------------- gradient tables
 // Per atom: chi_i = phi_i - mean(phi); radial coefficient tables
 //   hE[t][k] = sum_n (gU_n + chi gq_n) cR[ti][t][n][k],  hq[t][k] = s sum_n gq_n cR[ti][t][n][k]
-// stored atom-major hT[i][T][2][NBP] (rows padded to 16 bytes) so that a neighbour's
-// row for one species is a few aligned vector loads.
+// stored atom-major, one record of REC floats per (atom, species t) holding the two
+// rows interleaved, (hE[t][0], hq[t][0], hE[t][1], hq[t][1], ...), padded to 16 bytes:
+// a neighbour's rows for one species are REC / 4 aligned vector loads.
+template <int NB>
+struct RadRec {
+    static constexpr int v = (2 * NB + 3) / 4 * 4;  // floats per record
+};
+
 template <int T, int NR, int NB>
 __global__ __launch_bounds__(256) void k_radial_tables(int N, const int *__restrict__ ts,
                                                        const float *__restrict__ gU, const float *__restrict__ gq,
@@ -156,7 +162,7 @@ __global__ __launch_bounds__(256) void k_radial_tables(int N, const int *__restr
                                                        const double *__restrict__ scalars,
                                                        const float *__restrict__ theta, int64_t off_cR,
                                                        int64_t off_s, float *__restrict__ hT) {
-    constexpr int NBP = Pad4<NB>::v;
+    constexpr int REC = RadRec<NB>::v;
     __shared__ float cR[T * T * NR * NB];
     for (int k = threadIdx.x; k < T * T * NR * NB; k += blockDim.x) cR[k] = theta[off_cR + k];
     __syncthreads();
@@ -172,11 +178,11 @@ __global__ __launch_bounds__(256) void k_radial_tables(int N, const int *__restr
         GE[n] = fmaf(chi, b, a);
         GQ[n] = s * b;
     }
-    float *out = hT + (size_t)i * (2 * T * NBP);
 #pragma unroll
-    for (int t = 0; t < T; ++t)
+    for (int t = 0; t < T; ++t) {
+        float v[REC];
 #pragma unroll
-        for (int k = 0; k < NBP; ++k) {
+        for (int k = 0; k < REC / 2; ++k) {
             float e = 0.f, q = 0.f;
             if (k < NB) {
 #pragma unroll
@@ -186,9 +192,14 @@ __global__ __launch_bounds__(256) void k_radial_tables(int N, const int *__restr
                     q = fmaf(GQ[n], cv, q);
                 }
             }
-            out[(2 * t) * NBP + k] = e;
-            out[(2 * t + 1) * NBP + k] = q;
+            v[2 * k] = e;
+            v[2 * k + 1] = q;
         }
+        float4 *out = reinterpret_cast<float4 *>(hT + ((size_t)i * T + t) * REC);
+#pragma unroll
+        for (int k4 = 0; k4 < REC / 4; ++k4)
+            out[k4] = make_float4(v[4 * k4], v[4 * k4 + 1], v[4 * k4 + 2], v[4 * k4 + 3]);
+    }
 }
 
 // ---------------------------------------------------------------- radial forces
@@ -206,7 +217,7 @@ __global__ __launch_bounds__(256) void k_radial_forces(int N, const float4 *__re
                                                        const int *__restrict__ cntR, int capR,
                                                        const float *__restrict__ hT, float *__restrict__ Fnep,
                                                        float *__restrict__ Znep, double *__restrict__ partials) {
-    constexpr int NBP = Pad4<NB>::v;
+    constexpr int REC = RadRec<NB>::v, R4 = REC / 4;
     const int gtid = xcd_block() * blockDim.x + threadIdx.x;
     const int i = gtid / RF_LANES, sub = gtid % RF_LANES;
     float acc[15];  // F (3), Z (xx yy zz xy xz yz), W (same order)
@@ -215,66 +226,55 @@ __global__ __launch_bounds__(256) void k_radial_forces(int N, const float4 *__re
     if (i < N) {
         const float4 pi = xyzt[i];
         const int ti = species_of(pi);
-        const float *own = hT + (size_t)i * (2 * T * NBP);
+        const float4 *own = reinterpret_cast<const float4 *>(hT + (size_t)i * T * REC);
         const int nR = cntR[i];
         // software pipeline: list entries two passes ahead; the neighbour's position and
-        // its rows for this atom's species (16-byte aligned) one pass ahead
+        // its record for this atom's species one pass ahead
         const uint32_t *lr = listR + (size_t)i * capR;
         uint32_t e_a = sub < nR ? lr[sub] : 0u, e_b = sub + RF_LANES < nR ? lr[sub + RF_LANES] : 0u;
-        float4 pj_n = pi, xr_n[NBP / 4], yr_n[NBP / 4];
+        float4 pj_n = pi, xr_n[R4];
         auto fetch = [&](uint32_t en) {
-            const float *nrow = hT + (size_t)nb_index(en) * (2 * T * NBP);
-            const float4 *ne = reinterpret_cast<const float4 *>(nrow + (2 * ti) * NBP);
-            const float4 *nq = reinterpret_cast<const float4 *>(nrow + (2 * ti + 1) * NBP);
+            const float4 *nrec = reinterpret_cast<const float4 *>(hT + ((size_t)nb_index(en) * T + ti) * REC);
 #pragma unroll
-            for (int k4 = 0; k4 < NBP / 4; ++k4) {
-                xr_n[k4] = ne[k4];
-                yr_n[k4] = nq[k4];
-            }
+            for (int k4 = 0; k4 < R4; ++k4) xr_n[k4] = nrec[k4];
             pj_n = xyzt[nb_index(en)];
         };
         if (sub < nR) fetch(e_a);
         for (int s = sub; s < nR; s += RF_LANES) {
             const uint32_t e = e_a;
             const float4 pj = pj_n;
-            float4 xr[NBP / 4], yr[NBP / 4];
+            float4 xr[R4];
 #pragma unroll
-            for (int k4 = 0; k4 < NBP / 4; ++k4) {
-                xr[k4] = xr_n[k4];
-                yr[k4] = yr_n[k4];
-            }
+            for (int k4 = 0; k4 < R4; ++k4) xr[k4] = xr_n[k4];
             e_a = e_b;
             if (s + RF_LANES < nR) fetch(e_a);
             if (s + 2 * RF_LANES < nR) e_b = lr[s + 2 * RF_LANES];
-            // this atom's rows for the neighbour's species
+            // this atom's record for the neighbour's species
             const int tj = species_of(pj);
-            const float4 *oe = reinterpret_cast<const float4 *>(own + (2 * tj) * NBP);
-            const float4 *oq = reinterpret_cast<const float4 *>(own + (2 * tj + 1) * NBP);
-            float4 ar[NBP / 4], br[NBP / 4];
+            float4 ar[R4];
 #pragma unroll
-            for (int k4 = 0; k4 < NBP / 4; ++k4) {
-                ar[k4] = oe[k4];
-                br[k4] = oq[k4];
-            }
+            for (int k4 = 0; k4 < R4; ++k4) ar[k4] = own[tj * R4 + k4];
             const float3 d = pair_displacement(pi, pj, e, c);
             const float r = sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
             float f[NB], df[NB];
             cheb_basis<NB>(r, rcR, f, df);
             float sij = 0.f, rij = 0.f, sji = 0.f, rji = 0.f;
 #pragma unroll
-            for (int k4 = 0; k4 < NBP / 4; ++k4) {
-                const float4 a = ar[k4], b = br[k4], x = xr[k4], y = yr[k4];
-                const float av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
-                const float xv[4] = {x.x, x.y, x.z, x.w}, yv[4] = {y.x, y.y, y.z, y.w};
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int k = 4 * k4 + u;
-                    if (k < NB) {
-                        sij = fmaf(av[u], df[k], sij);
-                        rij = fmaf(bv[u], df[k], rij);
-                        sji = fmaf(xv[u], df[k], sji);
-                        rji = fmaf(yv[u], df[k], rji);
-                    }
+            for (int k4 = 0; k4 < R4; ++k4) {
+                const float4 a = ar[k4], x = xr[k4];
+                // (hE_k, hq_k, hE_k+1, hq_k+1)
+                const int k = 2 * k4;
+                if (k < NB) {
+                    sij = fmaf(a.x, df[k], sij);
+                    rij = fmaf(a.y, df[k], rij);
+                    sji = fmaf(x.x, df[k], sji);
+                    rji = fmaf(x.y, df[k], rji);
+                }
+                if (k + 1 < NB) {
+                    sij = fmaf(a.z, df[k + 1], sij);
+                    rij = fmaf(a.w, df[k + 1], rij);
+                    sji = fmaf(x.z, df[k + 1], sji);
+                    rji = fmaf(x.w, df[k + 1], rji);
                 }
             }
             const float ir = 1.0f / r;
@@ -658,6 +658,6 @@ bool nep_supported(int T, int NR, int NA, int NBR, int NBA, int LMAX) {
     return (NR == 5 && NA == 5) || (NR == 9 && NA == 7);
 }
 
-int radial_table_row(int NB) { return (NB + 3) / 4 * 4; }
+int radial_record_floats(int NB) { return (2 * NB + 3) / 4 * 4; }
 
 }  // namespace qnep
