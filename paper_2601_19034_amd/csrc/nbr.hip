@@ -316,13 +316,15 @@ __global__ __launch_bounds__(RP_THREADS) void k_reduce_slices(const double *__re
     }
 }
 
-__global__ void k_reduce_final(const double *__restrict__ tmp, int nslice, int nv, double *__restrict__ out,
-                               int accumulate) {
-    const int k = threadIdx.x;
-    if (k >= nv) return;
-    double s = 0.0;
-    for (int b = 0; b < nslice; ++b) s += tmp[b * nv + k];
-    out[k] = accumulate ? out[k] + s : s;
+// one wave per value: lane b holds slice b (nslice <= 64), then a fixed butterfly
+__global__ __launch_bounds__(64 * RP_MAX_NV) void k_reduce_final(const double *__restrict__ tmp, int nslice,
+                                                                 int nv, double *__restrict__ out,
+                                                                 int accumulate) {
+    const int k = threadIdx.x / 64, b = threadIdx.x % 64;
+    if (k >= nv) return;  // whole waves leave together
+    double s = b < nslice ? tmp[b * nv + k] : 0.0;
+    s = wave_sum(s);
+    if (b == 0) out[k] = accumulate ? out[k] + s : s;
 }
 
 static hipError_t reduce_into(const Plan &p, int nblk, int nv, double *dst, bool accumulate) {
@@ -332,7 +334,7 @@ static hipError_t reduce_into(const Plan &p, int nblk, int nv, double *dst, bool
     hipLaunchKernelGGL(k_reduce_slices, dim3(nslice), dim3(RP_THREADS), 0, p.stream, p.partials, nblk, nv,
                        p.red_tmp, dst, accumulate ? 1 : 0);
     if (nslice > 1)
-        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, p.stream, p.red_tmp, nslice, nv, dst,
+        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64 * nv), 0, p.stream, p.red_tmp, nslice, nv, dst,
                            accumulate ? 1 : 0);
     return hipGetLastError();
 }
