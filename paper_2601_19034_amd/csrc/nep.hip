@@ -217,16 +217,22 @@ __global__ __launch_bounds__(256) void k_radial_forces(int N, const float4 *__re
                                                        const int *__restrict__ cntR, int capR,
                                                        const float *__restrict__ hT, float *__restrict__ Fnep,
                                                        float *__restrict__ Znep, double *__restrict__ partials) {
-    constexpr int REC = RadRec<NB>::v, R4 = REC / 4;
+    constexpr int REC = RadRec<NB>::v, R4 = REC / 4, APB = 256 / RF_LANES;
+    // this atom's own T records, read for every pair, sit in LDS: the vector memory
+    // path is left to the neighbours' records
+    __shared__ float4 own[APB][T * R4];
     const int gtid = xcd_block() * blockDim.x + threadIdx.x;
-    const int i = gtid / RF_LANES, sub = gtid % RF_LANES;
+    const int i = gtid / RF_LANES, sub = gtid % RF_LANES, a = threadIdx.x / RF_LANES;
+    for (int q = sub; q < T * R4; q += RF_LANES)
+        own[a][q] = i < N ? reinterpret_cast<const float4 *>(hT + (size_t)i * T * REC)[q]
+                          : make_float4(0.f, 0.f, 0.f, 0.f);
+    __syncthreads();
     float acc[15];  // F (3), Z (xx yy zz xy xz yz), W (same order)
 #pragma unroll
     for (int k = 0; k < 15; ++k) acc[k] = 0.f;
     if (i < N) {
         const float4 pi = xyzt[i];
         const int ti = species_of(pi);
-        const float4 *own = reinterpret_cast<const float4 *>(hT + (size_t)i * T * REC);
         const int nR = cntR[i];
         // software pipeline: list entries two passes ahead; the neighbour's position and
         // its record for this atom's species one pass ahead
@@ -253,7 +259,7 @@ __global__ __launch_bounds__(256) void k_radial_forces(int N, const float4 *__re
             const int tj = species_of(pj);
             float4 ar[R4];
 #pragma unroll
-            for (int k4 = 0; k4 < R4; ++k4) ar[k4] = own[tj * R4 + k4];
+            for (int k4 = 0; k4 < R4; ++k4) ar[k4] = own[a][tj * R4 + k4];
             const float3 d = pair_displacement(pi, pj, e, c);
             const float r = sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
             float f[NB], df[NB];
