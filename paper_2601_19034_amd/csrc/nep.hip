@@ -208,7 +208,7 @@ __global__ __launch_bounds__(256) void k_radial_tables(int N, const int *__restr
 // W -= sum_j sigma_ij r u (x) u (own partial forces only).
 // RF_LANES lanes share one atom and split its neighbours; the sums are combined
 // across the lane group with butterfly shuffles.
-constexpr int RF_LANES = 16;
+constexpr int RF_LANES = 8;
 static_assert(RF_LANES <= PARTIALS_LANES_MAX, "partials buffer sized for PARTIALS_LANES_MAX lanes per atom");
 
 template <int T, int NB>
