@@ -18,9 +18,9 @@ namespace qnep {
 // phi^r_i, the static pair force
 // F_i = -k_e q'_i sum_j q'_j [erfc(a r)/r + 2a e^{-a^2 r^2}/sqrt(pi)] r_ij / r^2
 // and the pair virial (each unordered pair is seen from both atoms with weight 1/2).
-constexpr int RS_LANES = 16;
+constexpr int RS_LANES = 8;
 constexpr int RS_APB = 256 / RS_LANES;  // atoms per work-group
-constexpr int RS_SEG = 128;             // segments of one atom held in LDS at a time
+constexpr int RS_SEG = 64;              // segments of one atom held in LDS at a time
 static_assert(RS_LANES <= PARTIALS_LANES_MAX, "partials buffer sized for PARTIALS_LANES_MAX lanes per atom");
 
 // positions with the corrected charge q' in w: one 16-byte load per candidate
