@@ -138,7 +138,8 @@ __global__ void k_gather_sorted(int N, const float *__restrict__ pos, const int3
 // sub-list.  The hits of one pass of the lane group are compacted with a ballot in
 // lane order, so both lists come out in the fixed walk order.  Lists are atom-major:
 // list[i * cap + k] and sub[i * cap_sub + k].
-constexpr int LS_LANES = 16;
+constexpr int LS_LANES = 8;
+constexpr uint32_t LS_MASK = (1u << LS_LANES) - 1u;  // one lane group in a ballot
 constexpr int LS_APB = 256 / LS_LANES;  // atoms per work-group
 constexpr int LS_SEG = 64;              // segments of one atom held in LDS at a time
 
@@ -196,8 +197,8 @@ __global__ __launch_bounds__(256) void k_lists(int N, const float4 *__restrict__
                 hit = r2 < rc2;
                 hs = r2 < rs2;
             }
-            const uint32_t gm = (uint32_t)(__ballot(hit) >> gshift) & 0xFFFFu;
-            const uint32_t gs = (uint32_t)(__ballot(hs) >> gshift) & 0xFFFFu;
+            const uint32_t gm = (uint32_t)(__ballot(hit) >> gshift) & LS_MASK;
+            const uint32_t gs = (uint32_t)(__ballot(hs) >> gshift) & LS_MASK;
             if (hit) {
                 const uint32_t code = (uint32_t)j | __float_as_uint(sf.w);
                 const int k = n_main + __popc(gm & below);
