@@ -78,6 +78,8 @@ def lib():
         L.oq_alias_poly5.argtypes = [C.c_double]
         L.oq_dft3.restype = None
         L.oq_dft3.argtypes = [_DP, _DP, C.POINTER(C.c_int), C.c_int]
+        L.oq_set_ablation.restype = None
+        L.oq_set_ablation.argtypes = [C.c_int]
         L.oq_neighbors.restype = C.c_int
         L.oq_neighbors.argtypes = [C.c_int, C.c_int, _DP, _DP, C.c_double, C.POINTER(C.c_int),
                                    C.POINTER(C.c_int), _DP, C.c_int]
@@ -149,6 +151,12 @@ def compute(hp, es, pos, types, cell, theta, forces: bool = True, cells: bool = 
     if rc != 0:
         raise ValueError(f"oracle rejected the input (code {rc})")
     return OracleResult(terms[0], terms, F, W, qs, qt, qr, Z, P, D, U, phi)
+
+
+def set_ablation(flags: int) -> None:
+    """Test-only mistake switch (0 = off): bit 1 makes the forces use chi_i = phi_i
+    instead of phi_i - mean(phi)."""
+    lib().oq_set_ablation(int(flags))
 
 
 def neighbors(pos, cell, rc, cells: bool = False, cap: int = 0):

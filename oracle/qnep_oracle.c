@@ -705,6 +705,13 @@ static void recip_pppm(const oq_es *es, int n, const double *pos, const double *
 /* ------------------------------------------------------------------ */
 /* full evaluation                                                      */
 /* ------------------------------------------------------------------ */
+/* Ablation switch for the tests (0 = off, the default): bit 1 drops the -mean(phi)
+   part of the chain rule through the neutrality correction, i.e. the forces use
+   chi_i = phi_i; the energy is unchanged.  A test sets it to show that the finite-
+   difference check of the forces detects that mistake. */
+static int oq_ablation = 0;
+void oq_set_ablation(int flags) { oq_ablation = flags; }
+
 int oq_compute(const oq_hparams *hp, const oq_es *es, int n, const double *pos, const int *type, const double *cell,
                const double *theta, int nbr_method, int want_forces, oq_out *out)
 {
@@ -844,7 +851,7 @@ int oq_compute(const oq_hparams *hp, const oq_es *es, int n, const double *pos, 
 #pragma omp parallel for schedule(dynamic, 16)
         for (int i = 0; i < n; ++i) {
             int ti = type[i];
-            double chi = phi[i] - phibar;
+            double chi = phi[i] - ((oq_ablation & 1) ? 0.0 : phibar);
             double *g = (double *)malloc(sizeof(double) * (size_t)ndes), *ga = (double *)malloc(sizeof(double) * (size_t)ndes);
             for (int q = 0; q < ndes; ++q) {
                 g[q] = gU[(size_t)i * ndes + q] + chi * gq[(size_t)i * ndes + q];

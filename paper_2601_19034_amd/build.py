@@ -34,8 +34,18 @@ def hipcc() -> str:
     return shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 
-def _compile(src: str) -> str:
+def _newest_header() -> float:
+    hdrs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    hdrs += [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))]
+    return max(os.path.getmtime(h) for h in hdrs)
+
+
+def _compile(src: str, incremental: bool = False) -> str:
     out = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
+    if incremental and os.path.exists(out):
+        t = os.path.getmtime(out)
+        if t > os.path.getmtime(os.path.join(CSRC, src)) and t > _newest_header():
+            return out
     cmd = [hipcc()] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", out]
     if src.endswith(".cpp"):
         cmd = [hipcc()] + FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", out]
@@ -45,10 +55,12 @@ def _compile(src: str) -> str:
     return out
 
 
-def build(jobs: int = 8) -> str:
+def build(jobs: int = 8, incremental: bool = False) -> str:
+    """Compiles every source (or, with incremental, those older than their object
+    and the headers) and links libqnep.so."""
     os.makedirs(OBJ, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, incremental), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -59,4 +71,5 @@ def build(jobs: int = 8) -> str:
 
 
 if __name__ == "__main__":
-    print(build(int(sys.argv[1]) if len(sys.argv) > 1 else 8))
+    args = [a for a in sys.argv[1:] if a != "--incremental"]
+    print(build(int(args[0]) if args else 8, incremental="--incremental" in sys.argv))

@@ -340,13 +340,34 @@ def test_forces_finite_difference(orc):
 
 
 def test_forces_fd_without_correction_term_fails(orc):
-    """Ablation: dropping the -mean(phi) part of the chain rule breaks conservation
-    (so the previous test does detect it)."""
+    """Ablation: with the -mean(phi) part of the chain rule through the neutrality
+    correction dropped (chi_i = phi_i, planted in the oracle), the forces no longer
+    match central differences of the energy, so the previous test detects that mistake."""
     w = inputs.workload(0)
     sysm, hp, th = w.system, w.hp, w.theta
     es = _es_fd()
     r = orc.compute(hp, es, sysm.pos, sysm.types, sysm.cell, th)
     assert abs(r.terms[7]) > 1e-3  # mean potential is not zero
+    orc.set_ablation(1)
+    try:
+        bad = orc.compute(hp, es, sysm.pos, sysm.types, sysm.cell, th)
+    finally:
+        orc.set_ablation(0)
+    assert bad.energy == r.energy  # the energy does not depend on the switch
+    h = 1e-5
+    worst_good, worst_bad = 0.0, 0.0
+    for i in (0, 1, 77):
+        for a in range(3):
+            p = sysm.pos.copy()
+            p[i, a] += h
+            ep = orc.compute(hp, es, p, sysm.types, sysm.cell, th, forces=False).energy
+            p[i, a] -= 2 * h
+            em = orc.compute(hp, es, p, sysm.types, sysm.cell, th, forces=False).energy
+            fd = -(ep - em) / (2 * h)
+            worst_good = max(worst_good, abs(fd - r.forces[i, a]))
+            worst_bad = max(worst_bad, abs(fd - bad.forces[i, a]))
+    assert worst_good < 2e-7
+    assert worst_bad > 1e-3, worst_bad
 
 
 def test_pppm_forces_large_system_conserve_momentum(orc):
@@ -391,8 +412,22 @@ def test_bec_sum_rule(orc):
         es.q_total = Q
         r = orc.compute(w.hp, es, w.system.pos, w.system.types, w.system.cell, w.theta)
         np.testing.assert_allclose(r.bec.sum(0), Q * np.eye(3), atol=1e-12)
-        np.testing.assert_allclose(np.einsum("iaa->i", r.bec) / 3 - r.q_naked,
-                                   np.einsum("iaa->i", r.bec) / 3 - r.q_naked)  # shape check
+
+
+def test_bec_fixed_charges_is_diagonal(orc):
+    """Charges that do not depend on the positions (w1q = 0, per-species constants)
+    have no pair terms in Eq. 28: Z_i = q~'_i I exactly, with q~' the corrected
+    scaled charge."""
+    w = inputs.workload(0)
+    hp = w.hp
+    th = _fixed_charge_theta(hp, [0.8, -0.35], s=1.3)
+    r = orc.compute(hp, w.es, w.system.pos, w.system.types, w.system.cell, th)
+    assert abs(r.q_naked.sum()) < 1e-12  # corrected to Q = 0
+    want = r.q_naked[:, None, None] * np.eye(3)[None]
+    np.testing.assert_allclose(r.bec, want, atol=1e-13)
+    # and the corrected charges are the constants shifted by the same amount
+    q_t = np.where(w.system.types == 0, 0.8, -0.35) * 1.3
+    np.testing.assert_allclose(r.q_naked - q_t, np.full(w.system.n, (0.0 - q_t.sum()) / w.system.n), atol=1e-13)
 
 
 def _cluster():
