@@ -145,6 +145,25 @@ qnep_status qnep_workspace_size(const void *model, const qnep_es_params *es, con
 qnep_status qnep_compute(void *model, const float *theta, const qnep_es_params *es, const qnep_system *sys,
                          const qnep_outputs *out, void *ws, size_t ws_bytes, void *stream);
 
+/* Allocation-free evaluation, for callers that cannot allocate device memory (code
+   under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+   qnep_compute with the workspace taken from a fixed device array that the library
+   holds, one per GPU, from the first call on that GPU until the process ends.
+     limit      structures whose qnep_workspace_size() exceeds QNEP_STATIC_WORKSPACE_BYTES
+                (64 MiB: about 12,000 water-like atoms with Ewald or PPPM) are rejected
+                with QNEP_E_WORKSPACE before anything is enqueued
+     flags_out  device int32 [1] or NULL: receives the device status bits of this call
+                (those qnep_check_status reports) at the end of the enqueued work
+   The call enqueues kernel launches only (no allocation, no memset, no event record, no
+   synchronization; per-stage timing is not recorded).  Its first call on a device
+   resolves the array's address (hipGetSymbolAddress), so make one call before
+   capturing.  Every call on one GPU shares that GPU's array and the array keeps the
+   last call's contents (every value read is first written by the same call): calls that
+   overlap on one GPU, on different streams or threads, race and give undefined results. */
+#define QNEP_STATIC_WORKSPACE_BYTES (64u * 1024u * 1024u)
+qnep_status qnep_compute_static(void *model, const float *theta, const qnep_es_params *es, const qnep_system *sys,
+                                const qnep_outputs *out, int32_t *flags_out, void *stream);
+
 /* Reverse mode for L = gE * E + gP . P (the adjoint of qnep_compute), recomputing the
    forward pass (descriptors are not kept between calls).  Writes, when non-NULL:
      d_pos   device FP32 SoA [3][N]  dL/dr_i = -gE F_i + sum_a gP_a Z_i[a][:]

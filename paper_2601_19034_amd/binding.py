@@ -78,6 +78,9 @@ def load(path: str = LIB_PATH):
     L.qnep_compute.restype = C.c_int
     L.qnep_compute.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(qnep_es_params), C.POINTER(qnep_system),
                                C.POINTER(qnep_outputs), C.c_void_p, C.c_size_t, C.c_void_p]
+    L.qnep_compute_static.restype = C.c_int
+    L.qnep_compute_static.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(qnep_es_params), C.POINTER(qnep_system),
+                                      C.POINTER(qnep_outputs), C.c_void_p, C.c_void_p]
     L.qnep_check_status.restype = C.c_int
     L.qnep_check_status.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]
     L.qnep_model_enable_timing.restype = C.c_int
@@ -145,6 +148,15 @@ def qnep_compute(model: int, theta_ptr: int, es: qnep_es_params, sysm: qnep_syst
                  ws_ptr: int, ws_bytes: int, stream: int):
     _check(load().qnep_compute(C.c_void_p(model), C.c_void_p(theta_ptr), C.byref(es), C.byref(sysm),
                                C.byref(outs), C.c_void_p(ws_ptr), ws_bytes, C.c_void_p(stream)))
+
+
+def qnep_compute_static(model: int, theta_ptr: int, es: qnep_es_params, sysm: qnep_system, outs: qnep_outputs,
+                        flags_ptr: int, stream: int):
+    _check(load().qnep_compute_static(C.c_void_p(model), C.c_void_p(theta_ptr), C.byref(es), C.byref(sysm),
+                                      C.byref(outs), C.c_void_p(flags_ptr or None), C.c_void_p(stream)))
+
+
+QNEP_STATIC_WORKSPACE_BYTES = 64 * 1024 * 1024
 
 
 def qnep_check_status(ws_ptr: int, stream: int) -> int:

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "batch.h"
@@ -511,6 +512,38 @@ qnep_status batch_layout(const Model &m, const qnep_es_params *es, const qnep_ba
         if (e_ != hipSuccess) return fail(QNEP_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+// workspace of qnep_compute_static (see the header for its size and sharing rules)
+__device__ __align__(256) char scratch[QNEP_STATIC_WORKSPACE_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mutex;
+char *g_scratch_ptr[MAX_DEVICES] = {};
+
+// device address of this GPU's `scratch`, resolved once per device with that device current
+qnep_status static_workspace(char **ptr) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(QNEP_E_UNSUPPORTED, "device ordinal beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *addr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch)));
+        if (!addr) return fail(QNEP_E_DEVICE, "hipGetSymbolAddress returned a null address");
+        g_scratch_ptr[dev] = static_cast<char *>(addr);
+    }
+    *ptr = g_scratch_ptr[dev];
+    return QNEP_OK;
+}
+
+__global__ void k_copy_flags(const int32_t *__restrict__ src, int32_t *__restrict__ dst) {
+    if (threadIdx.x == 0) dst[0] = src[0];
+}
+
+hipError_t copy_flags(const int32_t *src, int32_t *dst, hipStream_t st) {
+    hipLaunchKernelGGL(k_copy_flags, dim3(1), dim3(64), 0, st, src, dst);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 extern "C" {
@@ -603,6 +636,40 @@ qnep_status qnep_compute(void *model, const float *theta, const qnep_es_params *
         HIP_TRY(mm.timer.begin(p.stream));
     }
     HIP_TRY(run_forward(p));
+    return QNEP_OK;
+}
+
+// The allocation-free variant of qnep_compute: the whole workspace lives in `scratch`,
+// a file-scope device array (one per GPU, held while the process runs).  Host code
+// never passes the array's name to a kernel or a copy: its device address is resolved
+// with hipGetSymbolAddress once per device (the first call on that device) and only
+// that address is used afterwards.
+qnep_status qnep_compute_static(void *model, const float *theta, const qnep_es_params *es, const qnep_system *sys,
+                                const qnep_outputs *out, int32_t *flags_out, void *stream) {
+    if (!model || !theta || !out) return fail(QNEP_E_INVALID_ARG, "null argument");
+    const Model &m = *static_cast<const Model *>(model);
+    Plan p;
+    size_t need = 0;
+    qnep_status s = make_plan(m, es, sys, nullptr, p, &need);
+    if (s != QNEP_OK) return s;
+    if (need > (size_t)QNEP_STATIC_WORKSPACE_BYTES)
+        return fail(QNEP_E_WORKSPACE, "structure needs " + std::to_string(need) +
+                                          " bytes of workspace; the static workspace holds " +
+                                          std::to_string((size_t)QNEP_STATIC_WORKSPACE_BYTES));
+    if (p.N > 0 && (!sys->pos || !sys->type)) return fail(QNEP_E_INVALID_ARG, "null positions or types");
+    char *ws = nullptr;
+    s = static_workspace(&ws);
+    if (s != QNEP_OK) return s;
+    s = make_plan(m, es, sys, ws, p, &need);
+    if (s != QNEP_OK) return s;
+    p.pos = sys->pos;
+    p.type = sys->type;
+    p.theta = theta;
+    p.out = *out;
+    p.stream = static_cast<hipStream_t>(stream);
+    p.timer = nullptr;  // no event records: nothing but kernel launches is enqueued
+    HIP_TRY(run_forward(p));
+    if (flags_out) HIP_TRY(copy_flags(p.flags, flags_out, p.stream));
     return QNEP_OK;
 }
 
