@@ -66,8 +66,15 @@ typedef enum {
 
 /* MLP arithmetic */
 #define QNEP_MLP_FP32 0   /* FP32 vector ALU */
-#define QNEP_MLP_BF16 1   /* BF16 inputs on the matrix cores, FP32 accumulation */
-#define QNEP_MLP_BF16X3 2 /* BF16 matrix cores with operands split hi + lo (three products), FP32 accumulation */
+/* The BF16 forms run both products of the network on the matrix cores (BF16 inputs,
+   FP32 accumulation) with FP32 operands split as hi + lo BF16 parts:
+   QNEP_MLP_BF16    forward D W0^T with both operands split (three products), backward
+                    G W0 with the split weights against the activation gradient rounded
+                    once to BF16 (two products); forces within 5 meV/A of FP64 on the test
+                    workloads (a single rounding of every operand is not: about 1e-2)
+   QNEP_MLP_BF16X3  both products with both operands split (about 16 mantissa bits) */
+#define QNEP_MLP_BF16 1
+#define QNEP_MLP_BF16X3 2
 
 /* NEP hyper-parameters (Sec. 2.1; the descriptor definitions are the published
    NEP3/NEP4 ones the paper refers to):
@@ -96,6 +103,9 @@ typedef struct {
     int32_t mesh[3];        /* PPPM mesh along a, b, c: each a product of 2, 3, 5, at most 1024 */
     int32_t order;          /* PPPM assignment order, 5 */
     double q_total;         /* target total charge Q of Eq. 33 */
+    double efield[3];       /* external electric field E (V/Angstrom): adds F_i[b] += sum_a E_a Z_i[a][b]
+                               to the forces (Sec. 2.4 Eq. 29); the energy and virial carry no field
+                               term (the paper gives the force only).  Zero = no field */
 } qnep_es_params;
 
 /* one periodic structure */
@@ -116,6 +126,12 @@ typedef struct {
     float *bec;            /* [9][N]: Z_i[a][b] stored at bec[(3a+b)*N + i] */
     double *polarization;  /* [3] */
     double *energy_terms;  /* [8]: U_NEP, U_r, U_k, U_s, U_bg, sum q_raw, mean phi, number of k vectors */
+    float *virial_atom;    /* [9][N]: per-atom virial W_i[a][b] at virial_atom[(3a+b)*N + i] (Sec. 2.3
+                              Eq. 12, W_i = sum_j r_ij (x) F_ji over every partial force; reciprocal part
+                              per atom by Eq. 20 (Ewald) or Eq. 39 (PPPM, six more inverse transforms);
+                              the static real-space pair virial shared equally by the two atoms; the
+                              background virial U_bg I split evenly).  sum_i W_i = W.  NULL = skip (the
+                              extra work is only done when requested) */
 } qnep_outputs;
 
 /* number of entries of the flat FP32 parameter vector theta, laid out as
@@ -168,15 +184,45 @@ qnep_status qnep_compute_static(void *model, const float *theta, const qnep_es_p
    forward pass (descriptors are not kept between calls).  Writes, when non-NULL:
      d_pos   device FP32 SoA [3][N]  dL/dr_i = -gE F_i + sum_a gP_a Z_i[a][:]
              (the polarization term uses the periodic Born charges of Eq. 28)
-     d_cell  device FP64 [9]         dL/dh for the row-major cell at fixed Cartesian
-             positions, gE h^{-T} (sum_i F_i (x) r_i - W)^T (energy term only)
+     d_cell  device FP64 [9]         dE/dh for the row-major cell at fixed Cartesian
+             positions, gE h^{-T} (sum_i F_i (x) r_i - W)^T.  The energy term only: the
+             cell derivative of P (through the image shifts that enter the charges) is
+             not formed, so a call with d_cell != NULL and a non-zero gP is rejected
+             with QNEP_E_UNSUPPORTED before anything is enqueued
      d_theta device FP32 [n_theta]   exact dL/dtheta in the parameter layout above
-   gP may be NULL (zero).  ws must hold qnep_backward_workspace_size() bytes. */
+   gP may be NULL (zero).  es->efield must be zero (the adjoint is of the field-free
+   energy; QNEP_E_UNSUPPORTED otherwise).  ws must hold qnep_backward_workspace_size() bytes. */
 qnep_status qnep_backward_workspace_size(const void *model, const qnep_es_params *es, const qnep_system *sys,
                                          size_t *bytes);
 qnep_status qnep_backward(void *model, const float *theta, const qnep_es_params *es, const qnep_system *sys,
                           double gE, const double *gP, float *d_pos, double *d_cell, float *d_theta, void *ws,
                           size_t ws_bytes, void *stream);
+
+/* Molecular dynamics in the microcanonical ensemble (velocity Verlet), the workload the
+   paper's speed figures refer to (Sec. 3.1), with the time series of the polarization
+   current P_dot_a = sum_i sum_b Z_i[a][b] v_i[b] (Sec. 2.4 Eq. 30).  Every step runs one
+   full evaluation (neighbour lists rebuilt from the sorted bins each step).
+     md->dt        time step, fs;  md->n_steps  number of steps (>= 0)
+     md->masses    host, [n_types], atomic mass units
+     type          device, [N];  cell: host [9] as in qnep_system
+     pos, vel      device FP32 SoA [3][N], Angstrom and Angstrom/fs, updated in place
+                   (positions are not wrapped back into the cell)
+     series        device FP64 [n_steps + 1][8]: E_pot, E_kin, P_dot (3, e*Angstrom/fs),
+                   P (3, e*Angstrom); row 0 is the initial state, row s the state after
+                   step s.  With an external field (es->efield) the forces include the
+                   field force and E_pot excludes the field's work.
+   ws must hold qnep_md_workspace_size() bytes; the device status word is at its start
+   (qnep_check_status).  Asynchronous; nothing is allocated. */
+typedef struct {
+    double dt;
+    int32_t n_steps;
+    const double *masses;
+} qnep_md_params;
+qnep_status qnep_md_workspace_size(const void *model, const qnep_es_params *es, int64_t n_atoms,
+                                   const double *cell, size_t *bytes);
+qnep_status qnep_md_nve(void *model, const float *theta, const qnep_es_params *es, const qnep_md_params *md,
+                        int64_t n_atoms, const int32_t *type, const double *cell, float *pos, float *vel,
+                        double *series, void *ws, size_t ws_bytes, void *stream);
 
 /* synchronizes `stream` and returns the device status bits of the last call that
    used this workspace (0 = no device-side condition). */
@@ -246,6 +292,7 @@ typedef struct {
 qnep_status qnep_batch_workspace_size(const void *model, const qnep_es_params *es, const qnep_batch *batch,
                                       int32_t max_candidates, size_t *bytes);
 /* enqueues the parameter-independent setup (lists, k-sets, Ewald pair matrices).
+   es->efield must be zero (QNEP_E_UNSUPPORTED otherwise).
    Raises QNEP_FLAG_RADIAL_OVERFLOW / QNEP_FLAG_BAD_SPECIES in the status word. */
 qnep_status qnep_batch_prepare(void *model, const qnep_es_params *es, const qnep_batch *batch,
                                int32_t max_candidates, void *ws, size_t ws_bytes, void *stream);
@@ -265,6 +312,25 @@ qnep_status qnep_batch_compute(void *model, const float *thetas, int32_t n_candi
 qnep_status qnep_batch_gradient(void *model, const float *thetas, int32_t n_candidates,
                                 const qnep_batch_targets *targets, const qnep_batch_outputs *outputs,
                                 float *d_thetas, void *ws, size_t ws_bytes, void *stream);
+/* One generation of the separable natural evolution strategy the paper trains with
+   (Sec. 2.5; Schaul, Glasmachers and Schmidhuber 2011) on the prepared batch:
+     1. population   thetas[k] = mu + sigma * noise[k]   (k = 0..C-1)
+     2. fitness      qnep_batch_compute on the population; outputs->loss[k] (required)
+                     receives each member's loss (the other outputs as in that call)
+     3. update       members ranked by loss (ties by index), rank utilities
+                     u_r = max(0, ln(C/2+1) - ln r) / sum_j max(0, ln(C/2+1) - ln j) - 1/C,
+                     mu += eta_mu sigma sum_k u_k noise[k],
+                     sigma *= exp(eta_sigma / 2 sum_k u_k (noise[k]^2 - 1))
+   mu, sigma: device FP32 [n_theta], updated in place.  noise: device FP32 [C][n_theta],
+   standard-normal draws chosen by the caller (the library draws no random numbers).
+   thetas: device FP32 [C][n_theta], receives the population.  2 <= C <= min(1024,
+   max_candidates of the prepare call).  eta_sigma <= 0 selects the published default
+   (3 + ln d) / (5 sqrt d), d = n_theta.  Asynchronous like qnep_batch_compute. */
+qnep_status qnep_snes_generation(void *model, float *mu, float *sigma, const float *noise, int32_t n_candidates,
+                                 double eta_mu, double eta_sigma, const qnep_batch_targets *targets,
+                                 const qnep_batch_outputs *outputs, float *thetas, void *ws, size_t ws_bytes,
+                                 void *stream);
+
 /* Autotuner: times the lanes-per-atom choice for each structure-size class (fewer
    than 48, 48-127, 128-383, 384 or more atoms) over {1, 2, 4, 8, 16} and then the
    number of resident workgroups per compute unit over {1, 2, 3, 4}, on the prepared

@@ -48,7 +48,7 @@ class _HP(C.Structure):
 class _ES(C.Structure):
     _fields_ = [("mode", C.c_int), ("method", C.c_int), ("alpha", C.c_double), ("rc_coul", C.c_double),
                 ("kmax", C.c_double), ("kmax_inclusive", C.c_int), ("mesh", C.c_int * 3), ("order", C.c_int),
-                ("q_total", C.c_double)]
+                ("q_total", C.c_double), ("efield", C.c_double * 3)]
 
 
 _DP = C.POINTER(C.c_double)
@@ -56,7 +56,7 @@ _DP = C.POINTER(C.c_double)
 
 class _OUT(C.Structure):
     _fields_ = [(name, _DP) for name in ("terms", "forces", "virial", "q_screened", "q_naked", "q_raw", "bec",
-                                         "pol", "desc", "site_energy", "phi")]
+                                         "pol", "desc", "site_energy", "phi", "vatom")]
 
 
 def lib():
@@ -93,7 +93,8 @@ def _hp(hp) -> _HP:
 
 def _es(es) -> _ES:
     m = (C.c_int * 3)(*[int(x) for x in es.mesh])
-    return _ES(es.mode, es.method, es.alpha, es.rc_coul, es.kmax, es.kmax_inclusive, m, es.order, es.q_total)
+    E = (C.c_double * 3)(*[float(x) for x in getattr(es, "efield", (0.0, 0.0, 0.0))])
+    return _ES(es.mode, es.method, es.alpha, es.rc_coul, es.kmax, es.kmax_inclusive, m, es.order, es.q_total, E)
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -116,6 +117,7 @@ class OracleResult:
     desc: np.ndarray
     site_energy: np.ndarray
     phi: np.ndarray
+    vatom: Optional[np.ndarray] = None  # (N, 3, 3) per-atom virial W_i[a][b]
 
 
 def theta_count(hp) -> int:
@@ -123,11 +125,14 @@ def theta_count(hp) -> int:
     return int(lib().oq_theta_count(C.byref(h)))
 
 
-def compute(hp, es, pos, types, cell, theta, forces: bool = True, cells: bool = False) -> OracleResult:
+def compute(hp, es, pos, types, cell, theta, forces: bool = True, cells: bool = False,
+            per_atom_virial: bool = False) -> OracleResult:
     """Evaluate E, F, W, q, Z*, P (and intermediates) in FP64.
 
     pos (N, 3) Angstrom, types (N,) int, cell (3, 3) rows a, b, c, theta flat vector.
-    ``cells`` selects the cell-list neighbour search instead of brute force."""
+    ``cells`` selects the cell-list neighbour search instead of brute force;
+    ``per_atom_virial`` also returns W_i (needs ``forces``).  A non-zero ``es.efield``
+    adds the external-field force to the forces."""
     pos = np.ascontiguousarray(pos, dtype=np.float64)
     types = np.ascontiguousarray(types, dtype=np.int32)
     cell = np.ascontiguousarray(cell, dtype=np.float64)
@@ -143,14 +148,15 @@ def compute(hp, es, pos, types, cell, theta, forces: bool = True, cells: bool = 
     D = np.zeros((n, ndes))
     U = np.zeros(n)
     phi = np.zeros(n)
+    Va = np.zeros((n, 3, 3)) if (forces and per_atom_virial) else None
     out = _OUT(_ptr(terms), _ptr(F), _ptr(W), _ptr(qs), _ptr(qt), _ptr(qr), _ptr(Z), _ptr(P), _ptr(D), _ptr(U),
-               _ptr(phi))
+               _ptr(phi), _ptr(Va))
     h, e = _hp(hp), _es(es)
     rc = lib().oq_compute(C.byref(h), C.byref(e), n, _ptr(pos), types.ctypes.data_as(C.POINTER(C.c_int)),
                           _ptr(cell), _ptr(theta), 1 if cells else 0, 1 if forces else 0, C.byref(out))
     if rc != 0:
         raise ValueError(f"oracle rejected the input (code {rc})")
-    return OracleResult(terms[0], terms, F, W, qs, qt, qr, Z, P, D, U, phi)
+    return OracleResult(terms[0], terms, F, W, qs, qt, qr, Z, P, D, U, phi, Va)
 
 
 def set_ablation(flags: int) -> None:

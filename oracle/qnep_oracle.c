@@ -32,7 +32,12 @@
  *   - the influence function's denominator is squared and its z^6 coefficient is
  *     -17/189 (the value of the P = 5 alias sum);
  *   - the PPPM virial uses the Ewald stress kernel B(k) with G_opt in place of G;
- *   - background term -k_e pi Q'^2 / (2 Omega alpha^2) in mode 1 for Q != 0.
+ *   - background term -k_e pi Q'^2 / (2 Omega alpha^2) in mode 1 for Q != 0;
+ *   - per-atom virial W_i = sum_j r_ij (x) F_ji over every partial force, the static
+ *     real-space pair virial shared equally, the reciprocal per-atom forms, and the
+ *     background virial split evenly over the atoms;
+ *   - an external field E adds F_i += sum_a E_a Z_i[a][:] (Eq. 29) to the forces only
+ *     (no energy or virial term: the paper gives the force alone).
  *
  * Units: eV, Angstrom, elementary charge.  Virial W = -dE/d(strain).
  */
@@ -60,6 +65,7 @@ typedef struct {
     int mesh[3];
     int order;           /* assignment order P (5, Sec. 2.6) */
     double q_total;      /* target total charge Q */
+    double efield[3];    /* external electric field E (V/Angstrom), Sec. 2.4 */
 } oq_es;
 
 /* any pointer may be NULL */
@@ -75,6 +81,7 @@ typedef struct {
     double *desc;         /* N*n_des */
     double *site_energy;  /* N */
     double *phi;          /* N: dU_ES/dq'_i */
+    double *vatom;        /* N*9: per-atom virial W_i[a][b] (Sec. 2.3 Eq. 12 and the per-atom reciprocal terms) */
 } oq_out;
 
 /* ------------------------------------------------------------------ */
@@ -511,7 +518,7 @@ void oq_dft3(double *re, double *im, const int *N, int sign)
 /* q is the screened corrected charge q'                                */
 /* ------------------------------------------------------------------ */
 static void recip_ewald(const oq_es *es, int n, const double *pos, const double *h, const double *q, double *Uk,
-                        double *phik, double *Fk, double *Wk, double *nk_out)
+                        double *phik, double *Fk, double *Wk, double *nk_out, double *Wa)
 {
     double hi[9];
     inv3(h, hi);
@@ -571,10 +578,11 @@ static void recip_ewald(const oq_es *es, int n, const double *pos, const double 
     }
     *Uk = U;
     for (int t = 0; t < 9; ++t) Wk[t] = W[t];
-    /* phi^k_i = 2 k_e sum_k G Re[S e^{i k.r_i}],  F^k_i = 2 k_e q_i sum_k k G Im[S e^{i k.r_i}] (Eq. 18) */
+    /* phi^k_i = 2 k_e sum_k G Re[S e^{i k.r_i}],  F^k_i = 2 k_e q_i sum_k k G Im[S e^{i k.r_i}] (Eq. 18);
+       per-atom virial W^k_i = k_e q_i sum_k G Re[S e^{i k.r_i}] B(k) (Eq. 20) */
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < n; ++i) {
-        double ph = 0.0, f[3] = {0, 0, 0};
+        double ph = 0.0, f[3] = {0, 0, 0}, wa[9] = {0};
         for (int s = 0; s < nk; ++s) {
             const double *k = kv + 3 * s;
             double a = k[0] * pos[3 * i] + k[1] * pos[3 * i + 1] + k[2] * pos[3 * i + 2];
@@ -582,15 +590,23 @@ static void recip_ewald(const oq_es *es, int n, const double *pos, const double 
             double re = Sre[s] * c - Sim[s] * sn, im = Sre[s] * sn + Sim[s] * c;
             ph += G[s] * re;
             for (int b = 0; b < 3; ++b) f[b] += k[b] * G[s] * im;
+            if (Wa) {
+                double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+                double cb = 2.0 / (4.0 * alpha * alpha) + 2.0 / k2;
+                for (int x = 0; x < 3; ++x)
+                    for (int y = 0; y < 3; ++y) wa[3 * x + y] += G[s] * re * ((x == y ? 1.0 : 0.0) - cb * k[x] * k[y]);
+            }
         }
         phik[i] = 2.0 * ORC_KE * ph;
         for (int b = 0; b < 3; ++b) Fk[3 * i + b] = 2.0 * ORC_KE * q[i] * f[b];
+        if (Wa)
+            for (int t = 0; t < 9; ++t) Wa[9 * i + t] = ORC_KE * q[i] * wa[t];
     }
     free(kv); free(Sre); free(Sim); free(G);
 }
 
 static void recip_pppm(const oq_es *es, int n, const double *pos, const double *h, const double *q, double *Uk,
-                       double *phik, double *Fk, double *Wk)
+                       double *phik, double *Fk, double *Wk, double *Wa)
 {
     const int P = es->order;
     const int *N = es->mesh;
@@ -632,6 +648,11 @@ static void recip_pppm(const oq_es *es, int n, const double *pos, const double *
     double *Are = (double *)calloc((size_t)M, sizeof(double)), *Aim = (double *)calloc((size_t)M, sizeof(double));
     double *Ex[3];
     for (int a = 0; a < 3; ++a) Ex[a] = (double *)calloc((size_t)M * 2, sizeof(double));
+    /* per-atom virial: S G_opt B_xy for the six independent components (Eq. 39) */
+    static const int VX[6] = {0, 1, 2, 0, 0, 1}, VY[6] = {0, 1, 2, 1, 2, 2};
+    double *Vm[6] = {0};
+    if (Wa)
+        for (int c = 0; c < 6; ++c) Vm[c] = (double *)calloc((size_t)M * 2, sizeof(double));
     double U = 0.0, W[9] = {0};
     for (int j0 = 0; j0 < N[0]; ++j0)
         for (int j1 = 0; j1 < N[1]; ++j1)
@@ -668,12 +689,20 @@ static void recip_pppm(const oq_es *es, int n, const double *pos, const double *
                     Ex[a][lin] = -kt[a] * Aim[lin];          /* real part of i k (A_re + i A_im) */
                     Ex[a][M + lin] = kt[a] * Are[lin];       /* imaginary part */
                 }
+                if (Wa)
+                    for (int cc = 0; cc < 6; ++cc) {
+                        double B = (VX[cc] == VY[cc] ? 1.0 : 0.0) - c * k[VX[cc]] * k[VY[cc]];
+                        Vm[cc][lin] = Are[lin] * B;
+                        Vm[cc][M + lin] = Aim[lin] * B;
+                    }
             }
     *Uk = U;
     for (int t = 0; t < 9; ++t) Wk[t] = W[t];
     /* inverse transforms (unnormalized, e^{+ik.r}) */
     oq_dft3(Are, Aim, N, +1);
     for (int a = 0; a < 3; ++a) oq_dft3(Ex[a], Ex[a] + M, N, +1);
+    if (Wa)
+        for (int cc = 0; cc < 6; ++cc) oq_dft3(Vm[cc], Vm[cc] + M, N, +1);
     /* gather: phi^k_i = 2 k_e sum_s W F^-1[S G_opt]  (Eq. 38 form),
                F^k_i  = -2 k_e q_i sum_s W F^-1[i k S G_opt]  (Eq. 37) */
     for (int i = 0; i < n; ++i) {
@@ -683,7 +712,7 @@ static void recip_pppm(const oq_es *es, int n, const double *pos, const double *
             m0[a] = (int)floor(u[3 * i + a] + 0.5);
             for (int t = -half; t <= half; ++t) w[a][t + half] = assign_w(P, u[3 * i + a] - (m0[a] + t));
         }
-        double ph = 0.0, e[3] = {0, 0, 0};
+        double ph = 0.0, e[3] = {0, 0, 0}, vv[6] = {0, 0, 0, 0, 0, 0};
         for (int t0 = -half; t0 <= half; ++t0)
             for (int t1 = -half; t1 <= half; ++t1)
                 for (int t2 = -half; t2 <= half; ++t2) {
@@ -694,12 +723,21 @@ static void recip_pppm(const oq_es *es, int n, const double *pos, const double *
                     double ww = w[0][t0 + half] * w[1][t1 + half] * w[2][t2 + half];
                     ph += ww * Are[lin];
                     for (int a = 0; a < 3; ++a) e[a] += ww * Ex[a][lin];
+                    if (Wa)
+                        for (int cc = 0; cc < 6; ++cc) vv[cc] += ww * Vm[cc][lin];
                 }
         phik[i] = 2.0 * ORC_KE * ph;
         for (int a = 0; a < 3; ++a) Fk[3 * i + a] = -2.0 * ORC_KE * q[i] * e[a];
+        /* W^k_i = k_e q_i sum_s W(r_i - r_s) F^-1[S G_opt B] (Eq. 39) */
+        if (Wa)
+            for (int cc = 0; cc < 6; ++cc) {
+                Wa[9 * i + 3 * VX[cc] + VY[cc]] = ORC_KE * q[i] * vv[cc];
+                Wa[9 * i + 3 * VY[cc] + VX[cc]] = ORC_KE * q[i] * vv[cc];
+            }
     }
     free(u); free(rre); free(rim); free(Are); free(Aim);
     for (int a = 0; a < 3; ++a) free(Ex[a]);
+    for (int cc = 0; cc < 6; ++cc) free(Vm[cc]);
 }
 
 /* ------------------------------------------------------------------ */
@@ -762,6 +800,7 @@ int oq_compute(const oq_hparams *hp, const oq_es *es, int n, const double *pos, 
     /* electrostatics on q' */
     double *phi = (double *)calloc((size_t)n, sizeof(double));
     double *Fst = (double *)calloc((size_t)n * 3, sizeof(double));
+    double *Va = want_forces && out->vatom ? (double *)calloc((size_t)n * 9, sizeof(double)) : NULL;
     double Ur = 0.0, Us = 0.0, Ubg = 0.0, Uk = 0.0, Wst[9] = {0}, nk = 0.0;
     if (es->mode == 1) {
         /* real space (Sec. 2.2.1 Eq. 6; static pair force Eq. 15) */
@@ -783,6 +822,10 @@ int oq_compute(const oq_hparams *hp, const oq_es *es, int n, const double *pos, 
                     /* W = -sum_{pairs} u'(r) r_a r_b / r, each unordered pair seen twice */
                     for (int a = 0; a < 3; ++a)
                         for (int b = 0; b < 3; ++b) Wl[3 * a + b] -= 0.5 * du * pp->d[a] * pp->d[b] / r;
+                    /* per atom: W_i += r_ij (x) F_ji with the static partial force F_ji = u'(r) r_ji / (2 r) */
+                    if (Va)
+                        for (int a = 0; a < 3; ++a)
+                            for (int b = 0; b < 3; ++b) Va[9 * i + 3 * a + b] -= 0.5 * du * pp->d[a] * pp->d[b] / r;
                 }
                 phi[i] += ph;
                 Ur += 0.5 * qs[i] * ph;
@@ -801,16 +844,23 @@ int oq_compute(const oq_hparams *hp, const oq_es *es, int n, const double *pos, 
         Ubg = -ORC_KE * ORC_PI * Qs * Qs / (2.0 * vol * alpha * alpha);
         for (int i = 0; i < n; ++i) phi[i] += -ORC_KE * ORC_PI * Qs / (vol * alpha * alpha);
         for (int a = 0; a < 3; ++a) Wst[4 * a] += Ubg;
+        if (Va)
+            for (int i = 0; i < n; ++i)
+                for (int a = 0; a < 3; ++a) Va[9 * i + 4 * a] += Ubg / n;
     }
     {
         double *phik = (double *)calloc((size_t)n, sizeof(double)), *Fk = (double *)calloc((size_t)n * 3, sizeof(double));
         double Wk[9] = {0};
-        if (es->method == 0) recip_ewald(es, n, pos, cell, qs, &Uk, phik, Fk, Wk, &nk);
-        else recip_pppm(es, n, pos, cell, qs, &Uk, phik, Fk, Wk);
+        double *Wka = Va ? (double *)calloc((size_t)n * 9, sizeof(double)) : NULL;
+        if (es->method == 0) recip_ewald(es, n, pos, cell, qs, &Uk, phik, Fk, Wk, &nk, Wka);
+        else recip_pppm(es, n, pos, cell, qs, &Uk, phik, Fk, Wk, Wka);
         for (int i = 0; i < n; ++i) {
             phi[i] += phik[i];
             for (int b = 0; b < 3; ++b) Fst[3 * i + b] += Fk[3 * i + b];
+            if (Va)
+                for (int t = 0; t < 9; ++t) Va[9 * i + t] += Wka[9 * i + t];
         }
+        free(Wka);
         for (int t = 0; t < 9; ++t) Wst[t] += Wk[t];
         free(phik); free(Fk);
     }
@@ -934,13 +984,21 @@ int oq_compute(const oq_hparams *hp, const oq_es *es, int n, const double *pos, 
                     for (int a = 0; a < 3; ++a)
                         for (int b = 0; b < 3; ++b) {
                             W[3 * a + b] -= fij[a] * pp->d[b];
+                            /* per atom (Eq. 12): W_j += r_ji (x) F_ij */
+                            if (Va) Va[9 * j + 3 * a + b] -= pp->d[a] * fij[b];
                             double c = 0.5 * pp->d[a] * aij[b];
                             Zl[9 * i + 3 * a + b] += c;
                             Zl[9 * j + 3 * a + b] -= c;
                         }
                 }
         }
+        /* external field (Eq. 29): F_i[b] += sum_a E_a Z_i[a][b] */
+        if (es->efield[0] != 0.0 || es->efield[1] != 0.0 || es->efield[2] != 0.0)
+            for (int i = 0; i < n; ++i)
+                for (int b = 0; b < 3; ++b)
+                    for (int a = 0; a < 3; ++a) Fl[3 * i + b] += es->efield[a] * Zl[9 * i + 3 * a + b];
         if (F) memcpy(F, Fl, sizeof(double) * 3 * (size_t)n);
+        if (Va) memcpy(out->vatom, Va, sizeof(double) * 9 * (size_t)n);
         if (Z) memcpy(Z, Zl, sizeof(double) * 9 * (size_t)n);
         if (out->virial) memcpy(out->virial, W, sizeof(double) * 9);
         free(Fl); free(Zl);
@@ -949,5 +1007,6 @@ int oq_compute(const oq_hparams *hp, const oq_es *es, int n, const double *pos, 
 
     free_lists(n, LR); free_lists(n, LA); free_lists(n, LC);
     free(frac); free(wpos); free(D); free(gU); free(gq); free(U); free(qraw); free(qt); free(qs); free(phi); free(Fst);
+    free(Va);
     return 0;
 }

@@ -15,7 +15,9 @@ import torch
 
 from . import binding as B
 
-ALL_OUTPUTS = ("energy", "forces", "virial", "charges", "charges_naked", "bec", "polarization", "energy_terms")
+ALL_OUTPUTS = ("energy", "forces", "virial", "charges", "charges_naked", "bec", "polarization", "energy_terms",
+               "virial_atom")
+DEFAULT_OUTPUTS = ALL_OUTPUTS[:-1]  # the per-atom virial costs extra work and is requested explicitly
 
 
 def _require_gpu():
@@ -59,7 +61,7 @@ class QNEP:
         return self._ws
 
     def compute(self, pos: torch.Tensor, types: torch.Tensor, cell, theta: torch.Tensor, es,
-                outputs=ALL_OUTPUTS, out: Optional[Dict[str, torch.Tensor]] = None,
+                outputs=DEFAULT_OUTPUTS, out: Optional[Dict[str, torch.Tensor]] = None,
                 stream: Optional[torch.cuda.Stream] = None) -> Dict[str, torch.Tensor]:
         """pos: float32 device tensor [3, N] (SoA); types: int32 [N]; cell: (3, 3) rows a, b, c;
         theta: float32 device [n_theta].  Returns device tensors (energy, virial, polarization in
@@ -80,7 +82,8 @@ class QNEP:
             shapes = {"energy": ((1,), torch.float64), "forces": ((3, n), torch.float32),
                       "virial": ((9,), torch.float64), "charges": ((n,), torch.float32),
                       "charges_naked": ((n,), torch.float32), "bec": ((9, n), torch.float32),
-                      "polarization": ((3,), torch.float64), "energy_terms": ((8,), torch.float64)}
+                      "polarization": ((3,), torch.float64), "energy_terms": ((8,), torch.float64),
+                      "virial_atom": ((9, n), torch.float32)}
             for k in outputs:
                 shp, dt = shapes[k]
                 out[k] = torch.empty(shp, dtype=dt, device=dev)
@@ -114,8 +117,8 @@ def to_device_inputs(system, theta: np.ndarray, device="cuda"):
 def _backward(self, pos, types, cell, theta, es, gE: float = 1.0, gP=None, want=("pos", "cell", "theta"),
               stream=None):
     """Adjoint of ``compute`` for L = gE E + gP . P.  Returns a dict with
-    ``pos`` ([3, N] float32, dL/dr), ``cell`` ([3, 3] float64, dL/dh at fixed positions,
-    energy term) and ``theta`` ([n_theta] float32, exact dL/dtheta), all device tensors."""
+    ``pos`` ([3, N] float32, dL/dr), ``cell`` ([3, 3] float64, dE/dh at fixed positions;
+    only with gP = 0, the library rejects the cell derivative of P) and ``theta`` ([n_theta] float32, exact dL/dtheta), all device tensors."""
     _require_gpu()
     n = pos.shape[1]
     dev = pos.device
@@ -164,7 +167,11 @@ class QnepFunction(torch.autograd.Function):
         pos, theta = ctx.saved_tensors
         ge = float(gE.detach().cpu()) if gE is not None else 0.0
         gp = gP.detach().cpu().numpy().astype(np.float64) if gP is not None else None
-        g = ctx.model.backward(pos.detach(), ctx.types, ctx.cell_np, theta.detach(), ctx.es, ge, gp)
+        if ctx.needs_input_grad[2] and gp is not None and np.any(gp != 0.0):
+            raise NotImplementedError("the cell gradient covers the energy only: P enters the loss while the "
+                                      "cell requires a gradient")
+        want = ("pos", "theta", "cell") if ctx.needs_input_grad[2] else ("pos", "theta")
+        g = ctx.model.backward(pos.detach(), ctx.types, ctx.cell_np, theta.detach(), ctx.es, ge, gp, want=want)
         dcell = g["cell"].to("cpu") if ctx.needs_input_grad[2] else None
         return g["pos"], g["theta"], dcell, None, None, None
 
@@ -245,6 +252,26 @@ class QNEPBatch:
                               self.ws.numel(), s.cuda_stream)
         self._stream = s
         return out, d
+
+    def snes_generation(self, mu: torch.Tensor, sigma: torch.Tensor, noise: torch.Tensor, E_ref: torch.Tensor,
+                        F_ref: torch.Tensor, lambdas=(1.0, 1.0, 1.0, 0.0, 0.0), eta_mu: float = 1.0,
+                        eta_sigma: float = 0.0, outputs=("loss",),
+                        stream: Optional[torch.cuda.Stream] = None) -> Dict[str, torch.Tensor]:
+        """One SNES generation: mu, sigma (float32 [n_theta]) are updated in place from
+        the population mu + sigma * noise (noise float32 [C, n_theta]); returns the
+        outputs (``loss`` per member always) and the population under ``thetas``."""
+        assert mu.dtype == torch.float32 and sigma.dtype == torch.float32 and noise.dtype == torch.float32
+        assert mu.is_contiguous() and sigma.is_contiguous() and noise.is_contiguous()
+        thetas = torch.empty_like(noise)
+        outs = tuple(outputs) if "loss" in outputs else ("loss",) + tuple(outputs)
+        C_, tg, oc, out = self._args(thetas, E_ref, F_ref, lambdas, outs)
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        B.qnep_snes_generation(self.model.handle, mu.data_ptr(), sigma.data_ptr(), noise.data_ptr(), C_, eta_mu,
+                               eta_sigma, tg, oc, thetas.data_ptr(), self.ws.data_ptr(), self.ws.numel(),
+                               s.cuda_stream)
+        self._stream = s
+        out["thetas"] = thetas
+        return out
 
     def tune(self, thetas, E_ref, F_ref, lambdas=(1.0, 1.0, 1.0, 0.0, 0.0)):
         """Autotunes lanes per atom (per size class) and workgroups per CU; returns the choice."""

@@ -31,7 +31,7 @@ class qnep_hparams(C.Structure):
 class qnep_es_params(C.Structure):
     _fields_ = [("mode", C.c_int32), ("method", C.c_int32), ("alpha", C.c_double), ("rc_coul", C.c_double),
                 ("kmax", C.c_double), ("kmax_inclusive", C.c_int32), ("mesh", C.c_int32 * 3), ("order", C.c_int32),
-                ("q_total", C.c_double)]
+                ("q_total", C.c_double), ("efield", C.c_double * 3)]
 
 
 class qnep_system(C.Structure):
@@ -41,7 +41,7 @@ class qnep_system(C.Structure):
 class qnep_outputs(C.Structure):
     _fields_ = [("energy", C.c_void_p), ("forces", C.c_void_p), ("virial", C.c_void_p), ("charges", C.c_void_p),
                 ("charges_naked", C.c_void_p), ("bec", C.c_void_p), ("polarization", C.c_void_p),
-                ("energy_terms", C.c_void_p)]
+                ("energy_terms", C.c_void_p), ("virial_atom", C.c_void_p)]
 
 
 class QnepError(RuntimeError):
@@ -111,8 +111,9 @@ def make_hparams(hp) -> qnep_hparams:
 
 def make_es(es) -> qnep_es_params:
     mesh = (C.c_int32 * 3)(*[int(m) for m in es.mesh])
+    field = (C.c_double * 3)(*[float(x) for x in getattr(es, "efield", (0.0, 0.0, 0.0))])
     return qnep_es_params(int(es.mode), int(es.method), float(es.alpha), float(es.rc_coul), float(es.kmax),
-                          int(es.kmax_inclusive), mesh, int(es.order), float(es.q_total))
+                          int(es.kmax_inclusive), mesh, int(es.order), float(es.q_total), field)
 
 
 def make_system(n: int, pos_ptr: int, type_ptr: int, cell) -> qnep_system:
@@ -236,7 +237,7 @@ class qnep_batch_outputs(C.Structure):
 
 
 EXPORTED += ["qnep_batch_workspace_size", "qnep_batch_prepare", "qnep_batch_compute", "qnep_batch_gradient",
-             "qnep_batch_tune"]
+             "qnep_batch_tune", "qnep_snes_generation"]
 
 
 def _bind_batch(L):
@@ -259,6 +260,10 @@ def _bind_batch(L):
     L.qnep_batch_tune.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(qnep_batch_targets),
                                   C.POINTER(qnep_batch_outputs), C.c_void_p, C.c_size_t, C.c_void_p,
                                   C.POINTER(C.c_int32)]
+    L.qnep_snes_generation.restype = C.c_int
+    L.qnep_snes_generation.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_double,
+                                       C.c_double, C.POINTER(qnep_batch_targets), C.POINTER(qnep_batch_outputs),
+                                       C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
     L._batch_bound = True
 
 
@@ -310,3 +315,14 @@ def qnep_batch_gradient(model: int, thetas_ptr: int, n_candidates: int, targets:
     _check(L.qnep_batch_gradient(C.c_void_p(model), C.c_void_p(thetas_ptr), int(n_candidates), C.byref(targets),
                                  C.byref(outputs), C.c_void_p(dthetas_ptr), C.c_void_p(ws_ptr), ws_bytes,
                                  C.c_void_p(stream)))
+
+
+def qnep_snes_generation(model: int, mu_ptr: int, sigma_ptr: int, noise_ptr: int, n_candidates: int, eta_mu: float,
+                         eta_sigma: float, targets: qnep_batch_targets, outputs: qnep_batch_outputs, thetas_ptr: int,
+                         ws_ptr: int, ws_bytes: int, stream: int):
+    L = load()
+    _bind_batch(L)
+    _check(L.qnep_snes_generation(C.c_void_p(model), C.c_void_p(mu_ptr), C.c_void_p(sigma_ptr),
+                                  C.c_void_p(noise_ptr), int(n_candidates), float(eta_mu), float(eta_sigma),
+                                  C.byref(targets), C.byref(outputs), C.c_void_p(thetas_ptr), C.c_void_p(ws_ptr),
+                                  ws_bytes, C.c_void_p(stream)))

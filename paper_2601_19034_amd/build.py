@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqnep.so")
 
-SOURCES = ["nbr.hip", "nep.hip", "mlp.hip", "mlp_bf16.hip", "coul.hip", "fft.hip", "pppm.hip", "finalize.hip", "backward.hip", "batch_setup.hip", "batch_eval.hip",
+SOURCES = ["nbr.hip", "nep.hip", "mlp.hip", "mlp_bf16.hip", "coul.hip", "fft.hip", "pppm.hip", "finalize.hip", "backward.hip", "batch_setup.hip", "batch_eval.hip", "snes.hip", "md.hip",
            "api.cpp"]
 
 ARCH = os.environ.get("QNEP_ARCH", "gfx950")

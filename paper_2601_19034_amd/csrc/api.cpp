@@ -13,7 +13,14 @@
 #include "plan.h"
 
 namespace qnep {
+hipError_t snes_sample(int64_t d, int C, const float *mu, const float *sigma, const float *noise, float *thetas,
+                       hipStream_t st);
+hipError_t snes_update(int64_t d, int C, const double *loss, const float *noise, double eta_mu, double eta_sigma,
+                       float *mu, float *sigma, hipStream_t st);
 bool nep_supported(int T, int NR, int NA, int NBR, int NBA, int LMAX);
+hipError_t md_kick_drift(const Plan &p, const double *masses, double dt, float *pos, float *vel, const float *F);
+hipError_t md_kick_record(const Plan &p, const double *masses, double dt, float *vel, const float *F,
+                          const float *Z, const double *energy, const double *pol, double *sums, double *row);
 hipError_t launch_phi_mean(const Plan &p);
 bool mlp_bf16_supported(int ndes, int H);
 int radial_record_floats(int NB);
@@ -230,6 +237,10 @@ qnep_status make_plan(const Model &m, const qnep_es_params *es, const qnep_syste
     p.kinc = es->kmax_inclusive ? 1 : 0;
     p.order = es->order;
     p.qtot = es->q_total;
+    for (int a = 0; a < 3; ++a) {
+        if (!std::isfinite(es->efield[a])) return fail(QNEP_E_INVALID_ARG, "efield must be finite");
+        p.efield[a] = (float)es->efield[a];
+    }
     for (int a = 0; a < 3; ++a) p.mesh[a] = es->mesh[a];
     std::memcpy(p.cell.h, sys->cell, sizeof(double) * 9);
     if (!invert_cell(p.cell.h, p.cell.hinv, &p.vol))
@@ -314,6 +325,7 @@ qnep_status make_plan(const Model &m, const qnep_es_params *es, const qnep_syste
     p.pairFA = c.take<float>((size_t)8 * p.capA * N);
     p.Fnep = c.take<float>(3 * (size_t)N);
     p.Znep = c.take<float>(9 * (size_t)N);
+    p.Vat = c.take<float>(6 * (size_t)N);
     if (p.method == 0) {
         p.kvec = c.take<float4>(2 * (size_t)p.nk_cap);  // kv then kn (int4)
         p.kcount = c.take<int>(1);
@@ -323,6 +335,7 @@ qnep_status make_plan(const Model &m, const qnep_es_params *es, const qnep_syste
         if (!p.bricks) p.rho = c.take<float>(p.mesh_pts);
         p.meshA = c.take<float2>(p.mesh_pts);
         p.meshAB = c.take<float2>(2 * p.mesh_pts);
+        p.meshV = c.take<float2>(3 * p.mesh_pts);
     }
     if (backward) {
         Backward &b = p.bw;
@@ -690,6 +703,8 @@ qnep_status qnep_backward(void *model, const float *theta, const qnep_es_params 
     qnep_status s = make_plan(m, es, sys, static_cast<char *>(ws), p, &need, true);
     if (s != QNEP_OK) return s;
     if (ws_bytes < need) return fail(QNEP_E_WORKSPACE, "workspace smaller than qnep_backward_workspace_size()");
+    if (p.efield[0] != 0.f || p.efield[1] != 0.f || p.efield[2] != 0.f)
+        return fail(QNEP_E_UNSUPPORTED, "the adjoint is of the field-free energy: pass efield = 0");
     if (p.N == 0) return fail(QNEP_E_INVALID_ARG, "backward needs at least one atom");
     if (!sys->pos || !sys->type) return fail(QNEP_E_INVALID_ARG, "null positions or types");
     p.pos = sys->pos;
@@ -699,12 +714,85 @@ qnep_status qnep_backward(void *model, const float *theta, const qnep_es_params 
     Backward &b = p.bw;
     b.gE = gE;
     for (int a = 0; a < 3; ++a) b.gP[a] = gP ? gP[a] : 0.0;
+    if (d_cell && (b.gP[0] != 0.0 || b.gP[1] != 0.0 || b.gP[2] != 0.0))
+        return fail(QNEP_E_UNSUPPORTED,
+                    "d_cell covers the energy term only: pass gP = 0 (or NULL) when d_cell is requested");
     b.dpos = d_pos;
     b.dcell = d_cell;
     b.dtheta = d_theta;
     p.out = qnep_outputs{b.energy, b.Fout, b.virial, nullptr, nullptr, b.Zout, b.pol, b.terms};
     HIP_TRY(run_forward(p));
     HIP_TRY(launch_backward(p));
+    return QNEP_OK;
+}
+
+namespace {
+// device buffers of the MD driver, after the evaluation's workspace
+struct MdBuffers {
+    float *F = nullptr, *Z = nullptr;
+    double *energy = nullptr, *pol = nullptr, *sums = nullptr;
+};
+
+qnep_status md_layout(const Model &m, const qnep_es_params *es, int64_t n_atoms, const double *cell, char *ws,
+                      Plan &p, MdBuffers &b, size_t *bytes) {
+    if (!cell) return fail(QNEP_E_INVALID_ARG, "null cell");
+    qnep_system sys{n_atoms, nullptr, nullptr, {0}};
+    std::memcpy(sys.cell, cell, sizeof(double) * 9);
+    size_t need = 0;
+    qnep_status s = make_plan(m, es, &sys, ws, p, &need);
+    if (s != QNEP_OK) return s;
+    Carver c{ws, need, ws == nullptr};
+    const size_t N = (size_t)std::max<int64_t>(n_atoms, 1);
+    b.F = c.take<float>(3 * N);
+    b.Z = c.take<float>(9 * N);
+    b.energy = c.take<double>(1);
+    b.pol = c.take<double>(3);
+    b.sums = c.take<double>(4);
+    *bytes = (c.off + ALIGN - 1) / ALIGN * ALIGN;
+    return QNEP_OK;
+}
+}  // namespace
+
+qnep_status qnep_md_workspace_size(const void *model, const qnep_es_params *es, int64_t n_atoms,
+                                   const double *cell, size_t *bytes) {
+    if (!model || !bytes) return fail(QNEP_E_INVALID_ARG, "null argument");
+    Plan p;
+    MdBuffers b;
+    return md_layout(*static_cast<const Model *>(model), es, n_atoms, cell, nullptr, p, b, bytes);
+}
+
+qnep_status qnep_md_nve(void *model, const float *theta, const qnep_es_params *es, const qnep_md_params *md,
+                        int64_t n_atoms, const int32_t *type, const double *cell, float *pos, float *vel,
+                        double *series, void *ws, size_t ws_bytes, void *stream) {
+    if (!model || !theta || !md || !pos || !vel || !type || !series || !ws)
+        return fail(QNEP_E_INVALID_ARG, "null argument");
+    if (n_atoms < 1) return fail(QNEP_E_INVALID_ARG, "MD needs at least one atom");
+    if (!(md->dt > 0) || !std::isfinite(md->dt) || md->n_steps < 0)
+        return fail(QNEP_E_INVALID_ARG, "dt must be positive and n_steps non-negative");
+    const Model &m = *static_cast<const Model *>(model);
+    if (!md->masses) return fail(QNEP_E_INVALID_ARG, "null masses");
+    for (int t = 0; t < m.hp.n_types; ++t)
+        if (!(md->masses[t] > 0) || !std::isfinite(md->masses[t]))
+            return fail(QNEP_E_INVALID_ARG, "masses must be positive");
+    Plan p;
+    MdBuffers b;
+    size_t need = 0;
+    qnep_status s = md_layout(m, es, n_atoms, cell, static_cast<char *>(ws), p, b, &need);
+    if (s != QNEP_OK) return s;
+    if (ws_bytes < need) return fail(QNEP_E_WORKSPACE, "workspace smaller than qnep_md_workspace_size()");
+    p.pos = pos;
+    p.type = type;
+    p.theta = theta;
+    p.stream = static_cast<hipStream_t>(stream);
+    p.out = qnep_outputs{b.energy, b.F, nullptr, nullptr, nullptr, b.Z, b.pol, nullptr, nullptr};
+    HIP_TRY(run_forward(p));
+    HIP_TRY(md_kick_record(p, md->masses, 0.0, vel, b.F, b.Z, b.energy, b.pol, b.sums, series));
+    for (int step = 1; step <= md->n_steps; ++step) {
+        HIP_TRY(md_kick_drift(p, md->masses, md->dt, pos, vel, b.F));
+        HIP_TRY(run_forward(p));
+        HIP_TRY(md_kick_record(p, md->masses, md->dt, vel, b.F, b.Z, b.energy, b.pol, b.sums,
+                               series + (size_t)8 * step));
+    }
     return QNEP_OK;
 }
 
@@ -732,6 +820,8 @@ qnep_status qnep_batch_prepare(void *model, const qnep_es_params *es, const qnep
     if (s != QNEP_OK) return s;
     if (ws_bytes < need) return fail(QNEP_E_WORKSPACE, "workspace smaller than qnep_batch_workspace_size()");
     if (!batch->pos || !batch->type) return fail(QNEP_E_INVALID_ARG, "null positions or types");
+    if (es->efield[0] != 0.0 || es->efield[1] != 0.0 || es->efield[2] != 0.0)
+        return fail(QNEP_E_UNSUPPORTED, "batched evaluation has no external field: pass efield = 0");
     int dev = 0, cus = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -840,6 +930,28 @@ qnep_status qnep_batch_compute(void *model, const float *thetas, int32_t n_candi
         HIP_TRY(batch_loss(m.batch.stats, targets->energy, thetas, a.n_theta, a.S, a.C, a.qtot, lam, outputs->loss,
                            m.batch.rmse, st));
     }
+    return QNEP_OK;
+}
+
+qnep_status qnep_snes_generation(void *model, float *mu, float *sigma, const float *noise, int32_t n_candidates,
+                                 double eta_mu, double eta_sigma, const qnep_batch_targets *targets,
+                                 const qnep_batch_outputs *outputs, float *thetas, void *ws, size_t ws_bytes,
+                                 void *stream) {
+    if (!model || !mu || !sigma || !noise || !thetas) return fail(QNEP_E_INVALID_ARG, "null argument");
+    if (!outputs || !outputs->loss) return fail(QNEP_E_INVALID_ARG, "outputs->loss receives the fitness: required");
+    if (n_candidates < 2 || n_candidates > 1024) return fail(QNEP_E_INVALID_ARG, "n_candidates must be in [2, 1024]");
+    if (!(eta_mu > 0) || !std::isfinite(eta_mu)) return fail(QNEP_E_INVALID_ARG, "eta_mu must be positive");
+    const Model &m = *static_cast<const Model *>(model);
+    BatchArgs a;
+    qnep_status s = batch_args(m, thetas, n_candidates, targets, outputs, ws, ws_bytes, a);
+    if (s != QNEP_OK) return s;
+    const int64_t d = a.n_theta;
+    if (!(eta_sigma > 0)) eta_sigma = (3.0 + std::log((double)d)) / (5.0 * std::sqrt((double)d));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIP_TRY(snes_sample(d, n_candidates, mu, sigma, noise, thetas, st));
+    s = qnep_batch_compute(model, thetas, n_candidates, targets, outputs, ws, ws_bytes, stream);
+    if (s != QNEP_OK) return s;
+    HIP_TRY(snes_update(d, n_candidates, outputs->loss, noise, eta_mu, eta_sigma, mu, sigma, st));
     return QNEP_OK;
 }
 

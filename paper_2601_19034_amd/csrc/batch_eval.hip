@@ -195,7 +195,7 @@ __device__ __forceinline__ void item_network(const BatchArgs &a, const Item &it,
         constexpr int KDT = (NDES + 15) / 16;
         const int lane = tid & 63, wave = tid >> 6;
         const int li = lane & 15, lg = lane >> 4;
-        const int nsplit = a.prec == QNEP_MLP_BF16X3 ? 3 : 1;
+        const int fmask = forward_mask(a.prec), bmask = backward_mask(a.prec);
         const int nJT = (a.H + 15) >> 4;
         for (int tt = wave; tt < (it.n + 15) / 16; tt += BATCH_THREADS / 64) {
             const int row = 16 * tt + li;
@@ -230,7 +230,7 @@ __device__ __forceinline__ void item_network(const BatchArgs &a, const Item &it,
                             const int k = 16 * kk + 4 * lg + e;
                             ao[e] = (j < a.H && k < NDES) ? W0[j * NDES + k] : 0.f;
                         }
-                        acc[jt] = mfma_split_rt(ao, bo, acc[jt], nsplit);
+                        acc[jt] = mfma_split_rt(ao, bo, acc[jt], fmask);
                     }
                 }
             }
@@ -287,8 +287,8 @@ __device__ __forceinline__ void item_network(const BatchArgs &a, const Item &it,
                             const int j = 16 * jj + 4 * lg + e;
                             ao[e] = (j < a.H && v < NDES) ? W0[j * NDES + v] : 0.f;
                         }
-                        gA[vt] = mfma_split_rt(ao, be, gA[vt], nsplit);
-                        gB[vt] = mfma_split_rt(ao, bq, gB[vt], nsplit);
+                        gA[vt] = mfma_split_rt(ao, be, gA[vt], bmask);
+                        gB[vt] = mfma_split_rt(ao, bq, gB[vt], bmask);
                     }
                 }
             }

@@ -66,7 +66,7 @@ __global__ __launch_bounds__(256) void k_real_space(int N, const float4 *__restr
                                                     const float *__restrict__ qraw,
                                                     const double *__restrict__ scalars, float alpha,
                                                     float *__restrict__ phi, float *__restrict__ Fst,
-                                                    double *__restrict__ partials) {
+                                                    float *__restrict__ Vat, double *__restrict__ partials) {
     __shared__ int2 seg[RS_APB][RS_SEG];
     __shared__ float4 shift_tab[SEG_NIMG];
     const int nimg = 2 * st.R + 1;
@@ -124,13 +124,24 @@ __global__ __launch_bounds__(256) void k_real_space(int N, const float4 *__restr
         red[2] = hw * acc[4]; red[3] = hw * acc[7]; red[4] = hw * acc[8];
         red[5] = hw * acc[7]; red[6] = hw * acc[5]; red[7] = hw * acc[9];
         red[8] = hw * acc[8]; red[9] = hw * acc[9]; red[10] = hw * acc[6];
+        if (Vat) {  // per atom: half of each pair virial (xx yy zz xy xz yz)
+            const float hwf = 0.5f * ke * qi;
+            Vat[i] = hwf * acc[4];
+            Vat[(size_t)N + i] = hwf * acc[5];
+            Vat[(size_t)2 * N + i] = hwf * acc[6];
+            Vat[(size_t)3 * N + i] = hwf * acc[7];
+            Vat[(size_t)4 * N + i] = hwf * acc[8];
+            Vat[(size_t)5 * N + i] = hwf * acc[9];
+        }
     }
     block_partials<11>(red, partials);
 }
 
 hipError_t launch_real_space(const Plan &p) {
+    float *Vat = p.out.virial_atom ? p.Vat : nullptr;
     if (p.mode != 1) {
         hipError_t e = fill_zero(p.phi, sizeof(float) * (size_t)p.N, p.stream);
+        if (e == hipSuccess && Vat) e = fill_zero(Vat, sizeof(float) * 6 * (size_t)p.N, p.stream);
         if (e != hipSuccess) return e;
         return fill_zero(p.Fst, sizeof(float) * 3 * (size_t)p.N, p.stream);
     }
@@ -141,7 +152,7 @@ hipError_t launch_real_space(const Plan &p) {
     if (!stencil_setup(st, p.nc, p.mC, p.cell.h, p.rc_coul, RS_SEG)) return hipErrorInvalidValue;
     const int G = (p.N + RS_APB - 1) / RS_APB;
     hipLaunchKernelGGL(k_real_space, dim3(G), dim3(256), 0, p.stream, p.N, p.xyzq, p.cell, st, p.cell_start,
-                       p.rc_coul * p.rc_coul, p.qraw, p.scalars, (float)p.alpha, p.phi, p.Fst, p.partials);
+                       p.rc_coul * p.rc_coul, p.qraw, p.scalars, (float)p.alpha, p.phi, p.Fst, Vat, p.partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     stage_mark(p, ST_REAL, 1);
@@ -350,6 +361,63 @@ __global__ __launch_bounds__(256) void k_ewald_atoms(int N, const float4 *__rest
     }
 }
 
+// per-atom reciprocal virial (Eq. 20) over the half set: W^k_i = 2 k_e q'_i sum_half G
+// Re[S e^{i k.r_i}] B(k), B = I - (2/(4 alpha^2) + 2/k^2) k k; added to Vat
+__global__ __launch_bounds__(256) void k_ewald_virial_atoms(int N, const float4 *__restrict__ xyzt, Cell c,
+                                                            float alpha, const float *__restrict__ qraw,
+                                                            const double *__restrict__ scalars,
+                                                            const float4 *__restrict__ kv,
+                                                            const int4 *__restrict__ kn,
+                                                            const float2 *__restrict__ Sk,
+                                                            const int *__restrict__ kcount, float *__restrict__ Vat) {
+    __shared__ int4 ln[256];
+    __shared__ float4 lk[256];
+    __shared__ float2 ls[256];
+    const int nk = *kcount;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const float cB0 = 2.0f / (4.0f * alpha * alpha);
+    double s0 = 0, s1 = 0, s2 = 0;
+    if (i < N) {
+        const float4 pa = xyzt[i];
+        frac_coords(pa.x, pa.y, pa.z, c, s0, s1, s2);
+    }
+    float v[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // xx yy zz xy xz yz
+    for (int t0 = 0; t0 < nk; t0 += 256) {
+        int k = t0 + threadIdx.x;
+        if (k < nk) {
+            ln[threadIdx.x] = kn[k];
+            lk[threadIdx.x] = kv[k];
+            ls[threadIdx.x] = Sk[k];
+        }
+        __syncthreads();
+        const int m = min(256, nk - t0);
+        if (i < N) {
+            for (int u = 0; u < m; ++u) {
+                float cs, sn;
+                int4 n = ln[u];
+                phase_cs(n.x, n.y, n.z, s0, s1, s2, cs, sn);
+                const float2 S = ls[u];
+                const float4 q = lk[u];
+                const float gre = q.w * (S.x * cs - S.y * sn);
+                const float k2 = q.x * q.x + q.y * q.y + q.z * q.z;
+                const float cb = gre * (cB0 + 2.0f / k2);
+                v[0] = fmaf(-cb * q.x, q.x, v[0] + gre);
+                v[1] = fmaf(-cb * q.y, q.y, v[1] + gre);
+                v[2] = fmaf(-cb * q.z, q.z, v[2] + gre);
+                v[3] = fmaf(-cb * q.x, q.y, v[3]);
+                v[4] = fmaf(-cb * q.x, q.z, v[4]);
+                v[5] = fmaf(-cb * q.y, q.z, v[5]);
+            }
+        }
+        __syncthreads();
+    }
+    if (i < N) {
+        const float f = 2.0f * (float)KE * (qraw[i] + (float)scalars[S_DELTA]);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) Vat[(size_t)k * N + i] += f * v[k];
+    }
+}
+
 hipError_t launch_ewald(const Plan &p) {
     int4 *kn = (int4 *)(p.kvec + p.nk_cap);
     hipLaunchKernelGGL(k_kvectors, dim3(1), dim3(1024), 0, p.stream, p.cell, p.nk_box[0], p.nk_box[1],
@@ -367,7 +435,10 @@ hipError_t launch_ewald(const Plan &p) {
     const int G = (p.N + 255) / 256;
     hipLaunchKernelGGL(k_ewald_atoms, dim3(G), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, p.qraw,
                        p.scalars, p.kvec, (const int4 *)kn, p.Sk, p.kcount, p.phi, p.Fst);
-    stage_mark(p, ST_EWALD_ATOMS);
+    if (p.out.virial_atom)
+        hipLaunchKernelGGL(k_ewald_virial_atoms, dim3(G), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell,
+                           (float)p.alpha, p.qraw, p.scalars, p.kvec, (const int4 *)kn, p.Sk, p.kcount, p.Vat);
+    stage_mark(p, ST_EWALD_ATOMS, p.out.virial_atom ? 2 : 1);
     return hipGetLastError();
 }
 

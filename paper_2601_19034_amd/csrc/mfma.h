@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/qnep.h"
+
 namespace qnep {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
@@ -18,31 +20,12 @@ __device__ inline short to_bf16(float f) {  // round to nearest even
 //   A[i][k]: i = l % 16, k = 4 (l / 16) + e  (element e of the 4-vector)
 //   B[k][j]: j = l % 16, k = 4 (l / 16) + e
 //   D[i][j]: j = l % 16, i = 4 (l / 16) + e
-// NSPLIT = 1: one BF16 product per term.  NSPLIT = 3: operands split x = hi + lo in
-// BF16 and hi*hi + hi*lo + lo*hi accumulated (about 16 mantissa bits).
-template <int NSPLIT>
-__device__ inline floatx4 mfma_split(const float (&a)[4], const float (&b)[4], floatx4 acc) {
-    bf16x4 ah, bh;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        ah[e] = to_bf16(a[e]);
-        bh[e] = to_bf16(b[e]);
-    }
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
-    if (NSPLIT == 3) {
-        bf16x4 al, bl;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            al[e] = to_bf16(a[e] - __uint_as_float((uint32_t)(unsigned short)ah[e] << 16));
-            bl[e] = to_bf16(b[e] - __uint_as_float((uint32_t)(unsigned short)bh[e] << 16));
-        }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
-    }
-    return acc;
-}
+// Operands are split x = hi + lo with hi, lo in BF16 (hi carries 8 mantissa bits,
+// hi + lo about 16).  A product of split operands keeps the terms selected by MASK:
+// hi*hi always, bit 0 adds A_lo*B_hi, bit 1 adds A_hi*B_lo (lo*lo is below FP32
+// accumulation noise and is never formed).
+constexpr int SPLIT_A_LO = 1, SPLIT_B_LO = 2, SPLIT_BOTH = 3;
 
-// x = hi + lo with hi, lo in BF16 (lo = 0 when only hi is used)
 __device__ inline void split_bf16(const float (&x)[4], bf16x4 &hi, bf16x4 &lo) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -51,20 +34,32 @@ __device__ inline void split_bf16(const float (&x)[4], bf16x4 &hi, bf16x4 &lo) {
     }
 }
 
-// products of operands already split into BF16 parts: hi*hi (+ hi*lo + lo*hi)
-template <int NSPLIT>
+template <int MASK>
 __device__ inline floatx4 mfma_parts(bf16x4 ah, bf16x4 al, bf16x4 bh, bf16x4 bl, floatx4 acc) {
     acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
-    if (NSPLIT == 3) {
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
-    }
+    if (MASK & SPLIT_B_LO) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
+    if (MASK & SPLIT_A_LO) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
     return acc;
 }
 
-// the same with the split chosen at run time (1 or 3 products)
-__device__ inline floatx4 mfma_split_rt(const float (&a)[4], const float (&b)[4], floatx4 acc, int nsplit) {
-    return nsplit == 3 ? mfma_split<3>(a, b, acc) : mfma_split<1>(a, b, acc);
+// FP32 operands split on the fly; the mask is chosen at run time
+__device__ inline floatx4 mfma_split_rt(const float (&a)[4], const float (&b)[4], floatx4 acc, int mask) {
+    bf16x4 ah, al, bh, bl;
+    split_bf16(a, ah, al);
+    split_bf16(b, bh, bl);
+    if (mask == SPLIT_BOTH) return mfma_parts<SPLIT_BOTH>(ah, al, bh, bl, acc);
+    if (mask == SPLIT_B_LO) return mfma_parts<SPLIT_B_LO>(ah, al, bh, bl, acc);
+    if (mask == SPLIT_A_LO) return mfma_parts<SPLIT_A_LO>(ah, al, bh, bl, acc);
+    return mfma_parts<0>(ah, al, bh, bl, acc);
 }
+
+// Products of the network in each BF16 form (A = weights, B = activations):
+//   QNEP_MLP_BF16    forward D W0^T with both operands split, backward G W0 with the
+//                    weights split and the activation gradient rounded once to BF16;
+//   QNEP_MLP_BF16X3  both products with both operands split.
+// Rounding the weights of the backward product instead would make the gradient that of
+// a slightly different network, an error that adds up coherently in the virial.
+__host__ __device__ constexpr int forward_mask(int) { return SPLIT_BOTH; }
+__host__ __device__ constexpr int backward_mask(int prec) { return prec == QNEP_MLP_BF16X3 ? SPLIT_BOTH : SPLIT_A_LO; }
 
 }  // namespace qnep

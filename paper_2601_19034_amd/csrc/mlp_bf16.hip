@@ -7,11 +7,14 @@
 //   gU^T = sum_t W0_t^T G_t^T with G = (1 - h^2) w1E (and likewise for q).
 // After the first product the lane that holds column `row` holds the hidden units
 // 16 jt + 4 lg + e of that atom, which are exactly the B-operand elements of G^T the
-// second product needs, so no activation goes through LDS.  The weights of all
-// species are split into BF16 parts once per work-group and kept in LDS in the two
-// layouts the products read (rows of W0 and rows of W0^T, four consecutive elements
-// per lane); every activation operand is split once and reused across the tiles of
-// the other dimension.  tanh and the output layers stay in FP32.
+// second product needs, so no activation goes through LDS.
+// Precision: operands are split into BF16 hi + lo parts.  The forward product keeps
+// hi*hi + hi*lo + lo*hi; the backward product keeps the split weights against the
+// activation gradient's hi part (QNEP_MLP_BF16), or both splits (QNEP_MLP_BF16X3).  The
+// descriptors enter tanh and through (1 - h^2) every force, so their rounding matters
+// most; a single BF16 rounding of both operands misses 5 meV/A on the forces.
+// The BF16 weight parts of the species present sit in LDS in the two layouts the
+// products read (rows of W0 and rows of W0^T, four consecutive elements per lane).
 #include "mfma.h"
 #include "plan.h"
 
@@ -19,7 +22,7 @@ namespace qnep {
 
 constexpr int MLPB_BLOCKS_MAX = 2048;
 
-template <int KD, int KH, int NSPLIT>
+template <int KD, int KH, int BMASK>
 __global__ __launch_bounds__(256) void k_mlp_bf16(int N, int T, int H, int ndes, const int *__restrict__ ts,
                                                   const float *__restrict__ D, const float *__restrict__ theta,
                                                   int64_t off_nn, int64_t per_species, int64_t off_b1E,
@@ -27,22 +30,20 @@ __global__ __launch_bounds__(256) void k_mlp_bf16(int N, int T, int H, int ndes,
                                                   float *__restrict__ gU, float *__restrict__ gq,
                                                   double *__restrict__ partials) {
     constexpr int RF = KD + 4, RB = KH + 4;  // padded row lengths (elements)
+    constexpr bool BLO = (BMASK & SPLIT_A_LO) != 0;  // weights' lo part in the backward product
     extern __shared__ short wlds[];
-    // [t][j][k] rows of W0 (forward) and [t][v][j] rows of W0^T (backward), hi then lo parts
-    short *fh = wlds, *bh = fh + MAX_T * KH * RF;
-    short *fl = bh + MAX_T * KD * RB, *bl = fl + MAX_T * KH * RF;
+    // [t][j][k] rows of W0 (forward, hi and lo) and [t][v][j] rows of W0^T (backward, hi [and lo])
+    short *fh = wlds, *fl = fh + T * KH * RF, *bh = fl + T * KH * RF, *bl = bh + T * KD * RB;
     __shared__ float sb0[MAX_T][KH], sw1E[MAX_T][KH], sw1q[MAX_T][KH], sb1q[MAX_T];
     for (int idx = threadIdx.x; idx < T * KH * KD; idx += blockDim.x) {
         const int t = idx / (KH * KD), r = idx - t * KH * KD, j = r / KD, k = r - j * KD;
         const float w = (j < H && k < ndes) ? theta[off_nn + t * per_species + (int64_t)j * ndes + k] : 0.0f;
         const short h = to_bf16(w);
+        const short l = to_bf16(w - __uint_as_float((uint32_t)(unsigned short)h << 16));
         fh[(t * KH + j) * RF + k] = h;
+        fl[(t * KH + j) * RF + k] = l;
         bh[(t * KD + k) * RB + j] = h;
-        if (NSPLIT == 3) {
-            const short l = to_bf16(w - __uint_as_float((uint32_t)(unsigned short)h << 16));
-            fl[(t * KH + j) * RF + k] = l;
-            bl[(t * KD + k) * RB + j] = l;
-        }
+        if (BLO) bl[(t * KD + k) * RB + j] = l;
     }
     for (int idx = threadIdx.x; idx < T * KH; idx += blockDim.x) {
         const int t = idx / KH, j = idx % KH;
@@ -57,10 +58,11 @@ __global__ __launch_bounds__(256) void k_mlp_bf16(int N, int T, int H, int ndes,
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lg = lane >> 4;
     const int ntiles = (N + 15) / 16;
+    const int stride = gridDim.x * 4;
     const bf16x4 zero4 = {0, 0, 0, 0};
     double red[2] = {0.0, 0.0};
-    for (int tile = blockIdx.x * 4 + wave; tile < ntiles; tile += gridDim.x * 4) {
-        const int row = 16 * tile + li;  // this lane's atom (column of the transposed products)
+    for (int tile = blockIdx.x * 4 + wave; tile < ntiles; tile += stride) {
+        const int row = 16 * tile + li;
         const bool rok = row < N;
         const int tr = rok ? ts[row] : -1;
         bf16x4 dh[KD / 16], dl[KD / 16];
@@ -87,8 +89,8 @@ __global__ __launch_bounds__(256) void k_mlp_bf16(int N, int T, int H, int ndes,
                 for (int jt = 0; jt < KH / 16; ++jt) {
                     const int o = (t * KH + 16 * jt + li) * RF + 16 * kk + 4 * lg;
                     const bf16x4 a_h = *reinterpret_cast<const bf16x4 *>(fh + o);
-                    const bf16x4 a_l = NSPLIT == 3 ? *reinterpret_cast<const bf16x4 *>(fl + o) : zero4;
-                    acc[jt] = mfma_parts<NSPLIT>(a_h, a_l, b_h, b_l, acc[jt]);
+                    const bf16x4 a_l = *reinterpret_cast<const bf16x4 *>(fl + o);
+                    acc[jt] = mfma_parts<SPLIT_BOTH>(a_h, a_l, b_h, b_l, acc[jt]);
                 }
             }
         }
@@ -139,9 +141,9 @@ __global__ __launch_bounds__(256) void k_mlp_bf16(int N, int T, int H, int ndes,
                 for (int vt = 0; vt < KD / 16; ++vt) {
                     const int o = (t * KD + 16 * vt + li) * RB + 16 * jj + 4 * lg;
                     const bf16x4 a_h = *reinterpret_cast<const bf16x4 *>(bh + o);
-                    const bf16x4 a_l = NSPLIT == 3 ? *reinterpret_cast<const bf16x4 *>(bl + o) : zero4;
-                    gA[vt] = mfma_parts<NSPLIT>(a_h, a_l, beh, bel, gA[vt]);
-                    gB[vt] = mfma_parts<NSPLIT>(a_h, a_l, bqh, bql, gB[vt]);
+                    const bf16x4 a_l = BLO ? *reinterpret_cast<const bf16x4 *>(bl + o) : zero4;
+                    gA[vt] = mfma_parts<BMASK>(a_h, a_l, beh, bel, gA[vt]);
+                    gB[vt] = mfma_parts<BMASK>(a_h, a_l, bqh, bql, gB[vt]);
                 }
             }
         }
@@ -168,18 +170,19 @@ bool mlp_bf16_supported(int ndes, int H) {
     return (kd == 32 || kd == 48) && (kh == 32 || kh == 48 || kh == 64);
 }
 
-template <int KD, int KH, int NSPLIT>
-static hipError_t run_bf16_split(const Plan &p, int G) {
-    // BF16 weights: forward and backward layouts, hi (and lo) parts, MAX_T species
-    const size_t lds = sizeof(short) * (size_t)MAX_T * (KH * (KD + 4) + KD * (KH + 4)) * (NSPLIT == 3 ? 2 : 1);
+template <int KD, int KH, int BMASK>
+static hipError_t run_bf16_form(const Plan &p, int G) {
+    // BF16 weight parts of the T species: forward rows hi + lo, backward rows hi (+ lo)
+    const int nb = (BMASK & SPLIT_A_LO) ? 2 : 1;
+    const size_t lds = sizeof(short) * (size_t)p.T * (2 * KH * (KD + 4) + nb * KD * (KH + 4));
     static bool raised = false;
     if (!raised && lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_mlp_bf16<KD, KH, NSPLIT>,
+        hipError_t e = hipFuncSetAttribute((const void *)k_mlp_bf16<KD, KH, BMASK>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         raised = true;
     }
-    hipLaunchKernelGGL((k_mlp_bf16<KD, KH, NSPLIT>), dim3(G), dim3(256), lds, p.stream, p.N, p.T, p.H, p.ndes, p.ts,
+    hipLaunchKernelGGL((k_mlp_bf16<KD, KH, BMASK>), dim3(G), dim3(256), lds, p.stream, p.N, p.T, p.H, p.ndes, p.ts,
                        p.D, p.theta, p.off_nn, p.per_species, p.off_b1E, p.U, p.qraw, p.gU, p.gq, p.partials);
     return hipGetLastError();
 }
@@ -190,7 +193,8 @@ static hipError_t run_bf16(const Plan &p) {
     int G = (tiles + 3) / 4;
     if (G > MLPB_BLOCKS_MAX) G = MLPB_BLOCKS_MAX;
     if (G < 1) G = 1;
-    hipError_t e = p.mlp_prec == QNEP_MLP_BF16X3 ? run_bf16_split<KD, KH, 3>(p, G) : run_bf16_split<KD, KH, 1>(p, G);
+    hipError_t e = backward_mask(p.mlp_prec) == SPLIT_BOTH ? run_bf16_form<KD, KH, SPLIT_BOTH>(p, G)
+                                                           : run_bf16_form<KD, KH, SPLIT_A_LO>(p, G);
     if (e != hipSuccess) return e;
     return reduce_partials(p, G, 2, S_UNEP, false);
 }

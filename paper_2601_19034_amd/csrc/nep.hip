@@ -211,12 +211,15 @@ __global__ __launch_bounds__(256) void k_radial_tables(int N, const int *__restr
 constexpr int RF_LANES = 8;
 static_assert(RF_LANES <= PARTIALS_LANES_MAX, "partials buffer sized for PARTIALS_LANES_MAX lanes per atom");
 
-template <int T, int NB>
+// With VAT the per-atom virial W_i += r_ij (x) F_ji = -sigma_ji r u (x) u (Eq. 12) is
+// added to Vat as well.
+template <int T, int NB, bool VAT>
 __global__ __launch_bounds__(256) void k_radial_forces(int N, const float4 *__restrict__ xyzt, Cell c, float rcR,
                                                        const uint32_t *__restrict__ listR,
                                                        const int *__restrict__ cntR, int capR,
                                                        const float *__restrict__ hT, float *__restrict__ Fnep,
-                                                       float *__restrict__ Znep, double *__restrict__ partials) {
+                                                       float *__restrict__ Znep, float *__restrict__ Vat,
+                                                       double *__restrict__ partials) {
     constexpr int REC = RadRec<NB>::v, R4 = REC / 4, APB = 256 / RF_LANES;
     // this atom's own T records, read for every pair, sit in LDS: the vector memory
     // path is left to the neighbours' records
@@ -227,9 +230,10 @@ __global__ __launch_bounds__(256) void k_radial_forces(int N, const float4 *__re
         own[a][q] = i < N ? reinterpret_cast<const float4 *>(hT + (size_t)i * T * REC)[q]
                           : make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
-    float acc[15];  // F (3), Z (xx yy zz xy xz yz), W (same order)
+    constexpr int NACC = VAT ? 21 : 15;
+    float acc[NACC];  // F (3), Z (xx yy zz xy xz yz), W (same order)[, per-atom W (same order)]
 #pragma unroll
-    for (int k = 0; k < 15; ++k) acc[k] = 0.f;
+    for (int k = 0; k < NACC; ++k) acc[k] = 0.f;
     if (i < N) {
         const float4 pi = xyzt[i];
         const int ti = species_of(pi);
@@ -296,10 +300,15 @@ __global__ __launch_bounds__(256) void k_radial_forces(int N, const float4 *__re
                 acc[3 + k] = fmaf(zr, uu[k], acc[3 + k]);
                 acc[9 + k] = fmaf(wr, uu[k], acc[9 + k]);
             }
+            if constexpr (VAT) {
+                const float wa = -sji * r;
+#pragma unroll
+                for (int k = 0; k < 6; ++k) acc[15 + k] = fmaf(wa, uu[k], acc[15 + k]);
+            }
         }
     }
 #pragma unroll
-    for (int k = 0; k < 15; ++k)
+    for (int k = 0; k < NACC; ++k)
 #pragma unroll
         for (int o = RF_LANES / 2; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o, 64);
     double w[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -321,6 +330,10 @@ __global__ __launch_bounds__(256) void k_radial_forces(int N, const float4 *__re
         w[1] = w[3] = acc[12];
         w[2] = w[6] = acc[13];
         w[5] = w[7] = acc[14];
+        if constexpr (VAT) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) Vat[(size_t)k * N + i] += acc[15 + k];
+        }
     }
     block_partials<9>(w, partials);
 }
@@ -528,19 +541,31 @@ __device__ inline int find_slot(const uint32_t *__restrict__ listA, const int *_
 constexpr int AS_LANES = 8;
 static_assert(AS_LANES <= PARTIALS_LANES_MAX, "partials buffer sized for PARTIALS_LANES_MAX lanes per atom");
 
+// With an external field E the force gains sum_a E_a Z_i[a][:] (Eq. 29).  With VAT the
+// per-atom virial is completed (angular reverse terms r_ij (x) F_ji, Eq. 12, and the
+// background U_bg I / N) from the symmetric parts gathered in Vat and written out.
+struct AssembleExtra {
+    float ex, ey, ez;   // external field
+    float ubg_coef;     // -k_e pi Q^2 / (2 Omega alpha^2 N) (mode 1), times 1/s^2 on the device
+    const float *Vat;   // symmetric per-atom virial parts [6][N]
+    float *vatom;       // output [9][N], input order
+};
+
+template <bool VAT>
 __global__ __launch_bounds__(256) void k_assemble(
     int N, const float4 *__restrict__ xyzt, Cell c, const uint32_t *__restrict__ listA,
     const int *__restrict__ cntA, int capA, const float4 *__restrict__ pairFA,
     const float *__restrict__ Fnep, const float *__restrict__ Znep, const float *__restrict__ Fst,
     const float *__restrict__ qraw, const double *__restrict__ scalars, const float *__restrict__ theta,
     int64_t off_s, const int *__restrict__ perm, const float *__restrict__ pos, float *__restrict__ forces,
-    float *__restrict__ bec, float *__restrict__ charges, float *__restrict__ charges_naked,
+    float *__restrict__ bec, float *__restrict__ charges, float *__restrict__ charges_naked, AssembleExtra ext,
     double *__restrict__ partials) {
     const int gtid = xcd_block() * blockDim.x + threadIdx.x;
     const int i = gtid / AS_LANES, sub = gtid % AS_LANES;
-    float acc[12];  // F (3), Z (9)
+    constexpr int NACC = VAT ? 21 : 12;
+    float acc[NACC];  // F (3), Z (9)[, per-atom W (9)]
 #pragma unroll
-    for (int k = 0; k < 12; ++k) acc[k] = 0.f;
+    for (int k = 0; k < NACC; ++k) acc[k] = 0.f;
     if (i < N) {
         const float4 pi = xyzt[i];
         const int nA = cntA[i];
@@ -564,10 +589,17 @@ __global__ __launch_bounds__(256) void k_assemble(
             for (int a = 0; a < 3; ++a)
 #pragma unroll
                 for (int b = 0; b < 3; ++b) acc[3 + 3 * a + b] = fmaf(dv[a], av[b], acc[3 + 3 * a + b]);
+            if constexpr (VAT) {  // W_i += r_ij (x) F_ji
+                const float dd[3] = {d.x, d.y, d.z}, fv[3] = {fji.x, fji.y, fji.z};
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) acc[12 + 3 * a + b] = fmaf(dd[a], fv[b], acc[12 + 3 * a + b]);
+            }
         }
     }
 #pragma unroll
-    for (int k = 0; k < 12; ++k)
+    for (int k = 0; k < NACC; ++k)
 #pragma unroll
         for (int o = AS_LANES / 2; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o, 64);
     double pv[3] = {0, 0, 0};
@@ -576,16 +608,31 @@ __global__ __launch_bounds__(256) void k_assemble(
         const float qp = (float)((double)qraw[i] + scalars[S_DELTA]);  // q'
         const float qt = s * qp;                                        // q~'
         const int o = perm[i];
+        float z[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const float diag = (k == 0 || k == 4 || k == 8) ? qt : 0.0f;
+            z[k] = Znep[(size_t)k * N + i] + acc[3 + k] + diag;
+        }
         if (forces) {
 #pragma unroll
-            for (int a = 0; a < 3; ++a)
-                forces[(size_t)a * N + o] = Fnep[(size_t)a * N + i] + Fst[(size_t)a * N + i] + acc[a];
+            for (int b = 0; b < 3; ++b) {
+                const float fext = ext.ex * z[b] + ext.ey * z[3 + b] + ext.ez * z[6 + b];
+                forces[(size_t)b * N + o] = Fnep[(size_t)b * N + i] + Fst[(size_t)b * N + i] + acc[b] + fext;
+            }
         }
         if (bec) {
 #pragma unroll
+            for (int k = 0; k < 9; ++k) bec[(size_t)k * N + o] = z[k];
+        }
+        if constexpr (VAT) {
+            // symmetric parts (xx yy zz xy xz yz) + angular reverse terms + background
+            const int sym[9] = {0, 3, 4, 3, 1, 5, 4, 5, 2};
+            const float ubg = ext.ubg_coef / (s * s);
+#pragma unroll
             for (int k = 0; k < 9; ++k) {
-                const float diag = (k == 0 || k == 4 || k == 8) ? qt : 0.0f;
-                bec[(size_t)k * N + o] = Znep[(size_t)k * N + i] + acc[3 + k] + diag;
+                const float diag = (k == 0 || k == 4 || k == 8) ? ubg : 0.0f;
+                ext.vatom[(size_t)k * N + o] = ext.Vat[(size_t)sym[k] * N + i] + acc[12 + k] + diag;
             }
         }
         if (charges) charges[o] = qp;
@@ -615,8 +662,13 @@ static hipError_t run_forces(const Plan &p) {
     hipLaunchKernelGGL((k_radial_tables<T, NR, NB>), dim3(G), dim3(256), 0, p.stream, p.N, p.ts, p.gU, p.gq,
                        p.phi, p.scalars, p.theta, p.off_cR, p.off_s, p.hT);
     const int GR = (int)(((int64_t)p.N * RF_LANES + 255) / 256);
-    hipLaunchKernelGGL((k_radial_forces<T, NB>), dim3(GR), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell,
-                       (float)p.rcR, p.listR, p.cntR, p.capR, p.hT, p.Fnep, p.Znep, p.partials);
+    const bool vat = p.out.virial_atom != nullptr;
+    if (vat)
+        hipLaunchKernelGGL((k_radial_forces<T, NB, true>), dim3(GR), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell,
+                           (float)p.rcR, p.listR, p.cntR, p.capR, p.hT, p.Fnep, p.Znep, p.Vat, p.partials);
+    else
+        hipLaunchKernelGGL((k_radial_forces<T, NB, false>), dim3(GR), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell,
+                           (float)p.rcR, p.listR, p.cntR, p.capR, p.hT, p.Fnep, p.Znep, p.Vat, p.partials);
     hipError_t e = reduce_partials(p, GR, 9, S_WNEP, false);
     if (e != hipSuccess) return e;
     stage_mark(p, ST_RADIAL, 3);
@@ -629,10 +681,20 @@ static hipError_t run_forces(const Plan &p) {
     if (e != hipSuccess) return e;
     stage_mark(p, ST_OTHER);
     const int GA = (int)(((int64_t)p.N * AS_LANES + 255) / 256);
-    hipLaunchKernelGGL(k_assemble, dim3(GA), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, p.listA, p.cntA, p.capA,
-                       (const float4 *)p.pairFA, p.Fnep, p.Znep, p.Fst, p.qraw, p.scalars,
-                       p.theta, p.off_s, p.perm, p.pos, p.out.forces, p.out.bec, p.out.charges,
-                       p.out.charges_naked, p.partials);
+    AssembleExtra ext{p.efield[0], p.efield[1], p.efield[2],
+                      p.mode == 1 ? (float)(-KE * PI_D * p.qtot * p.qtot / (2.0 * p.vol * p.alpha * p.alpha * p.N))
+                                  : 0.0f,
+                      p.Vat, p.out.virial_atom};
+    if (vat)
+        hipLaunchKernelGGL(k_assemble<true>, dim3(GA), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, p.listA, p.cntA,
+                           p.capA, (const float4 *)p.pairFA, p.Fnep, p.Znep, p.Fst, p.qraw, p.scalars, p.theta,
+                           p.off_s, p.perm, p.pos, p.out.forces, p.out.bec, p.out.charges, p.out.charges_naked, ext,
+                           p.partials);
+    else
+        hipLaunchKernelGGL(k_assemble<false>, dim3(GA), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, p.listA,
+                           p.cntA, p.capA, (const float4 *)p.pairFA, p.Fnep, p.Znep, p.Fst, p.qraw, p.scalars,
+                           p.theta, p.off_s, p.perm, p.pos, p.out.forces, p.out.bec, p.out.charges,
+                           p.out.charges_naked, ext, p.partials);
     e = reduce_partials(p, GA, 3, S_POL, false);
     stage_mark(p, ST_ASSEMBLE, 2);
     return e;

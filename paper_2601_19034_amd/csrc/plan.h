@@ -38,6 +38,7 @@ struct Plan {
     // ---- electrostatics
     int mode = 1, method = 0, kinc = 0, order = 5;
     double alpha = 0.3, rc_coul = 9.0, kmax = 0, qtot = 0;
+    float efield[3] = {0.f, 0.f, 0.f};  // external field (V/Angstrom)
     int mesh[3] = {0, 0, 0};
     int64_t mesh_pts = 0;
     Cell cell;
@@ -71,6 +72,7 @@ struct Plan {
     float *phi = nullptr, *Fst = nullptr, *hT = nullptr;
     float *pairFA = nullptr;  // angular pair buffer [i][capA][2] float4: F_ij, then a_ij
     float *Fnep = nullptr, *Znep = nullptr;
+    float *Vat = nullptr;  // per-atom virial, symmetric parts [6][N] (xx yy zz xy xz yz), sorted order
     float4 *kvec = nullptr;   // (kx, ky, kz, G) of the half set
     int *kcount = nullptr;
     float2 *Spart = nullptr;  // [s_chunks][nk_cap]
@@ -80,6 +82,7 @@ struct Plan {
     float *rho = nullptr;
     float2 *meshA = nullptr;   // rho, then its transform S
     float2 *meshAB = nullptr;  // the two packed spectra / fields, interleaved [point][2]
+    float2 *meshV = nullptr;   // per-atom virial: three packed spectra / fields [3][point]
     // ---- call arguments
     const float *pos = nullptr;
     const int32_t *type = nullptr;

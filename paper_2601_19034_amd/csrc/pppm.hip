@@ -342,6 +342,47 @@ __global__ __launch_bounds__(256) void k_influence(MeshGeom g, Cell c, float alp
     block_partials<10>(red, partials);
 }
 
+// Per-atom reciprocal virial (Eq. 39): X B_ab with X = S G_opt and the stress kernel
+// B = I - (2/(4 alpha^2) + 2/k^2) k k, for the six components packed two per complex
+// spectrum (each X B_ab is Hermitian, so its inverse transform is real):
+//   V0 = X B_xx + i X B_yy,  V1 = X B_zz + i X B_xy,  V2 = X B_xz + i X B_yz.
+__global__ __launch_bounds__(256) void k_influence_virial(MeshGeom g, Cell c, float alpha, double vol,
+                                                          const float2 *__restrict__ Sk, float2 *__restrict__ V) {
+    const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
+    const size_t M = (size_t)n0 * n1 * n2;
+    const float gk = (float)(2.0 * PI_D / vol), ia2 = 1.0f / (4.0f * alpha * alpha), cB0 = 2.0f * ia2;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < M; idx += (size_t)gridDim.x * blockDim.x) {
+        const int j2 = (int)(idx % n2), row = (int)(idx / n2);
+        const int j0 = row / n1, j1 = row - j0 * n1;
+        const int nv0 = 2 * j0 < n0 ? j0 : j0 - n0, nv1 = 2 * j1 < n1 ? j1 : j1 - n1;
+        const int nv2 = 2 * j2 < n2 ? j2 : j2 - n2;
+        if (nv0 == 0 && nv1 == 0 && nv2 == 0) {
+            V[idx] = V[M + idx] = V[2 * M + idx] = make_float2(0.f, 0.f);
+            continue;
+        }
+        float k[3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            k[b] = (float)(2.0 * PI_D * (c.hinv[3 * b] * nv0 + c.hinv[3 * b + 1] * nv1 + c.hinv[3 * b + 2] * nv2));
+        float num0, den0, num1, den1, num2, den2;
+        gopt_axis((float)nv0 / (float)n0, num0, den0);
+        gopt_axis((float)nv1 / (float)n1, num1, den1);
+        gopt_axis((float)nv2 / (float)n2, num2, den2);
+        const float k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+        const float ik2 = 1.0f / k2;
+        const float Gopt = gk * __expf(-k2 * ia2) * ik2 * ((num0 * num1 * num2) / (den0 * den1 * den2));
+        const float2 S = Sk[idx];
+        const float2 X = make_float2(S.x * Gopt, S.y * Gopt);
+        const float cB = cB0 + 2.0f * ik2;
+        const float Bxx = 1.0f - cB * k[0] * k[0], Byy = 1.0f - cB * k[1] * k[1], Bzz = 1.0f - cB * k[2] * k[2];
+        const float Bxy = -cB * k[0] * k[1], Bxz = -cB * k[0] * k[2], Byz = -cB * k[1] * k[2];
+        // P + i Q with P = X B_p and Q = X B_q: (X.x B_p - X.y B_q, X.y B_p + X.x B_q)
+        V[idx] = make_float2(X.x * Bxx - X.y * Byy, X.y * Bxx + X.x * Byy);
+        V[M + idx] = make_float2(X.x * Bzz - X.y * Bxy, X.y * Bzz + X.x * Bxy);
+        V[2 * M + idx] = make_float2(X.x * Bxz - X.y * Byz, X.y * Bxz + X.x * Byz);
+    }
+}
+
 // phi^k_i += 2 k_e sum_s W phi'_s,  F^k_i += -2 k_e q'_i sum_s W E_s.
 // GA_LANES lanes share one atom: lane a < 5 reads the 25 points of stencil plane a, so
 // five shorter chains of loads are in flight per atom instead of one long one
@@ -401,6 +442,60 @@ __global__ __launch_bounds__(256) void k_gather(int N, const float4 *__restrict_
     }
 }
 
+// W^k_i[ab] += k_e q'_i sum_s W(r_i - r_s) v_ab(r_s) from the three inverse-transformed
+// packed meshes; GA_LANES lanes per atom, lane a < 5 takes stencil plane a
+__global__ __launch_bounds__(256) void k_gather_virial(int N, const float4 *__restrict__ xyzt, Cell c, MeshGeom g,
+                                                       const float *__restrict__ qraw,
+                                                       const double *__restrict__ scalars,
+                                                       const float2 *__restrict__ V, float *__restrict__ Vat) {
+    const int gtid = xcd_block() * blockDim.x + threadIdx.x;
+    const int i = gtid / GA_LANES, pa_ = gtid % GA_LANES;
+    const size_t M = (size_t)g.n[0] * g.n[1] * g.n[2];
+    float v[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // xx yy zz xy xz yz
+    if (i < N && pa_ < 5) {
+        int m0[3];
+        float w[3][5];
+        const float4 pa = xyzt[i];
+        mesh_stencil(pa.x, pa.y, pa.z, c, g, m0, w);
+        float wa = 0.f;
+#pragma unroll
+        for (int t = 0; t < 5; ++t) wa = pa_ == t ? w[0][t] : wa;
+        const int j0 = wrap_index(m0[0] + pa_ - 2, g.n[0]);
+        int j1[5], j2[5];
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+            j1[t] = wrap_index(m0[1] + t - 2, g.n[1]);
+            j2[t] = wrap_index(m0[2] + t - 2, g.n[2]);
+        }
+#pragma unroll
+        for (int b = 0; b < 5; ++b) {
+            const float wab = wa * w[1][b];
+            const size_t row = ((size_t)j0 * g.n[1] + j1[b]) * g.n[2];
+#pragma unroll
+            for (int e = 0; e < 5; ++e) {
+                const float ww = wab * w[2][e];
+                const size_t pt = row + j2[e];
+                const float2 a0 = V[pt], a1 = V[M + pt], a2 = V[2 * M + pt];
+                v[0] = fmaf(ww, a0.x, v[0]);
+                v[1] = fmaf(ww, a0.y, v[1]);
+                v[2] = fmaf(ww, a1.x, v[2]);
+                v[3] = fmaf(ww, a1.y, v[3]);
+                v[4] = fmaf(ww, a2.x, v[4]);
+                v[5] = fmaf(ww, a2.y, v[5]);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+#pragma unroll
+        for (int o = GA_LANES / 2; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+    if (i < N && pa_ == 0) {
+        const float f = (float)KE * (qraw[i] + (float)scalars[S_DELTA]);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) Vat[(size_t)k * N + i] += f * v[k];
+    }
+}
+
 hipError_t launch_pppm(const Plan &p) {
     MeshGeom g{{p.mesh[0], p.mesh[1], p.mesh[2]}};
     const int64_t M = p.mesh_pts;
@@ -448,6 +543,17 @@ hipError_t launch_pppm(const Plan &p) {
     hipLaunchKernelGGL(k_gather, dim3(GG), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, g, p.qraw,
                        p.scalars, (const float4 *)p.meshAB, p.phi, p.Fst);
     stage_mark(p, ST_GATHER);
+    if (p.out.virial_atom) {
+        // six more inverse transforms, two per packed complex mesh (Eq. 39)
+        hipLaunchKernelGGL(k_influence_virial, dim3(GM < 8192 ? GM : 8192), dim3(256), 0, p.stream, g, p.cell,
+                           (float)p.alpha, p.vol, p.meshA, p.meshV);
+        e = hipGetLastError();
+        for (int v = 0; v < 3 && e == hipSuccess; ++v) e = fft3d(p.meshV + (size_t)v * M, nullptr, p.mesh, +1, p.stream);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_gather_virial, dim3(GG), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, g, p.qraw,
+                           p.scalars, p.meshV, p.Vat);
+        stage_mark(p, ST_OTHER);
+    }
     return hipGetLastError();
 }
 

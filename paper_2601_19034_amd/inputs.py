@@ -64,6 +64,7 @@ class ESParams:
     mesh: tuple = (0, 0, 0)
     order: int = 5
     q_total: float = 0.0
+    efield: tuple = (0.0, 0.0, 0.0)  # external electric field, V/Angstrom
 
 
 @dataclasses.dataclass

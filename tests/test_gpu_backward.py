@@ -64,13 +64,15 @@ def _sample_indices(hp, per_block, seed):
     return np.array(sorted(idx))
 
 
-def _gpu_backward(w, es, gE, gP, sysm=None):
+def _gpu_backward(w, es, gE, gP, sysm=None, want=None):
     from paper_2601_19034_amd.api import QNEP, to_device_inputs
 
     sysm = sysm or w.system
     model = QNEP(w.hp)
     pos, types, th = to_device_inputs(sysm, w.theta)
-    g = model.backward(pos, types, sysm.cell, th, es, gE, gP)
+    if want is None:  # the cell derivative is formed for the energy term only
+        want = ("pos", "theta") if gP is not None else ("pos", "cell", "theta")
+    g = model.backward(pos, types, sysm.cell, th, es, gE, gP, want=want)
     return {k: v.cpu().numpy().astype(np.float64) for k, v in g.items()}
 
 
@@ -133,14 +135,16 @@ def test_position_and_cell_gradient(torch_dev, orc):
     w = inputs.workload(0)
     es = _es_smooth(w.system.cell[0, 0])
     gP = np.array([0.2, 0.5, -0.3])
-    _say("case backward dL/dr, dL/dh water-192")
-    g = _gpu_backward(w, es, 1.0, gP)
+    _say("case backward dL/dr, dE/dh water-192")
+    g = _gpu_backward(w, es, 1.0, gP, want=("pos",))
     r = orc.compute(w.hp, es, w.system.pos, w.system.types, w.system.cell, w.theta)
     want = -r.forces + np.einsum("a,iab->ib", gP, r.bec)
     err = np.abs(g["pos"].T - want).max()
     _say(f"[dL/dr] max err {err:.2e}")
     assert err < 2e-4
-    # cell: central difference at fixed Cartesian positions
+    # cell: central difference of E at fixed Cartesian positions (gP = 0: the cell
+    # derivative of P is not formed and is rejected)
+    g = _gpu_backward(w, es, 1.0, None, want=("cell",))
     h = 1e-5
     fd = np.zeros((3, 3))
     for a in range(3):
@@ -167,12 +171,23 @@ def test_autograd_function(torch_dev, orc):
     pos, types, th = to_device_inputs(w.system, w.theta)
     pos.requires_grad_(True)
     th.requires_grad_(True)
-    cell = torch.tensor(w.system.cell, dtype=torch.float64, requires_grad=True)
+    cell = torch.tensor(w.system.cell, dtype=torch.float64, requires_grad=False)
     E, P, F, Z, q = QnepFunction.apply(pos, th, cell, model, types, es)
     loss = 2.0 * E + (P * torch.tensor([0.1, 0.2, -0.3], dtype=torch.float64, device=P.device)).sum()
     loss.backward()
-    g = model.backward(pos.detach(), types, w.system.cell, th.detach(), es, 2.0, np.array([0.1, 0.2, -0.3]))
+    g = model.backward(pos.detach(), types, w.system.cell, th.detach(), es, 2.0, np.array([0.1, 0.2, -0.3]),
+                       want=("pos", "theta"))
     assert torch.allclose(pos.grad, g["pos"]) and torch.allclose(th.grad, g["theta"])
-    assert torch.allclose(cell.grad, g["cell"].cpu())
     assert torch.allclose(pos.grad, -2.0 * F + torch.einsum("a,abn->bn", torch.tensor(
         [0.1, 0.2, -0.3], device=F.device), Z.reshape(3, 3, -1)), atol=1e-5)
+    # the cell gradient of an energy-only loss
+    cell = torch.tensor(w.system.cell, dtype=torch.float64, requires_grad=True)
+    E, P, F, Z, q = QnepFunction.apply(pos.detach(), th.detach(), cell, model, types, es)
+    (2.0 * E).backward()
+    g = model.backward(pos.detach(), types, w.system.cell, th.detach(), es, 2.0, None, want=("cell",))
+    assert torch.allclose(cell.grad, g["cell"].cpu())
+    # P in the loss while the cell needs a gradient: refused, not silently wrong
+    cell = torch.tensor(w.system.cell, dtype=torch.float64, requires_grad=True)
+    E, P, F, Z, q = QnepFunction.apply(pos.detach(), th.detach(), cell, model, types, es)
+    with pytest.raises(NotImplementedError):
+        (E + P.sum()).backward()

@@ -2,7 +2,10 @@
 box (58^3 cells, PPPM 256^3, order 5, alpha 0.3, rc 9 A), evaluated in the launch
 configuration the benchmark times, against FP64 oracle values stored by
 tests/golden/make_perovskite975560.py (global outputs, and every per-atom output at
-512 seeded sample atoms).  Tolerances as in the small-size parity tests."""
+512 seeded sample atoms).  Tolerances as in the small-size parity tests; the
+polarization bound 8 sqrt(N) eps32 max|q~'| max|r| is FP32 rounding of its N terms
+(the scale max|q~'| is taken over all atoms of the evaluated charges)."""
+import math
 import os
 import sys
 
@@ -15,7 +18,7 @@ pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 GOLDEN = os.path.join(HERE, "golden", "perovskite975560_oracle.npz")
-TOL = dict(e=2e-6, f=1e-4, w=2e-5, q=2e-6, z=1e-4, p=1e-5)
+TOL = dict(e=2e-6, f=1e-4, w=2e-5, q=2e-6, z=1e-4)
 
 
 def _say(msg):
@@ -50,15 +53,95 @@ def test_perovskite975560_sampled():
     dqt = np.abs(g["charges_naked"][idx] - ref["q_naked"]).max()
     dZ = np.abs(g["bec"][:, idx].T.reshape(-1, 3, 3) - ref["bec"]).max()
     dP = np.abs(g["polarization"] - ref["pol"]).max()
-    pscale = 1.0 + float(ref["sum_abs_qnaked"]) * 100
+    pbound = 8.0 * math.sqrt(n) * 2.0 ** -24 * float(np.abs(g["charges_naked"]).max()) * float(np.abs(s.pos).max())
     _say(f"[perovskite975560] dE/N={dE:.2e} dF={dF:.2e} dW/N={dW:.2e} dq={dq:.2e} dq~={dqt:.2e} dZ={dZ:.2e} "
-         f"dP={dP:.2e} |F|max(sample)={np.abs(ref['forces']).max():.3f}")
+         f"dP={dP:.2e} (bound {pbound:.2e}) |F|max(sample)={np.abs(ref['forces']).max():.3f}")
     assert dE <= TOL["e"], dE
     assert dF <= TOL["f"], dF
     assert dW <= TOL["w"], dW
     assert dq <= TOL["q"] and dqt <= TOL["q"] * 2, (dq, dqt)
     assert dZ <= TOL["z"], dZ
-    assert dP <= TOL["p"] * pscale, dP
+    assert dP <= pbound, (dP, pbound)
     t, terms = g["energy_terms"], ref["terms"]
     assert abs(t[0] - terms[1]) / n <= TOL["e"]  # U_NEP
     assert abs(t[2] - terms[3]) / n <= TOL["e"]  # U_k
+
+
+def _load(name, w):
+    sys.path.insert(0, os.path.join(HERE, "golden"))
+    from make_perovskite975560 import input_digest
+
+    ref = np.load(os.path.join(HERE, "golden", f"{name}_oracle.npz"))
+    assert str(ref["digest"]) == input_digest(w.system, w.theta), "input generator changed; rewrite the fixture"
+    return ref
+
+
+def _check_sampled(g, ref, w, label):
+    s = w.system
+    n, idx = s.n, ref["idx"]
+    dE = abs(g["energy"][0] - float(ref["energy"])) / n
+    dF = np.abs(g["forces"][:, idx].T - ref["forces"]).max()
+    dW = np.abs(g["virial"].reshape(3, 3) - ref["virial"]).max() / n
+    dq = np.abs(g["charges"][idx] - ref["q_screened"]).max()
+    dqt = np.abs(g["charges_naked"][idx] - ref["q_naked"]).max()
+    dZ = np.abs(g["bec"][:, idx].T.reshape(-1, 3, 3) - ref["bec"]).max()
+    dP = np.abs(g["polarization"] - ref["pol"]).max()
+    pbound = 8.0 * math.sqrt(n) * 2.0 ** -24 * float(np.abs(g["charges_naked"]).max()) * float(np.abs(s.pos).max())
+    _say(f"[{label}] dE/N={dE:.2e} dF={dF:.2e} dW/N={dW:.2e} dq={dq:.2e} dq~={dqt:.2e} dZ={dZ:.2e} "
+         f"dP={dP:.2e} (bound {pbound:.2e}) |F|max(sample)={np.abs(ref['forces']).max():.3f}")
+    assert dE <= TOL["e"], dE
+    assert dF <= TOL["f"], dF
+    assert dW <= TOL["w"], dW
+    assert dq <= TOL["q"] and dqt <= TOL["q"] * 2, (dq, dqt)
+    assert dZ <= TOL["z"], dZ
+    assert dP <= pbound, (dP, pbound)
+
+
+def test_garnet153600_forward_and_adjoint():
+    """Garnet-like box, 153,600 atoms, PPPM 128^3 (length-128 transforms take the
+    staged Stockham path): sampled forward parity, then the adjoint's position
+    gradient dL/dr = -gE F + Z^T gP against the stored FP64 F and Z* at the samples."""
+    import torch
+
+    from paper_2601_19034_amd.api import QNEP, to_device_inputs
+
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    w = inputs.workload(2, "full")
+    ref = _load("garnet153600", w)
+    _say(f"case garnet-153600 PPPM 128^3 (full size, {w.system.n} atoms)")
+    model = QNEP(w.hp, "fp32")
+    pos, types, th = to_device_inputs(w.system, w.theta)
+    out = model.compute(pos, types, w.system.cell, th, w.es)
+    assert model.check_status() == 0
+    g = {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
+    _check_sampled(g, ref, w, "garnet153600")
+    gE, gP = 0.7, np.array([0.3, -0.2, 0.45])
+    _say("case garnet-153600 adjoint dL/dr")
+    d = model.backward(pos, types, w.system.cell, th, w.es, gE, gP, want=("pos",))
+    assert model.check_status() == 0
+    idx = ref["idx"]
+    want = -gE * ref["forces"] + np.einsum("a,iab->ib", gP, ref["bec"])
+    err = np.abs(d["pos"].cpu().numpy()[:, idx].T - want).max()
+    _say(f"[garnet153600 adjoint] max |dL/dr - (-gE F + Z^T gP)| = {err:.2e}")
+    assert err <= gE * TOL["f"] + np.abs(gP).sum() * TOL["z"]
+
+
+def test_water24000_ewald():
+    """Water-like box, 24,000 atoms, direct Ewald with kmax = 2 pi alpha (27,200 wave
+    vectors), against the stored FP64 values at 512 sampled atoms."""
+    import torch
+
+    from paper_2601_19034_amd.api import QNEP, to_device_inputs
+
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    w = inputs.workload(1, "full")
+    w.es.method = 0
+    ref = _load("water24000_ewald", w)
+    _say(f"case water-24000 Ewald ({w.system.n} atoms)")
+    model = QNEP(w.hp, "fp32")
+    pos, types, th = to_device_inputs(w.system, w.theta)
+    out = model.compute(pos, types, w.system.cell, th, w.es)
+    assert model.check_status() == 0
+    g = {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
+    assert g["energy_terms"][7] == float(ref["terms"][9])  # the same wave-vector set
+    _check_sampled(g, ref, w, "water24000-ewald")

@@ -9,7 +9,10 @@ in FP64:
   virial        max |dW| / N    <= 2e-5 eV
   charges       max |dq|        <= 2e-6 e
   Born charges  max |dZ|        <= 1e-4 e
-  polarization  max |dP|        <= 1e-5 * (1 + sum_i |q~'_i r_i|) e A
+  polarization  max |dP|        <= 8 sqrt(N) eps max|q~'| max|r| e A, eps = 2^-24
+The polarization bound is FP32 rounding of its N terms q~'_i r_i (FP64 sum): each
+charge carries a relative error of a few units of eps32 = 2^-24 and the errors of
+different atoms are independent, so their sum grows like sqrt(N).
 """
 import copy
 import math
@@ -22,7 +25,13 @@ from paper_2601_19034_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-TOL = dict(e=2e-6, f=1e-4, w=2e-5, q=2e-6, z=1e-4, p=1e-5)
+# p: the relative rounding unit of one charge (FP32 here) in the polarization bound
+TOL = dict(e=2e-6, f=1e-4, w=2e-5, q=2e-6, z=1e-4, p=2.0 ** -24)
+
+
+def p_bound(n, q_naked, r_max, eps):
+    """8 sqrt(N) eps max|q~'| max|r| (see the module docstring)."""
+    return 8.0 * math.sqrt(max(n, 1)) * eps * max(np.abs(q_naked).max(initial=0.0), 1e-3) * max(r_max, 1.0)
 
 
 def _say(msg):
@@ -38,15 +47,17 @@ def torch_dev():
     return torch
 
 
-def run_gpu(hp, es, sysm, theta, precision="fp32"):
-    from paper_2601_19034_amd.api import QNEP, to_device_inputs
+def run_gpu(hp, es, sysm, theta, precision="fp32", per_atom_virial=False):
+    from paper_2601_19034_amd.api import ALL_OUTPUTS, DEFAULT_OUTPUTS, QNEP, to_device_inputs
 
     model = QNEP(hp, precision)
     pos, types, th = to_device_inputs(sysm, theta)
-    out = model.compute(pos, types, sysm.cell, th, es)
+    out = model.compute(pos, types, sysm.cell, th, es, outputs=ALL_OUTPUTS if per_atom_virial else DEFAULT_OUTPUTS)
     flags = model.check_status()
     assert flags == 0, f"device status flags {flags}"
-    return {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
+    g = {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
+    g["pos_used"] = np.asarray(sysm.pos, dtype=np.float64)
+    return g
 
 
 def compare(g, r, n, tol=TOL, label=""):
@@ -58,16 +69,16 @@ def compare(g, r, n, tol=TOL, label=""):
     dqt = np.abs(g["charges_naked"] - r.q_naked).max()
     Z = g["bec"].T.reshape(n, 3, 3)
     dZ = np.abs(Z - r.bec).max()
-    pscale = 1.0 + np.abs(r.q_naked[:, None] * 1.0).sum() * 100
+    pbound = p_bound(n, r.q_naked, np.abs(g["pos_used"]).max(initial=0.0), tol["p"])
     dP = np.abs(g["polarization"] - r.pol).max()
     _say(f"[{label}] dE/N={dE:.2e} dF={dF:.2e} dW/N={dW:.2e} dq={dq:.2e} dq~={dqt:.2e} dZ={dZ:.2e} dP={dP:.2e} "
-         f"|F|max={np.abs(r.forces).max():.3f}")
+         f"(P bound {pbound:.2e}) |F|max={np.abs(r.forces).max():.3f}")
     assert dE <= tol["e"], dE
     assert dF <= tol["f"], dF
     assert dW <= tol["w"], dW
     assert dq <= tol["q"] and dqt <= tol["q"] * 2, (dq, dqt)
     assert dZ <= tol["z"], dZ
-    assert dP <= tol["p"] * pscale, dP
+    assert dP <= pbound, (dP, pbound)
     t = g["energy_terms"]
     assert abs(t[0] - r.terms[1]) / n <= tol["e"]        # U_NEP
     assert abs(t[2] - r.terms[3]) / n <= tol["e"]        # U_k
@@ -213,11 +224,12 @@ def test_water24000_full(torch_dev, orc):
     compare(g, r, w.system.n, label="water24000-pppm")
 
 
-# BF16 network on the matrix cores (FP32 accumulation).  Split form (hi + lo operands,
-# three products): spec force target 5 meV/A.  Plain one-product form: its
-# measured precision (about 1e-2 eV/A at the largest forces) is the bound.
-TOL_BF16X3 = dict(e=2e-4, f=5e-3, w=5e-4, q=5e-4, z=5e-3, p=5e-4)
-TOL_BF16 = dict(e=5e-3, f=2e-2, w=2e-3, q=5e-3, z=1e-2, p=2e-3)
+# BF16 network on the matrix cores (FP32 accumulation), both forms held to the
+# spec force target of 5 meV/A.  The forward product splits both operands in
+# both forms, so the energy and the charges keep about 16 mantissa bits (p: that
+# rounding unit in the polarization bound).
+TOL_BF16X3 = dict(e=2e-4, f=5e-3, w=5e-4, q=5e-4, z=5e-3, p=2.0 ** -16)
+TOL_BF16 = dict(TOL_BF16X3)
 
 
 @pytest.mark.parametrize("wid,variant", [(0, "full"), (3, "crop"), (2, "crop")])
@@ -229,3 +241,58 @@ def test_bf16_mlp(torch_dev, orc, wid, variant, precision):
     r = _oracle(orc, w.hp, w.es, w.system, w.theta)
     compare(g, r, w.system.n, tol=TOL_BF16X3 if precision == "bf16x3" else TOL_BF16,
             label=f"{precision}-{w.name}")
+
+
+# ------------------------------------------------------------------ external field (Eq. 29)
+@pytest.mark.parametrize("wid,variant", [(0, "full"), (2, "crop")])
+def test_external_field_force(torch_dev, orc, wid, variant):
+    """F with a uniform field E against the oracle (same bounds), and the field term
+    itself equal to sum_a E_a Z_i[a][:] with the GPU's own Born charges."""
+    w = inputs.workload(wid, variant)
+    es = copy.copy(w.es)
+    es.efield = (0.05, -0.02, 0.035)
+    _say(f"case external field {w.name}")
+    g0 = run_gpu(w.hp, w.es, w.system, w.theta)
+    g = run_gpu(w.hp, es, w.system, w.theta)
+    r = _oracle(orc, w.hp, es, w.system, w.theta)
+    compare(g, r, w.system.n, label=f"field-{w.name}")
+    Z = g["bec"].T.reshape(-1, 3, 3)
+    want = np.einsum("a,iab->ib", np.array(es.efield), Z)
+    err = np.abs((g["forces"] - g0["forces"]).T - want).max()
+    _say(f"[field-{w.name}] F(E) - F(0) vs Z^T E: {err:.2e} (max field force {np.abs(want).max():.3f})")
+    assert err <= 2e-6
+    assert g["energy"][0] == g0["energy"][0] and np.array_equal(g["virial"], g0["virial"])
+
+
+# ------------------------------------------------------------------ per-atom virial (Eqs. 12, 20, 39)
+@pytest.mark.parametrize("case", ["water192-ewald", "water192-pppm-Q", "garnet768-pppm", "water111-tri"])
+def test_per_atom_virial(torch_dev, orc, case):
+    """W_i against the oracle's per-atom virial (every partial force, the reciprocal
+    per-atom forms and the background share) and sum_i W_i against the total W."""
+    if case.startswith("water111"):
+        hp, th = inputs.WATER_HP, inputs.theta0(inputs.WATER_HP, 17)
+        s = inputs.water_box(4, spacing=10.3 / 4, seed=21, n_mol=37)
+        cell = s.cell.copy()
+        cell[1, 0], cell[2, 0], cell[2, 1] = 1.7, -0.9, 1.1
+        sysm = inputs._finish("tri", s.pos, s.types, cell)
+        es = inputs.ESParams(mode=1, method=0, alpha=0.35, rc_coul=9.0, kmax=2.2)
+    else:
+        w = inputs.workload(0 if case.startswith("water") else 2, "full" if case.startswith("water") else "crop")
+        hp, th, sysm, es = w.hp, w.theta, w.system, copy.copy(w.es)
+        if case == "water192-pppm-Q":
+            es.method, es.mesh, es.q_total = 1, (16, 15, 18), 0.7
+    _say(f"case per-atom virial {case}")
+    g = run_gpu(hp, es, sysm, th, per_atom_virial=True)
+    r = orc.compute(hp, es, sysm.pos, sysm.types, sysm.cell, th, cells=sysm.n > 1000, per_atom_virial=True)
+    Va = g["virial_atom"].T.reshape(-1, 3, 3)
+    scale = np.abs(r.vatom).max()
+    err = np.abs(Va - r.vatom).max()
+    dsum = np.abs(Va.sum(0) - g["virial"].reshape(3, 3)).max()
+    _say(f"[vatom-{case}] max|dW_i|={err:.2e} (max|W_i| {scale:.2f}) |sum W_i - W|={dsum:.2e}")
+    # FP32 partial forces times displacements of a few Angstrom, summed over ~300 pairs
+    assert err <= 2e-5 * scale + 1e-5
+    assert dsum <= 1e-5 * np.abs(g["virial"]).max() + 1e-4
+    # the default outputs are unchanged by the extra work
+    g0 = run_gpu(hp, es, sysm, th)
+    for k in ("forces", "virial", "bec", "energy"):
+        assert np.array_equal(g0[k], g[k]), k

@@ -522,3 +522,174 @@ def test_invariances(orc):
     assert abs(rp.energy - r.energy) < 1e-9
     np.testing.assert_allclose(rp.forces, r.forces[perm], atol=1e-10)
     np.testing.assert_allclose(rp.bec, r.bec[perm], atol=1e-10)
+
+
+# ---------------------------------------------------------------- external field (Eq. 29)
+def test_external_field_fixed_charges_is_qE(orc):
+    """With charges that do not depend on the geometry, Z_i = q~'_i I and the field
+    force is the textbook force on a point charge, q~'_i E."""
+    w = inputs.workload(0)
+    th = _fixed_charge_theta(w.hp, [0.8, -0.35], s=1.3)
+    es0 = copy.copy(w.es)
+    es1 = copy.copy(w.es)
+    es1.efield = (0.02, -0.05, 0.013)
+    r0 = orc.compute(w.hp, es0, w.system.pos, w.system.types, w.system.cell, th)
+    r1 = orc.compute(w.hp, es1, w.system.pos, w.system.types, w.system.cell, th)
+    want = r0.q_naked[:, None] * np.array(es1.efield)[None, :]
+    np.testing.assert_allclose(r1.forces - r0.forces, want, atol=1e-13)
+    assert abs(r1.energy - r0.energy) < 1e-9 and np.allclose(r1.virial, r0.virial, rtol=0, atol=1e-9)
+
+
+def _cluster_dP_and_a(orc, hp, es, sysm, th, h=1e-5):
+    """Central differences in a cluster: dP[i, a, b] = dP_a/dr_{i b} and a[k, i, b] =
+    s dq_k/dr_{i b} (raw network charges)."""
+    n = sysm.n
+    dP = np.zeros((n, 3, 3))
+    dq = np.zeros((n, n, 3))
+    for i in range(n):
+        for b in range(3):
+            p = sysm.pos.copy()
+            p[i, b] += h
+            rp = orc.compute(hp, es, p, sysm.types, sysm.cell, th, forces=False)
+            p[i, b] -= 2 * h
+            rm = orc.compute(hp, es, p, sysm.types, sysm.cell, th, forces=False)
+            dP[i, :, b] = (rp.pol - rm.pol) / (2 * h)
+            dq[:, i, b] = (rp.q_raw - rm.q_raw) / (2 * h)
+    return dP, th[-1] * dq
+
+
+def test_external_field_cluster_finite_difference(orc):
+    """In a cluster the field force is sum_a E_a dP_a/dr_i (the derivative of E.P) plus
+    the pair term of the neutrality correction, sum_a E_a sum_j (m_ij - rbar)_a
+    (a_ij - a_ji), everything from finite differences of P and of the raw charges."""
+    sysm = _cluster()
+    hp = inputs.WATER_HP
+    th = inputs.theta0(hp, 99)
+    th[-1] = 1.4
+    es0 = inputs.ESParams(mode=2, method=0, alpha=0.3, kmax=1.2)
+    es1 = copy.copy(es0)
+    E = np.array([0.03, -0.011, 0.02])
+    es1.efield = tuple(E)
+    r0 = orc.compute(hp, es0, sysm.pos, sysm.types, sysm.cell, th)
+    r1 = orc.compute(hp, es1, sysm.pos, sysm.types, sysm.cell, th)
+    dP, a = _cluster_dP_and_a(orc, hp, es0, sysm, th)
+    rbar = sysm.pos.mean(0)
+    for i in range(sysm.n):
+        want = E @ dP[i]
+        for j in range(sysm.n):
+            if j != i:
+                m = 0.5 * (sysm.pos[i] + sysm.pos[j])
+                want = want + (E @ (m - rbar)) * (a[i, j] - a[j, i])
+        np.testing.assert_allclose(r1.forces[i] - r0.forces[i], want, atol=5e-9)
+    assert np.abs(r1.forces - r0.forces).max() > 1e-3
+
+
+# ---------------------------------------------------------------- per-atom virial (Eqs. 12, 20, 39)
+@pytest.mark.parametrize("method,Q", [(0, 0.0), (0, 0.9), (1, 0.0)])
+def test_per_atom_virial_sums_to_virial(orc, method, Q):
+    """sum_i W_i equals the total virial (itself pinned by strain finite differences)
+    for Ewald and PPPM, with and without a net charge (background term)."""
+    w = inputs.workload(0)
+    es = copy.copy(w.es)
+    es.q_total = Q
+    if method == 1:
+        es.method, es.mesh = 1, (20, 20, 20)
+    r = orc.compute(w.hp, es, w.system.pos, w.system.types, w.system.cell, w.theta, per_atom_virial=True)
+    np.testing.assert_allclose(r.vatom.sum(0), r.virial, atol=1e-10 * np.abs(r.virial).max())
+    assert np.abs(r.vatom).max() > 1e-2
+
+
+def test_per_atom_virial_dimer_assignment(orc):
+    """Two neutral atoms of different species in a large box (no Coulomb term): the
+    partial force of atom j on the pair is dU_j/dr r_hat, so W_i = r_ij (x) F_ji =
+    -r dU_j/dr r_hat (x) r_hat, with dU_j/dr from a finite difference of the site
+    energies -- each atom carries the radial derivative of the *other* atom's energy."""
+    hp = inputs.WATER_HP
+    th = inputs.theta0(hp, 5)
+    T, ndes, H = hp.n_types, hp.n_des, hp.n_neu
+    off = T * T * (hp.n_max_R + 1) * (hp.basis_R + 1) + T * T * (hp.n_max_A + 1) * (hp.basis_A + 1)
+    per = H * ndes + 3 * H + 1
+    for t in range(T):  # no charges at all: w1q = 0, b1q = 0
+        th[off + t * per + H * ndes + 2 * H: off + t * per + H * ndes + 3 * H + 1] = 0.0
+    # make atom 0's descriptors (species 0 as the centre) far more distance-sensitive
+    nR, nA = (hp.n_max_R + 1) * (hp.basis_R + 1), (hp.n_max_A + 1) * (hp.basis_A + 1)
+    cR = th[:T * T * nR].reshape(T, T, nR)
+    cR[0] *= 20.0
+    cA = th[T * T * nR:T * T * (nR + nA)].reshape(T, T, nA)
+    cA[0] *= 20.0
+    L = 30.0
+    u = np.array([0.48, -0.36, 0.8])
+    u /= np.linalg.norm(u)
+    es = inputs.ESParams(mode=1, method=0, alpha=0.3, rc_coul=9.0, kmax=1.0)
+
+    def dimer(r):
+        pos = np.array([[L / 2, L / 2, L / 2], [L / 2, L / 2, L / 2]]) + np.outer([-0.5 * r, 0.5 * r], u)
+        return pos, np.array([0, 1], dtype=np.int32)
+
+    r0, h = 2.3, 1e-5
+    pos, types = dimer(r0)
+    res = orc.compute(hp, es, pos, types, np.eye(3) * L, th, per_atom_virial=True)
+    assert np.abs(res.q_naked).max() == 0.0
+    Up = orc.compute(hp, es, *dimer(r0 + h), np.eye(3) * L, th, forces=False).site_energy
+    Um = orc.compute(hp, es, *dimer(r0 - h), np.eye(3) * L, th, forces=False).site_energy
+    dU = (Up - Um) / (2 * h)
+    assert abs(dU[0] - dU[1]) > 1e-3  # the two species respond differently
+    for i, j in ((0, 1), (1, 0)):
+        want = -r0 * dU[j] * np.outer(u, u)
+        np.testing.assert_allclose(res.vatom[i], want, atol=1e-7)
+
+
+def test_pppm_per_atom_virial_converges_to_ewald(orc):
+    """The PPPM per-atom reciprocal virial (six extra inverse transforms) approaches
+    the Ewald per-atom form as the mesh is refined."""
+    w = inputs.workload(0)
+    es_e = _converged_es(0.3)
+    re = orc.compute(w.hp, es_e, w.system.pos, w.system.types, w.system.cell, w.theta, per_atom_virial=True)
+    errs = []
+    for mesh in (12, 20):
+        es_p = copy.copy(es_e)
+        es_p.method, es_p.mesh = 1, (mesh,) * 3
+        rp = orc.compute(w.hp, es_p, w.system.pos, w.system.types, w.system.cell, w.theta, per_atom_virial=True)
+        errs.append(np.abs(rp.vatom - re.vatom).max() / np.abs(re.vatom).max())
+    assert errs[1] < errs[0] and errs[1] < 2e-3, errs
+
+
+# ---------------------------------------------------------------- SNES generation (Sec. 2.5)
+def test_snes_utilities_definition():
+    """Rank utilities sum to zero, do not increase with rank, and for lambda = 2 are
+    (+1/2, -1/2): the better member pulls the mean towards its draw."""
+    from oracle import snes
+
+    for lam in (2, 5, 64):
+        u = snes.utilities(lam)
+        assert abs(u.sum()) < 1e-14 and np.all(np.diff(u) <= 1e-15)
+    np.testing.assert_allclose(snes.utilities(2), [0.5, -0.5], atol=1e-15)
+    mu, sig = np.array([0.3, -1.0]), np.array([0.5, 2.0])
+    s = np.array([[1.0, -2.0], [0.5, 0.25]])
+    m2, s2 = snes.update(mu, sig, s, loss=[3.0, 1.0], eta_mu=1.0, eta_sigma=0.4)
+    g_mu = 0.5 * (s[1] - s[0])
+    g_sig = 0.5 * ((s[1] ** 2 - 1) - (s[0] ** 2 - 1))
+    np.testing.assert_allclose(m2, mu + sig * g_mu, atol=1e-15)
+    np.testing.assert_allclose(s2, sig * np.exp(0.2 * g_sig), atol=1e-15)
+
+
+def test_snes_rank_invariance_and_convergence():
+    """Only the ordering of the losses matters (a monotone transform of the fitness
+    gives the same update), and on the sphere function the mean converges to the
+    optimum while the step sizes shrink."""
+    from oracle import snes
+
+    rng = np.random.default_rng(7)
+    d, lam = 20, 16
+    mu, sig = rng.normal(size=d) * 3.0, np.ones(d)
+    s = rng.normal(size=(lam, d))
+    loss = ((snes.population(mu, sig, s)) ** 2).sum(1)
+    a = snes.update(mu, sig, s, loss)
+    b = snes.update(mu, sig, s, np.exp(0.01 * loss) - 5.0)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+    f0 = (mu ** 2).sum()
+    for _ in range(400):
+        s = rng.normal(size=(lam, d))
+        mu, sig = snes.update(mu, sig, s, ((snes.population(mu, sig, s)) ** 2).sum(1))
+    assert (mu ** 2).sum() < 1e-6 * f0 and sig.max() < 1e-2
