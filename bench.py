@@ -48,6 +48,13 @@ REAL_SPACE_FLOPS_PER_PAIR = 61
 
 KERNEL_HEADERS = ("common.h", "plan.h", "nep_math.h")
 
+# Algorithmic budget of one atom-step of the perovskite workload (design notes, the
+# measurement section): FP32 operations (descriptors, network, electrostatics,
+# FFTs and forces) and HBM bytes (per-atom inputs and outputs plus each mesh field
+# written and read once, 17.2 mesh points per atom).
+STEP_FLOPS_PER_ATOM = 1.3e5
+STEP_BYTES_PER_ATOM = 940.0
+
 
 def traffic_from_profile(kernel, workload, source):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary,
@@ -107,6 +114,115 @@ def timed_run(model, pos, types, th, w, steps, warmup, torch):
     model.enable_timing(False)
     ms = t0.elapsed_time(t1) / steps
     return ms, wall / steps * 1e3, ms_stage, launches, calls, float(out["energy"][0])
+
+
+def crop_errors(torch, forms):
+    """|dE|/N, max |dF|, max |dW|/N and max |dZ*| of every network form against the stored
+    FP64 oracle values of the 5,000-atom perovskite crop (PPPM 45^3), written by
+    tests/golden/make_fixtures.py from the oracle alone."""
+    import numpy as np
+
+    from paper_2601_19034_amd import inputs
+    from paper_2601_19034_amd.api import QNEP, to_device_inputs
+
+    ref = np.load(os.path.join(ROOT, "tests", "golden", "perovskite5000_oracle.npz"))
+    w = inputs.workload(3, "crop")
+    pos, types, th = to_device_inputs(w.system, w.theta, "cuda:0")
+    n = w.system.n
+    res = {}
+    for form in forms:
+        model = QNEP(w.hp, form)
+        out = model.compute(pos, types, w.system.cell, th, w.es)
+        if model.check_status():
+            raise SystemExit("crop evaluation: device status flags set")
+        g = {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
+        res[form] = {
+            "dE_per_atom": abs(g["energy"][0] - float(ref["energy"])) / n,
+            "max_dF": float(np.abs(g["forces"].T - ref["forces"]).max()),
+            "max_dW_per_atom": float(np.abs(g["virial"].reshape(3, 3) - ref["virial"]).max() / n),
+            "max_dZ": float(np.abs(g["bec"].T.reshape(-1, 3, 3) - ref["bec"]).max()),
+        }
+        log(f"# crop errors {form}: " + ", ".join(f"{k}={v:.2e}" for k, v in res[form].items()))
+        del model
+    return {"workload": f"{w.name} (PPPM {'x'.join(map(str, w.es.mesh))}) vs FP64 oracle", "forms": res}
+
+
+def workload_bench(torch, steps, warmup):
+    """The other workloads of the method on one GPU: water-24,000 with PPPM 64^3 and with
+    direct Ewald (27,200 wave vectors); garnet-153,600 with PPPM 128^3, forward and the
+    adjoint (qnep_backward: forward recomputed plus the reverse pass); and NVE molecular
+    dynamics of the water box (velocity Verlet, one full evaluation per step)."""
+    import numpy as np
+
+    from paper_2601_19034_amd import inputs
+    from paper_2601_19034_amd.api import QNEP, to_device_inputs
+
+    lines = []
+
+    def timed(fn, reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    for wid, method in ((1, 1), (1, 0), (2, 1)):
+        w = inputs.workload(wid, "full")
+        w.es.method = method
+        model = QNEP(w.hp, "fp32")
+        pos, types, th = to_device_inputs(w.system, w.theta, "cuda:0")
+        out = model.compute(pos, types, w.system.cell, th, w.es)
+        if model.check_status():
+            raise SystemExit(f"{w.name}: device status flags set")
+        ms = timed(lambda: model.compute(pos, types, w.system.cell, th, w.es, out=out), steps)
+        rec = {"workload": w.name, "n_atoms": w.system.n, "method": "PPPM" if method == 1 else "Ewald",
+               "ms_per_step": ms, "atom_steps_per_s": w.system.n / (ms * 1e-3), "mlp": "fp32"}
+        if method == 1:
+            rec["mesh"] = list(w.es.mesh)
+        else:
+            rec["k_vectors"] = int(out["energy_terms"][7].item())
+        if wid == 2:
+            ms_b = timed(lambda: model.backward(pos, types, w.system.cell, th, w.es, 1.0, None,
+                                                want=("pos", "cell", "theta")), max(steps // 2, 3))
+            rec["adjoint_ms"] = ms_b
+            rec["adjoint_atom_steps_per_s"] = w.system.n / (ms_b * 1e-3)
+        log(f"# {w.name} {rec['method']}: {ms:.3f} ms/step ({rec['atom_steps_per_s']:.3e} atom-steps/s)"
+            + (f", adjoint {rec['adjoint_ms']:.3f} ms" if "adjoint_ms" in rec else ""))
+        lines.append(rec)
+        del model, out
+        torch.cuda.empty_cache()
+    # NVE MD of the water box with PPPM: the paper's speed figures are MD rates
+    w = inputs.workload(1, "full")
+    model = QNEP(w.hp, "fp32")
+    pos, types, th = to_device_inputs(w.system, w.theta, "cuda:0")
+    masses = [15.999, 1.008]
+    rng = np.random.default_rng(5)
+    mt = np.array([masses[t] for t in w.system.types])
+    v = rng.normal(size=(3, w.system.n)) * np.sqrt(0.025 / (mt * 103.6427))[None, :]
+    vel = torch.from_numpy(v.astype(np.float32)).cuda()
+    # the random-weight model has no physical repulsion, so the run is kept short (the
+    # rate does not depend on the trajectory as long as no list overflows)
+    md_steps, dt = 5 * steps, 0.25
+    model.md_nve(pos, vel, types, w.system.cell, th, w.es, masses, dt, warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    model.md_nve(pos, vel, types, w.system.cell, th, w.es, masses, dt, md_steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / md_steps
+    rec = {"workload": f"{w.name} NVE MD", "n_atoms": w.system.n, "method": "PPPM", "mesh": list(w.es.mesh),
+           "dt_fs": dt, "steps": md_steps, "ms_per_step": ms, "atom_steps_per_s": w.system.n / (ms * 1e-3),
+           "status_flags": model.check_status()}
+    log(f"# {rec['workload']}: {ms:.3f} ms/step ({rec['atom_steps_per_s']:.3e} atom-steps/s), "
+        f"{md_steps} steps of {dt} fs, status flags {rec['status_flags']}")
+    lines.append(rec)
+    return lines
 
 
 def batch_bench(torch, reps=3):
@@ -202,6 +318,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched (structures x candidates) line")
     ap.add_argument("--batch-only", action="store_true", help="only the batched line")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the water, garnet and MD lines and the per-form crop errors")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run three 1 GiB device copies first (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -284,13 +402,24 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if head == "fp32" else "bf16+f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "n_atoms": n, "method": "PPPM", "mesh": list(w.es.mesh),
-                   "mlp": head},
+        "config": {"workload": w.name, "n_atoms": n, "method": "PPPM" if w.es.method == 1 else "Ewald",
+                   "mesh": list(w.es.mesh), "mlp": head},
         "forms": {k: {"atom_steps_per_s": v["atom_steps_per_s"], "ms_per_step": v["ms_per_step"]}
                   for k, v in forms.items()},
         "stage_ms": {k: round(v, 4) for k, v in stages[head][0].items()},
         "roofline": roof,
     }
+    # the whole step against the per-atom-step budgets of the path (algorithmic FP32
+    # operations and HBM bytes per atom-step for this workload, derived in the design notes)
+    rec["step_roofline"] = {
+        "flops_per_atom_step": STEP_FLOPS_PER_ATOM, "hbm_bytes_per_atom_step": STEP_BYTES_PER_ATOM,
+        "valu_tflops": rec["value"] * STEP_FLOPS_PER_ATOM / 1e12,
+        "valu_frac": rec["value"] * STEP_FLOPS_PER_ATOM / 1e12 / FP32_VALU_PEAK_TF,
+        "hbm_gbs": rec["value"] * STEP_BYTES_PER_ATOM / 1e9,
+        "hbm_frac": rec["value"] * STEP_BYTES_PER_ATOM / 1e9 / HBM_PEAK_GBS}
+    if not args.no_workloads and args.workload == 3:
+        rec["accuracy"] = crop_errors(torch, list(forms))
+        rec["workloads"] = workload_bench(torch, args.steps, args.warmup)
     if not args.no_batch:
         rec["batch"] = batch_bench(torch)
     if not args.no_cpu_baseline:

@@ -106,6 +106,30 @@ class QNEP:
         return B.qnep_check_status(self._ws.data_ptr(), self._last_stream.cuda_stream)
 
 
+def _md_nve(self, pos: torch.Tensor, vel: torch.Tensor, types: torch.Tensor, cell, theta: torch.Tensor, es,
+            masses, dt: float, n_steps: int, stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """n_steps velocity-Verlet steps (qnep_md_nve); pos and vel (float32 [3, N], Angstrom
+    and Angstrom/fs) are advanced in place.  Returns the series float64 [n_steps + 1, 8]
+    (E_pot, E_kin, P_dot, P) as a device tensor.  masses: per species, amu."""
+    _require_gpu()
+    assert pos.dtype == torch.float32 and vel.dtype == torch.float32 and pos.is_contiguous() and vel.is_contiguous()
+    assert pos.shape == vel.shape and pos.shape[0] == 3 and types.dtype == torch.int32
+    n = pos.shape[1]
+    cell = np.asarray(cell, dtype=np.float64)
+    es_c = B.make_es(es)
+    nbytes = B.qnep_md_workspace_size(self.handle, es_c, n, cell)
+    ws = self.workspace(nbytes, pos.device)
+    series = torch.empty((n_steps + 1, 8), dtype=torch.float64, device=pos.device)
+    s = stream if stream is not None else torch.cuda.current_stream(pos.device)
+    B.qnep_md_nve(self.handle, theta.data_ptr(), es_c, dt, n_steps, list(masses), n, types.data_ptr(), cell,
+                  pos.data_ptr(), vel.data_ptr(), series.data_ptr(), ws.data_ptr(), ws.numel(), s.cuda_stream)
+    self._last_stream = s
+    return series
+
+
+QNEP.md_nve = _md_nve
+
+
 def to_device_inputs(system, theta: np.ndarray, device="cuda"):
     """Seeded host arrays -> the device tensors ``QNEP.compute`` takes."""
     pos = torch.from_numpy(system.pos_f32_soa()).to(device)

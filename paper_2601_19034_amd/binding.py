@@ -326,3 +326,46 @@ def qnep_snes_generation(model: int, mu_ptr: int, sigma_ptr: int, noise_ptr: int
                                   C.c_void_p(noise_ptr), int(n_candidates), float(eta_mu), float(eta_sigma),
                                   C.byref(targets), C.byref(outputs), C.c_void_p(thetas_ptr), C.c_void_p(ws_ptr),
                                   ws_bytes, C.c_void_p(stream)))
+
+
+class qnep_md_params(C.Structure):
+    _fields_ = [("dt", C.c_double), ("n_steps", C.c_int32), ("masses", C.c_void_p)]
+
+
+EXPORTED += ["qnep_md_workspace_size", "qnep_md_nve"]
+
+
+def _bind_md(L):
+    if getattr(L, "_md_bound", False):
+        return
+    L.qnep_md_workspace_size.restype = C.c_int
+    L.qnep_md_workspace_size.argtypes = [C.c_void_p, C.POINTER(qnep_es_params), C.c_int64, C.c_void_p,
+                                         C.POINTER(C.c_size_t)]
+    L.qnep_md_nve.restype = C.c_int
+    L.qnep_md_nve.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(qnep_es_params), C.POINTER(qnep_md_params),
+                              C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                              C.c_size_t, C.c_void_p]
+    L._md_bound = True
+
+
+def qnep_md_workspace_size(model: int, es: qnep_es_params, n_atoms: int, cell) -> int:
+    L = load()
+    _bind_md(L)
+    c = (C.c_double * 9)(*[float(v) for v in list(cell.reshape(-1))])
+    n = C.c_size_t()
+    _check(L.qnep_md_workspace_size(C.c_void_p(model), C.byref(es), int(n_atoms), C.cast(c, C.c_void_p),
+                                    C.byref(n)))
+    return int(n.value)
+
+
+def qnep_md_nve(model: int, theta_ptr: int, es: qnep_es_params, dt: float, n_steps: int, masses, n_atoms: int,
+                type_ptr: int, cell, pos_ptr: int, vel_ptr: int, series_ptr: int, ws_ptr: int, ws_bytes: int,
+                stream: int):
+    L = load()
+    _bind_md(L)
+    m = (C.c_double * len(masses))(*[float(v) for v in masses])
+    md = qnep_md_params(float(dt), int(n_steps), C.cast(m, C.c_void_p))
+    c = (C.c_double * 9)(*[float(v) for v in list(cell.reshape(-1))])
+    _check(L.qnep_md_nve(C.c_void_p(model), C.c_void_p(theta_ptr), C.byref(es), C.byref(md), int(n_atoms),
+                         C.c_void_p(type_ptr), C.cast(c, C.c_void_p), C.c_void_p(pos_ptr), C.c_void_p(vel_ptr),
+                         C.c_void_p(series_ptr), C.c_void_p(ws_ptr), ws_bytes, C.c_void_p(stream)))

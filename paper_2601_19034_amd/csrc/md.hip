@@ -10,7 +10,7 @@ namespace qnep {
 
 // 1 eV/(Angstrom amu) in Angstrom/fs^2, and 1 amu Angstrom^2/fs^2 in eV (CODATA 2018:
 // e = 1.602176634e-19 C, u = 1.66053906660e-27 kg)
-constexpr double MD_ACC = 1.602176634e-19 / 1.66053906660e-27 * 1e-20;
+constexpr double MD_ACC = 1.602176634e-19 / 1.66053906660e-27 * 1e-10;
 constexpr double MD_EKIN = 1.66053906660e-27 / 1.602176634e-19 * 1e10;
 
 struct MdMasses {
