@@ -60,11 +60,16 @@ class _OUT(C.Structure):
 
 
 def lib():
+    """The compiled oracle (QNEP_ORACLE_LIBRARY in the environment selects another
+    build of the same source, for example one with sanitizers)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build()
-        L = C.CDLL(_LIB)
+        path = os.environ.get("QNEP_ORACLE_LIBRARY")
+        if not path:
+            path = _LIB
+            if not os.path.exists(path):
+                build()
+        L = C.CDLL(path)
         L.oq_compute.restype = C.c_int
         L.oq_compute.argtypes = [C.POINTER(_HP), C.POINTER(_ES), C.c_int, _DP, C.POINTER(C.c_int), _DP, _DP,
                                  C.c_int, C.c_int, C.POINTER(_OUT)]

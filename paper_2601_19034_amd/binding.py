@@ -56,11 +56,13 @@ EXPORTED = ["qnep_param_count", "qnep_model_create", "qnep_model_destroy", "qnep
 _lib = None
 
 
-def load(path: str = LIB_PATH):
-    """Loads the library (raises if it has not been built)."""
+def load(path: str = None):
+    """Loads the library (raises if it has not been built).  QNEP_LIBRARY in the
+    environment selects another build of it (for example one with host sanitizers)."""
     global _lib
     if _lib is not None:
         return _lib
+    path = path or os.environ.get("QNEP_LIBRARY") or LIB_PATH
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_2601_19034_amd.build`")
     L = C.CDLL(path)

@@ -143,3 +143,52 @@ def test_batch_workspace_and_validation(qlib):
             B.qnep_batch_workspace_size(hb, es, b0, 4)
     finally:
         B.qnep_model_destroy(hb)
+
+
+def test_new_entry_points_validation(qlib):
+    """Host-side checks of the allocation-free call, the MD driver, the SNES generation
+    and the field argument: each bad argument is refused before any device work."""
+    from paper_2601_19034_amd import binding as B
+    w = inputs.workload(0)
+    h = B.qnep_model_create(w.hp, 0)
+    try:
+        n = w.system.n
+        es = B.make_es(w.es)
+        # field: must be finite; the adjoint refuses a non-zero field
+        bad = inputs.ESParams(**{**w.es.__dict__, "efield": (float("nan"), 0.0, 0.0)})
+        with pytest.raises(B.QnepError, match="efield"):
+            B.qnep_workspace_size(h, B.make_es(bad), B.make_system(n, 0, 0, w.system.cell))
+        fld = B.make_es(inputs.ESParams(**{**w.es.__dict__, "efield": (0.1, 0.0, 0.0)}))
+        nbw = B.qnep_backward_workspace_size(h, fld, B.make_system(n, 0, 0, w.system.cell))
+        with pytest.raises(B.QnepError, match="efield"):
+            B.qnep_backward(h, 1, fld, B.make_system(n, 1, 1, w.system.cell), 1.0, None, 0, 0, 0, 1, nbw, 0)
+        # the static workspace refuses structures that do not fit in it
+        big = inputs.workload(1)
+        hb = B.qnep_model_create(big.hp, 0)
+        try:
+            with pytest.raises(B.QnepError, match="static workspace"):
+                B.qnep_compute_static(hb, 1, B.make_es(big.es), B.make_system(big.system.n, 1, 1, big.system.cell),
+                                      B.qnep_outputs(), 0, 0)
+        finally:
+            B.qnep_model_destroy(hb)
+        # MD: workspace grows with N; bad time step, masses and sizes are refused
+        n1 = B.qnep_md_workspace_size(h, es, n, w.system.cell)
+        assert n1 > B.qnep_workspace_size(h, es, B.make_system(n, 0, 0, w.system.cell))
+        with pytest.raises(B.QnepError, match="dt"):
+            B.qnep_md_nve(h, 1, es, -0.5, 10, [16.0, 1.0], n, 1, w.system.cell, 1, 1, 1, 1, n1, 0)
+        with pytest.raises(B.QnepError, match="masses"):
+            B.qnep_md_nve(h, 1, es, 0.5, 10, [16.0, 0.0], n, 1, w.system.cell, 1, 1, 1, 1, n1, 0)
+        with pytest.raises(B.QnepError, match="workspace"):
+            B.qnep_md_nve(h, 1, es, 0.5, 10, [16.0, 1.0], n, 1, w.system.cell, 1, 1, 1, 1, 64, 0)
+        # SNES: population size and the prepared batch are checked first
+        tg = B.qnep_batch_targets(1, 1, 1.0, 1.0, 1.0, 0.0, 0.0)
+        oc = B.qnep_batch_outputs(1, 1, None, None, None, None)
+        with pytest.raises(B.QnepError, match="n_candidates"):
+            B.qnep_snes_generation(h, 1, 1, 1, 1, 1.0, 0.0, tg, oc, 1, 1, 1 << 20, 0)
+        with pytest.raises(B.QnepError, match="prepared"):
+            B.qnep_snes_generation(h, 1, 1, 1, 8, 1.0, 0.0, tg, oc, 1, 1, 1 << 20, 0)
+        oc_noloss = B.qnep_batch_outputs(1, None, None, None, None, None)
+        with pytest.raises(B.QnepError, match="loss"):
+            B.qnep_snes_generation(h, 1, 1, 1, 8, 1.0, 0.0, tg, oc_noloss, 1, 1, 1 << 20, 0)
+    finally:
+        B.qnep_model_destroy(h)
