@@ -55,9 +55,15 @@ __device__ inline int lm_degree(int m) { return m < 3 ? 0 : (m < 8 ? 1 : (m < 15
 
 // work item shared by the phases
 struct Item {
-    int s, c, n, G, lig, grp, per_round;
+    int s, c, n, G, lig, grp, per_round, cls;
     int64_t atom0, mat0;
 };
+
+// Lanes per atom of the descriptor sums and of the FP32 network's hidden-unit sums, per
+// size class: fixed (not tuned), so that the FP32 order of those sums, and with it every
+// output, does not depend on the autotuner's choice for the other phases (the forces
+// accumulate in fixed point, independent of the order).
+__constant__ int kDescGroups[BATCH_CLASSES] = {8, 4, 2, 1};
 
 __device__ inline Item make_item(const BatchArgs &a, int item, int4 groups) {
     Item it;
@@ -67,6 +73,7 @@ __device__ inline Item make_item(const BatchArgs &a, int item, int4 groups) {
     it.n = b.n;
     it.atom0 = b.atom0;
     it.mat0 = b.mat0;
+    it.cls = b.group;
     it.G = b.group == 0 ? groups.x : (b.group == 1 ? groups.y : (b.group == 2 ? groups.z : groups.w));
     it.per_round = BATCH_THREADS / it.G;
     it.lig = threadIdx.x % it.G;
@@ -81,9 +88,9 @@ template <int T, int NR, int NA, int NB>
 __device__ __forceinline__ void item_descriptors(const BatchArgs &a, const Item &it, const float *th, int M,
                                                  float *sD, float *sA, float *sB) {
     const float *cR = th, *cA = th + a.off_cA;
-    const int G = it.G, lig = it.lig;
-    for (int i0 = 0; i0 < it.n; i0 += it.per_round) {
-        const int i = i0 + it.grp;
+    const int G = kDescGroups[it.cls], lig = threadIdx.x % G, grp = threadIdx.x / G, per_round = BATCH_THREADS / G;
+    for (int i0 = 0; i0 < it.n; i0 += per_round) {
+        const int i = i0 + grp;
         const bool act = i < it.n;
         const int64_t g = it.atom0 + (act ? i : 0);
         const int tI = act ? a.types[g] : 0;
@@ -307,9 +314,9 @@ __device__ __forceinline__ void item_network(const BatchArgs &a, const Item &it,
         }
         return;
     }
-    const int G = it.G, lig = it.lig;
-    for (int i0 = 0; i0 < it.n; i0 += it.per_round) {
-        const int i = i0 + it.grp;
+    const int G = kDescGroups[it.cls], lig = threadIdx.x % G, grp = threadIdx.x / G, per_round = BATCH_THREADS / G;
+    for (int i0 = 0; i0 < it.n; i0 += per_round) {
+        const int i = i0 + grp;
         const bool act = i < it.n;
         const int tI = act ? a.types[it.atom0 + i] : 0;
         float Dv[NDES];

@@ -191,11 +191,11 @@ def test_batch_full_population_and_tuner(torch_dev, orc, wl):
     out2 = batch.compute(th, E_ref, F_ref, outputs=("loss", "energy", "forces"))
     res2 = {k: v.cpu().numpy() for k, v in out2.items()}
     assert np.abs(res2["energy"] - res["energy"]).max() <= 1e-6 * np.abs(res["energy"]).max()
-    # other lane groupings change the FP32 summation order of the descriptors; on cells
-    # only 4 A wide (1 x 1 x n perovskite chains, where every atom sees many of its own
-    # images) that reordering alone moves a force by up to about 1e-4 eV/A.  Each
-    # configuration is held to the oracle bound on those chains below, so the two agree
-    # to twice that bound (triangle inequality).
+    # the descriptor sums use a fixed lane partition whatever the tuner picks for the
+    # other phases, so the tuned launch reproduces the default one up to the FP32
+    # order of the network's hidden-unit sums (forces accumulate in fixed point).
+    # The 1 x 1 x n perovskite chains (cells 4 A wide, every atom sees many of its own
+    # images) are the hardest FP32 case against the oracle.
     for s, c in ((294, 18), (446, 30)):
         sysm = wl.systems[s]
         r = _oracle(orc, wl.hp, wl.es, sysm, wl.thetas[c])
@@ -205,7 +205,7 @@ def test_batch_full_population_and_tuner(torch_dev, orc, wl):
             assert dF <= TOL["f"]
     dFc = np.abs(res2["forces"] - res["forces"]).max()
     _say(f"[default vs tuned] max dF={dFc:.2e}")
-    assert dFc <= 2 * TOL["f"]
+    assert dFc <= 1e-5
 
 
 # BF16 network on the matrix cores (FP32 accumulation): both forms are held to the
