@@ -63,6 +63,8 @@ typedef enum {
 #define QNEP_FLAG_COULOMB_OVERFLOW 4
 #define QNEP_FLAG_BAD_SPECIES 8
 #define QNEP_FLAG_INTERNAL 16  /* an atom fell outside its charge-assignment tile (should not happen) */
+#define QNEP_FLAG_OUTSIDE 32   /* isolated system: an atom lies outside the bounding box */
+#define QNEP_FLAG_IMAGE 64     /* isolated system: a periodic image of the bounding box is within a cutoff */
 
 /* MLP arithmetic */
 #define QNEP_MLP_FP32 0   /* FP32 vector ALU */
@@ -92,10 +94,15 @@ typedef struct {
     double rc_R, rc_A; /* cutoffs, Angstrom, rc_A <= rc_R */
 } qnep_hparams;
 
+#define QNEP_ES_EWALD 0
+#define QNEP_ES_PPPM 1
+#define QNEP_ES_DIRECT 2
+
 /* electrostatics (Sec. 2.2 and 2.6) */
 typedef struct {
     int32_t mode;           /* 1: real + reciprocal + self (Eq. 3); 2: reciprocal only (Eq. 5) */
-    int32_t method;         /* 0: direct Ewald; 1: PPPM */
+    int32_t method;         /* 0: direct Ewald; 1: PPPM (periodic systems); 2 (QNEP_ES_DIRECT): the
+                               plain Coulomb sum over all pairs of an isolated system (mode ignored) */
     double alpha;           /* Ewald splitting parameter, 1/Angstrom */
     double rc_coul;         /* real-space cutoff (mode 1), Angstrom */
     double kmax;            /* Ewald: wave vectors with |k| < kmax (Eq. 7) */
@@ -108,12 +115,19 @@ typedef struct {
                                term (the paper gives the force only).  Zero = no field */
 } qnep_es_params;
 
-/* one periodic structure */
+/* one structure */
 typedef struct {
     int64_t n_atoms;      /* N >= 0, N < 2^23 */
     const float *pos;     /* device, SoA [3][N]: x[0..N), y[0..N), z[0..N), Angstrom, any image */
     const int32_t *type;  /* device, [N], species in [0, n_types) */
     double cell[9];       /* host, row-major, rows are the cell vectors a, b, c (right-handed) */
+    int32_t pbc[3];       /* periodicity along a, b, c: {1, 1, 1} periodic; {0, 0, 0} an isolated
+                             system (cluster, molecule) whose cell is a bounding box: every atom
+                             inside it (QNEP_FLAG_OUTSIDE otherwise) and no atom within a cutoff of
+                             another atom's periodic image (QNEP_FLAG_IMAGE otherwise); isolated
+                             systems take es->method = QNEP_ES_DIRECT and their Born charges are the
+                             derivative of P with absolute positions (Sec. 2.4 Eq. 27).  Mixed
+                             periodicity is not supported (QNEP_E_UNSUPPORTED). */
 } qnep_system;
 
 /* outputs; any pointer may be NULL to skip that output (all device) */

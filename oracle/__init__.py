@@ -72,7 +72,7 @@ def lib():
         L = C.CDLL(path)
         L.oq_compute.restype = C.c_int
         L.oq_compute.argtypes = [C.POINTER(_HP), C.POINTER(_ES), C.c_int, _DP, C.POINTER(C.c_int), _DP, _DP,
-                                 C.c_int, C.c_int, C.POINTER(_OUT)]
+                                 C.c_int, C.c_int, C.POINTER(_OUT), C.c_int]
         L.oq_theta_count.restype = C.c_int64
         L.oq_theta_count.argtypes = [C.POINTER(_HP)]
         L.oq_radial_basis.restype = None
@@ -131,13 +131,15 @@ def theta_count(hp) -> int:
 
 
 def compute(hp, es, pos, types, cell, theta, forces: bool = True, cells: bool = False,
-            per_atom_virial: bool = False) -> OracleResult:
+            per_atom_virial: bool = False, periodic: bool = True) -> OracleResult:
     """Evaluate E, F, W, q, Z*, P (and intermediates) in FP64.
 
     pos (N, 3) Angstrom, types (N,) int, cell (3, 3) rows a, b, c, theta flat vector.
     ``cells`` selects the cell-list neighbour search instead of brute force;
     ``per_atom_virial`` also returns W_i (needs ``forces``).  A non-zero ``es.efield``
-    adds the external-field force to the forces."""
+    adds the external-field force to the forces.  ``periodic=False`` evaluates an
+    isolated system (no images; es.method must be 2, the direct Coulomb sum; the cell
+    only bounds the cluster) with the Born charges of Eq. 27."""
     pos = np.ascontiguousarray(pos, dtype=np.float64)
     types = np.ascontiguousarray(types, dtype=np.int32)
     cell = np.ascontiguousarray(cell, dtype=np.float64)
@@ -158,7 +160,8 @@ def compute(hp, es, pos, types, cell, theta, forces: bool = True, cells: bool = 
                _ptr(phi), _ptr(Va))
     h, e = _hp(hp), _es(es)
     rc = lib().oq_compute(C.byref(h), C.byref(e), n, _ptr(pos), types.ctypes.data_as(C.POINTER(C.c_int)),
-                          _ptr(cell), _ptr(theta), 1 if cells else 0, 1 if forces else 0, C.byref(out))
+                          _ptr(cell), _ptr(theta), 1 if cells else 0, 1 if forces else 0, C.byref(out),
+                          1 if periodic else 0)
     if rc != 0:
         raise ValueError(f"oracle rejected the input (code {rc})")
     return OracleResult(terms[0], terms, F, W, qs, qt, qr, Z, P, D, U, phi, Va)

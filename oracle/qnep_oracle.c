@@ -37,7 +37,9 @@
  *     real-space pair virial shared equally, the reciprocal per-atom forms, and the
  *     background virial split evenly over the atoms;
  *   - an external field E adds F_i += sum_a E_a Z_i[a][:] (Eq. 29) to the forces only
- *     (no energy or virial term: the paper gives the force alone).
+ *     (no energy or virial term: the paper gives the force alone);
+ *   - isolated systems (no periodic images): direct Coulomb sum over all pairs and the
+ *     Born charges of Eq. 27, the derivative of P with absolute positions.
  *
  * Units: eV, Angstrom, elementary charge.  Virial W = -dE/d(strain).
  */
@@ -242,6 +244,23 @@ static oq_plist *nbr_cells(int n, const double *frac, const double *wpos, const 
 static oq_plist *build_list(int method, int n, const double *frac, const double *wpos, const double *h, double rc)
 {
     return method == 1 ? nbr_cells(n, frac, wpos, h, rc) : nbr_brute(n, wpos, h, rc);
+}
+
+/* isolated system: every j != i with |r_j - r_i| < rc, no periodic images */
+static oq_plist *nbr_free(int n, const double *pos, double rc)
+{
+    oq_plist *L = (oq_plist *)calloc((size_t)(n > 0 ? n : 1), sizeof(oq_plist));
+    double rc2 = rc * rc;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double d[3];
+            for (int b = 0; b < 3; ++b) d[b] = pos[3 * j + b] - pos[3 * i + b];
+            double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            if (r2 < rc2) plist_push(&L[i], j, d, sqrt(r2));
+        }
+    return L;
 }
 
 /* exported for the tests: per-atom neighbour counts and, when js/ds are given,
@@ -751,8 +770,11 @@ static int oq_ablation = 0;
 void oq_set_ablation(int flags) { oq_ablation = flags; }
 
 int oq_compute(const oq_hparams *hp, const oq_es *es, int n, const double *pos, const int *type, const double *cell,
-               const double *theta, int nbr_method, int want_forces, oq_out *out)
+               const double *theta, int nbr_method, int want_forces, oq_out *out, int periodic)
 {
+    /* isolated systems (periodic = 0) take the direct Coulomb sum (method 2) only, and
+       periodic ones Ewald or PPPM */
+    if (periodic ? es->method == 2 : es->method != 2) return -3;
     if (n < 1 || hp->n_types > ORC_MAXT || hp->basis_R > ORC_MAXB || hp->basis_A > ORC_MAXB || hp->l_max > ORC_MAXL)
         return -1;
     if (es->method == 1 && es->order != 5) return -2;
@@ -766,15 +788,16 @@ int oq_compute(const oq_hparams *hp, const oq_es *es, int n, const double *pos, 
     const double vol = fabs(det3(cell));
 
     double *frac = (double *)malloc(sizeof(double) * 3 * (size_t)n), *wpos = (double *)malloc(sizeof(double) * 3 * (size_t)n);
-    wrap_positions(n, pos, cell, frac, wpos);
+    if (periodic) wrap_positions(n, pos, cell, frac, wpos);
+    else memcpy(wpos, pos, sizeof(double) * 3 * (size_t)n);
 
     /* neighbour lists: radial (NEP radial cutoff), angular (sub-list), Coulomb */
-    oq_plist *LR = build_list(nbr_method, n, frac, wpos, cell, v.rcR);
+    oq_plist *LR = periodic ? build_list(nbr_method, n, frac, wpos, cell, v.rcR) : nbr_free(n, pos, v.rcR);
     oq_plist *LA = (oq_plist *)calloc((size_t)n, sizeof(oq_plist));
     for (int i = 0; i < n; ++i)
         for (int p = 0; p < LR[i].n; ++p)
             if (LR[i].p[p].r < v.rcA) plist_push(&LA[i], LR[i].p[p].j, LR[i].p[p].d, LR[i].p[p].r);
-    oq_plist *LC = es->mode == 1 ? build_list(nbr_method, n, frac, wpos, cell, es->rc_coul) : NULL;
+    oq_plist *LC = periodic && es->mode == 1 ? build_list(nbr_method, n, frac, wpos, cell, es->rc_coul) : NULL;
 
     /* descriptors, network outputs and their gradients */
     double *D = (double *)malloc(sizeof(double) * (size_t)n * ndes);
@@ -802,7 +825,31 @@ int oq_compute(const oq_hparams *hp, const oq_es *es, int n, const double *pos, 
     double *Fst = (double *)calloc((size_t)n * 3, sizeof(double));
     double *Va = want_forces && out->vatom ? (double *)calloc((size_t)n * 9, sizeof(double)) : NULL;
     double Ur = 0.0, Us = 0.0, Ubg = 0.0, Uk = 0.0, Wst[9] = {0}, nk = 0.0;
-    if (es->mode == 1) {
+    if (!periodic) {
+        /* isolated system: direct Coulomb sum over all pairs, U = 1/2 k_e sum_{i != j}
+           q'_i q'_j / r_ij (Eq. 6 with alpha -> 0 and no images) */
+        double Wl[9] = {0};
+        for (int i = 0; i < n; ++i) {
+            double ph = 0.0;
+            for (int j = 0; j < n; ++j) {
+                if (j == i) continue;
+                double d[3];
+                for (int b = 0; b < 3; ++b) d[b] = pos[3 * j + b] - pos[3 * i + b];
+                double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                ph += ORC_KE * qs[j] / r;
+                double du = -ORC_KE * qs[i] * qs[j] / (r * r);
+                for (int b = 0; b < 3; ++b) Fst[3 * i + b] += du * d[b] / r;
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) {
+                        Wl[3 * a + b] -= 0.5 * du * d[a] * d[b] / r;
+                        if (Va) Va[9 * i + 3 * a + b] -= 0.5 * du * d[a] * d[b] / r;
+                    }
+            }
+            phi[i] = ph;
+            Ur += 0.5 * qs[i] * ph;
+        }
+        for (int t = 0; t < 9; ++t) Wst[t] += Wl[t];
+    } else if (es->mode == 1) {
         /* real space (Sec. 2.2.1 Eq. 6; static pair force Eq. 15) */
         double Wr[9] = {0};
 #pragma omp parallel
@@ -848,7 +895,7 @@ int oq_compute(const oq_hparams *hp, const oq_es *es, int n, const double *pos, 
             for (int i = 0; i < n; ++i)
                 for (int a = 0; a < 3; ++a) Va[9 * i + 4 * a] += Ubg / n;
     }
-    {
+    if (periodic) {
         double *phik = (double *)calloc((size_t)n, sizeof(double)), *Fk = (double *)calloc((size_t)n * 3, sizeof(double));
         double Wk[9] = {0};
         double *Wka = Va ? (double *)calloc((size_t)n * 9, sizeof(double)) : NULL;
@@ -971,6 +1018,13 @@ int oq_compute(const oq_hparams *hp, const oq_es *es, int n, const double *pos, 
             for (int b = 0; b < 3; ++b) Fl[3 * i + b] += Fst[3 * i + b];
             for (int a = 0; a < 3; ++a) Zl[9 * i + 4 * a] += qt[i];
         }
+        /* isolated system: Z_k = dP/dr_k with absolute positions (Eq. 27) and the
+           corrected charges, q~'_k I + sum_i (r_i - rbar) (x) dq~_i/dr_k */
+        double rbar[3] = {0, 0, 0};
+        if (!periodic) {
+            for (int i = 0; i < n; ++i)
+                for (int a = 0; a < 3; ++a) rbar[a] += pos[3 * i + a] / n;
+        }
         for (int pass = 0; pass < 2; ++pass) {
             oq_plist *L = pass == 0 ? LR : LA;
             size_t *off = pass == 0 ? offR : offA;
@@ -986,9 +1040,17 @@ int oq_compute(const oq_hparams *hp, const oq_es *es, int n, const double *pos, 
                             W[3 * a + b] -= fij[a] * pp->d[b];
                             /* per atom (Eq. 12): W_j += r_ji (x) F_ij */
                             if (Va) Va[9 * j + 3 * a + b] -= pp->d[a] * fij[b];
-                            double c = 0.5 * pp->d[a] * aij[b];
-                            Zl[9 * i + 3 * a + b] += c;
-                            Zl[9 * j + 3 * a + b] -= c;
+                            if (periodic) {
+                                /* Eq. 28 */
+                                double c = 0.5 * pp->d[a] * aij[b];
+                                Zl[9 * i + 3 * a + b] += c;
+                                Zl[9 * j + 3 * a + b] -= c;
+                            } else {
+                                /* dq~_i/dr_j = a_ij, dq~_i/dr_i = -sum_j a_ij */
+                                double c = (pos[3 * i + a] - rbar[a]) * aij[b];
+                                Zl[9 * j + 3 * a + b] += c;
+                                Zl[9 * i + 3 * a + b] -= c;
+                            }
                         }
                 }
         }

@@ -51,8 +51,8 @@ class QNEP:
     def n_theta(self) -> int:
         return B.qnep_param_count(self.hp)
 
-    def workspace_bytes(self, es, n_atoms: int, cell) -> int:
-        sysm = B.make_system(n_atoms, 0, 0, np.asarray(cell, dtype=np.float64))
+    def workspace_bytes(self, es, n_atoms: int, cell, periodic: bool = True) -> int:
+        sysm = B.make_system(n_atoms, 0, 0, np.asarray(cell, dtype=np.float64), periodic)
         return B.qnep_workspace_size(self.handle, B.make_es(es), sysm)
 
     def workspace(self, nbytes: int, device) -> torch.Tensor:
@@ -62,10 +62,11 @@ class QNEP:
 
     def compute(self, pos: torch.Tensor, types: torch.Tensor, cell, theta: torch.Tensor, es,
                 outputs=DEFAULT_OUTPUTS, out: Optional[Dict[str, torch.Tensor]] = None,
-                stream: Optional[torch.cuda.Stream] = None) -> Dict[str, torch.Tensor]:
+                stream: Optional[torch.cuda.Stream] = None, periodic: bool = True) -> Dict[str, torch.Tensor]:
         """pos: float32 device tensor [3, N] (SoA); types: int32 [N]; cell: (3, 3) rows a, b, c;
         theta: float32 device [n_theta].  Returns device tensors (energy, virial, polarization in
-        float64; forces [3, N]; bec [9, N]; charges [N]) enqueued on ``stream``."""
+        float64; forces [3, N]; bec [9, N]; charges [N]) enqueued on ``stream``.  periodic=False
+        evaluates an isolated system in the bounding box ``cell`` (es.method = 2)."""
         _require_gpu()
         assert pos.dtype == torch.float32 and pos.is_cuda and pos.dim() == 2 and pos.shape[0] == 3
         assert pos.is_contiguous() and types.dtype == torch.int32 and types.is_contiguous()
@@ -74,7 +75,7 @@ class QNEP:
         dev = pos.device
         cell = np.asarray(cell, dtype=np.float64)
         es_c = B.make_es(es)
-        sysm = B.make_system(n, pos.data_ptr(), types.data_ptr(), cell)
+        sysm = B.make_system(n, pos.data_ptr(), types.data_ptr(), cell, periodic)
         nbytes = B.qnep_workspace_size(self.handle, es_c, sysm)
         ws = self.workspace(nbytes, dev)
         if out is None:
@@ -139,7 +140,7 @@ def to_device_inputs(system, theta: np.ndarray, device="cuda"):
 
 
 def _backward(self, pos, types, cell, theta, es, gE: float = 1.0, gP=None, want=("pos", "cell", "theta"),
-              stream=None):
+              stream=None, periodic: bool = True):
     """Adjoint of ``compute`` for L = gE E + gP . P.  Returns a dict with
     ``pos`` ([3, N] float32, dL/dr), ``cell`` ([3, 3] float64, dE/dh at fixed positions;
     only with gP = 0, the library rejects the cell derivative of P) and ``theta`` ([n_theta] float32, exact dL/dtheta), all device tensors."""
@@ -148,7 +149,7 @@ def _backward(self, pos, types, cell, theta, es, gE: float = 1.0, gP=None, want=
     dev = pos.device
     cell = np.asarray(cell, dtype=np.float64)
     es_c = B.make_es(es)
-    sysm = B.make_system(n, pos.data_ptr(), types.data_ptr(), cell)
+    sysm = B.make_system(n, pos.data_ptr(), types.data_ptr(), cell, periodic)
     nbytes = B.qnep_backward_workspace_size(self.handle, es_c, sysm)
     ws = self.workspace(nbytes, dev)
     out = {}

@@ -6,6 +6,7 @@ from __future__ import annotations
 import ctypes as C
 import os
 
+import numpy as np
 import torch  # loads the HIP runtime that libqnep.so links against
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -20,6 +21,9 @@ FLAG_RADIAL_OVERFLOW = 1
 FLAG_ANGULAR_OVERFLOW = 2
 FLAG_COULOMB_OVERFLOW = 4
 FLAG_BAD_SPECIES = 8
+FLAG_OUTSIDE = 32
+FLAG_IMAGE = 64
+QNEP_ES_DIRECT = 2
 
 
 class qnep_hparams(C.Structure):
@@ -35,7 +39,8 @@ class qnep_es_params(C.Structure):
 
 
 class qnep_system(C.Structure):
-    _fields_ = [("n_atoms", C.c_int64), ("pos", C.c_void_p), ("type", C.c_void_p), ("cell", C.c_double * 9)]
+    _fields_ = [("n_atoms", C.c_int64), ("pos", C.c_void_p), ("type", C.c_void_p), ("cell", C.c_double * 9),
+                ("pbc", C.c_int32 * 3)]
 
 
 class qnep_outputs(C.Structure):
@@ -118,9 +123,10 @@ def make_es(es) -> qnep_es_params:
                           int(es.kmax_inclusive), mesh, int(es.order), float(es.q_total), field)
 
 
-def make_system(n: int, pos_ptr: int, type_ptr: int, cell) -> qnep_system:
-    c = (C.c_double * 9)(*[float(v) for v in list(cell.reshape(-1))])
-    return qnep_system(int(n), C.c_void_p(pos_ptr), C.c_void_p(type_ptr), c)
+def make_system(n: int, pos_ptr: int, type_ptr: int, cell, periodic: bool = True) -> qnep_system:
+    c = (C.c_double * 9)(*[float(v) for v in list(np.asarray(cell).reshape(-1))])
+    p = (C.c_int32 * 3)(*([1, 1, 1] if periodic else [0, 0, 0]))
+    return qnep_system(int(n), C.c_void_p(pos_ptr), C.c_void_p(type_ptr), c, p)
 
 
 def qnep_param_count(hp) -> int:

@@ -225,11 +225,20 @@ qnep_status make_plan(const Model &m, const qnep_es_params *es, const qnep_syste
     p.off_b1E = p.off_nn + p.T * p.per_species;
     p.off_s = p.off_b1E + 1;
     p.n_theta = p.off_s + 1;
-    if (es->mode != 1 && es->mode != 2) return fail(QNEP_E_INVALID_ARG, "mode must be 1 or 2");
-    if (es->method != 0 && es->method != 1) return fail(QNEP_E_INVALID_ARG, "method must be 0 (Ewald) or 1 (PPPM)");
-    if (!(es->alpha > 0)) return fail(QNEP_E_INVALID_ARG, "alpha must be positive");
-    if (es->mode == 1 && !(es->rc_coul > 0)) return fail(QNEP_E_INVALID_ARG, "rc_coul must be positive");
-    p.mode = es->mode;
+    const int np = (sys->pbc[0] != 0) + (sys->pbc[1] != 0) + (sys->pbc[2] != 0);
+    if (np != 0 && np != 3) return fail(QNEP_E_UNSUPPORTED, "pbc must be {1,1,1} or {0,0,0}");
+    p.iso = np == 0 ? 1 : 0;
+    if (p.iso) {
+        if (es->method != QNEP_ES_DIRECT)
+            return fail(QNEP_E_INVALID_ARG, "an isolated system (pbc = 0) takes method QNEP_ES_DIRECT");
+    } else {
+        if (es->mode != 1 && es->mode != 2) return fail(QNEP_E_INVALID_ARG, "mode must be 1 or 2");
+        if (es->method != 0 && es->method != 1)
+            return fail(QNEP_E_INVALID_ARG, "a periodic system takes method 0 (Ewald) or 1 (PPPM)");
+        if (!(es->alpha > 0)) return fail(QNEP_E_INVALID_ARG, "alpha must be positive");
+        if (es->mode == 1 && !(es->rc_coul > 0)) return fail(QNEP_E_INVALID_ARG, "rc_coul must be positive");
+    }
+    p.mode = p.iso ? 1 : es->mode;
     p.method = es->method;
     p.alpha = es->alpha;
     p.rc_coul = es->rc_coul;
@@ -253,20 +262,29 @@ qnep_status make_plan(const Model &m, const qnep_es_params *es, const qnep_syste
     for (int a = 0; a < 3; ++a) {
         p.nc[a] = std::max(1, (int)std::floor(w[a] / (a == 2 ? 0.5 * rbin : rbin)));
         p.mR[a] = (int)std::ceil(std::max(p.rcR, p.rcA) * p.nc[a] / w[a] - 1e-12);
-        p.mC[a] = (int)std::ceil(p.rc_coul * p.nc[a] / w[a] - 1e-12);
+        p.mC[a] = p.iso ? 1 : (int)std::ceil(p.rc_coul * p.nc[a] / w[a] - 1e-12);
         if (p.mR[a] < 1) p.mR[a] = 1;
         if (p.mC[a] < 1) p.mC[a] = 1;
         if (p.mR[a] > 3 * p.nc[a] || (p.mode == 1 && p.mC[a] > 3 * p.nc[a]))
             return fail(QNEP_E_UNSUPPORTED, "cell thinner than a third of a cutoff along an axis");
     }
     p.ncell = p.nc[0] * p.nc[1] * p.nc[2];
-    const double density = p.N / p.vol;
+    // an isolated system's box is mostly empty: its mean density says nothing about the
+    // local one, so a condensed-matter density (0.15 per cubic Angstrom) is assumed, and
+    // no atom can have more than N - 1 neighbours
+    const double density = p.iso ? std::max(p.N / p.vol, 0.15) : p.N / p.vol;
     p.capR = capacity(density, p.rcR, m.cap_factor);
     p.capA = capacity(density, p.rcA, m.cap_factor);
+    if (p.iso) {  // capacities stay multiples of 8 (rows are read in 16- and 32-byte pieces)
+        p.capR = std::max(8, std::min(p.capR, (p.N + 7) / 8 * 8));
+        p.capA = std::max(8, std::min(p.capA, (p.N + 7) / 8 * 8));
+    }
     p.nblk = (p.N + RED_THREADS - 1) / RED_THREADS;
     int64_t red_blocks = std::max(p.nblk, 1);
     red_blocks = std::max<int64_t>(red_blocks, ((int64_t)p.N * PARTIALS_LANES_MAX + RED_THREADS - 1) / RED_THREADS);
-    if (p.method == 0) {
+    if (p.iso) {
+        // the direct sum over all pairs: blocks of RED_THREADS atoms
+    } else if (p.method == 0) {
         if (!(p.kmax > 0)) return fail(QNEP_E_INVALID_ARG, "kmax must be positive for Ewald");
         for (int a = 0; a < 3; ++a) {
             const double *v = p.cell.h + 3 * a;
@@ -275,6 +293,8 @@ qnep_status make_plan(const Model &m, const qnep_es_params *es, const qnep_syste
         }
         int64_t nh = count_half_k(p.cell.hinv, p.nk_box[0], p.nk_box[1], p.nk_box[2], p.kmax, p.kinc);
         p.nk_cap = nh + 16;
+        // every row (n0, n1) of the box adds at most one segment beyond count / EW_SEG
+        p.seg_cap = (int64_t)(2 * p.nk_box[0] + 1) * (2 * p.nk_box[1] + 1) + p.nk_cap / 32 + 16;
         p.s_chunks = std::max(1, (p.N + 511) / 512);
         red_blocks = std::max<int64_t>(red_blocks, (p.nk_cap + 255) / 256);
     } else {
@@ -326,9 +346,14 @@ qnep_status make_plan(const Model &m, const qnep_es_params *es, const qnep_syste
     p.Fnep = c.take<float>(3 * (size_t)N);
     p.Znep = c.take<float>(9 * (size_t)N);
     p.Vat = c.take<float>(6 * (size_t)N);
-    if (p.method == 0) {
+    p.Siso = c.take<float>(p.iso ? 3 * (size_t)N : 1);
+    if (p.iso) {
+    } else if (p.method == 0) {
         p.kvec = c.take<float4>(2 * (size_t)p.nk_cap);  // kv then kn (int4)
         p.kcount = c.take<int>(1);
+        p.ksegs = c.take<int4>(p.seg_cap);
+        p.ksegoff = c.take<int>(p.seg_cap);
+        p.knseg = c.take<int>(1);
         p.Spart = c.take<float2>((size_t)p.s_chunks * p.nk_cap);
         p.Sk = c.take<float2>(p.nk_cap);
     } else {
@@ -380,12 +405,17 @@ hipError_t run_forward(Plan &p) {
     FW_TRY(launch_mlp(p));
     FW_TRY(launch_charges(p));
     stage_mark(p, ST_MLP, 3);
-    FW_TRY(launch_real_space(p));  // marks the real-space kernel itself
-    stage_mark(p, ST_OTHER, 1);
-    if (p.method == 0) {
-        FW_TRY(launch_ewald(p));
+    if (p.iso) {
+        FW_TRY(launch_direct_coulomb(p));
+        FW_TRY(launch_centroid(p));
     } else {
-        FW_TRY(launch_pppm(p));
+        FW_TRY(launch_real_space(p));  // marks the real-space kernel itself
+        stage_mark(p, ST_OTHER, 1);
+        if (p.method == 0) {
+            FW_TRY(launch_ewald(p));
+        } else {
+            FW_TRY(launch_pppm(p));
+        }
     }
     FW_TRY(launch_phi_mean(p));
     stage_mark(p, ST_PHI, 3);
@@ -736,7 +766,7 @@ struct MdBuffers {
 qnep_status md_layout(const Model &m, const qnep_es_params *es, int64_t n_atoms, const double *cell, char *ws,
                       Plan &p, MdBuffers &b, size_t *bytes) {
     if (!cell) return fail(QNEP_E_INVALID_ARG, "null cell");
-    qnep_system sys{n_atoms, nullptr, nullptr, {0}};
+    qnep_system sys{n_atoms, nullptr, nullptr, {0}, {1, 1, 1}};
     std::memcpy(sys.cell, cell, sizeof(double) * 9);
     size_t need = 0;
     qnep_status s = make_plan(m, es, &sys, ws, p, &need);

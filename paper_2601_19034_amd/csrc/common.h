@@ -342,7 +342,8 @@ enum ScalarSlot : int {
     S_PHIBAR = 25,         // mean phi
     S_WNEP = 26,           // 9: many-body virial from the partial forces
     S_POL = 35,            // 3: polarization
-    S_COUNT = 38
+    S_CENT = 38,           // 3: centroid of the caller's positions (isolated systems)
+    S_COUNT = 41
 };
 
 }  // namespace qnep

@@ -159,60 +159,108 @@ hipError_t launch_real_space(const Plan &p) {
     return reduce_partials(p, G, 11, S_UREAL, false);  // S_UREAL, S_QSQ, S_WREAL[9]
 }
 
-// ---------------------------------------------------------------- Ewald
-// Builds the half set {n : n3 > 0, or n3 = 0 and n2 > 0, or n3 = n2 = 0 and n1 > 0}
-// with |k| within kmax, k = 2 pi h^{-1} n, in box order (deterministic).  One block.
-__global__ void k_kvectors(Cell c, int M0, int M1, int M2, double kmax2, int inclusive, double alpha,
-                           double vol, int64_t cap, float4 *__restrict__ kv, int4 *__restrict__ kn,
-                           int *__restrict__ kcount) {
-    __shared__ int scan[1024];
-    __shared__ int base;
-    if (threadIdx.x == 0) base = 0;
-    __syncthreads();
-    const int n0 = 2 * M0 + 1, n1w = 2 * M1 + 1;
-    const int64_t total = (int64_t)n0 * n1w * (M2 + 1);
-    for (int64_t b = 0; b < total; b += 1024) {
-        int64_t idx = b + threadIdx.x;
-        int keep = 0;
-        int a0 = 0, a1 = 0, a2 = 0;
-        double kx = 0, ky = 0, kz = 0, k2 = 0;
-        if (idx < total) {
-            a2 = (int)(idx / ((int64_t)n0 * n1w));
-            int rem = (int)(idx % ((int64_t)n0 * n1w));
-            a1 = rem / n0 - M1;
-            a0 = rem % n0 - M0;
-            bool half = a2 > 0 || (a2 == 0 && (a1 > 0 || (a1 == 0 && a0 > 0)));
-            if (half) {
-                kx = 2.0 * PI_D * (c.hinv[0] * a0 + c.hinv[1] * a1 + c.hinv[2] * a2);
-                ky = 2.0 * PI_D * (c.hinv[3] * a0 + c.hinv[4] * a1 + c.hinv[5] * a2);
-                kz = 2.0 * PI_D * (c.hinv[6] * a0 + c.hinv[7] * a1 + c.hinv[8] * a2);
-                k2 = kx * kx + ky * ky + kz * kz;
-                keep = inclusive ? (k2 <= kmax2 * (1.0 + 1e-9)) : (k2 < kmax2 * (1.0 - 1e-9));
-            }
-        }
-        scan[threadIdx.x] = keep;
+// ---------------------------------------------------------------- isolated systems
+// Plain Coulomb sum over all pairs of an isolated system (the real-space sum of Eq. 6
+// without the splitting and without images): phi_i = k_e sum_{j != i} q'_j / r_ij, the
+// static pair forces and the pair virial, each thread one atom against tiles of all
+// atoms staged in LDS.  Writes the same outputs and partials as the real-space kernel.
+constexpr int DC_TILE = 256;
+
+__global__ __launch_bounds__(256) void k_direct_coulomb(int N, const float4 *__restrict__ xyzq,
+                                                        const float *__restrict__ qraw,
+                                                        const double *__restrict__ scalars,
+                                                        float *__restrict__ phi, float *__restrict__ Fst,
+                                                        float *__restrict__ Vat, double *__restrict__ partials) {
+    __shared__ float4 tile[DC_TILE];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = i < N;
+    const float4 pi = xyzq[live ? i : 0];
+    float acc[10];  // phi, B r (3), B r r (xx yy zz xy xz yz)
+#pragma unroll
+    for (int k = 0; k < 10; ++k) acc[k] = 0.f;
+    for (int t0 = 0; t0 < N; t0 += DC_TILE) {
         __syncthreads();
-        for (int o = 1; o < 1024; o <<= 1) {
-            int t = threadIdx.x >= (unsigned)o ? scan[threadIdx.x - o] : 0;
-            __syncthreads();
-            scan[threadIdx.x] += t;
-            __syncthreads();
-        }
-        if (keep) {
-            int64_t pos = base + scan[threadIdx.x] - 1;
-            if (pos < cap) {
-                double G = 2.0 * PI_D / vol * exp(-k2 / (4.0 * alpha * alpha)) / k2;
-                kv[pos] = make_float4((float)kx, (float)ky, (float)kz, (float)G);
-                kn[pos] = make_int4(a0, a1, a2, 0);
-            }
-        }
+        const int j0 = t0 + threadIdx.x;
+        tile[threadIdx.x] = j0 < N ? xyzq[j0] : make_float4(0.f, 0.f, 0.f, 0.f);
         __syncthreads();
-        if (threadIdx.x == 1023) base += scan[1023];
-        __syncthreads();
+        const int m = min(DC_TILE, N - t0);
+        for (int u = 0; u < m; ++u) {
+            const float4 pj = tile[u];
+            const float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            const bool other = t0 + u != i;
+            const float qj = other ? pj.w : 0.0f;
+            const float ir = __builtin_amdgcn_rsqf(other ? r2 : 1.0f);
+            acc[0] = fmaf(qj, ir, acc[0]);
+            const float B = qj * ir * ir * ir;
+            const float bx = B * dx, by = B * dy, bz = B * dz;
+            acc[1] += bx;
+            acc[2] += by;
+            acc[3] += bz;
+            acc[4] = fmaf(bx, dx, acc[4]);
+            acc[5] = fmaf(by, dy, acc[5]);
+            acc[6] = fmaf(bz, dz, acc[6]);
+            acc[7] = fmaf(bx, dy, acc[7]);
+            acc[8] = fmaf(bx, dz, acc[8]);
+            acc[9] = fmaf(by, dz, acc[9]);
+        }
     }
-    if (threadIdx.x == 0) *kcount = base < cap ? base : (int)cap;
+    double red[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (live) {
+        const float qi = qraw[i] + (float)scalars[S_DELTA];
+        const float ke = (float)KE;
+        phi[i] = ke * acc[0];
+        Fst[i] = -ke * qi * acc[1];
+        Fst[(size_t)N + i] = -ke * qi * acc[2];
+        Fst[(size_t)2 * N + i] = -ke * qi * acc[3];
+        red[0] = 0.5 * (double)qi * (double)(ke * acc[0]);
+        const double hw = 0.5 * KE * (double)qi;
+        red[2] = hw * acc[4]; red[3] = hw * acc[7]; red[4] = hw * acc[8];
+        red[5] = hw * acc[7]; red[6] = hw * acc[5]; red[7] = hw * acc[9];
+        red[8] = hw * acc[8]; red[9] = hw * acc[9]; red[10] = hw * acc[6];
+        if (Vat) {
+            const float hwf = 0.5f * ke * qi;
+            Vat[i] = hwf * acc[4];
+            Vat[(size_t)N + i] = hwf * acc[5];
+            Vat[(size_t)2 * N + i] = hwf * acc[6];
+            Vat[(size_t)3 * N + i] = hwf * acc[7];
+            Vat[(size_t)4 * N + i] = hwf * acc[8];
+            Vat[(size_t)5 * N + i] = hwf * acc[9];
+        }
+    }
+    block_partials<11>(red, partials);
 }
 
+hipError_t launch_direct_coulomb(const Plan &p) {
+    hipLaunchKernelGGL(k_pack_charges, dim3((p.N + 255) / 256), dim3(256), 0, p.stream, p.N, p.xyzt, p.qraw,
+                       p.scalars, p.xyzq);
+    const int G = (p.N + 255) / 256;
+    hipLaunchKernelGGL(k_direct_coulomb, dim3(G), dim3(256), 0, p.stream, p.N, p.xyzq, p.qraw, p.scalars, p.phi,
+                       p.Fst, p.out.virial_atom ? p.Vat : nullptr, p.partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    stage_mark(p, ST_REAL, 2);
+    return reduce_partials(p, G, 11, S_UREAL, false);  // S_UREAL, S_QSQ (zero: no self term), S_WREAL[9]
+}
+
+// FP64 partials of the centroid of the caller's positions (Born charges of an isolated system)
+__global__ __launch_bounds__(256) void k_centroid(int N, const float *__restrict__ pos, double *__restrict__ partials) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double red[3] = {0.0, 0.0, 0.0};
+    if (i < N)
+        for (int a = 0; a < 3; ++a) red[a] = (double)pos[(size_t)a * N + i];
+    block_partials<3>(red, partials);
+}
+
+hipError_t launch_centroid(const Plan &p) {
+    const int G = (p.N + 255) / 256;
+    hipLaunchKernelGGL(k_centroid, dim3(G), dim3(256), 0, p.stream, p.N, p.pos, p.partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return reduce_partials(p, G, 3, S_CENT, false);  // sums; the assembly divides by N
+}
+
+// ---------------------------------------------------------------- Ewald
 // fractional coordinates wrapped to [0, 1) in FP64
 __device__ inline void frac_coords(double x, double y, double z, const Cell &c, double &s0, double &s1,
                                    double &s2) {
@@ -231,47 +279,157 @@ __device__ inline void phase_cs(int n0, int n1, int n2, double s0, double s1, do
     sincospif(2.0f * (float)t, &sn, &cs);
 }
 
+// The half set in rows: for every (n0, n1) the wave vectors with consecutive n2 are
+// stored consecutively and described by row segments of at most EW_SEG entries,
+// (n0, n1, first n2, count) and the index of their first wave vector.  Along a segment
+// the phase 2 pi n.s of an atom advances by 2 pi s2 per entry, so it is formed once per
+// (segment, atom) and then carried by a complex rotation.  One block.
+constexpr int EW_SEG = 32;
+
+__global__ void k_kvector_rows(Cell c, int M0, int M1, int M2, double kmax2, int inclusive, double alpha,
+                               double vol, int64_t cap, int64_t seg_cap, float4 *__restrict__ kv,
+                               int4 *__restrict__ kn, int4 *__restrict__ segs, int *__restrict__ segoff,
+                               int *__restrict__ kcount, int *__restrict__ nseg) {
+    __shared__ int scan_k[1024], scan_s[1024];
+    __shared__ int base_k, base_s;
+    if (threadIdx.x == 0) base_k = base_s = 0;
+    __syncthreads();
+    const int n0w = 2 * M0 + 1, n1w = 2 * M1 + 1;
+    const int rows = n0w * n1w;
+    for (int r0 = 0; r0 < rows; r0 += 1024) {
+        const int r = r0 + threadIdx.x;
+        int a0 = 0, a1 = 0, lo = 0, cnt = 0;
+        if (r < rows) {
+            a1 = r / n0w - M1;
+            a0 = r % n0w - M0;
+            // half set: n2 > 0, or n2 = 0 with (n1 > 0, or n1 = 0 and n0 > 0)
+            const int first = (a1 > 0 || (a1 == 0 && a0 > 0)) ? 0 : 1;
+            int hi = -1;
+            lo = -1;
+            for (int a2 = first; a2 <= M2; ++a2) {  // |k|^2 is convex in n2: one interval
+                const double kx = 2.0 * PI_D * (c.hinv[0] * a0 + c.hinv[1] * a1 + c.hinv[2] * a2);
+                const double ky = 2.0 * PI_D * (c.hinv[3] * a0 + c.hinv[4] * a1 + c.hinv[5] * a2);
+                const double kz = 2.0 * PI_D * (c.hinv[6] * a0 + c.hinv[7] * a1 + c.hinv[8] * a2);
+                const double k2 = kx * kx + ky * ky + kz * kz;
+                const bool keep = inclusive ? (k2 <= kmax2 * (1.0 + 1e-9)) : (k2 < kmax2 * (1.0 - 1e-9));
+                if (keep) {
+                    if (lo < 0) lo = a2;
+                    hi = a2;
+                }
+            }
+            cnt = lo < 0 ? 0 : hi - lo + 1;
+        }
+        const int ns = (cnt + EW_SEG - 1) / EW_SEG;
+        scan_k[threadIdx.x] = cnt;
+        scan_s[threadIdx.x] = ns;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            const int tk = threadIdx.x >= (unsigned)o ? scan_k[threadIdx.x - o] : 0;
+            const int ts = threadIdx.x >= (unsigned)o ? scan_s[threadIdx.x - o] : 0;
+            __syncthreads();
+            scan_k[threadIdx.x] += tk;
+            scan_s[threadIdx.x] += ts;
+            __syncthreads();
+        }
+        const int kb = base_k + scan_k[threadIdx.x] - cnt, sb = base_s + scan_s[threadIdx.x] - ns;
+        for (int m = 0; m < cnt; ++m) {
+            const int64_t pos = (int64_t)kb + m;
+            if (pos >= cap) break;
+            const int a2 = lo + m;
+            const double kx = 2.0 * PI_D * (c.hinv[0] * a0 + c.hinv[1] * a1 + c.hinv[2] * a2);
+            const double ky = 2.0 * PI_D * (c.hinv[3] * a0 + c.hinv[4] * a1 + c.hinv[5] * a2);
+            const double kz = 2.0 * PI_D * (c.hinv[6] * a0 + c.hinv[7] * a1 + c.hinv[8] * a2);
+            const double k2 = kx * kx + ky * ky + kz * kz;
+            const double G = 2.0 * PI_D / vol * exp(-k2 / (4.0 * alpha * alpha)) / k2;
+            kv[pos] = make_float4((float)kx, (float)ky, (float)kz, (float)G);
+            kn[pos] = make_int4(a0, a1, a2, 0);
+        }
+        for (int q = 0; q < ns; ++q) {
+            const int m0 = q * EW_SEG, len = min(EW_SEG, cnt - m0);
+            if (sb + q >= seg_cap) break;
+            // a segment past the wave-vector capacity is emptied (never happens when the
+            // host count and this one agree, which they do up to the same tie rule)
+            const bool fits = (int64_t)kb + m0 + len <= cap;
+            segs[sb + q] = make_int4(a0, a1, lo + m0, fits ? len : 0);
+            segoff[sb + q] = fits ? kb + m0 : 0;
+        }
+        __syncthreads();
+        if (threadIdx.x == 1023) {
+            base_k += scan_k[1023];
+            base_s += scan_s[1023];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *kcount = base_k < cap ? base_k : (int)cap;
+        *nseg = base_s < seg_cap ? base_s : (int)seg_cap;
+    }
+}
+
 constexpr int EW_CHUNK = 512;
 
-// partial structure factors: block (kb, chunk); each thread owns one wave vector
-__global__ __launch_bounds__(256) void k_structure_factor(int N, const float4 *__restrict__ xyzt, Cell c,
-                                                          const float *__restrict__ qraw,
-                                                          const double *__restrict__ scalars,
-                                                          const int4 *__restrict__ kn,
-                                                          const int *__restrict__ kcount, int64_t cap,
-                                                          float2 *__restrict__ Spart) {
+// partial structure factors by row segments: block (segment block, atom chunk); each
+// thread owns one segment and carries every atom's phase along it
+__global__ __launch_bounds__(256) void k_structure_factor_rows(int N, const float4 *__restrict__ xyzt, Cell c,
+                                                               const float *__restrict__ qraw,
+                                                               const double *__restrict__ scalars,
+                                                               const int4 *__restrict__ segs,
+                                                               const int *__restrict__ segoff,
+                                                               const int *__restrict__ nseg, int64_t cap,
+                                                               float2 *__restrict__ Spart) {
     __shared__ double sx[256], sy[256], sz[256];
     __shared__ float sq[256];
-    const int nk = *kcount;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    const int a0 = blockIdx.y * EW_CHUNK, a1 = min(N, a0 + EW_CHUNK);
+    __shared__ float2 st[256];  // (cos, sin) of 2 pi s2: the rotation along a segment
+    const int ns = *nseg;
+    const int sg = blockIdx.x * blockDim.x + threadIdx.x;
+    const int4 g = sg < ns ? segs[sg] : make_int4(0, 0, 0, 0);
     const float delta = (float)scalars[S_DELTA];
-    int4 n = k < nk ? kn[k] : make_int4(0, 0, 0, 0);
-    float re = 0.f, im = 0.f;
+    float re[EW_SEG], im[EW_SEG];
+#pragma unroll
+    for (int m = 0; m < EW_SEG; ++m) re[m] = im[m] = 0.f;
+    const int a0 = blockIdx.y * EW_CHUNK, a1 = min(N, a0 + EW_CHUNK);
     for (int t0 = a0; t0 < a1; t0 += 256) {
-        int a = t0 + threadIdx.x;
+        __syncthreads();
+        const int a = t0 + threadIdx.x;
         if (a < a1) {
-            double s0, s1, s2;
             const float4 pa = xyzt[a];
+            double s0, s1, s2;
             frac_coords(pa.x, pa.y, pa.z, c, s0, s1, s2);
             sx[threadIdx.x] = s0;
             sy[threadIdx.x] = s1;
             sz[threadIdx.x] = s2;
             sq[threadIdx.x] = qraw[a] + delta;
+            float cs, sn;
+            phase_cs(0, 0, 1, s0, s1, s2, cs, sn);
+            st[threadIdx.x] = make_float2(cs, sn);
         }
         __syncthreads();
         const int m = min(256, a1 - t0);
-        if (k < nk) {
+        if (sg < ns) {
             for (int u = 0; u < m; ++u) {
                 float cs, sn;
-                phase_cs(n.x, n.y, n.z, sx[u], sy[u], sz[u], cs, sn);
-                re = fmaf(sq[u], cs, re);
-                im = fmaf(-sq[u], sn, im);
+                phase_cs(g.x, g.y, g.z, sx[u], sy[u], sz[u], cs, sn);
+                const float q = sq[u];
+                const float2 r = st[u];
+#pragma unroll
+                for (int e = 0; e < EW_SEG; ++e) {
+                    if (e < g.w) {
+                        re[e] = fmaf(q, cs, re[e]);
+                        im[e] = fmaf(-q, sn, im[e]);
+                        const float c2 = fmaf(cs, r.x, -sn * r.y);
+                        sn = fmaf(sn, r.x, cs * r.y);
+                        cs = c2;
+                    }
+                }
             }
         }
-        __syncthreads();
     }
-    if (k < nk) Spart[(size_t)blockIdx.y * cap + k] = make_float2(re, im);
+    if (sg < ns) {
+        const int k0 = segoff[sg];
+#pragma unroll
+        for (int e = 0; e < EW_SEG; ++e)
+            if (e < g.w) Spart[(size_t)blockIdx.y * cap + k0 + e] = make_float2(re[e], im[e]);
+    }
 }
 
 // S(k) = sum over chunks (FP64); energy 2 k_e G |S|^2 and virial 2 k_e G |S|^2 B(k)
@@ -307,49 +465,47 @@ __global__ __launch_bounds__(256) void k_structure_reduce(int nchunks, const flo
 }
 
 // phi^k_i = 4 k_e sum_half G Re[S e^{i k.r_i}],  F^k_i = 4 k_e q'_i sum_half k G Im[S e^{i k.r_i}]
-__global__ __launch_bounds__(256) void k_ewald_atoms(int N, const float4 *__restrict__ xyzt, Cell c,
-                                                     const float *__restrict__ qraw,
-                                                     const double *__restrict__ scalars,
-                                                     const float4 *__restrict__ kv, const int4 *__restrict__ kn,
-                                                     const float2 *__restrict__ Sk, const int *__restrict__ kcount,
-                                                     float *__restrict__ phi, float *__restrict__ Fst) {
-    __shared__ int4 ln[256];
-    __shared__ float4 lk[256];
-    __shared__ float2 ls[256];
-    const int nk = *kcount;
+// by row segments: the segment and wave-vector data are uniform across the block
+// (scalar loads); each atom's phase is formed once per segment and rotated by 2 pi s2
+// along it.
+__global__ __launch_bounds__(256) void k_ewald_atoms_rows(int N, const float4 *__restrict__ xyzt, Cell c,
+                                                          const float *__restrict__ qraw,
+                                                          const double *__restrict__ scalars,
+                                                          const float4 *__restrict__ kv,
+                                                          const int4 *__restrict__ segs,
+                                                          const int *__restrict__ segoff,
+                                                          const int *__restrict__ nseg,
+                                                          const float2 *__restrict__ Sk,
+                                                          float *__restrict__ phi, float *__restrict__ Fst) {
+    const int ns = *nseg;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double s0 = 0, s1 = 0, s2 = 0;
     if (i < N) {
         const float4 pa = xyzt[i];
         frac_coords(pa.x, pa.y, pa.z, c, s0, s1, s2);
     }
+    float rc, rs;
+    phase_cs(0, 0, 1, s0, s1, s2, rc, rs);
     float ph = 0.f, fx = 0.f, fy = 0.f, fz = 0.f;
-    for (int t0 = 0; t0 < nk; t0 += 256) {
-        int k = t0 + threadIdx.x;
-        if (k < nk) {
-            ln[threadIdx.x] = kn[k];
-            lk[threadIdx.x] = kv[k];
-            ls[threadIdx.x] = Sk[k];
+    for (int sg = 0; sg < ns; ++sg) {
+        const int4 g = segs[sg];
+        const int k0 = segoff[sg];
+        float cs, sn;
+        phase_cs(g.x, g.y, g.z, s0, s1, s2, cs, sn);
+        for (int e = 0; e < g.w; ++e) {
+            const float2 S = Sk[k0 + e];
+            const float4 q = kv[k0 + e];
+            const float re = S.x * cs - S.y * sn;
+            const float im = S.x * sn + S.y * cs;
+            ph = fmaf(q.w, re, ph);
+            const float gi = q.w * im;
+            fx = fmaf(q.x, gi, fx);
+            fy = fmaf(q.y, gi, fy);
+            fz = fmaf(q.z, gi, fz);
+            const float c2 = fmaf(cs, rc, -sn * rs);
+            sn = fmaf(sn, rc, cs * rs);
+            cs = c2;
         }
-        __syncthreads();
-        const int m = min(256, nk - t0);
-        if (i < N) {
-            for (int u = 0; u < m; ++u) {
-                float cs, sn;
-                int4 n = ln[u];
-                phase_cs(n.x, n.y, n.z, s0, s1, s2, cs, sn);
-                float2 S = ls[u];
-                float4 q = lk[u];
-                float re = S.x * cs - S.y * sn;
-                float im = S.x * sn + S.y * cs;
-                ph = fmaf(q.w, re, ph);
-                float gi = q.w * im;
-                fx = fmaf(q.x, gi, fx);
-                fy = fmaf(q.y, gi, fy);
-                fz = fmaf(q.z, gi, fz);
-            }
-        }
-        __syncthreads();
     }
     if (i < N) {
         const float qi = qraw[i] + (float)scalars[S_DELTA];
@@ -420,11 +576,13 @@ __global__ __launch_bounds__(256) void k_ewald_virial_atoms(int N, const float4 
 
 hipError_t launch_ewald(const Plan &p) {
     int4 *kn = (int4 *)(p.kvec + p.nk_cap);
-    hipLaunchKernelGGL(k_kvectors, dim3(1), dim3(1024), 0, p.stream, p.cell, p.nk_box[0], p.nk_box[1],
-                       p.nk_box[2], p.kmax * p.kmax, p.kinc, p.alpha, p.vol, p.nk_cap, p.kvec, kn, p.kcount);
+    hipLaunchKernelGGL(k_kvector_rows, dim3(1), dim3(1024), 0, p.stream, p.cell, p.nk_box[0], p.nk_box[1],
+                       p.nk_box[2], p.kmax * p.kmax, p.kinc, p.alpha, p.vol, p.nk_cap, p.seg_cap, p.kvec, kn,
+                       p.ksegs, p.ksegoff, p.kcount, p.knseg);
     const int kb = (int)((p.nk_cap + 255) / 256);
-    hipLaunchKernelGGL(k_structure_factor, dim3(kb, p.s_chunks), dim3(256), 0, p.stream, p.N, p.xyzt,
-                       p.cell, p.qraw, p.scalars, (const int4 *)kn, p.kcount, p.nk_cap, p.Spart);
+    const int sbk = (int)((p.seg_cap + 255) / 256);
+    hipLaunchKernelGGL(k_structure_factor_rows, dim3(sbk, p.s_chunks), dim3(256), 0, p.stream, p.N, p.xyzt,
+                       p.cell, p.qraw, p.scalars, p.ksegs, p.ksegoff, p.knseg, p.nk_cap, p.Spart);
     hipLaunchKernelGGL(k_structure_reduce, dim3(kb), dim3(256), 0, p.stream, p.s_chunks, p.Spart, p.kvec,
                        p.kcount, p.nk_cap, p.alpha, p.Sk, p.partials);
     hipError_t e = hipGetLastError();
@@ -433,8 +591,8 @@ hipError_t launch_ewald(const Plan &p) {
     if (e != hipSuccess) return e;
     stage_mark(p, ST_EWALD_SK, 4);
     const int G = (p.N + 255) / 256;
-    hipLaunchKernelGGL(k_ewald_atoms, dim3(G), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, p.qraw,
-                       p.scalars, p.kvec, (const int4 *)kn, p.Sk, p.kcount, p.phi, p.Fst);
+    hipLaunchKernelGGL(k_ewald_atoms_rows, dim3(G), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, p.qraw,
+                       p.scalars, p.kvec, p.ksegs, p.ksegoff, p.knseg, p.Sk, p.phi, p.Fst);
     if (p.out.virial_atom)
         hipLaunchKernelGGL(k_ewald_virial_atoms, dim3(G), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell,
                            (float)p.alpha, p.qraw, p.scalars, p.kvec, (const int4 *)kn, p.Sk, p.kcount, p.Vat);
@@ -472,7 +630,7 @@ __global__ void k_phi_mean(int N, double *__restrict__ scalars) {
 
 hipError_t launch_phi_mean(const Plan &p) {
     const int G = (p.N + 255) / 256;
-    hipLaunchKernelGGL(k_phi_total, dim3(G), dim3(256), 0, p.stream, p.N, p.mode, (float)p.alpha, p.vol, p.qtot,
+    hipLaunchKernelGGL(k_phi_total, dim3(G), dim3(256), 0, p.stream, p.N, p.iso ? 0 : p.mode, (float)p.alpha, p.vol, p.qtot,
                        p.qraw, p.scalars, p.theta, p.off_s, p.phi, p.partials);
     hipError_t e = reduce_partials(p, G, 1, S_SUMPHI, false);
     if (e != hipSuccess) return e;

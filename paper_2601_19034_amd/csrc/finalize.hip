@@ -1,12 +1,13 @@
 // Global scalars of the evaluation, assembled in FP64:
 //   E = U_NEP + U_ES (Eqs. 2-4), U_ES = U_r + U_k + U_s (+ background) in mode 1 or
-//   U_k in mode 2 (Eq. 5); W = static real + reciprocal + many-body partial-force
+//   U_k in mode 2 (Eq. 5), the direct Coulomb sum for an isolated system; W = static
+//   real + reciprocal + many-body partial-force
 //   virial (+ background); P = sum_i q~'_i r_i (Eq. 26).
 #include "plan.h"
 
 namespace qnep {
 
-__global__ void k_finalize(int mode, double alpha, double vol, double qtot, const float *__restrict__ theta,
+__global__ void k_finalize(int mode, int iso, double alpha, double vol, double qtot, const float *__restrict__ theta,
                            int64_t off_s, const double *__restrict__ scalars, const int *__restrict__ kcount,
                            double nk_default, double *__restrict__ energy, double *__restrict__ virial,
                            double *__restrict__ pol, double *__restrict__ terms) {
@@ -15,7 +16,10 @@ __global__ void k_finalize(int mode, double alpha, double vol, double qtot, cons
     double Ur = 0, Us = 0, Ubg = 0;
     double W[9];
     for (int k = 0; k < 9; ++k) W[k] = scalars[S_WK + k] + scalars[S_WNEP + k];
-    if (mode == 1) {
+    if (iso) {  // direct Coulomb sum: no self or background term
+        Ur = scalars[S_UREAL];
+        for (int k = 0; k < 9; ++k) W[k] += scalars[S_WREAL + k];
+    } else if (mode == 1) {
         Ur = scalars[S_UREAL];
         Us = -KE * alpha / sqrt(PI_D) * scalars[S_QSQ];
         const double Qs = qtot / s;
@@ -44,10 +48,10 @@ __global__ void k_finalize(int mode, double alpha, double vol, double qtot, cons
 }
 
 hipError_t launch_finalize(const Plan &p) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, p.stream, p.mode, p.alpha, p.vol, p.qtot, p.theta,
-                       p.off_s, p.scalars, p.method == 0 ? p.kcount : (const int *)nullptr,
-                       (double)(p.mesh_pts - 1), p.out.energy, p.out.virial, p.out.polarization,
-                       p.out.energy_terms);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, p.stream, p.mode, p.iso, p.alpha, p.vol, p.qtot, p.theta,
+                       p.off_s, p.scalars, (p.method == 0 && !p.iso) ? p.kcount : (const int *)nullptr,
+                       p.method == 1 ? (double)(p.mesh_pts - 1) : 0.0, p.out.energy, p.out.virial,
+                       p.out.polarization, p.out.energy_terms);
     return hipGetLastError();
 }
 

@@ -13,7 +13,7 @@ namespace qnep {
 
 // ---------------------------------------------------------------- binning
 __global__ void k_bin(int N, const float *__restrict__ pos, const int32_t *__restrict__ type, int T, Cell c,
-                      int nc0, int nc1, int nc2, int *__restrict__ cid, int *__restrict__ count,
+                      int nc0, int nc1, int nc2, int iso, int *__restrict__ cid, int *__restrict__ count,
                       int32_t *__restrict__ flags) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
@@ -22,6 +22,7 @@ __global__ void k_bin(int N, const float *__restrict__ pos, const int32_t *__res
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         double s = x * c.hinv[a] + y * c.hinv[3 + a] + z * c.hinv[6 + a];
+        if (iso && (s < 0.0 || s >= 1.0)) atomicOr(flags, QNEP_FLAG_OUTSIDE);  // an isolated system's box
         s -= floor(s);
         int k = (int)(s * nc[a]);
         cc[a] = k < 0 ? 0 : (k >= nc[a] ? nc[a] - 1 : k);
@@ -147,7 +148,7 @@ __global__ __launch_bounds__(256) void k_lists(int N, const float4 *__restrict__
                                                const int *__restrict__ start, double rc2, int cap,
                                                uint32_t *__restrict__ list, int *__restrict__ cnt, double rs2,
                                                int cap_sub, uint32_t *__restrict__ sub,
-                                               int *__restrict__ cnt_sub, int32_t *__restrict__ flags) {
+                                               int *__restrict__ cnt_sub, int iso, int32_t *__restrict__ flags) {
     __shared__ int2 seg[LS_APB][LS_SEG];
     __shared__ float4 shf[SEG_NIMG];  // (shift rounded to FP32, the image part of a list entry)
     const int nimg = 2 * st.R + 1;
@@ -200,6 +201,7 @@ __global__ __launch_bounds__(256) void k_lists(int N, const float4 *__restrict__
             const uint32_t gm = (uint32_t)(__ballot(hit) >> gshift) & LS_MASK;
             const uint32_t gs = (uint32_t)(__ballot(hs) >> gshift) & LS_MASK;
             if (hit) {
+                if (iso && g != self_img) atomicOr(flags, QNEP_FLAG_IMAGE);  // an isolated system sees an image
                 const uint32_t code = (uint32_t)j | __float_as_uint(sf.w);
                 const int k = n_main + __popc(gm & below);
                 if (k < cap) list[(size_t)i * cap + k] = code;
@@ -236,7 +238,7 @@ hipError_t launch_neighbors(const Plan &p) {
     hipError_t e = fill_zero(p.cell_count, sizeof(int) * (size_t)p.ncell, p.stream);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_bin, dim3(G), dim3(B), 0, p.stream, N, p.pos, p.type, p.T, p.cell, p.nc[0], p.nc[1],
-                       p.nc[2], p.cid, p.cell_count, p.flags);
+                       p.nc[2], p.iso, p.cid, p.cell_count, p.flags);
     const int nsb = (p.ncell + SCAN_B - 1) / SCAN_B;
     hipLaunchKernelGGL(k_scan_blocks, dim3(nsb), dim3(SCAN_B), 0, p.stream, p.ncell, p.cell_count, p.cell_start,
                        p.scan_tmp);
@@ -254,7 +256,7 @@ hipError_t launch_neighbors(const Plan &p) {
     if (!stencil_setup(st, p.nc, p.mR, p.cell.h, p.rcR > p.rcA ? p.rcR : p.rcA, LS_SEG)) return hipErrorInvalidValue;
     const int GL = (N + LS_APB - 1) / LS_APB;
     hipLaunchKernelGGL(k_lists, dim3(GL), dim3(B), 0, p.stream, N, p.xyzt, p.cell, st, p.cell_start, rcR2, p.capR,
-                       p.listR, p.cntR, rcA2, p.capA, p.listA, p.cntA, p.flags);
+                       p.listR, p.cntR, rcA2, p.capA, p.listA, p.cntA, p.iso, p.flags);
     stage_mark(p, ST_LISTS);
     return hipGetLastError();
 }

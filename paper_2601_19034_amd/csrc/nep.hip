@@ -212,14 +212,16 @@ constexpr int RF_LANES = 8;
 static_assert(RF_LANES <= PARTIALS_LANES_MAX, "partials buffer sized for PARTIALS_LANES_MAX lanes per atom");
 
 // With VAT the per-atom virial W_i += r_ij (x) F_ji = -sigma_ji r u (x) u (Eq. 12) is
-// added to Vat as well.
-template <int T, int NB, bool VAT>
+// added to Vat as well.  ISO (isolated systems, Born charges of Eq. 27): the pair part
+// of Z_i is sum_j r_ij (x) a_ji = -rho_ji r u (x) u, and S_i = sum_j (a_ji - a_ij) =
+// -(rho_ij + rho_ji) u goes to Siso for the centroid term of the assembly.
+template <int T, int NB, bool VAT, bool ISO>
 __global__ __launch_bounds__(256) void k_radial_forces(int N, const float4 *__restrict__ xyzt, Cell c, float rcR,
                                                        const uint32_t *__restrict__ listR,
                                                        const int *__restrict__ cntR, int capR,
                                                        const float *__restrict__ hT, float *__restrict__ Fnep,
                                                        float *__restrict__ Znep, float *__restrict__ Vat,
-                                                       double *__restrict__ partials) {
+                                                       float *__restrict__ Siso, double *__restrict__ partials) {
     constexpr int REC = RadRec<NB>::v, R4 = REC / 4, APB = 256 / RF_LANES;
     // this atom's own T records, read for every pair, sit in LDS: the vector memory
     // path is left to the neighbours' records
@@ -230,8 +232,8 @@ __global__ __launch_bounds__(256) void k_radial_forces(int N, const float4 *__re
         own[a][q] = i < N ? reinterpret_cast<const float4 *>(hT + (size_t)i * T * REC)[q]
                           : make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
-    constexpr int NACC = VAT ? 21 : 15;
-    float acc[NACC];  // F (3), Z (xx yy zz xy xz yz), W (same order)[, per-atom W (same order)]
+    constexpr int NACC = 15 + (VAT ? 6 : 0) + (ISO ? 3 : 0), KS = 15 + (VAT ? 6 : 0);
+    float acc[NACC];  // F (3), Z (xx yy zz xy xz yz), W (same order)[, per-atom W (same order)][, S (3)]
 #pragma unroll
     for (int k = 0; k < NACC; ++k) acc[k] = 0.f;
     if (i < N) {
@@ -293,7 +295,13 @@ __global__ __launch_bounds__(256) void k_radial_forces(int N, const float4 *__re
             acc[0] = fmaf(sf, ux, acc[0]);
             acc[1] = fmaf(sf, uy, acc[1]);
             acc[2] = fmaf(sf, uz, acc[2]);
-            const float zr = 0.5f * (rij - rji) * r, wr = -sij * r;
+            const float zr = ISO ? -rji * r : 0.5f * (rij - rji) * r, wr = -sij * r;
+            if constexpr (ISO) {
+                const float sr = -(rij + rji);
+                acc[KS] = fmaf(sr, ux, acc[KS]);
+                acc[KS + 1] = fmaf(sr, uy, acc[KS + 1]);
+                acc[KS + 2] = fmaf(sr, uz, acc[KS + 2]);
+            }
             const float uu[6] = {ux * ux, uy * uy, uz * uz, ux * uy, ux * uz, uy * uz};
 #pragma unroll
             for (int k = 0; k < 6; ++k) {
@@ -333,6 +341,10 @@ __global__ __launch_bounds__(256) void k_radial_forces(int N, const float4 *__re
         if constexpr (VAT) {
 #pragma unroll
             for (int k = 0; k < 6; ++k) Vat[(size_t)k * N + i] += acc[15 + k];
+        }
+        if constexpr (ISO) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) Siso[(size_t)k * N + i] = acc[KS + k];
         }
     }
     block_partials<9>(w, partials);
@@ -384,13 +396,14 @@ __device__ __forceinline__ float3 angular_pair(const float4 *__restrict__ At4, c
                        radial * uz + (gz - ug * uz) * ir);
 }
 
-template <int T, int NR, int NA, int NB>
+// ISO (isolated systems): the own a_ij enter Z only through S_i -= a_ij (Siso).
+template <int T, int NR, int NA, int NB, bool ISO>
 __global__ __launch_bounds__(256) void k_angular_forces(
     int N, const float4 *__restrict__ xyzt, Cell c, float rcA, const uint32_t *__restrict__ listA,
     const int *__restrict__ cntA, int capA, const float *__restrict__ Amom, const float *__restrict__ gU,
     const float *__restrict__ gq, const float *__restrict__ phi, const double *__restrict__ scalars,
     const float *__restrict__ theta, int64_t off_cA, int64_t off_s, float4 *__restrict__ pairFA,
-    float *__restrict__ Fnep, float *__restrict__ Znep, double *__restrict__ partials) {
+    float *__restrict__ Fnep, float *__restrict__ Znep, float *__restrict__ Siso, double *__restrict__ partials) {
     constexpr int NAL = NA * LM;
     static_assert(NA <= 8 && LM % 4 == 0, "angular table layout");
     // cA8[ti tj][k][n], n padded to 8: the two float4 of one k serve all g_n
@@ -417,9 +430,10 @@ __global__ __launch_bounds__(256) void k_angular_forces(
         }
     }
     __syncthreads();
-    float acc[21];  // own force (3), virial W_ab -= F_a r_b (9), Z_ab += 1/2 r_a a_b (9)
+    constexpr int NACC = ISO ? 24 : 21;
+    float acc[NACC];  // own force (3), virial W_ab -= F_a r_b (9), Z_ab += 1/2 r_a a_b (9) [ISO: S -= a (3)]
 #pragma unroll
-    for (int k = 0; k < 21; ++k) acc[k] = 0.f;
+    for (int k = 0; k < NACC; ++k) acc[k] = 0.f;
     if (live) {
         const float4 pi = xyzt[i];
         const int ti = species_of(pi);
@@ -475,13 +489,14 @@ __global__ __launch_bounds__(256) void k_angular_forces(
 #pragma unroll
                 for (int y = 0; y < 3; ++y) {
                     acc[3 + 3 * x + y] = fmaf(-fv[x], dv[y], acc[3 + 3 * x + y]);
-                    acc[12 + 3 * x + y] = fmaf(0.5f * dv[x], av[y], acc[12 + 3 * x + y]);
+                    if constexpr (!ISO) acc[12 + 3 * x + y] = fmaf(0.5f * dv[x], av[y], acc[12 + 3 * x + y]);
                 }
+                if constexpr (ISO) acc[21 + x] -= av[x];
             }
         }
     }
 #pragma unroll
-    for (int k = 0; k < 21; ++k)
+    for (int k = 0; k < NACC; ++k)
 #pragma unroll
         for (int o = AF_LANES / 2; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o, 64);
     double w[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -493,6 +508,10 @@ __global__ __launch_bounds__(256) void k_angular_forces(
         for (int k = 0; k < 9; ++k) {
             w[k] = acc[3 + k];
             Znep[(size_t)k * N + i] += acc[12 + k];
+        }
+        if constexpr (ISO) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) Siso[(size_t)k * N + i] += acc[21 + k];
         }
     }
     block_partials<9>(w, partials);
@@ -549,9 +568,13 @@ struct AssembleExtra {
     float ubg_coef;     // -k_e pi Q^2 / (2 Omega alpha^2 N) (mode 1), times 1/s^2 on the device
     const float *Vat;   // symmetric per-atom virial parts [6][N]
     float *vatom;       // output [9][N], input order
+    const float *Siso;  // isolated systems: sum_j (a_ji - a_ij) from the radial and angular kernels
 };
 
-template <bool VAT>
+// ISO (isolated systems, Eq. 27 with the corrected charges): Z_i = q~'_i I +
+// sum_j r_ij (x) a_ji + (r_i - rbar) (x) sum_j (a_ji - a_ij), r_i the caller's position and
+// rbar the centroid.
+template <bool VAT, bool ISO>
 __global__ __launch_bounds__(256) void k_assemble(
     int N, const float4 *__restrict__ xyzt, Cell c, const uint32_t *__restrict__ listA,
     const int *__restrict__ cntA, int capA, const float4 *__restrict__ pairFA,
@@ -562,8 +585,8 @@ __global__ __launch_bounds__(256) void k_assemble(
     double *__restrict__ partials) {
     const int gtid = xcd_block() * blockDim.x + threadIdx.x;
     const int i = gtid / AS_LANES, sub = gtid % AS_LANES;
-    constexpr int NACC = VAT ? 21 : 12;
-    float acc[NACC];  // F (3), Z (9)[, per-atom W (9)]
+    constexpr int NACC = 12 + (VAT ? 9 : 0) + (ISO ? 3 : 0), KS = 12 + (VAT ? 9 : 0);
+    float acc[NACC];  // F (3), Z (9)[, per-atom W (9)][, S (3)]
 #pragma unroll
     for (int k = 0; k < NACC; ++k) acc[k] = 0.f;
     if (i < N) {
@@ -583,8 +606,14 @@ __global__ __launch_bounds__(256) void k_assemble(
             acc[1] -= fji.y;
             acc[2] -= fji.z;
             const float3 d = displacement(pi, xyzt, e, c);  // r_ij = -r_ji
-            // -1/2 r_ji (x) a_ji = +1/2 r_ij (x) a_ji
-            const float dv[3] = {0.5f * d.x, 0.5f * d.y, 0.5f * d.z}, av[3] = {aji.x, aji.y, aji.z};
+            // -1/2 r_ji (x) a_ji = +1/2 r_ij (x) a_ji (ISO: r_ij (x) a_ji)
+            const float hz = ISO ? 1.0f : 0.5f;
+            const float dv[3] = {hz * d.x, hz * d.y, hz * d.z}, av[3] = {aji.x, aji.y, aji.z};
+            if constexpr (ISO) {
+                acc[KS] += aji.x;
+                acc[KS + 1] += aji.y;
+                acc[KS + 2] += aji.z;
+            }
 #pragma unroll
             for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -613,6 +642,18 @@ __global__ __launch_bounds__(256) void k_assemble(
         for (int k = 0; k < 9; ++k) {
             const float diag = (k == 0 || k == 4 || k == 8) ? qt : 0.0f;
             z[k] = Znep[(size_t)k * N + i] + acc[3 + k] + diag;
+        }
+        if constexpr (ISO) {
+            float sv[3], rv[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                sv[a] = ext.Siso[(size_t)a * N + i] + acc[KS + a];
+                rv[a] = (float)((double)pos[(size_t)a * N + o] - scalars[S_CENT + a] / (double)N);
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) z[3 * a + b] = fmaf(rv[a], sv[b], z[3 * a + b]);
         }
         if (forces) {
 #pragma unroll
@@ -662,39 +703,46 @@ static hipError_t run_forces(const Plan &p) {
     hipLaunchKernelGGL((k_radial_tables<T, NR, NB>), dim3(G), dim3(256), 0, p.stream, p.N, p.ts, p.gU, p.gq,
                        p.phi, p.scalars, p.theta, p.off_cR, p.off_s, p.hT);
     const int GR = (int)(((int64_t)p.N * RF_LANES + 255) / 256);
-    const bool vat = p.out.virial_atom != nullptr;
-    if (vat)
-        hipLaunchKernelGGL((k_radial_forces<T, NB, true>), dim3(GR), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell,
-                           (float)p.rcR, p.listR, p.cntR, p.capR, p.hT, p.Fnep, p.Znep, p.Vat, p.partials);
-    else
-        hipLaunchKernelGGL((k_radial_forces<T, NB, false>), dim3(GR), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell,
-                           (float)p.rcR, p.listR, p.cntR, p.capR, p.hT, p.Fnep, p.Znep, p.Vat, p.partials);
+    const bool vat = p.out.virial_atom != nullptr, iso = p.iso != 0;
+#define QNEP_RADIAL(V, I)                                                                                        \
+    hipLaunchKernelGGL((k_radial_forces<T, NB, V, I>), dim3(GR), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell,      \
+                       (float)p.rcR, p.listR, p.cntR, p.capR, p.hT, p.Fnep, p.Znep, p.Vat, p.Siso, p.partials)
+    if (vat && iso) QNEP_RADIAL(true, true);
+    else if (vat) QNEP_RADIAL(true, false);
+    else if (iso) QNEP_RADIAL(false, true);
+    else QNEP_RADIAL(false, false);
+#undef QNEP_RADIAL
     hipError_t e = reduce_partials(p, GR, 9, S_WNEP, false);
     if (e != hipSuccess) return e;
     stage_mark(p, ST_RADIAL, 3);
     const int GF = (p.N + AF_APB - 1) / AF_APB;
-    hipLaunchKernelGGL((k_angular_forces<T, NR, NA, NB>), dim3(GF), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell,
-                       (float)p.rcA, p.listA, p.cntA, p.capA, p.Amom, p.gU, p.gq, p.phi, p.scalars, p.theta,
-                       p.off_cA, p.off_s, (float4 *)p.pairFA, p.Fnep, p.Znep, p.partials);
+#define QNEP_ANGULAR(I)                                                                                          \
+    hipLaunchKernelGGL((k_angular_forces<T, NR, NA, NB, I>), dim3(GF), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, \
+                       (float)p.rcA, p.listA, p.cntA, p.capA, p.Amom, p.gU, p.gq, p.phi, p.scalars, p.theta,       \
+                       p.off_cA, p.off_s, (float4 *)p.pairFA, p.Fnep, p.Znep, p.Siso, p.partials)
+    if (iso) QNEP_ANGULAR(true);
+    else QNEP_ANGULAR(false);
+#undef QNEP_ANGULAR
     stage_mark(p, ST_ANG);
     e = reduce_partials(p, GF, 9, S_WNEP, true);
     if (e != hipSuccess) return e;
     stage_mark(p, ST_OTHER);
     const int GA = (int)(((int64_t)p.N * AS_LANES + 255) / 256);
     AssembleExtra ext{p.efield[0], p.efield[1], p.efield[2],
-                      p.mode == 1 ? (float)(-KE * PI_D * p.qtot * p.qtot / (2.0 * p.vol * p.alpha * p.alpha * p.N))
-                                  : 0.0f,
-                      p.Vat, p.out.virial_atom};
-    if (vat)
-        hipLaunchKernelGGL(k_assemble<true>, dim3(GA), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, p.listA, p.cntA,
-                           p.capA, (const float4 *)p.pairFA, p.Fnep, p.Znep, p.Fst, p.qraw, p.scalars, p.theta,
-                           p.off_s, p.perm, p.pos, p.out.forces, p.out.bec, p.out.charges, p.out.charges_naked, ext,
-                           p.partials);
-    else
-        hipLaunchKernelGGL(k_assemble<false>, dim3(GA), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, p.listA,
-                           p.cntA, p.capA, (const float4 *)p.pairFA, p.Fnep, p.Znep, p.Fst, p.qraw, p.scalars,
-                           p.theta, p.off_s, p.perm, p.pos, p.out.forces, p.out.bec, p.out.charges,
-                           p.out.charges_naked, ext, p.partials);
+                      (p.mode == 1 && !iso)
+                          ? (float)(-KE * PI_D * p.qtot * p.qtot / (2.0 * p.vol * p.alpha * p.alpha * p.N))
+                          : 0.0f,
+                      p.Vat, p.out.virial_atom, p.Siso};
+#define QNEP_ASSEMBLE(V, I)                                                                                      \
+    hipLaunchKernelGGL((k_assemble<V, I>), dim3(GA), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, p.listA, p.cntA, \
+                       p.capA, (const float4 *)p.pairFA, p.Fnep, p.Znep, p.Fst, p.qraw, p.scalars, p.theta,       \
+                       p.off_s, p.perm, p.pos, p.out.forces, p.out.bec, p.out.charges, p.out.charges_naked, ext,  \
+                       p.partials)
+    if (vat && iso) QNEP_ASSEMBLE(true, true);
+    else if (vat) QNEP_ASSEMBLE(true, false);
+    else if (iso) QNEP_ASSEMBLE(false, true);
+    else QNEP_ASSEMBLE(false, false);
+#undef QNEP_ASSEMBLE
     e = reduce_partials(p, GA, 3, S_POL, false);
     stage_mark(p, ST_ASSEMBLE, 2);
     return e;

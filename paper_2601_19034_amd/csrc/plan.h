@@ -37,6 +37,7 @@ struct Plan {
     int64_t off_cR = 0, off_cA = 0, off_nn = 0, per_species = 0, off_b1E = 0, off_s = 0, n_theta = 0;
     // ---- electrostatics
     int mode = 1, method = 0, kinc = 0, order = 5;
+    int iso = 0;  // isolated system: no periodic images, direct Coulomb sum, Born charges of Eq. 27
     double alpha = 0.3, rc_coul = 9.0, kmax = 0, qtot = 0;
     float efield[3] = {0.f, 0.f, 0.f};  // external field (V/Angstrom)
     int mesh[3] = {0, 0, 0};
@@ -73,8 +74,13 @@ struct Plan {
     float *pairFA = nullptr;  // angular pair buffer [i][capA][2] float4: F_ij, then a_ij
     float *Fnep = nullptr, *Znep = nullptr;
     float *Vat = nullptr;  // per-atom virial, symmetric parts [6][N] (xx yy zz xy xz yz), sorted order
+    float *Siso = nullptr; // isolated systems: sum_j (a_ji - a_ij) per atom [3][N], sorted order
     float4 *kvec = nullptr;   // (kx, ky, kz, G) of the half set
     int *kcount = nullptr;
+    int4 *ksegs = nullptr;    // row segments of the half set: (n0, n1, first n2, count)
+    int *ksegoff = nullptr;   // index of each segment's first wave vector
+    int *knseg = nullptr;     // number of segments
+    int64_t seg_cap = 0;
     float2 *Spart = nullptr;  // [s_chunks][nk_cap]
     float2 *Sk = nullptr;     // [nk_cap]
     bool bricks = false;      // charge assignment by mesh bricks (else global atomics into rho)
@@ -102,6 +108,8 @@ hipError_t launch_descriptors(const Plan &p);
 hipError_t launch_mlp(const Plan &p);
 hipError_t launch_charges(const Plan &p);
 hipError_t launch_real_space(const Plan &p);
+hipError_t launch_direct_coulomb(const Plan &p);
+hipError_t launch_centroid(const Plan &p);
 hipError_t launch_ewald(const Plan &p);
 hipError_t launch_pppm(const Plan &p);
 // mesh bricks of the charge assignment: edge P (points) and count nb per axis

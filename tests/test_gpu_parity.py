@@ -296,3 +296,85 @@ def test_per_atom_virial(torch_dev, orc, case):
     g0 = run_gpu(hp, es, sysm, th)
     for k in ("forces", "virial", "bec", "energy"):
         assert np.array_equal(g0[k], g[k]), k
+
+
+def test_spread_atomic_fallback(torch_dev, orc):
+    """A mesh so coarse against the bins that a brick's bin rows or segments would not
+    fit the per-work-group tables: the charge assignment takes the atomic path (float
+    atomics into a real mesh).  Garnet-768 (20.6 A, bins of 3.4 x 3.4 x 1.6 A) with a
+    3^3 mesh: 16 x 16 rows and 32 bins along c per brick, 1024 segments > 512."""
+    w = inputs.workload(2, "crop")
+    es = copy.copy(w.es)
+    es.mesh = (3, 3, 3)
+    nc = [int(np.floor(w.system.cell[a, a] / (3.0 if a < 2 else 1.5))) for a in range(3)]
+    cnt = [int(np.floor((3 + 4.02) * nc[a] / 3)) + 2 for a in range(3)]
+    assert cnt[0] * cnt[1] * ((cnt[2] - 1) // nc[2] + 2) > 512  # the brick tables do not fit
+    _say("case garnet-768 PPPM 3^3 (atomic charge assignment)")
+    g = run_gpu(w.hp, es, w.system, w.theta)
+    r = _oracle(orc, w.hp, es, w.system, w.theta)
+    compare(g, r, w.system.n, label="garnet768-pppm3-atomic")
+
+
+# ------------------------------------------------------------------ isolated systems (Eqs. 26, 27)
+def _droplet(n_side, radius, box, seed):
+    """Water molecules whose oxygen lies within `radius` of the centre of a water box,
+    moved to the centre of an empty cubic box of edge `box` (an isolated cluster)."""
+    w = inputs.water_box(n_side, seed=seed)
+    c = w.cell.diagonal() / 2
+    keep = []
+    for m in range(w.n // 3):
+        if np.linalg.norm(w.pos[3 * m] - c) < radius:
+            keep += [3 * m, 3 * m + 1, 3 * m + 2]
+    pos = w.pos[keep] - c + box / 2
+    return inputs.System("droplet", pos.astype(np.float32).astype(np.float64), w.types[keep].copy(), np.eye(3) * box)
+
+
+def run_gpu_iso(hp, es, sysm, theta, per_atom_virial=False):
+    from paper_2601_19034_amd.api import ALL_OUTPUTS, DEFAULT_OUTPUTS, QNEP, to_device_inputs
+
+    model = QNEP(hp)
+    pos, types, th = to_device_inputs(sysm, theta)
+    out = model.compute(pos, types, sysm.cell, th, es, periodic=False,
+                        outputs=ALL_OUTPUTS if per_atom_virial else DEFAULT_OUTPUTS)
+    flags = model.check_status()
+    g = {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
+    g["pos_used"] = np.asarray(sysm.pos, dtype=np.float64)
+    return g, flags
+
+
+@pytest.mark.parametrize("radius", [4.0, 11.0])
+def test_isolated_droplet(torch_dev, orc, radius):
+    """A water droplet in free space (direct Coulomb sum over all pairs, Born charges as
+    the derivative of P with absolute positions) against the oracle, with the per-atom
+    virial; the default outputs are the same with or without it."""
+    hp, th = inputs.WATER_HP, inputs.theta0(inputs.WATER_HP, 31)
+    s = _droplet(8, radius, 2 * radius + 2 * 9.5, seed=7)
+    es = inputs.ESParams(method=2)
+    _say(f"case isolated droplet N={s.n}")
+    g, flags = run_gpu_iso(hp, es, s, th, per_atom_virial=True)
+    assert flags == 0, flags
+    r = orc.compute(hp, es, s.pos, s.types, s.cell, th, periodic=False, per_atom_virial=True)
+    compare(g, r, s.n, label=f"droplet-{s.n}")
+    Va = g["virial_atom"].T.reshape(-1, 3, 3)
+    err = np.abs(Va - r.vatom).max()
+    _say(f"[droplet-{s.n}] max|dW_i|={err:.2e} (max|W_i| {np.abs(r.vatom).max():.2f})")
+    assert err <= 2e-5 * np.abs(r.vatom).max() + 1e-5
+    assert g["energy_terms"][2] == 0.0 and g["energy_terms"][3] == 0.0
+
+
+def test_isolated_flags(torch_dev):
+    """An isolated system must fit its bounding box: an atom outside raises
+    QNEP_FLAG_OUTSIDE, and a box so tight that an atom sees a periodic image within a
+    cutoff raises QNEP_FLAG_IMAGE."""
+    from paper_2601_19034_amd import binding as B
+
+    hp, th = inputs.WATER_HP, inputs.theta0(inputs.WATER_HP, 31)
+    s = _droplet(8, 4.0, 30.0, seed=7)
+    es = inputs.ESParams(method=2)
+    out_of_box = inputs.System("out", s.pos + np.array([0.0, 0.0, 16.0]), s.types, s.cell)
+    _say("case isolated flags")
+    _, flags = run_gpu_iso(hp, es, out_of_box, th)
+    assert flags & B.FLAG_OUTSIDE
+    tight = inputs.System("tight", s.pos - 15.0 + 4.5, s.types, np.eye(3) * 9.0)  # images 4 A apart
+    _, flags = run_gpu_iso(hp, es, tight, th)
+    assert flags & B.FLAG_IMAGE and not flags & B.FLAG_OUTSIDE

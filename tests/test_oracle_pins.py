@@ -747,3 +747,93 @@ def test_md_polarization_current_fixed_charges(orc):
     np.testing.assert_allclose(ser[0, 2:5], (qt[:, None] * v0).sum(0), atol=1e-13)
     dPdt = (ser[2:, 5:8] - ser[:-2, 5:8]) / (2 * 0.2)
     np.testing.assert_allclose(ser[1:-1, 2:5], dPdt, atol=2e-4 * np.abs(ser[:, 2:5]).max())
+
+
+# ---------------------------------------------------------------- isolated systems (Eqs. 26, 27)
+def _iso_es():
+    return inputs.ESParams(mode=1, method=2)
+
+
+def test_isolated_two_ions_coulomb(orc):
+    """Two fixed charges in free space: U_ES = k_e q1 q2 / r exactly, forces +-k_e q1 q2 / r^2
+    along the axis, Z_i = q~'_i I and P = q~'_1 r_1 + q~'_2 r_2."""
+    hp = inputs.WATER_HP
+    th = _fixed_charge_theta(hp, [0.7, -0.3], s=1.0)
+    pos = np.array([[10.0, 11.0, 12.0], [13.1, 9.4, 14.2]])
+    types = np.array([0, 1], dtype=np.int32)
+    es = _iso_es()
+    es.q_total = 0.4  # the corrected charges equal the raw ones: 0.7 - 0.3 = 0.4
+    r = orc.compute(hp, es, pos, types, np.eye(3) * 25.0, th, periodic=False)
+    d = pos[1] - pos[0]
+    rr = np.linalg.norm(d)
+    np.testing.assert_allclose(r.q_naked, [0.7, -0.3], atol=1e-14)
+    assert abs(r.terms[2] - _ke() * 0.7 * -0.3 / rr) < 1e-6 * abs(r.terms[2])
+    assert r.terms[3] == 0.0 and r.terms[4] == 0.0 and r.terms[5] == 0.0
+    np.testing.assert_allclose(r.bec, np.array([0.7, -0.3])[:, None, None] * np.eye(3)[None], atol=1e-14)
+    np.testing.assert_allclose(r.pol, 0.7 * pos[0] - 0.3 * pos[1], atol=1e-12)
+
+
+def _iso_cluster():
+    full = inputs.water_box(2, spacing=3.0, seed=17)
+    pos = full.pos[:15].copy()
+    pos = pos - pos.mean(0) + 20.0
+    return inputs.System("iso", pos, full.types[:15].copy(), np.eye(3) * 40.0)
+
+
+def test_isolated_born_charges_are_dP_dr(orc):
+    """For an isolated system P = sum_i q~'_i r_i with absolute positions is single-valued
+    and Z_i (Eq. 27, corrected charges) is exactly its derivative: central differences
+    of P, no correction term."""
+    sysm = _iso_cluster()
+    hp = inputs.WATER_HP
+    th = inputs.theta0(hp, 77)
+    th[-1] = 1.3
+    es = _iso_es()
+    r = orc.compute(hp, es, sysm.pos, sysm.types, sysm.cell, th, periodic=False)
+    h = 1e-5
+    for i in range(sysm.n):
+        for b in range(3):
+            p = sysm.pos.copy()
+            p[i, b] += h
+            rp = orc.compute(hp, es, p, sysm.types, sysm.cell, th, forces=False, periodic=False)
+            p[i, b] -= 2 * h
+            rm = orc.compute(hp, es, p, sysm.types, sysm.cell, th, forces=False, periodic=False)
+            np.testing.assert_allclose(r.bec[i, :, b], (rp.pol - rm.pol) / (2 * h), atol=2e-8)
+    assert np.abs(r.bec - r.q_naked[:, None, None] * np.eye(3)).max() > 1e-3  # charges respond
+
+
+def test_isolated_forces_virial_and_invariance(orc):
+    """Forces are central differences of E (direct Coulomb and the charge chain rule),
+    the virial is the strain derivative, the net force vanishes, and a rigid rotation
+    leaves E unchanged while Z* rotates as a tensor."""
+    sysm = _iso_cluster()
+    hp = inputs.WATER_HP
+    th = inputs.theta0(hp, 78)
+    es = _iso_es()
+    r = orc.compute(hp, es, sysm.pos, sysm.types, sysm.cell, th, periodic=False, per_atom_virial=True)
+    h = 1e-5
+    for i in (0, 4, 9):
+        for b in range(3):
+            p = sysm.pos.copy()
+            p[i, b] += h
+            ep = orc.compute(hp, es, p, sysm.types, sysm.cell, th, forces=False, periodic=False).energy
+            p[i, b] -= 2 * h
+            em = orc.compute(hp, es, p, sysm.types, sysm.cell, th, forces=False, periodic=False).energy
+            assert abs(r.forces[i, b] + (ep - em) / (2 * h)) < 1e-6
+    assert np.abs(r.forces.sum(0)).max() < 1e-10
+    for a, b in ((0, 0), (0, 1), (2, 1)):
+        vals = []
+        for sg in (1, -1):
+            eps = np.zeros((3, 3))
+            eps[a, b] += 0.5 * sg * 1e-6
+            eps[b, a] += 0.5 * sg * 1e-6
+            p = sysm.pos @ (np.eye(3) + eps).T
+            vals.append(orc.compute(hp, es, p, sysm.types, sysm.cell, th, forces=False, periodic=False).energy)
+        assert abs(r.virial[a, b] + (vals[0] - vals[1]) / 2e-6) < 1e-5
+    np.testing.assert_allclose(r.vatom.sum(0), r.virial, atol=1e-10)
+    Rm = _rot(5)
+    c = sysm.pos.mean(0)
+    pr = (sysm.pos - c) @ Rm.T + c
+    rr = orc.compute(hp, es, pr, sysm.types, sysm.cell, th, periodic=False)
+    assert abs(rr.energy - r.energy) < 1e-9
+    np.testing.assert_allclose(rr.bec, np.einsum("ab,ibc,dc->iad", Rm, r.bec, Rm), atol=1e-9)
