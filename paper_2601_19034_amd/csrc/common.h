@@ -166,13 +166,31 @@ __device__ inline AtomBin atom_bin(float4 p, const Cell &c, const Stencil &st) {
     return b;
 }
 
-// bins [zl, zh] along c (unwrapped) of stencil row r that can hold a neighbour
-__device__ inline bool stencil_row(const Stencil &st, const Cell &c, const AtomBin &b, int r, int &zl, int &zh) {
-    const int w1n = 2 * st.m[1] + 1;
+// floor(a / n) for a in [-SEG_RMAX n, (SEG_RMAX + 1) n), the range of unwrapped bin
+// coordinates a stencil reaches: the image of the bin, by comparisons (an integer
+// division by a value known only at run time costs dozens of instructions)
+__device__ inline int image_index(int a, int n) {
+    int k = 0;
+#pragma unroll
+    for (int t = 1; t <= SEG_RMAX; ++t) k += (int)(a >= t * n) - (int)(a < (1 - t) * n);
+    return k;
+}
+
+// LDS written by other lanes of the same wave becomes visible to this lane
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// bins [zl, zh] along c (unwrapped) of the stencil row at offsets (d0, d1) in
+// [0, 2 m0] x [0, 2 m1] that can hold a neighbour
+__device__ inline bool stencil_row(const Stencil &st, const Cell &c, const AtomBin &b, int d0, int d1, int &zl,
+                                   int &zh) {
     zl = b.ci[2] - st.m[2];
     zh = b.ci[2] + st.m[2];
     if (!st.trim) return true;
-    const float l0 = (float)(b.ci[0] + (r / w1n - st.m[0])), l1 = (float)(b.ci[1] + (r % w1n - st.m[1]));
+    const float l0 = (float)(b.ci[0] + (d0 - st.m[0])), l1 = (float)(b.ci[1] + (d1 - st.m[1]));
     const float g0 = fmaxf(0.0f, fmaxf(l0 - b.u[0], b.u[0] - l0 - 1.0f)) * st.bw0;
     const float g1 = fmaxf(0.0f, fmaxf(l1 - b.u[1], b.u[1] - l1 - 1.0f)) * st.bw1;
     const float h2 = st.rtrim2 - g0 * g0 - g1 * g1;
@@ -193,10 +211,12 @@ __device__ inline int stencil_segments(const Stencil &st, const Cell &c, const A
     const int nimg = 2 * st.R + 1;
     const int rpl = (rn + LANES - 1) / LANES;  // rows per lane, contiguous: the table keeps row order
     const int rb = r0 + sub * rpl, re = min(rb + rpl, r0 + rn);
+    const int d0b = rb / w1n, d1b = rb - d0b * w1n;  // row rb at offsets (d0b, d1b); later rows by counting
     int cnt = 0;
-    for (int r = rb; live && r < re; ++r) {
+    for (int r = rb, d0 = d0b, d1 = d1b; live && r < re; ++r) {
         int zl, zh;
-        if (stencil_row(st, c, b, r, zl, zh)) cnt += floor_div(zh, nc2) - floor_div(zl, nc2) + 1;
+        if (stencil_row(st, c, b, d0, d1, zl, zh)) cnt += image_index(zh, nc2) - image_index(zl, nc2) + 1;
+        if (++d1 == w1n) { d1 = 0; ++d0; }
     }
     int incl = cnt;
 #pragma unroll
@@ -205,18 +225,21 @@ __device__ inline int stencil_segments(const Stencil &st, const Cell &c, const A
         if (sub >= o) incl += v;
     }
     int pos = incl - cnt;
-    for (int r = rb; live && r < re; ++r) {
+    for (int r = rb, d0 = d0b, d1 = d1b; live && r < re; ++r) {
         int zl, zh;
-        if (!stencil_row(st, c, b, r, zl, zh)) continue;
-        const int u0 = b.ci[0] + r / w1n - st.m[0], i0 = floor_div(u0, nc0), b0 = u0 - i0 * nc0;
-        const int u1 = b.ci[1] + r % w1n - st.m[1], i1 = floor_div(u1, nc1), b1 = u1 - i1 * nc1;
-        const int rowbase = row_rank(b0, b1, nc0, nc1) * nc2;
-        for (int i2 = floor_div(zl, nc2); i2 <= floor_div(zh, nc2); ++i2) {
-            const int za = max(zl, i2 * nc2) - i2 * nc2, zb = min(zh, i2 * nc2 + nc2 - 1) - i2 * nc2;
-            const int jb = start[rowbase + za], je = start[rowbase + zb + 1];
-            const uint32_t img = (uint32_t)(((i0 + st.R) * nimg + (i1 + st.R)) * nimg + (i2 + st.R));
-            seg[pos++] = make_int2(jb, (int)((uint32_t)(je - jb) | (img << SEG_LEN_BITS)));
+        if (stencil_row(st, c, b, d0, d1, zl, zh)) {
+            const int u0 = b.ci[0] + d0 - st.m[0], i0 = image_index(u0, nc0), b0 = u0 - i0 * nc0;
+            const int u1 = b.ci[1] + d1 - st.m[1], i1 = image_index(u1, nc1), b1 = u1 - i1 * nc1;
+            const int rowbase = row_rank(b0, b1, nc0, nc1) * nc2;
+            const int z0 = image_index(zl, nc2), z1 = image_index(zh, nc2);
+            for (int i2 = z0; i2 <= z1; ++i2) {
+                const int za = max(zl, i2 * nc2) - i2 * nc2, zb = min(zh, i2 * nc2 + nc2 - 1) - i2 * nc2;
+                const int jb = start[rowbase + za], je = start[rowbase + zb + 1];
+                const uint32_t img = (uint32_t)(((i0 + st.R) * nimg + (i1 + st.R)) * nimg + (i2 + st.R));
+                seg[pos++] = make_int2(jb, (int)((uint32_t)(je - jb) | (img << SEG_LEN_BITS)));
+            }
         }
+        if (++d1 == w1n) { d1 = 0; ++d0; }
     }
     return live ? __shfl(incl, LANES - 1, LANES) : 0;
 }

@@ -86,11 +86,13 @@ __global__ __launch_bounds__(256) void k_real_space(int N, const float4 *__restr
     float acc[10];  // phi, B r (3), B r r (xx yy zz xy xz yz)
 #pragma unroll
     for (int k = 0; k < 10; ++k) acc[k] = 0.f;
+    __syncthreads();  // lattice shifts in place
+    // an atom's segment table is written and read by the atom's own lanes (one wave)
     for (int r0 = 0; r0 < st.nrows; r0 += st.rows_chunk) {  // the same trip count in every lane
-        __syncthreads();  // the previous chunk's walk is done with the table
+        wave_lds_sync();  // the previous chunk's walk is done with the table
         const int ns = stencil_segments<RS_LANES>(st, c, ab, live, sub, r0, min(st.rows_chunk, st.nrows - r0),
                                                   start, seg[a]);
-        __syncthreads();
+        wave_lds_sync();
         // this lane takes candidates sub, sub + RS_LANES, ... of the concatenation, two
         // per pass with both loads issued before either is used
         SegWalk wk(seg[a], ns, sub);

@@ -171,11 +171,13 @@ __global__ __launch_bounds__(256) void k_lists(int N, const float4 *__restrict__
     const int gshift = (threadIdx.x & 63) & ~(LS_LANES - 1);  // first lane of this group in the wave
     const uint32_t below = (1u << ln) - 1u;
     int n_main = 0, n_sub = 0;  // exact in lane 0, which has the most candidates of every chunk
+    __syncthreads();  // image table in place
+    // an atom's segment table is written and read by the atom's own lanes (one wave)
     for (int r0 = 0; r0 < st.nrows; r0 += st.rows_chunk) {
-        __syncthreads();
+        wave_lds_sync();  // the previous chunk's walk is done with the table
         const int ns = stencil_segments<LS_LANES>(st, c, ab, live, ln, r0, min(st.rows_chunk, st.nrows - r0),
                                                   start, seg[a]);
-        __syncthreads();
+        wave_lds_sync();
         SegWalk wk(seg[a], ns, ln);
         while (wk.valid()) {
             const int j = wk.atom(), g = wk.image();
