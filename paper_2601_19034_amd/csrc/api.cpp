@@ -293,10 +293,17 @@ qnep_status make_plan(const Model &m, const qnep_es_params *es, const qnep_syste
         }
         int64_t nh = count_half_k(p.cell.hinv, p.nk_box[0], p.nk_box[1], p.nk_box[2], p.kmax, p.kinc);
         p.nk_cap = nh + 16;
-        // every row (n0, n1) of the box adds at most one segment beyond count / EW_SEG
-        p.seg_cap = (int64_t)(2 * p.nk_box[0] + 1) * (2 * p.nk_box[1] + 1) + p.nk_cap / 32 + 16;
-        p.s_chunks = std::max(1, (p.N + 511) / 512);
-        red_blocks = std::max<int64_t>(red_blocks, (p.nk_cap + 255) / 256);
+        p.row_cap = (2 * p.nk_box[0] + 1) * (2 * p.nk_box[1] + 1);
+        p.NZP = (p.nk_box[2] + 1 + 15) / 16 * 16;
+        p.NZ4 = (p.nk_box[2] + 1 + 1) / 2 * 2;
+        // about two thousand work-groups for each matrix-core product
+        const int row_blocks = (p.row_cap + 63) / 64, zb = (p.NZP + 31) / 32;
+        p.s_chunks = std::max(1, std::min((p.N + 63) / 64, 2048 / std::max(1, row_blocks * zb)));
+        p.s_chunk = ((p.N + p.s_chunks - 1) / p.s_chunks + 1) / 2 * 2;
+        const int atom_blocks = std::max(1, (p.N + 127) / 128);
+        p.r_chunks = std::max(1, std::min((p.row_cap + 1) / 2, 2048 / atom_blocks));
+        p.r_chunk = ((p.row_cap + p.r_chunks - 1) / p.r_chunks + 1) / 2 * 2;
+        red_blocks = std::max<int64_t>(red_blocks, ((int64_t)p.row_cap * p.NZP + 255) / 256);
     } else {
         if (p.order != 5) return fail(QNEP_E_UNSUPPORTED, "PPPM assignment order must be 5");
         for (int a = 0; a < 3; ++a)
@@ -351,10 +358,15 @@ qnep_status make_plan(const Model &m, const qnep_es_params *es, const qnep_syste
     } else if (p.method == 0) {
         p.kvec = c.take<float4>(2 * (size_t)p.nk_cap);  // kv then kn (int4)
         p.kcount = c.take<int>(1);
-        p.ksegs = c.take<int4>(p.seg_cap);
-        p.ksegoff = c.take<int>(p.seg_cap);
-        p.knseg = c.take<int>(1);
-        p.Spart = c.take<float2>((size_t)p.s_chunks * p.nk_cap);
+        p.krows = c.take<int4>(p.row_cap);
+        p.krowoff = c.take<int>(p.row_cap);
+        p.knrows = c.take<int>(1);
+        p.ewX = c.take<float2>((size_t)(2 * p.nk_box[0] + 1) * N);
+        p.ewY = c.take<float2>((size_t)(2 * p.nk_box[1] + 1) * N);
+        p.ewZ = c.take<float2>((size_t)p.NZP * N);
+        p.Spart = c.take<float>((size_t)p.s_chunks * p.row_cap * p.NZP * 2);
+        p.Ubox = c.take<float2>((size_t)p.row_cap * 4 * p.NZ4);
+        p.ephi = c.take<float>((size_t)p.r_chunks * 4 * N);
         p.Sk = c.take<float2>(p.nk_cap);
     } else {
         if (!p.bricks) p.rho = c.take<float>(p.mesh_pts);

@@ -281,27 +281,38 @@ __device__ inline void phase_cs(int n0, int n1, int n2, double s0, double s1, do
     sincospif(2.0f * (float)t, &sn, &cs);
 }
 
-// The half set in rows: for every (n0, n1) the wave vectors with consecutive n2 are
-// stored consecutively and described by row segments of at most EW_SEG entries,
-// (n0, n1, first n2, count) and the index of their first wave vector.  Along a segment
-// the phase 2 pi n.s of an atom advances by 2 pi s2 per entry, so it is formed once per
-// (segment, atom) and then carried by a complex rotation.  One block.
-constexpr int EW_SEG = 32;
+// ---------------------------------------------------------------- Ewald on the matrix cores
+// The half set is stored in rows: for every (n0, n1) the wave vectors with consecutive
+// n2 >= 0 inside the cutoff sphere, described by (n0, n1, first n2, count) and the index
+// of the row's first wave vector; empty rows are left out.  With the per-atom phase
+// factors X_j(n0) = e^{-2 pi i n0 s0_j}, Y_j(n1), Z_j(n2) (s the fractional
+// coordinates) the structure factor of a row r and the per-atom sums separate:
+//   S(r, n2) = sum_j [q'_j X_j(n0_r) Y_j(n1_r)] Z_j(n2),
+//   sum_k w(k) G S e^{i k.r_i} = sum_n2 conj Z_i(n2) sum_r U(r, n2) conj(X_i Y_i)(r),
+// U = w G S with w = 1 (potential) and k_x, k_y, k_z (force).  The first is a complex
+// (rows x atoms)(atoms x n2) product, the second a (channels, n2) x rows x atoms
+// product; both run on v_mfma_f32_16x16x4f32 (FP32 operands and accumulation).  A
+// complex product a b takes real steps over K = (two complex terms) x (re, im) with A
+// arranged as [[a_re, -a_im], [a_im, a_re]] on the output rows (re, im).
+// Lane layout of v_mfma_f32_16x16x4f32 (wave64, lane l): A[i][k] at i = l % 16,
+// k = l / 16; B[k][j] at j = l % 16, k = l / 16; D[i][j] at j = l % 16, i = 4 (l / 16) + e.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 
+// One block.  Rows in the order of the (n0, n1) box with n1 slowest.
 __global__ void k_kvector_rows(Cell c, int M0, int M1, int M2, double kmax2, int inclusive, double alpha,
-                               double vol, int64_t cap, int64_t seg_cap, float4 *__restrict__ kv,
-                               int4 *__restrict__ kn, int4 *__restrict__ segs, int *__restrict__ segoff,
-                               int *__restrict__ kcount, int *__restrict__ nseg) {
-    __shared__ int scan_k[1024], scan_s[1024];
-    __shared__ int base_k, base_s;
-    if (threadIdx.x == 0) base_k = base_s = 0;
+                               double vol, int64_t cap, int row_cap, float4 *__restrict__ kv,
+                               int4 *__restrict__ kn, int4 *__restrict__ rows, int *__restrict__ rowoff,
+                               int *__restrict__ kcount, int *__restrict__ nrows) {
+    __shared__ int scan_k[1024], scan_r[1024];
+    __shared__ int base_k, base_r;
+    if (threadIdx.x == 0) base_k = base_r = 0;
     __syncthreads();
     const int n0w = 2 * M0 + 1, n1w = 2 * M1 + 1;
-    const int rows = n0w * n1w;
-    for (int r0 = 0; r0 < rows; r0 += 1024) {
+    const int box = n0w * n1w;
+    for (int r0 = 0; r0 < box; r0 += 1024) {
         const int r = r0 + threadIdx.x;
         int a0 = 0, a1 = 0, lo = 0, cnt = 0;
-        if (r < rows) {
+        if (r < box) {
             a1 = r / n0w - M1;
             a0 = r % n0w - M0;
             // half set: n2 > 0, or n2 = 0 with (n1 > 0, or n1 = 0 and n0 > 0)
@@ -321,19 +332,19 @@ __global__ void k_kvector_rows(Cell c, int M0, int M1, int M2, double kmax2, int
             }
             cnt = lo < 0 ? 0 : hi - lo + 1;
         }
-        const int ns = (cnt + EW_SEG - 1) / EW_SEG;
+        const int nr = cnt > 0 ? 1 : 0;
         scan_k[threadIdx.x] = cnt;
-        scan_s[threadIdx.x] = ns;
+        scan_r[threadIdx.x] = nr;
         __syncthreads();
         for (int o = 1; o < 1024; o <<= 1) {
             const int tk = threadIdx.x >= (unsigned)o ? scan_k[threadIdx.x - o] : 0;
-            const int ts = threadIdx.x >= (unsigned)o ? scan_s[threadIdx.x - o] : 0;
+            const int tr = threadIdx.x >= (unsigned)o ? scan_r[threadIdx.x - o] : 0;
             __syncthreads();
             scan_k[threadIdx.x] += tk;
-            scan_s[threadIdx.x] += ts;
+            scan_r[threadIdx.x] += tr;
             __syncthreads();
         }
-        const int kb = base_k + scan_k[threadIdx.x] - cnt, sb = base_s + scan_s[threadIdx.x] - ns;
+        const int kb = base_k + scan_k[threadIdx.x] - cnt, rb = base_r + scan_r[threadIdx.x] - nr;
         for (int m = 0; m < cnt; ++m) {
             const int64_t pos = (int64_t)kb + m;
             if (pos >= cap) break;
@@ -346,179 +357,290 @@ __global__ void k_kvector_rows(Cell c, int M0, int M1, int M2, double kmax2, int
             kv[pos] = make_float4((float)kx, (float)ky, (float)kz, (float)G);
             kn[pos] = make_int4(a0, a1, a2, 0);
         }
-        for (int q = 0; q < ns; ++q) {
-            const int m0 = q * EW_SEG, len = min(EW_SEG, cnt - m0);
-            if (sb + q >= seg_cap) break;
-            // a segment past the wave-vector capacity is emptied (never happens when the
+        if (nr && rb < row_cap) {
+            // a row past the wave-vector capacity is emptied (never happens when the
             // host count and this one agree, which they do up to the same tie rule)
-            const bool fits = (int64_t)kb + m0 + len <= cap;
-            segs[sb + q] = make_int4(a0, a1, lo + m0, fits ? len : 0);
-            segoff[sb + q] = fits ? kb + m0 : 0;
+            const bool fits = (int64_t)kb + cnt <= cap;
+            rows[rb] = make_int4(a0, a1, lo, fits ? cnt : 0);
+            rowoff[rb] = fits ? kb : 0;
         }
         __syncthreads();
         if (threadIdx.x == 1023) {
             base_k += scan_k[1023];
-            base_s += scan_s[1023];
+            base_r += scan_r[1023];
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         *kcount = base_k < cap ? base_k : (int)cap;
-        *nseg = base_s < seg_cap ? base_s : (int)seg_cap;
+        *nrows = base_r < row_cap ? base_r : row_cap;
     }
 }
 
-constexpr int EW_CHUNK = 512;
+__device__ inline float2 turn_phase(double t) {  // e^{-2 pi i t}
+    t -= rint(t);
+    float sn, cs;
+    sincospif(2.0f * (float)t, &sn, &cs);
+    return make_float2(cs, -sn);
+}
 
-// partial structure factors by row segments: block (segment block, atom chunk); each
-// thread owns one segment and carries every atom's phase along it
-__global__ __launch_bounds__(256) void k_structure_factor_rows(int N, const float4 *__restrict__ xyzt, Cell c,
-                                                               const float *__restrict__ qraw,
-                                                               const double *__restrict__ scalars,
-                                                               const int4 *__restrict__ segs,
-                                                               const int *__restrict__ segoff,
-                                                               const int *__restrict__ nseg, int64_t cap,
-                                                               float2 *__restrict__ Spart) {
-    __shared__ double sx[256], sy[256], sz[256];
-    __shared__ float sq[256];
-    __shared__ float2 st[256];  // (cos, sin) of 2 pi s2: the rotation along a segment
-    const int ns = *nseg;
-    const int sg = blockIdx.x * blockDim.x + threadIdx.x;
-    const int4 g = sg < ns ? segs[sg] : make_int4(0, 0, 0, 0);
+// Phase tables X[n0 + M0][j], Y[n1 + M1][j] (|n| <= M), Z[n2][j] (0 <= n2 < NZP, zero
+// past M2), each entry from the FP64 product n s reduced to [-1/2, 1/2].
+__global__ __launch_bounds__(256) void k_ewald_tables(int N, const float4 *__restrict__ xyzt, Cell c, int M0,
+                                                      int M1, int M2, int NZP, float2 *__restrict__ X,
+                                                      float2 *__restrict__ Y, float2 *__restrict__ Z) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    const float4 pa = xyzt[j];
+    double s0, s1, s2;
+    frac_coords(pa.x, pa.y, pa.z, c, s0, s1, s2);
+    for (int n = -M0; n <= M0; ++n) X[(size_t)(n + M0) * N + j] = turn_phase((double)n * s0);
+    for (int n = -M1; n <= M1; ++n) Y[(size_t)(n + M1) * N + j] = turn_phase((double)n * s1);
+    for (int n = 0; n < NZP; ++n) Z[(size_t)n * N + j] = n <= M2 ? turn_phase((double)n * s2) : make_float2(0.f, 0.f);
+}
+
+__device__ inline float2 cmul(float2 a, float2 b) {
+    return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+
+// Partial structure factors: block (row block, atom chunk, n2 tile pair); each wave 16
+// complex rows (two M-tiles of 8 rows x (re, im)) by 32 n2 (two N-tiles), two atoms per
+// step.  Spart[chunk][row][n2][re, im].
+constexpr int ESK_WROWS = 16, ESK_BROWS = 4 * ESK_WROWS;
+__global__ __launch_bounds__(256) void k_ewald_sk_mfma(int N, int chunk, const float *__restrict__ qraw,
+                                                       const double *__restrict__ scalars,
+                                                       const int4 *__restrict__ rows,
+                                                       const int *__restrict__ nrows_p, int row_cap, int NZP,
+                                                       int M0, int M1, const float2 *__restrict__ X,
+                                                       const float2 *__restrict__ Y, const float2 *__restrict__ Z,
+                                                       float *__restrict__ Spart) {
+    const int nrows = *nrows_p;
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int row0 = blockIdx.x * ESK_BROWS + wave * ESK_WROWS;
+    if (row0 >= nrows) return;  // the whole wave
+    const int jb = blockIdx.y * chunk, je = min(N, jb + chunk);
+    const int nt0 = blockIdx.z * 32;  // first n2 of this block
     const float delta = (float)scalars[S_DELTA];
-    float re[EW_SEG], im[EW_SEG];
+    const int m = l & 15, kk = l >> 4;
+    const int o = m >> 3, rho = m & 7, jj = kk >> 1, p = kk & 1;
+    // A = [[P_re, -P_im], [P_im, P_re]]: picks of (P_re, P_im) and a sign
+    const bool take_re = (o == p);
+    const float sgn = (o == 0 && p == 1) ? -1.0f : 1.0f;
+    int xa = 0, ya = 0, xb = 0, yb = 0;
+    bool va = false, vb = false;
+    {
+        const int ra = row0 + rho, rb = row0 + 8 + rho;
+        va = ra < nrows;
+        vb = rb < nrows;
+        const int4 ea = rows[va ? ra : 0], eb = rows[vb ? rb : 0];
+        xa = ea.x + M0; ya = ea.y + M1;
+        xb = eb.x + M0; yb = eb.y + M1;
+    }
+    const float2 *Xa = X + (size_t)xa * N, *Ya = Y + (size_t)ya * N;
+    const float2 *Xb = X + (size_t)xb * N, *Yb = Y + (size_t)yb * N;
+    const int n2a = nt0 + m, n2b = nt0 + 16 + m;  // B columns of the two N-tiles (n = l % 16)
+    const bool zb_ok = n2b < NZP;
+    const float2 *Za = Z + (size_t)n2a * N, *Zb = Z + (size_t)(zb_ok ? n2b : n2a) * N;
+    floatx4 acc[2][2];
 #pragma unroll
-    for (int m = 0; m < EW_SEG; ++m) re[m] = im[m] = 0.f;
-    const int a0 = blockIdx.y * EW_CHUNK, a1 = min(N, a0 + EW_CHUNK);
-    for (int t0 = a0; t0 < a1; t0 += 256) {
-        __syncthreads();
-        const int a = t0 + threadIdx.x;
-        if (a < a1) {
-            const float4 pa = xyzt[a];
-            double s0, s1, s2;
-            frac_coords(pa.x, pa.y, pa.z, c, s0, s1, s2);
-            sx[threadIdx.x] = s0;
-            sy[threadIdx.x] = s1;
-            sz[threadIdx.x] = s2;
-            sq[threadIdx.x] = qraw[a] + delta;
-            float cs, sn;
-            phase_cs(0, 0, 1, s0, s1, s2, cs, sn);
-            st[threadIdx.x] = make_float2(cs, sn);
-        }
-        __syncthreads();
-        const int m = min(256, a1 - t0);
-        if (sg < ns) {
-            for (int u = 0; u < m; ++u) {
-                float cs, sn;
-                phase_cs(g.x, g.y, g.z, sx[u], sy[u], sz[u], cs, sn);
-                const float q = sq[u];
-                const float2 r = st[u];
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-                for (int e = 0; e < EW_SEG; ++e) {
-                    if (e < g.w) {
-                        re[e] = fmaf(q, cs, re[e]);
-                        im[e] = fmaf(-q, sn, im[e]);
-                        const float c2 = fmaf(cs, r.x, -sn * r.y);
-                        sn = fmaf(sn, r.x, cs * r.y);
-                        cs = c2;
-                    }
-                }
+        for (int t = 0; t < 2; ++t) acc[a][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int j0 = jb; j0 < je; j0 += 2) {
+        const int j = j0 + jj;
+        const bool ok = j < je;
+        const int jc = ok ? j : jb;
+        const float q = ok ? qraw[jc] + delta : 0.0f;
+        const float2 pa = cmul(Xa[jc], Ya[jc]), pb = cmul(Xb[jc], Yb[jc]);
+        const float2 za = Za[jc], zb = Zb[jc];
+        const float aa = va ? sgn * q * (take_re ? pa.x : pa.y) : 0.0f;
+        const float ab = vb ? sgn * q * (take_re ? pb.x : pb.y) : 0.0f;
+        const float ba = p ? za.y : za.x;
+        const float bb = zb_ok ? (p ? zb.y : zb.x) : 0.0f;
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(aa, ba, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(aa, bb, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ab, ba, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(ab, bb, acc[1][1], 0, 0, 0);
+    }
+    // D[i][n]: n = l % 16, i = 4 (l / 16) + e: output part i / 8, complex row i % 8
+    float *out = Spart + (size_t)blockIdx.y * row_cap * NZP * 2;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int n2 = nt0 + 16 * t + (l & 15);
+            if (n2 >= NZP) continue;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int i = 4 * (l >> 4) + e;
+                const int row = row0 + 8 * a + (i & 7);
+                if (row < nrows) out[((size_t)row * NZP + n2) * 2 + (i >> 3)] = acc[a][t][e];
             }
         }
-    }
-    if (sg < ns) {
-        const int k0 = segoff[sg];
-#pragma unroll
-        for (int e = 0; e < EW_SEG; ++e)
-            if (e < g.w) Spart[(size_t)blockIdx.y * cap + k0 + e] = make_float2(re[e], im[e]);
-    }
 }
 
-// S(k) = sum over chunks (FP64); energy 2 k_e G |S|^2 and virial 2 k_e G |S|^2 B(k)
-__global__ __launch_bounds__(256) void k_structure_reduce(int nchunks, const float2 *__restrict__ Spart,
-                                                          const float4 *__restrict__ kv,
-                                                          const int *__restrict__ kcount, int64_t cap,
-                                                          double alpha, float2 *__restrict__ Sk,
+// S(k) = sum over chunks (FP64) for every (row, n2) of the box; energy 2 k_e G |S|^2
+// and virial 2 k_e G |S|^2 B(k) over the half set; Sk in the order of the wave-vector
+// list; U[row][c][n2] = w_c G S (w = 1, k_x, k_y, k_z), zero outside the row's range.
+__global__ __launch_bounds__(256) void k_ewald_reduce_box(int nchunks, const float *__restrict__ Spart,
+                                                          const int4 *__restrict__ rows,
+                                                          const int *__restrict__ rowoff,
+                                                          const int *__restrict__ nrows_p, int row_cap, int NZP,
+                                                          int NZ4, const float4 *__restrict__ kv, double alpha,
+                                                          float2 *__restrict__ Sk, float2 *__restrict__ U,
                                                           double *__restrict__ partials) {
-    const int nk = *kcount;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nrows = *nrows_p;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int row = (int)(t / NZP), n2 = (int)(t - (int64_t)row * NZP);
     double red[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    if (k < nk) {
+    if (row < nrows) {
         double re = 0.0, im = 0.0;
         for (int ch = 0; ch < nchunks; ++ch) {
-            float2 v = Spart[(size_t)ch * cap + k];
-            re += v.x;
-            im += v.y;
+            const float *v = Spart + (((size_t)ch * row_cap + row) * NZP + n2) * 2;
+            re += v[0];
+            im += v[1];
         }
-        Sk[k] = make_float2((float)re, (float)im);
-        float4 q = kv[k];
-        double kx = q.x, ky = q.y, kz = q.z, G = q.w;
-        double k2 = kx * kx + ky * ky + kz * kz;
-        double e = 2.0 * KE * G * (re * re + im * im);
-        double cB = 2.0 / (4.0 * alpha * alpha) + 2.0 / k2;
-        double kk[3] = {kx, ky, kz};
-        red[0] = e;
+        const int4 e = rows[row];
+        const bool in = n2 >= e.z && n2 < e.z + e.w;
+        float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (in) {
+            const int k = rowoff[row] + n2 - e.z;
+            q = kv[k];
+            Sk[k] = make_float2((float)re, (float)im);
+            const double kx = q.x, ky = q.y, kz = q.z, G = q.w;
+            const double k2 = kx * kx + ky * ky + kz * kz;
+            const double en = 2.0 * KE * G * (re * re + im * im);
+            const double cB = 2.0 / (4.0 * alpha * alpha) + 2.0 / k2;
+            const double kk[3] = {kx, ky, kz};
+            red[0] = en;
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
+            for (int a = 0; a < 3; ++a)
 #pragma unroll
-            for (int b = 0; b < 3; ++b) red[1 + 3 * a + b] = e * ((a == b ? 1.0 : 0.0) - cB * kk[a] * kk[b]);
+                for (int b = 0; b < 3; ++b) red[1 + 3 * a + b] = en * ((a == b ? 1.0 : 0.0) - cB * kk[a] * kk[b]);
+        }
+        if (n2 < NZ4) {
+            const float gr = q.w * (float)re, gi = q.w * (float)im;  // zero outside the range
+            float2 *u = U + (size_t)row * 4 * NZ4 + n2;
+            u[0] = make_float2(gr, gi);
+            u[NZ4] = make_float2(q.x * gr, q.x * gi);
+            u[2 * NZ4] = make_float2(q.y * gr, q.y * gi);
+            u[3 * NZ4] = make_float2(q.z * gr, q.z * gi);
+        }
     }
     block_partials<10>(red, partials);
 }
 
-// phi^k_i = 4 k_e sum_half G Re[S e^{i k.r_i}],  F^k_i = 4 k_e q'_i sum_half k G Im[S e^{i k.r_i}]
-// by row segments: the segment and wave-vector data are uniform across the block
-// (scalar loads); each atom's phase is formed once per segment and rotated by 2 pi s2
-// along it.
-__global__ __launch_bounds__(256) void k_ewald_atoms_rows(int N, const float4 *__restrict__ xyzt, Cell c,
-                                                          const float *__restrict__ qraw,
-                                                          const double *__restrict__ scalars,
-                                                          const float4 *__restrict__ kv,
-                                                          const int4 *__restrict__ segs,
-                                                          const int *__restrict__ segoff,
-                                                          const int *__restrict__ nseg,
-                                                          const float2 *__restrict__ Sk,
-                                                          float *__restrict__ phi, float *__restrict__ Fst) {
-    const int ns = *nseg;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    double s0 = 0, s1 = 0, s2 = 0;
-    if (i < N) {
-        const float4 pa = xyzt[i];
-        frac_coords(pa.x, pa.y, pa.z, c, s0, s1, s2);
-    }
-    float rc, rs;
-    phase_cs(0, 0, 1, s0, s1, s2, rc, rs);
-    float ph = 0.f, fx = 0.f, fy = 0.f, fz = 0.f;
-    for (int sg = 0; sg < ns; ++sg) {
-        const int4 g = segs[sg];
-        const int k0 = segoff[sg];
-        float cs, sn;
-        phase_cs(g.x, g.y, g.z, s0, s1, s2, cs, sn);
-        for (int e = 0; e < g.w; ++e) {
-            const float2 S = Sk[k0 + e];
-            const float4 q = kv[k0 + e];
-            const float re = S.x * cs - S.y * sn;
-            const float im = S.x * sn + S.y * cs;
-            ph = fmaf(q.w, re, ph);
-            const float gi = q.w * im;
-            fx = fmaf(q.x, gi, fx);
-            fy = fmaf(q.y, gi, fy);
-            fz = fmaf(q.z, gi, fz);
-            const float c2 = fmaf(cs, rc, -sn * rs);
-            sn = fmaf(sn, rc, cs * rs);
-            cs = c2;
+// Per-atom sums, block (atom block, row chunk): each wave 32 atoms (two N-tiles), the
+// outputs V_c(n2) of all (channel, n2) in M-tiles of 8 x (re, im), two rows per step;
+// then sum_n2 conj Z_i(n2) V_c(n2) per atom.  Writes the row chunk's partial potential
+// and force sums ephi[chunk][4][N] (summed in order by k_ewald_atoms_finish).
+constexpr int EA_MT = 12;  // M-tiles per pass: 4 channels x NZ4 x (re, im) / 16 = NZ4 / 2
+__global__ __launch_bounds__(256) void k_ewald_atoms_mfma(int N, const int4 *__restrict__ rows,
+                                                          const int *__restrict__ nrows_p, int rchunk, int NZ4,
+                                                          int M0, int M1, const float2 *__restrict__ U,
+                                                          const float2 *__restrict__ X, const float2 *__restrict__ Y,
+                                                          const float2 *__restrict__ Z, float *__restrict__ ephi) {
+    const int nrows = *nrows_p;
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int atom0 = (blockIdx.x * 4 + wave) * 32;
+    const int rb = blockIdx.y * rchunk, re = min(nrows, rb + rchunk);
+    const int n = l & 15, kk = l >> 4, rr = kk >> 1, p = kk & 1;
+    const int ia = atom0 + n, ib = atom0 + 16 + n;
+    const int ica = ia < N ? ia : 0, icb = ib < N ? ib : 0;
+    const int mtiles = NZ4 / 2;
+    float sums[2][4];  // per N-tile atom: potential, force x, y, z
+#pragma unroll
+    for (int w = 0; w < 2; ++w)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sums[w][c] = 0.f;
+    // this lane's A element: output index gm = 16 tile + n -> part o = gm & 1 of
+    // (channel, n2) = gm >> 1; A = [[U_re, -U_im], [U_im, U_re]]
+    const int o = n & 1;
+    const bool take_re = (o == p);
+    const float sgn = (o == 0 && p == 1) ? -1.0f : 1.0f;
+    for (int t0 = 0; t0 < mtiles; t0 += EA_MT) {
+        floatx4 acc[EA_MT][2];
+#pragma unroll
+        for (int t = 0; t < EA_MT; ++t) acc[t][0] = acc[t][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int r0 = rb; r0 < re; r0 += 2) {
+            const int r = r0 + rr;
+            const bool ok = r < re;
+            const int4 e = rows[ok ? r : rb];
+            // B = conj(X_i Y_i)(r): (re, im) on the two K rows p of this row
+            const float2 ca = cmul(X[(size_t)(e.x + M0) * N + ica], Y[(size_t)(e.y + M1) * N + ica]);
+            const float2 cb = cmul(X[(size_t)(e.x + M0) * N + icb], Y[(size_t)(e.y + M1) * N + icb]);
+            const float ba = ok ? (p ? -ca.y : ca.x) : 0.0f;
+            const float bb = ok ? (p ? -cb.y : cb.x) : 0.0f;
+            const float2 *ur = U + (size_t)(ok ? r : rb) * 4 * NZ4;
+#pragma unroll
+            for (int t = 0; t < EA_MT; ++t) {
+                if (t0 + t < mtiles) {
+                    const float2 u = ur[(16 * (t0 + t) + n) >> 1];
+                    const float av = ok ? sgn * (take_re ? u.x : u.y) : 0.0f;
+                    acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, ba, acc[t][0], 0, 0, 0);
+                    acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bb, acc[t][1], 0, 0, 0);
+                }
+            }
+        }
+        // D[i][n]: i = 4 (l / 16) + e -> gm = 16 tile + i; elements (0, 1) and (2, 3) are
+        // (re, im) of V at (channel, n2) = gm >> 1 for atom n of each N-tile
+#pragma unroll
+        for (int t = 0; t < EA_MT; ++t) {
+            if (t0 + t >= mtiles) continue;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int cn = (16 * (t0 + t) + 4 * kk + 2 * h) >> 1;
+                const int ch = cn / NZ4, n2 = cn - ch * NZ4;
+#pragma unroll
+                for (int w = 0; w < 2; ++w) {
+                    const float2 z = Z[(size_t)n2 * N + (w ? icb : ica)];
+                    const float vr = acc[t][w][2 * h], vi = acc[t][w][2 * h + 1];
+                    // (vr + i vi) conj(z): the real part for the potential, the imaginary for the force
+                    const float pr = fmaf(vr, z.x, vi * z.y), pim = fmaf(vi, z.x, -vr * z.y);
+                    sums[w][ch] += ch == 0 ? pr : pim;
+                }
+            }
         }
     }
-    if (i < N) {
-        const float qi = qraw[i] + (float)scalars[S_DELTA];
-        const float k4 = 4.0f * (float)KE;
-        phi[i] += k4 * ph;
-        Fst[i] += k4 * qi * fx;
-        Fst[(size_t)N + i] += k4 * qi * fy;
-        Fst[(size_t)2 * N + i] += k4 * qi * fz;
+    // the four lane groups (l / 16) hold different (channel, n2) of the same atoms
+#pragma unroll
+    for (int w = 0; w < 2; ++w)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            sums[w][c] += __shfl_xor(sums[w][c], 16, 64);
+            sums[w][c] += __shfl_xor(sums[w][c], 32, 64);
+        }
+    if (kk == 0) {
+        float *out = ephi + (size_t)blockIdx.y * 4 * N;
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+            const int i = w ? ib : ia;
+            if (i < N)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) out[(size_t)c * N + i] = sums[w][c];
+        }
     }
 }
 
+// phi^k_i = 4 k_e sum_half G Re[S e^{i k.r_i}],  F^k_i = 4 k_e q'_i sum_half k G Im[S e^{i k.r_i}]:
+// the row chunks' partial sums in chunk order, added to the real-space values
+__global__ __launch_bounds__(256) void k_ewald_atoms_finish(int N, int nchunks, const float *__restrict__ ephi,
+                                                            const float *__restrict__ qraw,
+                                                            const double *__restrict__ scalars,
+                                                            float *__restrict__ phi, float *__restrict__ Fst) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    float s[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int ch = 0; ch < nchunks; ++ch)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) s[c] += ephi[((size_t)ch * 4 + c) * N + i];
+    const float qi = qraw[i] + (float)scalars[S_DELTA];
+    const float k4 = 4.0f * (float)KE;
+    phi[i] += k4 * s[0];
+    Fst[i] += k4 * qi * s[1];
+    Fst[(size_t)N + i] += k4 * qi * s[2];
+    Fst[(size_t)2 * N + i] += k4 * qi * s[3];
+}
 // per-atom reciprocal virial (Eq. 20) over the half set: W^k_i = 2 k_e q'_i sum_half G
 // Re[S e^{i k.r_i}] B(k), B = I - (2/(4 alpha^2) + 2/k^2) k k; added to Vat
 __global__ __launch_bounds__(256) void k_ewald_virial_atoms(int N, const float4 *__restrict__ xyzt, Cell c,
@@ -578,27 +700,32 @@ __global__ __launch_bounds__(256) void k_ewald_virial_atoms(int N, const float4 
 
 hipError_t launch_ewald(const Plan &p) {
     int4 *kn = (int4 *)(p.kvec + p.nk_cap);
-    hipLaunchKernelGGL(k_kvector_rows, dim3(1), dim3(1024), 0, p.stream, p.cell, p.nk_box[0], p.nk_box[1],
-                       p.nk_box[2], p.kmax * p.kmax, p.kinc, p.alpha, p.vol, p.nk_cap, p.seg_cap, p.kvec, kn,
-                       p.ksegs, p.ksegoff, p.kcount, p.knseg);
-    const int kb = (int)((p.nk_cap + 255) / 256);
-    const int sbk = (int)((p.seg_cap + 255) / 256);
-    hipLaunchKernelGGL(k_structure_factor_rows, dim3(sbk, p.s_chunks), dim3(256), 0, p.stream, p.N, p.xyzt,
-                       p.cell, p.qraw, p.scalars, p.ksegs, p.ksegoff, p.knseg, p.nk_cap, p.Spart);
-    hipLaunchKernelGGL(k_structure_reduce, dim3(kb), dim3(256), 0, p.stream, p.s_chunks, p.Spart, p.kvec,
-                       p.kcount, p.nk_cap, p.alpha, p.Sk, p.partials);
+    const int M0 = p.nk_box[0], M1 = p.nk_box[1], M2 = p.nk_box[2];
+    hipLaunchKernelGGL(k_kvector_rows, dim3(1), dim3(1024), 0, p.stream, p.cell, M0, M1, M2, p.kmax * p.kmax,
+                       p.kinc, p.alpha, p.vol, p.nk_cap, p.row_cap, p.kvec, kn, p.krows, p.krowoff, p.kcount,
+                       p.knrows);
+    const int G = (p.N + 255) / 256;
+    hipLaunchKernelGGL(k_ewald_tables, dim3(G), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, M0, M1, M2, p.NZP,
+                       p.ewX, p.ewY, p.ewZ);
+    hipLaunchKernelGGL(k_ewald_sk_mfma, dim3((p.row_cap + ESK_BROWS - 1) / ESK_BROWS, p.s_chunks, (p.NZP + 31) / 32),
+                       dim3(256), 0, p.stream, p.N, p.s_chunk, p.qraw, p.scalars, p.krows, p.knrows, p.row_cap,
+                       p.NZP, M0, M1, p.ewX, p.ewY, p.ewZ, p.Spart);
+    const int kb = (int)(((int64_t)p.row_cap * p.NZP + 255) / 256);
+    hipLaunchKernelGGL(k_ewald_reduce_box, dim3(kb), dim3(256), 0, p.stream, p.s_chunks, p.Spart, p.krows,
+                       p.krowoff, p.knrows, p.row_cap, p.NZP, p.NZ4, p.kvec, p.alpha, p.Sk, p.Ubox, p.partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = reduce_partials(p, kb, 10, S_UK, false);  // S_UK, S_WK[9]
     if (e != hipSuccess) return e;
-    stage_mark(p, ST_EWALD_SK, 4);
-    const int G = (p.N + 255) / 256;
-    hipLaunchKernelGGL(k_ewald_atoms_rows, dim3(G), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, p.qraw,
-                       p.scalars, p.kvec, p.ksegs, p.ksegoff, p.knseg, p.Sk, p.phi, p.Fst);
+    stage_mark(p, ST_EWALD_SK, 5);
+    hipLaunchKernelGGL(k_ewald_atoms_mfma, dim3((p.N + 127) / 128, p.r_chunks), dim3(256), 0, p.stream, p.N,
+                       p.krows, p.knrows, p.r_chunk, p.NZ4, M0, M1, p.Ubox, p.ewX, p.ewY, p.ewZ, p.ephi);
+    hipLaunchKernelGGL(k_ewald_atoms_finish, dim3(G), dim3(256), 0, p.stream, p.N, p.r_chunks, p.ephi, p.qraw,
+                       p.scalars, p.phi, p.Fst);
     if (p.out.virial_atom)
         hipLaunchKernelGGL(k_ewald_virial_atoms, dim3(G), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell,
                            (float)p.alpha, p.qraw, p.scalars, p.kvec, (const int4 *)kn, p.Sk, p.kcount, p.Vat);
-    stage_mark(p, ST_EWALD_ATOMS, p.out.virial_atom ? 2 : 1);
+    stage_mark(p, ST_EWALD_ATOMS, p.out.virial_atom ? 3 : 2);
     return hipGetLastError();
 }
 

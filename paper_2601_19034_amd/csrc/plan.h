@@ -53,7 +53,11 @@ struct Plan {
     // ---- Ewald
     int nk_box[3] = {0, 0, 0};
     int64_t nk_cap = 0;      // capacity of the half k-set
-    int s_chunks = 0;        // atom chunks of the structure-factor kernel
+    int row_cap = 0;         // rows (n0, n1) of the k box: an upper bound of the nonempty rows
+    int NZP = 0;             // n2 entries per row in the structure-factor and phase tables (16 | NZP)
+    int NZ4 = 0;             // n2 entries per row in the per-atom product (even)
+    int s_chunks = 0, s_chunk = 0;  // atom chunks (count, atoms) of the structure-factor product
+    int r_chunks = 0, r_chunk = 0;  // row chunks (count, rows) of the per-atom product
     // ---- device workspace
     int32_t *flags = nullptr;
     double *scalars = nullptr;
@@ -77,11 +81,13 @@ struct Plan {
     float *Siso = nullptr; // isolated systems: sum_j (a_ji - a_ij) per atom [3][N], sorted order
     float4 *kvec = nullptr;   // (kx, ky, kz, G) of the half set
     int *kcount = nullptr;
-    int4 *ksegs = nullptr;    // row segments of the half set: (n0, n1, first n2, count)
-    int *ksegoff = nullptr;   // index of each segment's first wave vector
-    int *knseg = nullptr;     // number of segments
-    int64_t seg_cap = 0;
-    float2 *Spart = nullptr;  // [s_chunks][nk_cap]
+    int4 *krows = nullptr;    // nonempty rows of the half set: (n0, n1, first n2, count)
+    int *krowoff = nullptr;   // index of each row's first wave vector
+    int *knrows = nullptr;    // number of nonempty rows
+    float2 *ewX = nullptr, *ewY = nullptr, *ewZ = nullptr;  // phase tables [entry][N]
+    float *Spart = nullptr;   // [s_chunks][row_cap][NZP][re, im]
+    float2 *Ubox = nullptr;   // [row_cap][4][NZ4]: G S, k_x G S, k_y G S, k_z G S
+    float *ephi = nullptr;    // [r_chunks][4][N]: partial potential and force sums
     float2 *Sk = nullptr;     // [nk_cap]
     bool bricks = false;      // charge assignment by mesh bricks (else global atomics into rho)
     int brickP[3] = {0, 0, 0}, brickNb[3] = {0, 0, 0};

@@ -192,3 +192,22 @@ def test_new_entry_points_validation(qlib):
             B.qnep_snes_generation(h, 1, 1, 1, 8, 1.0, 0.0, tg, oc_noloss, 1, 1, 1 << 20, 0)
     finally:
         B.qnep_model_destroy(h)
+
+
+def test_workspace_size_of_tiny_systems(qlib):
+    """Sizing an empty or one-atom structure is valid under every electrostatics method
+    (the plan's work splits must not divide by a zero atom count)."""
+    from paper_2601_19034_amd import binding as B
+    w = inputs.workload(0)
+    h = B.qnep_model_create(w.hp, 0)
+    try:
+        cell = w.system.cell
+        for es_p in (w.es, inputs.ESParams(method=1, mesh=(16, 16, 16)),
+                     inputs.ESParams(**{**w.es.__dict__, "mode": 2})):
+            for n in (0, 1):
+                assert B.qnep_workspace_size(h, B.make_es(es_p), B.make_system(n, 0, 0, cell)) > 0
+        iso = inputs.ESParams(method=2)
+        for n in (0, 1):
+            assert B.qnep_workspace_size(h, B.make_es(iso), B.make_system(n, 0, 0, cell, periodic=False)) > 0
+    finally:
+        B.qnep_model_destroy(h)
