@@ -314,6 +314,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", type=int, default=3)
     ap.add_argument("--variant", default="full")
+    ap.add_argument("--method", choices=("pppm", "ewald"), default=None,
+                    help="reciprocal-space method of the timed workload (default: the workload's own)")
     ap.add_argument("--forms", default="fp32,bf16x3,bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched (structures x candidates) line")
@@ -344,8 +346,10 @@ def main():
         log("# copy calibration: 3 x 1 GiB device-to-device copies")
         del a, b
     w = inputs.workload(args.workload, args.variant)
+    if args.method is not None:
+        w.es.method = 1 if args.method == "pppm" else 0
     n = w.system.n
-    log(f"# workload {w.name}: N={n}, mesh={w.es.mesh}")
+    log(f"# workload {w.name}: N={n}, " + (f"mesh={w.es.mesh}" if w.es.method == 1 else f"Ewald kmax={w.es.kmax:.4f}"))
     pos, types, th = to_device_inputs(w.system, w.theta, "cuda:0")
     forms = {}
     stages = {}

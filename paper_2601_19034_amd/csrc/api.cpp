@@ -296,6 +296,8 @@ qnep_status make_plan(const Model &m, const qnep_es_params *es, const qnep_syste
         p.row_cap = (2 * p.nk_box[0] + 1) * (2 * p.nk_box[1] + 1);
         p.NZP = (p.nk_box[2] + 1 + 15) / 16 * 16;
         p.NZ4 = (p.nk_box[2] + 1 + 1) / 2 * 2;
+        if (ewald_atoms_lds_bytes(p.NZ4) > 65536)
+            return fail(QNEP_E_UNSUPPORTED, "Ewald: too many wave vectors along the third cell vector (kmax |c| / 2 pi > 93)");
         // about two thousand work-groups for each matrix-core product
         const int row_blocks = (p.row_cap + 63) / 64, zb = (p.NZP + 31) / 32;
         p.s_chunks = std::max(1, std::min((p.N + 63) / 64, 2048 / std::max(1, row_blocks * zb)));

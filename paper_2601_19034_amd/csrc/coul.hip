@@ -403,10 +403,12 @@ __device__ inline float2 cmul(float2 a, float2 b) {
     return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
 }
 
-// Partial structure factors: block (row block, atom chunk, n2 tile pair); each wave 16
-// complex rows (two M-tiles of 8 rows x (re, im)) by 32 n2 (two N-tiles), two atoms per
-// step.  Spart[chunk][row][n2][re, im].
-constexpr int ESK_WROWS = 16, ESK_BROWS = 4 * ESK_WROWS;
+// Partial structure factors: block (row block of 64, atom chunk, pair of n2 tiles).  Per
+// stage of ESK_SUB atoms the block forms P(r, j) = q'_j X_j(n0_r) Y_j(n1_r) for its rows
+// and copies Z_j(n2) for its n2 into LDS; each wave then multiplies 16 complex rows (two
+// M-tiles of 8 rows x (re, im)) by 32 n2 (two N-tiles), two atoms per step, from LDS.
+// Spart[chunk][row][n2][re, im].
+constexpr int ESK_WROWS = 16, ESK_BROWS = 4 * ESK_WROWS, ESK_SUB = 64, ESK_LD = ESK_SUB + 1;
 __global__ __launch_bounds__(256) void k_ewald_sk_mfma(int N, int chunk, const float *__restrict__ qraw,
                                                        const double *__restrict__ scalars,
                                                        const int4 *__restrict__ rows,
@@ -414,53 +416,63 @@ __global__ __launch_bounds__(256) void k_ewald_sk_mfma(int N, int chunk, const f
                                                        int M0, int M1, const float2 *__restrict__ X,
                                                        const float2 *__restrict__ Y, const float2 *__restrict__ Z,
                                                        float *__restrict__ Spart) {
+    __shared__ float2 Ps[ESK_BROWS][ESK_LD];
+    __shared__ float2 Zs[32][ESK_LD];
+    __shared__ int2 rowxy[ESK_BROWS];  // (n0 + M0, n1 + M1), or -1 past the last row
     const int nrows = *nrows_p;
+    const int brow0 = blockIdx.x * ESK_BROWS;
+    if (brow0 >= nrows) return;  // the whole block
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int row0 = blockIdx.x * ESK_BROWS + wave * ESK_WROWS;
-    if (row0 >= nrows) return;  // the whole wave
     const int jb = blockIdx.y * chunk, je = min(N, jb + chunk);
     const int nt0 = blockIdx.z * 32;  // first n2 of this block
     const float delta = (float)scalars[S_DELTA];
+    if (threadIdx.x < ESK_BROWS) {
+        const int r = brow0 + threadIdx.x;
+        const int4 e = rows[r < nrows ? r : 0];
+        rowxy[threadIdx.x] = r < nrows ? make_int2(e.x + M0, e.y + M1) : make_int2(-1, -1);
+    }
     const int m = l & 15, kk = l >> 4;
     const int o = m >> 3, rho = m & 7, jj = kk >> 1, p = kk & 1;
     // A = [[P_re, -P_im], [P_im, P_re]]: picks of (P_re, P_im) and a sign
     const bool take_re = (o == p);
     const float sgn = (o == 0 && p == 1) ? -1.0f : 1.0f;
-    int xa = 0, ya = 0, xb = 0, yb = 0;
-    bool va = false, vb = false;
-    {
-        const int ra = row0 + rho, rb = row0 + 8 + rho;
-        va = ra < nrows;
-        vb = rb < nrows;
-        const int4 ea = rows[va ? ra : 0], eb = rows[vb ? rb : 0];
-        xa = ea.x + M0; ya = ea.y + M1;
-        xb = eb.x + M0; yb = eb.y + M1;
-    }
-    const float2 *Xa = X + (size_t)xa * N, *Ya = Y + (size_t)ya * N;
-    const float2 *Xb = X + (size_t)xb * N, *Yb = Y + (size_t)yb * N;
-    const int n2a = nt0 + m, n2b = nt0 + 16 + m;  // B columns of the two N-tiles (n = l % 16)
-    const bool zb_ok = n2b < NZP;
-    const float2 *Za = Z + (size_t)n2a * N, *Zb = Z + (size_t)(zb_ok ? n2b : n2a) * N;
     floatx4 acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int t = 0; t < 2; ++t) acc[a][t] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int j0 = jb; j0 < je; j0 += 2) {
-        const int j = j0 + jj;
-        const bool ok = j < je;
-        const int jc = ok ? j : jb;
-        const float q = ok ? qraw[jc] + delta : 0.0f;
-        const float2 pa = cmul(Xa[jc], Ya[jc]), pb = cmul(Xb[jc], Yb[jc]);
-        const float2 za = Za[jc], zb = Zb[jc];
-        const float aa = va ? sgn * q * (take_re ? pa.x : pa.y) : 0.0f;
-        const float ab = vb ? sgn * q * (take_re ? pb.x : pb.y) : 0.0f;
-        const float ba = p ? za.y : za.x;
-        const float bb = zb_ok ? (p ? zb.y : zb.x) : 0.0f;
-        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(aa, ba, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(aa, bb, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ab, ba, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(ab, bb, acc[1][1], 0, 0, 0);
+    const int wr = wave * ESK_WROWS;
+    for (int j0 = jb; j0 < je; j0 += ESK_SUB) {
+        __syncthreads();  // row table in place / the previous stage consumed
+        const int ja = threadIdx.x & (ESK_SUB - 1), j = j0 + ja;
+        const bool jok = j < je;
+        const int jc = jok ? j : jb;
+        const float q = jok ? qraw[jc] + delta : 0.0f;
+        for (int r = threadIdx.x / ESK_SUB; r < ESK_BROWS; r += 256 / ESK_SUB) {
+            const int2 xy = rowxy[r];
+            float2 v = make_float2(0.f, 0.f);
+            if (xy.x >= 0) {
+                const float2 pr = cmul(X[(size_t)xy.x * N + jc], Y[(size_t)xy.y * N + jc]);
+                v = make_float2(q * pr.x, q * pr.y);
+            }
+            Ps[r][ja] = v;
+        }
+        for (int n = threadIdx.x / ESK_SUB; n < 32; n += 256 / ESK_SUB) {
+            const int n2 = nt0 + n;
+            Zs[n][ja] = (jok && n2 < NZP) ? Z[(size_t)n2 * N + jc] : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int s2 = 0; s2 < ESK_SUB; s2 += 2) {
+            const float2 pa = Ps[wr + rho][s2 + jj], pb = Ps[wr + 8 + rho][s2 + jj];
+            const float2 za = Zs[m][s2 + jj], zb = Zs[16 + m][s2 + jj];
+            const float aa = sgn * (take_re ? pa.x : pa.y), ab = sgn * (take_re ? pb.x : pb.y);
+            const float ba = p ? za.y : za.x, bb = p ? zb.y : zb.x;
+            acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(aa, ba, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(aa, bb, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ab, ba, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(ab, bb, acc[1][1], 0, 0, 0);
+        }
     }
     // D[i][n]: n = l % 16, i = 4 (l / 16) + e: output part i / 8, complex row i % 8
     float *out = Spart + (size_t)blockIdx.y * row_cap * NZP * 2;
@@ -473,7 +485,7 @@ __global__ __launch_bounds__(256) void k_ewald_sk_mfma(int N, int chunk, const f
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int i = 4 * (l >> 4) + e;
-                const int row = row0 + 8 * a + (i & 7);
+                const int row = brow0 + wr + 8 * a + (i & 7);
                 if (row < nrows) out[((size_t)row * NZP + n2) * 2 + (i >> 3)] = acc[a][t][e];
             }
         }
@@ -530,23 +542,34 @@ __global__ __launch_bounds__(256) void k_ewald_reduce_box(int nchunks, const flo
     block_partials<10>(red, partials);
 }
 
-// Per-atom sums, block (atom block, row chunk): each wave 32 atoms (two N-tiles), the
-// outputs V_c(n2) of all (channel, n2) in M-tiles of 8 x (re, im), two rows per step;
-// then sum_n2 conj Z_i(n2) V_c(n2) per atom.  Writes the row chunk's partial potential
-// and force sums ephi[chunk][4][N] (summed in order by k_ewald_atoms_finish).
+// Per-atom sums, block (atom block of 128, row chunk).  Per stage of EA_RB rows the block
+// copies U of those rows and forms conj(X_i Y_i)(r) of its atoms into LDS; each wave then
+// multiplies the outputs V_c(n2) of all (channel, n2) (M-tiles of 8 x (re, im)) for 32
+// atoms (two N-tiles), two rows per step, from LDS, and finally forms
+// sum_n2 conj Z_i(n2) V_c(n2).  Writes the row chunk's partial potential and force sums
+// ephi[chunk][4][N] (summed in order by k_ewald_atoms_finish).  LDS (dynamic):
+// U [EA_RB][4 NZ4] | conj(X Y) [EA_RB][128] | rows [EA_RB].
 constexpr int EA_MT = 12;  // M-tiles per pass: 4 channels x NZ4 x (re, im) / 16 = NZ4 / 2
+constexpr int EA_RB = 16;  // rows per stage
+size_t ewald_atoms_lds_bytes(int NZ4) {
+    return (size_t)EA_RB * 4 * NZ4 * sizeof(float2) + (size_t)EA_RB * 128 * sizeof(float2) + EA_RB * sizeof(int4);
+}
 __global__ __launch_bounds__(256) void k_ewald_atoms_mfma(int N, const int4 *__restrict__ rows,
                                                           const int *__restrict__ nrows_p, int rchunk, int NZ4,
                                                           int M0, int M1, const float2 *__restrict__ U,
                                                           const float2 *__restrict__ X, const float2 *__restrict__ Y,
                                                           const float2 *__restrict__ Z, float *__restrict__ ephi) {
+    extern __shared__ float2 ea_lds[];
+    const int nu = 4 * NZ4;
+    float2 *Us = ea_lds;                   // [EA_RB][nu]
+    float2 *Bs = Us + EA_RB * nu;          // [EA_RB][128]
+    int4 *rs = reinterpret_cast<int4 *>(Bs + EA_RB * 128);
     const int nrows = *nrows_p;
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int atom0 = (blockIdx.x * 4 + wave) * 32;
+    const int blk0 = blockIdx.x * 128, atom0 = blk0 + wave * 32;
     const int rb = blockIdx.y * rchunk, re = min(nrows, rb + rchunk);
     const int n = l & 15, kk = l >> 4, rr = kk >> 1, p = kk & 1;
     const int ia = atom0 + n, ib = atom0 + 16 + n;
-    const int ica = ia < N ? ia : 0, icb = ib < N ? ib : 0;
     const int mtiles = NZ4 / 2;
     float sums[2][4];  // per N-tile atom: potential, force x, y, z
 #pragma unroll
@@ -558,32 +581,48 @@ __global__ __launch_bounds__(256) void k_ewald_atoms_mfma(int N, const int4 *__r
     const int o = n & 1;
     const bool take_re = (o == p);
     const float sgn = (o == 0 && p == 1) ? -1.0f : 1.0f;
+    // this thread's atom in the LDS stage of conj(X Y)
+    const int sa = threadIdx.x & 127, sj = blk0 + sa, sjc = sj < N ? sj : 0;
     for (int t0 = 0; t0 < mtiles; t0 += EA_MT) {
         floatx4 acc[EA_MT][2];
 #pragma unroll
         for (int t = 0; t < EA_MT; ++t) acc[t][0] = acc[t][1] = floatx4{0.f, 0.f, 0.f, 0.f};
-        for (int r0 = rb; r0 < re; r0 += 2) {
-            const int r = r0 + rr;
-            const bool ok = r < re;
-            const int4 e = rows[ok ? r : rb];
-            // B = conj(X_i Y_i)(r): (re, im) on the two K rows p of this row
-            const float2 ca = cmul(X[(size_t)(e.x + M0) * N + ica], Y[(size_t)(e.y + M1) * N + ica]);
-            const float2 cb = cmul(X[(size_t)(e.x + M0) * N + icb], Y[(size_t)(e.y + M1) * N + icb]);
-            const float ba = ok ? (p ? -ca.y : ca.x) : 0.0f;
-            const float bb = ok ? (p ? -cb.y : cb.x) : 0.0f;
-            const float2 *ur = U + (size_t)(ok ? r : rb) * 4 * NZ4;
+        for (int r0 = rb; r0 < re; r0 += EA_RB) {
+            const int nr = min(EA_RB, re - r0);
+            __syncthreads();  // the previous stage consumed
+            if (threadIdx.x < EA_RB) rs[threadIdx.x] = rows[threadIdx.x < nr ? r0 + threadIdx.x : r0];
+            for (int k = threadIdx.x; k < EA_RB * nu; k += 256)
+                Us[k] = k < nr * nu ? U[(size_t)r0 * nu + k] : make_float2(0.f, 0.f);
+            __syncthreads();  // row table in place
+            for (int r = threadIdx.x >> 7; r < EA_RB; r += 2) {
+                float2 v = make_float2(0.f, 0.f);
+                if (r < nr && sj < N) {
+                    const int4 e = rs[r];
+                    const float2 c = cmul(X[(size_t)(e.x + M0) * N + sjc], Y[(size_t)(e.y + M1) * N + sjc]);
+                    v = make_float2(c.x, -c.y);
+                }
+                Bs[r * 128 + sa] = v;
+            }
+            __syncthreads();
+            for (int s2 = 0; s2 < nr; s2 += 2) {
+                const int r = s2 + rr;  // rows past nr are zero in both operands
+                const float2 ca = Bs[r * 128 + wave * 32 + n], cb = Bs[r * 128 + wave * 32 + 16 + n];
+                const float ba = p ? ca.y : ca.x, bb = p ? cb.y : cb.x;
+                const float2 *ur = Us + r * nu;
 #pragma unroll
-            for (int t = 0; t < EA_MT; ++t) {
-                if (t0 + t < mtiles) {
-                    const float2 u = ur[(16 * (t0 + t) + n) >> 1];
-                    const float av = ok ? sgn * (take_re ? u.x : u.y) : 0.0f;
-                    acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, ba, acc[t][0], 0, 0, 0);
-                    acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bb, acc[t][1], 0, 0, 0);
+                for (int t = 0; t < EA_MT; ++t) {
+                    if (t0 + t < mtiles) {
+                        const float2 u = ur[(16 * (t0 + t) + n) >> 1];
+                        const float av = sgn * (take_re ? u.x : u.y);
+                        acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, ba, acc[t][0], 0, 0, 0);
+                        acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bb, acc[t][1], 0, 0, 0);
+                    }
                 }
             }
         }
         // D[i][n]: i = 4 (l / 16) + e -> gm = 16 tile + i; elements (0, 1) and (2, 3) are
         // (re, im) of V at (channel, n2) = gm >> 1 for atom n of each N-tile
+        const int ica = ia < N ? ia : 0, icb = ib < N ? ib : 0;
 #pragma unroll
         for (int t = 0; t < EA_MT; ++t) {
             if (t0 + t >= mtiles) continue;
@@ -718,7 +757,8 @@ hipError_t launch_ewald(const Plan &p) {
     e = reduce_partials(p, kb, 10, S_UK, false);  // S_UK, S_WK[9]
     if (e != hipSuccess) return e;
     stage_mark(p, ST_EWALD_SK, 5);
-    hipLaunchKernelGGL(k_ewald_atoms_mfma, dim3((p.N + 127) / 128, p.r_chunks), dim3(256), 0, p.stream, p.N,
+    hipLaunchKernelGGL(k_ewald_atoms_mfma, dim3((p.N + 127) / 128, p.r_chunks), dim3(256),
+                       ewald_atoms_lds_bytes(p.NZ4), p.stream, p.N,
                        p.krows, p.knrows, p.r_chunk, p.NZ4, M0, M1, p.Ubox, p.ewX, p.ewY, p.ewZ, p.ephi);
     hipLaunchKernelGGL(k_ewald_atoms_finish, dim3(G), dim3(256), 0, p.stream, p.N, p.r_chunks, p.ephi, p.qraw,
                        p.scalars, p.phi, p.Fst);

@@ -117,6 +117,7 @@ hipError_t launch_real_space(const Plan &p);
 hipError_t launch_direct_coulomb(const Plan &p);
 hipError_t launch_centroid(const Plan &p);
 hipError_t launch_ewald(const Plan &p);
+size_t ewald_atoms_lds_bytes(int NZ4);  // dynamic LDS of the per-atom Ewald product
 hipError_t launch_pppm(const Plan &p);
 // mesh bricks of the charge assignment: edge P (points) and count nb per axis
 struct BrickGeom {
