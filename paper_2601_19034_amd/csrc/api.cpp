@@ -551,6 +551,12 @@ qnep_status batch_layout(const Model &m, const qnep_es_params *es, const qnep_ba
     bp.stats = c.take<double>((size_t)S * C_max * 4);
     bp.rmse = c.take<double>((size_t)C_max * 4);
     bp.scratch = c.take<float>((size_t)BATCH_MAX_SLOTS * bp.per_slot);
+    bp.F = LM * NA + 2 * ndes;
+    bp.C16_max = (C_max + 15) / 16 * 16;
+    bp.persist = c.take<float>((size_t)bp.F * C_max * bp.n_total);
+    bp.qbuf = c.take<float>((size_t)bp.n_total * bp.C16_max);
+    bp.ybuf = c.take<float>((size_t)bp.ncomp * C_max * bp.n_total);
+    bp.iscal = c.take<double>((size_t)S * C_max * 2);
     bp.grad = (bt->flags & QNEP_BATCH_GRADIENT) != 0;
     if (bp.grad) {
         bp.per_slot_adj = batch_adj_floats(T, NR, NA, NB, hp.n_neu) * bp.max_atoms;
@@ -943,6 +949,12 @@ qnep_status batch_args(const Model &m, const float *thetas, int C, const qnep_ba
     a.stats = b.stats;
     a.scratch = b.scratch;
     a.max_atoms = b.max_atoms;
+    a.persist = b.persist;
+    a.F = b.F;
+    a.qbuf = b.qbuf;
+    a.C16 = (a.C + 15) / 16 * 16;
+    a.ybuf = b.ybuf;
+    a.iscal = b.iscal;
     return QNEP_OK;
 }
 

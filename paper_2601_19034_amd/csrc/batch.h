@@ -64,6 +64,14 @@ struct BatchArgs {
     double *stats;           // [S][C][4]: E, sum |F - F_ref|^2, s sum q, 0
     float *scratch;          // per slot: [(3 ndes + 24 NA)][max_atoms]
     int max_atoms;
+    // between the forward launches
+    float *persist;          // per item (s, c): [F][n_s] moments A (24 NA), dU/dD, dq/dD (ndes each),
+                             // at F (C atom0_s + c n_s)
+    int F;                   // 24 NA + 2 ndes
+    float *qbuf;             // [n_total][C16] corrected charges q'
+    int C16;                 // candidates rounded up to 16
+    float *ybuf;             // per item: [ncomp][n_s] pair-matrix products, at ncomp (C atom0_s + c n_s)
+    double *iscal;           // [S][C][2]: sum U_i, sum q_i
 };
 
 // Extra arguments of the adjoint launch (gradient of the loss with respect to theta).
@@ -113,6 +121,9 @@ struct BatchPlan {
     float2 *ph = nullptr;
     float *mats = nullptr, *scratch = nullptr;
     double *stats = nullptr;
+    float *persist = nullptr, *qbuf = nullptr, *ybuf = nullptr;
+    double *iscal = nullptr;
+    int F = 0, C16_max = 0;
     // gradient buffers (QNEP_BATCH_GRADIENT)
     bool grad = false;
     int64_t per_slot_adj = 0;

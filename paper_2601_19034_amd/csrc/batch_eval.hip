@@ -86,7 +86,7 @@ __device__ inline Item make_item(const BatchArgs &a, int item, int4 groups) {
 // sums B[t][k] of every atom, SoA with stride M.
 template <int T, int NR, int NA, int NB>
 __device__ __forceinline__ void item_descriptors(const BatchArgs &a, const Item &it, const float *th, int M,
-                                                 float *sD, float *sA, float *sB) {
+                                                 float *sD, float *sA, float *sB, int MA) {
     const float *cR = th, *cA = th + a.off_cA;
     const int G = kDescGroups[it.cls], lig = threadIdx.x % G, grp = threadIdx.x / G, per_round = BATCH_THREADS / G;
     for (int i0 = 0; i0 < it.n; i0 += per_round) {
@@ -177,7 +177,7 @@ __device__ __forceinline__ void item_descriptors(const BatchArgs &a, const Item 
             sD[(size_t)(NR + 2 * NA + q) * M + i] = s3;
             sD[(size_t)(NR + 3 * NA + q) * M + i] = s4;
 #pragma unroll
-            for (int m = 0; m < LM; ++m) sA[(size_t)(q * LM + m) * M + i] = Am[q][m];
+            for (int m = 0; m < LM; ++m) sA[(size_t)(q * LM + m) * MA + i] = Am[q][m];
         }
     }
 }
@@ -193,7 +193,7 @@ __device__ __forceinline__ void item_descriptors(const BatchArgs &a, const Item 
 template <int T, int NR, int NA>
 __device__ __forceinline__ void item_network(const BatchArgs &a, const Item &it, const float *th, int M,
                                              const float *sD, float *sgU, float *sgq, float *qv, double &accU,
-                                             double &accQ, bool fp32) {
+                                             double &accQ, bool fp32, int MG) {
     constexpr int NDES = NR + 4 * NA;
     const float *nnet = th + a.off_nn;
     const float b1E = th[a.off_b1E];
@@ -306,8 +306,8 @@ __device__ __forceinline__ void item_network(const BatchArgs &a, const Item &it,
                     for (int e = 0; e < 4; ++e) {
                         const int v = 16 * vt + 4 * lg + e;
                         if (v < NDES) {
-                            sgU[(size_t)v * M + row] = gA[vt][e];
-                            sgq[(size_t)v * M + row] = gB[vt][e];
+                            sgU[(size_t)v * MG + row] = gA[vt][e];
+                            sgq[(size_t)v * MG + row] = gB[vt][e];
                         }
                     }
             }
@@ -355,8 +355,8 @@ __device__ __forceinline__ void item_network(const BatchArgs &a, const Item &it,
 #pragma unroll
         for (int d = 0; d < NDES; ++d) {
             if (d % G != lig) continue;
-            sgU[(size_t)d * M + i] = gu[d];
-            sgq[(size_t)d * M + i] = gqv[d];
+            sgU[(size_t)d * MG + i] = gu[d];
+            sgq[(size_t)d * MG + i] = gqv[d];
         }
         if (lig == 0) {
             const float qi = qp - w1q[a.H];  // b1q follows w1q
@@ -367,9 +367,120 @@ __device__ __forceinline__ void item_network(const BatchArgs &a, const Item &it,
     }
 }
 
-// ---------------------------------------------------------------- forward launch
+// ---------------------------------------------------------------- forward launches
+// Three launches per set of items: (1) k_batch_front, per item: parameters staged in
+// LDS, descriptors, network, charge scaling and neutrality correction; the moments and
+// the network gradients go to the item's block of a.persist and the corrected charges
+// q' to a.qbuf[atom][candidate]; (2) k_batch_es_gemm, per structure: the Ewald pair
+// matrices [comp][j][i] times the charges of all candidates [j][c] on the matrix cores
+// (each matrix is read once for all candidates), into a.ybuf; (3) k_batch_back, per
+// item: chi = phi - mean(phi), partial forces, energy, virial and losses.
 template <int T, int NR, int NA, int NB>
-__global__ __launch_bounds__(BATCH_THREADS) void k_batch_eval(BatchArgs a, int item_begin, int item_end,
+__global__ __launch_bounds__(BATCH_THREADS) void k_batch_front(BatchArgs a, int item_begin, int item_end,
+                                                               int4 groups) {
+    constexpr int NDES = NR + 4 * NA;
+    extern __shared__ double lds[];
+    __shared__ double red[4 * 16];
+    __shared__ int s_item;
+    const int M = a.max_atoms;
+    float *th = reinterpret_cast<float *>(lds);  // parameters of the candidate
+    float *qv = th + a.n_theta;                   // q per atom
+    const int tid = threadIdx.x;
+    float *sD = a.scratch + (size_t)blockIdx.x * (3 * NDES + LM * NA) * M;
+    for (;;) {
+        if (tid == 0) s_item = item_begin + atomicAdd(a.counter, 1);
+        __syncthreads();
+        const int item = s_item;
+        if (item >= item_end) break;
+        const Item it = make_item(a, item, groups);
+        const int n = it.n;
+        float *sA = a.persist + (size_t)a.F * ((size_t)a.C * it.atom0 + (size_t)it.c * n);
+        float *sgU = sA + (size_t)LM * NA * n, *sgq = sgU + (size_t)NDES * n;
+        const float *thc = a.thetas + (size_t)it.c * a.n_theta;
+        for (int k = tid; k < a.n_theta; k += BATCH_THREADS) th[k] = thc[k];
+        __syncthreads();
+        const float sc = th[a.off_s];
+        item_descriptors<T, NR, NA, NB>(a, it, th, M, sD, sA, nullptr, n);
+        __syncthreads();
+        double accU = 0.0, accQ = 0.0;
+        item_network<T, NR, NA>(a, it, th, M, sD, sgU, sgq, qv, accU, accQ, false, n);
+        double r1[2] = {accU, accQ};
+        block_sum<2>(r1, red);
+        // neutrality correction on the scaled charges: q~' = s q + (Q - s sum q)/N, q' = q~'/s
+        const float delta = (float)((a.qtot / (double)sc - r1[1]) / n);
+        for (int i = tid; i < n; i += BATCH_THREADS) a.qbuf[(size_t)(it.atom0 + i) * a.C16 + it.c] = qv[i] + delta;
+        if (tid == 0) {
+            const size_t sc_idx = (size_t)it.s * a.C + it.c;
+            a.iscal[2 * sc_idx] = r1[0];
+            a.iscal[2 * sc_idx + 1] = r1[1];
+        }
+        __syncthreads();
+    }
+}
+
+// y[c][comp][i] = sum_j M[comp][j][i] q'_c[j] for the structures of ranks [rank0, rank0 +
+// gridDim.y), all candidates at once: block (row block of 128 rows (comp, i), structure),
+// each wave 32 rows (two M-tiles) x 64 candidates (four N-tiles), four atoms j per step,
+// v_mfma_f32_16x16x4f32 (lane l: A[i][k] at i = l % 16, k = l / 16; B[k][j] at
+// j = l % 16, k = l / 16; D[i][j] at j = l % 16, i = 4 (l / 16) + e).
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_batch_es_gemm(BatchArgs a, int rank0) {
+    const int s = a.order[rank0 + blockIdx.y];
+    const BatchStruct &b = a.st[s];
+    const int n = b.n, rows = a.ncomp * n;
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int row0 = blockIdx.x * 128 + wave * 32;
+    if (row0 >= rows) return;  // the whole wave; no block-wide synchronization below
+    const float *Mb = a.mats + b.mat0;
+    const int64_t nn = (int64_t)n * n;
+    const int m = l & 15, k = l >> 4;
+    const int ra = row0 + m, rb = row0 + 16 + m;
+    const bool va = ra < rows, vb = rb < rows;
+    const int ca = va ? ra / n : 0, cb = vb ? rb / n : 0;
+    const float *pa = Mb + ca * nn + (va ? ra - ca * n : 0);
+    const float *pb = Mb + cb * nn + (vb ? rb - cb * n : 0);
+    const float *Q = a.qbuf + (size_t)b.atom0 * a.C16;
+    const int C = a.C;
+    floatx4_t acc[2][4];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[u][t] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    for (int j0 = 0; j0 < n; j0 += 4) {
+        const int j = j0 + k;
+        const bool ok = j < n;
+        const int jc = ok ? j : 0;
+        const float xa = (ok && va) ? pa[(int64_t)jc * n] : 0.f;
+        const float xb = (ok && vb) ? pb[(int64_t)jc * n] : 0.f;
+        float bv[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int c = 16 * t + m;
+            bv[t] = (ok && c < C) ? Q[(size_t)jc * a.C16 + c] : 0.f;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            acc[0][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa, bv[t], acc[0][t], 0, 0, 0);
+            acc[1][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xb, bv[t], acc[1][t], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int c = 16 * t + m;
+        if (c >= C) continue;
+        float *y = a.ybuf + (size_t)a.ncomp * ((size_t)C * b.atom0 + (size_t)c * n);
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = row0 + 16 * u + 4 * k + e;
+                if (row < rows) y[row] = acc[u][t][e];
+            }
+    }
+}
+
+template <int T, int NR, int NA, int NB>
+__global__ __launch_bounds__(BATCH_THREADS) void k_batch_back(BatchArgs a, int item_begin, int item_end,
                                                               int4 groups) {
     constexpr int NDES = NR + 4 * NA;
     extern __shared__ double lds[];
@@ -384,8 +495,6 @@ __global__ __launch_bounds__(BATCH_THREADS) void k_batch_eval(BatchArgs a, int i
     float *qv = th + a.n_theta;                      // q' per atom
     float *phi = qv + M;                             // potential, then chi
     const int tid = threadIdx.x;
-    float *scr = a.scratch + (size_t)blockIdx.x * (3 * NDES + LM * NA) * M;
-    float *sD = scr, *sA = scr + (size_t)NDES * M, *sgU = sA + (size_t)LM * NA * M, *sgq = sgU + (size_t)NDES * M;
     const float *cR = th, *cA = th + a.off_cA;
 
     for (;;) {
@@ -397,40 +506,22 @@ __global__ __launch_bounds__(BATCH_THREADS) void k_batch_eval(BatchArgs a, int i
         const int n = it.n, G = it.G, lig = it.lig;
         const float *thc = a.thetas + (size_t)it.c * a.n_theta;
         for (int k = tid; k < a.n_theta; k += BATCH_THREADS) th[k] = thc[k];
+        for (int i = tid; i < n; i += BATCH_THREADS) qv[i] = a.qbuf[(size_t)(it.atom0 + i) * a.C16 + it.c];
         __syncthreads();
         const float sc = th[a.off_s];
+        const size_t sc_idx0 = (size_t)it.s * a.C + it.c;
+        const double sumU = a.iscal[2 * sc_idx0], sumq = a.iscal[2 * sc_idx0 + 1];
+        const float *sA = a.persist + (size_t)a.F * ((size_t)a.C * it.atom0 + (size_t)it.c * n);
+        const float *sgU = sA + (size_t)LM * NA * n, *sgq = sgU + (size_t)NDES * n;
 
-        item_descriptors<T, NR, NA, NB>(a, it, th, M, sD, sA, nullptr);
-        __syncthreads();
-        double accU = 0.0, accQ = 0.0;
-        item_network<T, NR, NA>(a, it, th, M, sD, sgU, sgq, qv, accU, accQ, false);
-        double r1[2] = {accU, accQ};
-        block_sum<2>(r1, red);
-        const double sumU = r1[0], sumq = r1[1];
-        // neutrality correction on the scaled charges: q~' = s q + (Q - s sum q)/N, q' = q~'/s
-        const float delta = (float)((a.qtot / (double)sc - sumq) / n);
-        for (int i = tid; i < n; i += BATCH_THREADS) qv[i] += delta;
-        __syncthreads();
-
-        // ---- electrostatics: y = M q' for every stored component
+        // ---- electrostatics: y = M q' for every stored component (from the product launch)
         double accP = 0.0, accE = 0.0, wes[6] = {0, 0, 0, 0, 0, 0};
         {
-            const int64_t nn = (int64_t)n * n;
-            const float *Mb = a.mats + it.mat0;
+            const float *yb = a.ybuf + (size_t)a.ncomp * ((size_t)a.C * it.atom0 + (size_t)it.c * n);
             const int units = a.ncomp * n;
             for (int u = tid; u < units; u += BATCH_THREADS) {
                 const int comp = u / n, i = u - comp * n;
-                const float *col = Mb + comp * nn + i;
-                float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-                int j = 0;
-                for (; j + 3 < n; j += 4) {
-                    s0 = fmaf(col[(int64_t)j * n], qv[j], s0);
-                    s1 = fmaf(col[(int64_t)(j + 1) * n], qv[j + 1], s1);
-                    s2 = fmaf(col[(int64_t)(j + 2) * n], qv[j + 2], s2);
-                    s3 = fmaf(col[(int64_t)(j + 3) * n], qv[j + 3], s3);
-                }
-                for (; j < n; ++j) s0 = fmaf(col[(int64_t)j * n], qv[j], s0);
-                const float y = (s0 + s1) + (s2 + s3);
+                const float y = yb[u];
                 const float qi = qv[i];
                 if (comp == 0) {
                     phi[i] = y;
@@ -475,7 +566,7 @@ __global__ __launch_bounds__(BATCH_THREADS) void k_batch_eval(BatchArgs a, int i
                 float gR[NR];
 #pragma unroll
                 for (int q = 0; q < NR; ++q)
-                    gR[q] = act ? fmaf(chi, sgq[(size_t)q * M + i], sgU[(size_t)q * M + i]) : 0.f;
+                    gR[q] = act ? fmaf(chi, sgq[(size_t)q * n + i], sgU[(size_t)q * n + i]) : 0.f;
                 float ev[T][NB];
 #pragma unroll
                 for (int t = 0; t < T; ++t)
@@ -521,11 +612,11 @@ __global__ __launch_bounds__(BATCH_THREADS) void k_batch_eval(BatchArgs a, int i
                     float Gl[4];
 #pragma unroll
                     for (int l = 0; l < 4; ++l) {
-                        const size_t rw = (size_t)(NR + l * NA + q) * M + i;
+                        const size_t rw = (size_t)(NR + l * NA + q) * n + i;
                         Gl[l] = act ? 2.0f * fmaf(chi, sgq[rw], sgU[rw]) : 0.f;
                     }
 #pragma unroll
-                    for (int m = 0; m < LM; ++m) At[q][m] = act ? Gl[lm_degree(m)] * sA[(size_t)(q * LM + m) * M + i] : 0.f;
+                    for (int m = 0; m < LM; ++m) At[q][m] = act ? Gl[lm_degree(m)] * sA[(size_t)(q * LM + m) * n + i] : 0.f;
                 }
                 for (int p = lig; p < nA; p += G) {
                     const float4 e = row[p];
@@ -699,10 +790,10 @@ __global__ __launch_bounds__(BATCH_THREADS) void k_batch_adjoint(BatchArgs a, Ad
         const float epsQ = rm[2] > 0 ? (float)(g.lam[2] * (st4[2] - a.qtot) / (a.S * rm[2])) : 0.f;
 
         // ---- forward quantities
-        item_descriptors<T, NR, NA, NB>(a, it, th, M, sD, sA, sB);
+        item_descriptors<T, NR, NA, NB>(a, it, th, M, sD, sA, sB, M);
         __syncthreads();
         double accU = 0.0, accQ = 0.0;
-        item_network<T, NR, NA>(a, it, th, M, sD, sgU, sgq, qv, accU, accQ, true);
+        item_network<T, NR, NA>(a, it, th, M, sD, sgU, sgq, qv, accU, accQ, true, M);
         double r1[1] = {accQ};
         block_sum<1>(r1, red);
         const double sumq = r1[0];
@@ -1170,17 +1261,31 @@ static hipError_t launch_persistent(K kernel, size_t lds_bytes, int n_slots, hip
 
 #define QNEP_BATCH_DISPATCH(T_, NR_, NA_, NB_)                                                              \
     if (T == T_ && NR == NR_ && NA == NA_ && NB == NB_) {                                                   \
-        hipError_t e0 = launch_persistent(k_batch_eval<T_, NR_, NA_, NB_>, lds_bytes, n_slots, stream);    \
+        hipError_t e0 = launch_persistent(k_batch_front<T_, NR_, NA_, NB_>, lds_front, n_slots, stream);   \
+        if (e0 == hipSuccess) e0 = launch_persistent(k_batch_back<T_, NR_, NA_, NB_>, lds_back, n_slots, stream); \
         if (e0 != hipSuccess) return e0;                                                                    \
-        hipLaunchKernelGGL((k_batch_eval<T_, NR_, NA_, NB_>), dim3(n_slots), dim3(BATCH_THREADS), lds_bytes, \
-                           stream, a, item_begin, item_end, groups);                                        \
+        BatchArgs a1 = a, a3 = a;                                                                           \
+        a3.counter = a.counter + 1;                                                                         \
+        hipLaunchKernelGGL((k_batch_front<T_, NR_, NA_, NB_>), dim3(n_slots), dim3(BATCH_THREADS), lds_front, \
+                           stream, a1, item_begin, item_end, groups);                                       \
+        hipLaunchKernelGGL(k_batch_es_gemm, dim3(gx, rank_end - rank_begin), dim3(256), 0, stream, a,       \
+                           rank_begin);                                                                     \
+        hipLaunchKernelGGL((k_batch_back<T_, NR_, NA_, NB_>), dim3(n_slots), dim3(BATCH_THREADS), lds_back,  \
+                           stream, a3, item_begin, item_end, groups);                                       \
         return hipGetLastError();                                                                           \
     }
 
+// Items [item_begin, item_end) must cover whole structures (multiples of a.C); the
+// caller zeroes a.counter[0..1].
 hipError_t batch_eval(const BatchArgs &a, int T, int NR, int NA, int NB, int n_slots, int item_begin,
                       int item_end, int4 groups, hipStream_t stream) {
-    const size_t lds_bytes =
+    if (item_begin % a.C != 0 || item_end % a.C != 0) return hipErrorInvalidValue;
+    if (item_end <= item_begin) return hipSuccess;
+    const size_t lds_front = sizeof(float) * ((size_t)a.n_theta + (size_t)a.max_atoms);
+    const size_t lds_back =
         sizeof(double) * 3 * (size_t)a.max_atoms + sizeof(float) * ((size_t)a.n_theta + 2 * (size_t)a.max_atoms);
+    const int rank_begin = item_begin / a.C, rank_end = item_end / a.C;
+    const int gx = (a.ncomp * a.max_atoms + 127) / 128;
     QNEP_BATCH_DISPATCH(1, 5, 5, 9)
     QNEP_BATCH_DISPATCH(2, 5, 5, 9)
     QNEP_BATCH_DISPATCH(3, 5, 5, 9)
