@@ -252,7 +252,7 @@ __device__ __forceinline__ void item_network(const BatchArgs &a, const Item &it,
                     const int j = 16 * jt + 4 * lg + e;
                     ge[jt][e] = gqq[jt][e] = 0.f;
                     if (jt < nJT && j < a.H) {
-                        const float hh = tanhf(acc[jt][e] - b0[j]);
+                        const float hh = tanh_fast(acc[jt][e] - b0[j]);
                         up = fmaf(w1E[j], hh, up);
                         qp = fmaf(w1q[j], hh, qp);
                         const float dh = 1.0f - hh * hh;

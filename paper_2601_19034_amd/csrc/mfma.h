@@ -10,10 +10,16 @@ namespace qnep {
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-__device__ inline short to_bf16(float f) {  // round to nearest even
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (short)(u >> 16);
+__device__ inline short to_bf16(float f) {  // round to nearest even (v_cvt_pk_bf16_f32)
+    const __bf16 b = (__bf16)f;
+    return __builtin_bit_cast(short, b);
+}
+
+// tanh x = sign(x) (1 - e) / (1 + e) with e = exp(-2 |x|) = 2^(-2 log2(e) |x|): absolute
+// error about 1e-7, far below the rounding of the BF16 network forms that use it
+__device__ inline float tanh_fast(float x) {
+    const float e = __builtin_amdgcn_exp2f(-2.8853900817779268f * fabsf(x));
+    return copysignf((1.0f - e) * __builtin_amdgcn_rcpf(1.0f + e), x);
 }
 
 // Lane layout of the 16x16x16 BF16 MFMA (wave64, lane l):

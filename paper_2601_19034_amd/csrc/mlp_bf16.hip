@@ -104,7 +104,7 @@ __global__ __launch_bounds__(256) void k_mlp_bf16(int N, int T, int H, int ndes,
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int j = 16 * jt + 4 * lg + e;
-                const float hh = tanhf(acc[jt][e] - sb0[tl][j]);
+                const float hh = tanh_fast(acc[jt][e] - sb0[tl][j]);
                 const float wE = sw1E[tl][j], wQ = sw1q[tl][j];  // zero for padded j
                 up = fmaf(wE, hh, up);
                 qp = fmaf(wQ, hh, qp);
