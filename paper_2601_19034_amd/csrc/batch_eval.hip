@@ -807,23 +807,34 @@ __global__ __launch_bounds__(BATCH_THREADS) void k_batch_adjoint(BatchArgs a, Ad
             uz[i] = kf * (Fc[2 * a.n_total + gi] - a.F_ref[2 * a.n_total + gi]);
         }
         __syncthreads();
-        // phi = A q' and sum_a u_ia (G_a q')_i
+        // phi = A q' and sum_a u_ia (G_a q')_i: with the FP32 network the forward launch
+        // of this gradient call formed the same products from the same q' (a.ybuf)
         const int64_t nn = (int64_t)n * n;
         const float *Mb = a.mats + it.mat0;
         double accP = 0.0;
-        for (int i = tid; i < n; i += BATCH_THREADS) {
-            float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-            for (int j = 0; j < n; ++j) {
-                const float qj = qv[j];
-                const int64_t o = (int64_t)j * n + i;
-                s0 = fmaf(Mb[o], qj, s0);
-                s1 = fmaf(Mb[nn + o], qj, s1);
-                s2 = fmaf(Mb[2 * nn + o], qj, s2);
-                s3 = fmaf(Mb[3 * nn + o], qj, s3);
+        if (a.prec == QNEP_MLP_FP32) {
+            const float *yb = a.ybuf + (size_t)a.ncomp * ((size_t)a.C * it.atom0 + (size_t)it.c * n);
+            for (int i = tid; i < n; i += BATCH_THREADS) {
+                const float s0 = yb[i], s1 = yb[n + i], s2 = yb[2 * n + i], s3 = yb[3 * n + i];
+                phi[i] = s0;
+                accP += (double)s0;
+                qb[i] = ux[i] * s1 + uy[i] * s2 + uz[i] * s3;
             }
-            phi[i] = s0;
-            accP += (double)s0;
-            qb[i] = ux[i] * s1 + uy[i] * s2 + uz[i] * s3;
+        } else {
+            for (int i = tid; i < n; i += BATCH_THREADS) {
+                float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+                for (int j = 0; j < n; ++j) {
+                    const float qj = qv[j];
+                    const int64_t o = (int64_t)j * n + i;
+                    s0 = fmaf(Mb[o], qj, s0);
+                    s1 = fmaf(Mb[nn + o], qj, s1);
+                    s2 = fmaf(Mb[2 * nn + o], qj, s2);
+                    s3 = fmaf(Mb[3 * nn + o], qj, s3);
+                }
+                phi[i] = s0;
+                accP += (double)s0;
+                qb[i] = ux[i] * s1 + uy[i] * s2 + uz[i] * s3;
+            }
         }
         double r2[1] = {accP};
         block_sum<1>(r2, red);
