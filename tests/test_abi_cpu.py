@@ -211,3 +211,18 @@ def test_workspace_size_of_tiny_systems(qlib):
             assert B.qnep_workspace_size(h, B.make_es(iso), B.make_system(n, 0, 0, cell, periodic=False)) > 0
     finally:
         B.qnep_model_destroy(h)
+
+
+def test_ewald_rejects_oversized_k_rows(qlib):
+    """A cell so long along c that the per-atom Ewald product's LDS stage of n2 values
+    would not fit is rejected at sizing, before any device work."""
+    from paper_2601_19034_amd import binding as B
+    w = inputs.workload(0)
+    h = B.qnep_model_create(w.hp, 0)
+    try:
+        es = B.make_es(w.es)
+        cell = np.diag([12.42, 12.42, 12.42 * 40])  # kmax |c| / 2 pi = 6 * 40 > 93
+        with pytest.raises(B.QnepError, match="wave vectors"):
+            B.qnep_workspace_size(h, es, B.make_system(w.system.n, 0, 0, cell))
+    finally:
+        B.qnep_model_destroy(h)

@@ -98,6 +98,22 @@ def test_water192_ewald(torch_dev, orc):
     assert g["energy_terms"][7] == r.terms[9]  # same wave-vector set (924)
 
 
+def test_water192_ewald_many_wave_vectors(torch_dev, orc):
+    """A large k-set (|n| up to 32 along every axis): more n2 per row than one
+    structure-factor block holds (two blocks of 32) and more (channel, n2) outputs
+    than one pass of the per-atom product holds (17 tiles, two passes).  A wide alpha
+    keeps the high-k terms above FP32 underflow."""
+    w = inputs.workload(0)
+    es = copy.copy(w.es)
+    es.alpha, es.kmax = 1.5, 2 * math.pi * 2.5
+    _say("case water-192 Ewald alpha 1.5, kmax 2 pi 2.5")
+    g = run_gpu(w.hp, es, w.system, w.theta)
+    r = _oracle(orc, w.hp, es, w.system, w.theta)
+    compare(g, r, w.system.n, label="water192-ewald-bigk")
+    assert g["energy_terms"][7] == r.terms[9]
+    assert r.terms[9] > 60000
+
+
 def test_water192_mode2_and_charge(torch_dev, orc):
     w = inputs.workload(0)
     for mode, Q in ((2, 0.0), (1, 0.7), (2, -1.1)):
