@@ -42,7 +42,10 @@ __device__ inline void mesh_stencil(float x, float y, float z, const Cell &c, co
     }
 }
 
+// j mod n in [0, n); stencil indices lie within one period of the mesh (n >= 3), which
+// takes two comparisons instead of an integer division by a run-time value
 __device__ inline int wrap_index(int j, int n) {
+    if (j >= -n && j < 2 * n) return j < 0 ? j + n : (j >= n ? j - n : j);
     j %= n;
     return j < 0 ? j + n : j;
 }
