@@ -396,7 +396,7 @@ qnep_status make_plan(const Model &m, const qnep_es_params *es, const qnep_syste
         b.sCA = c.take<double>((size_t)p.T * p.T * p.NA * p.NBA);
         const int64_t widest = std::max(std::max<int64_t>((int64_t)p.H * p.ndes, 3 * p.H + 1),
                                         std::max<int64_t>((int64_t)p.NR * p.T * p.NBR, (int64_t)p.T * p.NA * p.NBA));
-        b.partials = c.take<double>((size_t)((N + 1023) / 1024) * p.T * widest);
+        b.partials = c.take<double>((size_t)masked_outer_chunks(N) * p.T * widest);
     }
     *bytes = (c.off + ALIGN - 1) / ALIGN * ALIGN;
     return QNEP_OK;

@@ -14,6 +14,7 @@
 //  dL/dh = gE h^{-T} (sum_i F_i (x) r_i - W)^T  (strain identity with W = -dE/d(strain)).
 // Parameter sums over atoms are species-masked outer products reduced per chunk of
 // atoms in FP32 and across chunks in FP64.
+#include "mfma.h"
 #include "nep_math.h"
 #include "plan.h"
 
@@ -149,65 +150,130 @@ __global__ __launch_bounds__(256) void k_bw_angular(int N, const float4 *__restr
     }
 }
 
-// out[blk][t][a][b] = sum_{i in chunk, ts_i = t} X[a][i] Y[b][i]   (Y = null: ones)
-constexpr int MO_CHUNK = 1024, MO_TILE = 32, MO_PER = 16;
+// Species-masked outer-product sums on the matrix cores (v_mfma_f32_16x16x4f32):
+//   partials[blk][t][a][b] = sum over the atoms i of chunk blk with ts_i = t of X[a][i] Y[b][i]
+// (Y = null: ones).  Per chunk this is the product X [A x K] Ym [K x T B] with
+// Ym[i][t B + b] = Y[b][i] [ts_i = t]; the mask is applied while forming the B operand.
+// Each wave owns up to MO_TPW output tiles of 16 x 16; a K tile of MO_KT atoms is staged
+// in LDS for the whole work-group.  FP32 accumulation within a chunk, FP64 across chunks.
+constexpr int MO_KT = 64, MO_LD = MO_KT + 1, MO_TPW = 8, MO_WAVES = 4;
 
-__global__ __launch_bounds__(256) void k_masked_outer(int N, int T, int A, int B, const float *__restrict__ X,
-                                                      const float *__restrict__ Y, const int *__restrict__ ts,
-                                                      double *__restrict__ partials) {
-    extern __shared__ float sm[];
-    float *sX = sm, *sY = sm + A * MO_TILE;
-    int *st = reinterpret_cast<int *>(sY + B * MO_TILE);
-    const int a0 = blockIdx.x * MO_CHUNK, a1 = min(N, a0 + MO_CHUNK);
-    const int npairs = A * B;
-    float acc[MO_PER][MAX_T];
+// rows [0, R) of atoms [b0, b0 + nv) of a [R][N] array into LDS rows of stride MO_LD,
+// zero past nv; MO_BATCH loads per thread are issued before their LDS stores (src = null:
+// the constant fill)
+constexpr int MO_BATCH = 8;
+__device__ inline void stage_rows(float *dst, const float *__restrict__ src, int R, int N, int b0, int nv, float fill) {
+    for (int base = threadIdx.x; base < R * MO_KT; base += MO_BATCH * 256) {
+        float v[MO_BATCH];
 #pragma unroll
-    for (int k = 0; k < MO_PER; ++k)
-#pragma unroll
-        for (int t = 0; t < MAX_T; ++t) acc[k][t] = 0.f;
-    for (int b0 = a0; b0 < a1; b0 += MO_TILE) {
-        const int nv = min(MO_TILE, a1 - b0);
-        for (int idx = threadIdx.x; idx < A * MO_TILE; idx += blockDim.x) {
-            const int a = idx / MO_TILE, u = idx % MO_TILE;
-            sX[idx] = u < nv ? X[(size_t)a * N + b0 + u] : 0.f;
+        for (int j = 0; j < MO_BATCH; ++j) {
+            const int idx = base + j * 256, r = idx / MO_KT, u = idx % MO_KT;
+            v[j] = (idx < R * MO_KT && u < nv) ? (src ? src[(size_t)r * N + b0 + u] : fill) : 0.f;
         }
-        for (int idx = threadIdx.x; idx < B * MO_TILE; idx += blockDim.x) {
-            const int b = idx / MO_TILE, u = idx % MO_TILE;
-            sY[idx] = u < nv ? (Y ? Y[(size_t)b * N + b0 + u] : 1.0f) : 0.f;
+#pragma unroll
+        for (int j = 0; j < MO_BATCH; ++j) {
+            const int idx = base + j * 256;
+            if (idx < R * MO_KT) dst[(idx / MO_KT) * MO_LD + idx % MO_KT] = v[j];
         }
-        for (int u = threadIdx.x; u < MO_TILE; u += blockDim.x) st[u] = u < nv ? ts[b0 + u] : 0;
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < MO_PER; ++k) {
-            const int p = threadIdx.x + k * 256;
-            if (p < npairs) {
-                const int a = p / B, b = p % B;
-                for (int u = 0; u < nv; ++u) {
-                    const float v = sX[a * MO_TILE + u] * sY[b * MO_TILE + u];
-                    const int t = st[u];
-#pragma unroll
-                    for (int tt = 0; tt < MAX_T; ++tt) acc[k][tt] += (t == tt) ? v : 0.f;
-                }
-            }
-        }
-        __syncthreads();
-    }
-    double *out = partials + (size_t)blockIdx.x * T * npairs;
-#pragma unroll
-    for (int k = 0; k < MO_PER; ++k) {
-        const int p = threadIdx.x + k * 256;
-        if (p < npairs)
-            for (int t = 0; t < T; ++t) out[(size_t)t * npairs + p] = acc[k][t];
     }
 }
 
-// fixed-order sum over blocks: dst[k] = sum_b partials[b][k]
-__global__ void k_sum_blocks(const double *__restrict__ partials, int nblk, int nv, double *__restrict__ dst) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nv) return;
+// Work-group (x, y) takes atom chunk x and output tiles [y tpb, (y + 1) tpb); wave w of it
+// takes the tiles y tpb + w + MO_WAVES s, s < TPW.
+template <int TPW>
+__global__ __launch_bounds__(256) void k_masked_outer(int N, int T, int A, int B, int chunk, int tpb,
+                                                      const float *__restrict__ X, const float *__restrict__ Y,
+                                                      const int *__restrict__ ts, double *__restrict__ partials) {
+    // LDS: X rows 0..A-1 and a zero row A, Y rows 0..B-1 and a zero row B, the species
+    // of the staged atoms; padding rows, columns and tiles read the zero rows, so the
+    // product loop has no branches
+    extern __shared__ float sm[];
+    float *sX = sm, *sY = sm + (A + 1) * MO_LD;
+    int *st = reinterpret_cast<int *>(sY + (B + 1) * MO_LD);
+    const int C = T * B, MC = (C + 15) / 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i16 = lane & 15, k4 = lane >> 4;
+    const int a0 = blockIdx.x * chunk, a1 = min(N, a0 + chunk);
+    const int t_lo = blockIdx.y * tpb, t_hi = t_lo + tpb;
+    for (int u = threadIdx.x; u < MO_KT; u += blockDim.x) {
+        sX[A * MO_LD + u] = 0.f;
+        sY[B * MO_LD + u] = 0.f;
+    }
+    // per tile: LDS offsets of the A-operand row and the B-operand row of this lane, and
+    // the species its column belongs to (-2: padding)
+    int xo[TPW], yo[TPW], tc[TPW];
+    floatx4 acc[TPW];
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) {
+        acc[s] = floatx4{0.f, 0.f, 0.f, 0.f};
+        const int tile = t_lo + wave + MO_WAVES * s;
+        const bool ok = tile < t_hi;
+        const int ra = (tile / MC) * 16 + i16, cc = (tile % MC) * 16 + i16;
+        xo[s] = (ok && ra < A ? ra : A) * MO_LD;
+        const int t = cc / B;
+        const bool okc = ok && cc < C;
+        tc[s] = okc ? t : -2;
+        yo[s] = (okc ? cc - t * B : B) * MO_LD;
+    }
+    for (int b0 = a0; b0 < a1; b0 += MO_KT) {
+        const int nv = min(MO_KT, a1 - b0);
+        stage_rows(sX, X, A, N, b0, nv, 0.f);
+        if (Y) stage_rows(sY, Y, B, N, b0, nv, 0.f);
+        else stage_rows(sY, (const float *)nullptr, B, N, b0, nv, 1.0f);
+        for (int u = threadIdx.x; u < MO_KT; u += blockDim.x) st[u] = u < nv ? ts[b0 + u] : -1;
+        __syncthreads();
+        for (int kk = 0; kk < MO_KT; kk += 4) {
+            const int u = kk + k4;
+            const int tu = st[u];
+            float av[TPW], bv[TPW];
+#pragma unroll
+            for (int s = 0; s < TPW; ++s) {
+                av[s] = sX[xo[s] + u];
+                bv[s] = sY[yo[s] + u];
+            }
+#pragma unroll
+            for (int s = 0; s < TPW; ++s)
+                acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], tc[s] == tu ? bv[s] : 0.f, acc[s], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // D[i][j] sits in lane j + 16 (i / 4), element i % 4
+    double *out = partials + (size_t)blockIdx.x * C * A;
+    const int tiles = ((A + 15) / 16) * MC;
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) {
+        const int tile = t_lo + wave + MO_WAVES * s;
+        if (tile >= t_hi || tile >= tiles) continue;
+        const int col = (tile % MC) * 16 + i16;
+        if (col >= C) continue;
+        const int t = col / B, b = col - t * B;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int row = (tile / MC) * 16 + 4 * k4 + e;
+            if (row < A) out[((size_t)t * A + row) * B + b] = acc[s][e];
+        }
+    }
+}
+
+// fixed-order sum over blocks: dst[k] = sum_b partials[b][k]; 16 strided partial sums
+// per output, combined in index order
+__global__ __launch_bounds__(256) void k_sum_blocks(const double *__restrict__ partials, int nblk, int nv,
+                                                    double *__restrict__ dst) {
+    __shared__ double red[16][17];
+    const int kl = threadIdx.x & 15, g = threadIdx.x >> 4;
+    const int k = blockIdx.x * 16 + kl;
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += partials[(size_t)b * nv + k];
-    dst[k] = s;
+    if (k < nv) {
+#pragma unroll 4
+        for (int b = g; b < nblk; b += 16) s += partials[(size_t)b * nv + k];
+    }
+    red[g][kl] = s;
+    __syncthreads();
+    if (g == 0 && k < nv) {
+        double t = 0.0;
+        for (int j = 0; j < 16; ++j) t += red[j][kl];
+        dst[k] = t;
+    }
 }
 
 struct BwLayout {
@@ -315,13 +381,35 @@ static hipError_t run_bw_angular(const Plan &p) {
 
 static hipError_t launch_bw_angular(const Plan &p) { QNEP_DISPATCH_BW(run_bw_angular) }
 
-static hipError_t masked_outer(const Plan &p, int A, int B, const float *X, const float *Y, double *dst) {
-    const int nblk = (p.N + MO_CHUNK - 1) / MO_CHUNK;
-    const int nv = p.T * A * B;
-    const size_t lds = sizeof(float) * (size_t)(A + B) * MO_TILE + sizeof(int) * MO_TILE;
-    hipLaunchKernelGGL(k_masked_outer, dim3(nblk), dim3(256), lds, p.stream, p.N, p.T, A, B, X, Y, p.ts,
+template <int TPW>
+static void launch_masked_outer(const Plan &p, dim3 grid, size_t lds, int A, int B, int chunk, int tpb, const float *X,
+                                const float *Y) {
+    hipLaunchKernelGGL(k_masked_outer<TPW>, grid, dim3(256), lds, p.stream, p.N, p.T, A, B, chunk, tpb, X, Y, p.ts,
                        p.bw.partials);
-    hipLaunchKernelGGL(k_sum_blocks, dim3((nv + 255) / 256), dim3(256), 0, p.stream, p.bw.partials, nblk, nv, dst);
+}
+
+static hipError_t masked_outer(const Plan &p, int A, int B, const float *X, const float *Y, double *dst) {
+    const int nblk = masked_outer_chunks(p.N);
+    const int chunk = (p.N + nblk - 1) / nblk;
+    const int tiles = ((A + 15) / 16) * ((p.T * B + 15) / 16);
+    const int gy = (tiles + MO_WAVES * MO_TPW - 1) / (MO_WAVES * MO_TPW);
+    const int tpb = (tiles + gy - 1) / gy;           // tiles per work-group, balanced over y
+    const int tpw = (tpb + MO_WAVES - 1) / MO_WAVES;  // tiles per wave, at most MO_TPW
+    const int nv = p.T * A * B;
+    const size_t lds = sizeof(float) * (size_t)(A + B + 2) * MO_LD + sizeof(int) * MO_KT;
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    const dim3 grid(nblk, gy);
+    switch (tpw) {
+        case 1: launch_masked_outer<1>(p, grid, lds, A, B, chunk, tpb, X, Y); break;
+        case 2: launch_masked_outer<2>(p, grid, lds, A, B, chunk, tpb, X, Y); break;
+        case 3: launch_masked_outer<3>(p, grid, lds, A, B, chunk, tpb, X, Y); break;
+        case 4: launch_masked_outer<4>(p, grid, lds, A, B, chunk, tpb, X, Y); break;
+        case 5: launch_masked_outer<5>(p, grid, lds, A, B, chunk, tpb, X, Y); break;
+        case 6: launch_masked_outer<6>(p, grid, lds, A, B, chunk, tpb, X, Y); break;
+        case 7: launch_masked_outer<7>(p, grid, lds, A, B, chunk, tpb, X, Y); break;
+        default: launch_masked_outer<8>(p, grid, lds, A, B, chunk, tpb, X, Y); break;
+    }
+    hipLaunchKernelGGL(k_sum_blocks, dim3((nv + 15) / 16), dim3(256), 0, p.stream, p.bw.partials, nblk, nv, dst);
     return hipGetLastError();
 }
 
