@@ -23,6 +23,7 @@ hipError_t md_kick_record(const Plan &p, const double *masses, double dt, float 
                           const float *Z, const double *energy, const double *pol, double *sums, double *row);
 hipError_t launch_phi_mean(const Plan &p);
 bool mlp_bf16_supported(int ndes, int H);
+int masked_outer_chunks(int N);  // atom chunks of the reverse pass's parameter sums
 int radial_record_floats(int NB);
 int reduce_tmp_doubles();
 }  // namespace qnep

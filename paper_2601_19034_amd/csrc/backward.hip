@@ -14,6 +14,8 @@
 //  dL/dh = gE h^{-T} (sum_i F_i (x) r_i - W)^T  (strain identity with W = -dE/d(strain)).
 // Parameter sums over atoms are species-masked outer products reduced per chunk of
 // atoms in FP32 and across chunks in FP64.
+#include <algorithm>
+
 #include "mfma.h"
 #include "nep_math.h"
 #include "plan.h"
@@ -380,6 +382,9 @@ static hipError_t run_bw_angular(const Plan &p) {
     return hipErrorInvalidValue;
 
 static hipError_t launch_bw_angular(const Plan &p) { QNEP_DISPATCH_BW(run_bw_angular) }
+
+// atom chunks of the species-masked parameter sums (one FP64 partial row per chunk)
+int masked_outer_chunks(int N) { return N <= 0 ? 1 : std::min((N + 127) / 128, 512); }
 
 template <int TPW>
 static void launch_masked_outer(const Plan &p, dim3 grid, size_t lds, int A, int B, int chunk, int tpb, const float *X,

@@ -17,10 +17,6 @@ enum Stage : int {
 
 struct Timer;
 
-// atom chunks of the species-masked parameter sums of the reverse pass (one FP64 partial
-// row per chunk)
-inline int masked_outer_chunks(int N) { return N <= 0 ? 1 : (N + 127) / 128 < 512 ? (N + 127) / 128 : 512; }
-
 // reverse-mode state (qnep_backward)
 struct Backward {
     double gE = 0.0, gP[3] = {0.0, 0.0, 0.0};
