@@ -363,61 +363,111 @@ __global__ __launch_bounds__(256) void k_fft256(float2 *__restrict__ data, int S
     }
 }
 
+// One axis: nouter groups of S interleaved lines of length L, element t of line s of
+// group o at (o L + t) S + s, transformed in place.
+static hipError_t fft_lines(float2 *data, int L, int S, int nouter, int sign, hipStream_t s) {
+    static size_t lds_allowed = 65536;  // the default limit of dynamic LDS per work-group
+    FftPlan1D plan;
+    if (!make_plan(L, plan)) return hipErrorInvalidValue;
+    if (L == 256 && (S == 1 || S % 16 == 0 || S == 2 || S == 4 || S == 8)) {
+        const int mode = S == 1 ? 0 : (S % 16 == 0 ? 1 : 2);
+        const int blocks = mode == 0 ? (nouter + 15) / 16
+                                     : (mode == 1 ? nouter * (S / 16) : (nouter + 16 / S - 1) / (16 / S));
+        if (sign < 0)
+            hipLaunchKernelGGL(k_fft256<-1>, dim3(blocks), dim3(256), 0, s, data, S, nouter, mode);
+        else
+            hipLaunchKernelGGL(k_fft256<1>, dim3(blocks), dim3(256), 0, s, data, S, nouter, mode);
+        return hipGetLastError();
+    }
+    int B = FFT_ELEMS / L;
+    if (B < 1) B = 1;
+    int blocks;
+    if (S > 1) {
+        if (B > S) B = S;
+        blocks = nouter * ((S + B - 1) / B);
+    } else {
+        blocks = (nouter + B - 1) / B;
+    }
+    // twiddle table plus two buffers of B lines of L + 1 elements (at most 139 KB)
+    const size_t lds = sizeof(float2) * ((size_t)L + 2 * (size_t)(L + 1) * B);
+    if (lds > lds_allowed) {
+        hipError_t e =
+            hipFuncSetAttribute((const void *)k_fft_axis<-1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void *)k_fft_axis<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds);
+        if (e != hipSuccess) return e;
+        lds_allowed = lds;
+    }
+    const int ls = (L & (L - 1)) == 0 ? __builtin_ctz(L) : -1;
+    const int bs = (B & (B - 1)) == 0 ? __builtin_ctz(B) : -1;
+    if (sign < 0)
+        hipLaunchKernelGGL(k_fft_axis<-1>, dim3(blocks), dim3(FFT_THREADS), lds, s, data, plan, S, nouter, B, ls, bs);
+    else
+        hipLaunchKernelGGL(k_fft_axis<1>, dim3(blocks), dim3(FFT_THREADS), lds, s, data, plan, S, nouter, B, ls, bs);
+    return hipGetLastError();
+}
+
 // `inner` interleaved transforms: element (m0, m1, m2, t) of transform t at
 // ((m0 n1 + m1) n2 + m2) inner + t; they go through the same launches
 hipError_t fft3d(float2 *data, float2 * /*tmp*/, const int *mesh, int sign, hipStream_t s, int inner) {
-    static size_t lds_allowed = 65536;  // the default limit of dynamic LDS per work-group
     const int64_t M = (int64_t)mesh[0] * mesh[1] * mesh[2] * inner;
     for (int axis = 2; axis >= 0; --axis) {
-        FftPlan1D plan;
-        if (!make_plan(mesh[axis], plan)) return hipErrorInvalidValue;
         const int L = mesh[axis];
         const int S = inner * (axis == 2 ? 1 : (axis == 1 ? mesh[2] : mesh[1] * mesh[2]));
         const int nouter = (int)(M / ((int64_t)L * S));
-        if (L == 256 && (S == 1 || S % 16 == 0 || S == 2 || S == 4 || S == 8)) {
-            const int mode = S == 1 ? 0 : (S % 16 == 0 ? 1 : 2);
-            const int blocks = mode == 0 ? (nouter + 15) / 16
-                                         : (mode == 1 ? nouter * (S / 16) : (nouter + 16 / S - 1) / (16 / S));
-            if (sign < 0)
-                hipLaunchKernelGGL(k_fft256<-1>, dim3(blocks), dim3(256), 0, s, data, S, nouter, mode);
-            else
-                hipLaunchKernelGGL(k_fft256<1>, dim3(blocks), dim3(256), 0, s, data, S, nouter, mode);
-            hipError_t e = hipGetLastError();
-            if (e != hipSuccess) return e;
-            continue;
-        }
-        int B = FFT_ELEMS / L;
-        if (B < 1) B = 1;
-        int blocks;
-        if (S > 1) {
-            if (B > S) B = S;
-            blocks = nouter * ((S + B - 1) / B);
-        } else {
-            blocks = (nouter + B - 1) / B;
-        }
-        // twiddle table plus two buffers of B lines of L + 1 elements (at most 139 KB)
-        const size_t lds = sizeof(float2) * ((size_t)L + 2 * (size_t)(L + 1) * B);
-        if (lds > lds_allowed) {
-            hipError_t e = hipFuncSetAttribute((const void *)k_fft_axis<-1>,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            if (e == hipSuccess)
-                e = hipFuncSetAttribute((const void *)k_fft_axis<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)lds);
-            if (e != hipSuccess) return e;
-            lds_allowed = lds;
-        }
-        const int ls = (L & (L - 1)) == 0 ? __builtin_ctz(L) : -1;
-        const int bs = (B & (B - 1)) == 0 ? __builtin_ctz(B) : -1;
-        if (sign < 0)
-            hipLaunchKernelGGL(k_fft_axis<-1>, dim3(blocks), dim3(FFT_THREADS), lds, s, data, plan, S, nouter, B, ls,
-                               bs);
-        else
-            hipLaunchKernelGGL(k_fft_axis<1>, dim3(blocks), dim3(FFT_THREADS), lds, s, data, plan, S, nouter, B, ls,
-                               bs);
-        hipError_t e = hipGetLastError();
+        hipError_t e = fft_lines(data, L, S, nouter, sign, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+// ---------------------------------------------------------------- real input
+// Forward transform of a real mesh x[j0][j1][j2] (n1 and n2 even).  Lines j1 = 2p and
+// 2p + 1 are given as one complex line z_m = x[j0][2p][m] + i x[j0][2p+1][m] (the pair
+// interleaved, complex element (j0 n1 / 2 + p) n2 + m) and transformed together along
+// c; the two real lines' spectra are X_k = (Z_k + conj Z_{-k}) / 2 and
+// Y_k = (Z_k - conj Z_{-k}) / 2i, of which k = 0 .. H = n2 / 2 are kept, X_0 and X_H
+// (real) packed as X_0 + i X_H into slot 0.  The transforms along b and a then run
+// over the H slots of every line, so `data` ends as the half spectrum T[j0][j1][k2],
+// k2 < H, of S(k) = sum_j x_j e^{-2 pi i k.j / n}:
+//   S(k0, k1, k2) = T[k0][k1][k2] for 0 < k2 < H, and with P = T[k0][k1][0],
+//   P' = T[-k0][-k1][0]: S(k0, k1, 0) = (P + conj P') / 2, S(k0, k1, H) = (P - conj P') / 2i.
+// The pair's n2 complex elements are exactly the two half lines, so this is in place.
+__global__ __launch_bounds__(256) void k_r2c_pairs(float2 *__restrict__ data, int n2) {
+    extern __shared__ float2 zl[];
+    const int H = n2 / 2;
+    float2 *line = data + (size_t)blockIdx.x * n2;
+    for (int m = threadIdx.x; m < n2; m += blockDim.x) zl[m] = line[m];
+    __syncthreads();
+    for (int k = threadIdx.x; k < H; k += blockDim.x) {
+        float2 X, Y;
+        if (k == 0) {
+            const float2 z0 = zl[0], zh = zl[H];
+            X = make_float2(z0.x, zh.x);  // X_0 + i X_H
+            Y = make_float2(z0.y, zh.y);  // Y_0 + i Y_H
+        } else {
+            const float2 a = zl[k], b = zl[n2 - k];  // Z_k, Z_{-k}
+            X = make_float2(0.5f * (a.x + b.x), 0.5f * (a.y - b.y));
+            Y = make_float2(0.5f * (a.y + b.y), -0.5f * (a.x - b.x));
+        }
+        line[k] = X;
+        line[H + k] = Y;
+    }
+}
+
+bool fft_r2c_supported(const int *mesh) { return mesh[1] % 2 == 0 && mesh[2] % 2 == 0 && mesh[2] >= 2; }
+
+hipError_t fft3d_r2c(float2 *data, const int *mesh, hipStream_t s) {
+    const int H = mesh[2] / 2, pairs = mesh[0] * (mesh[1] / 2);
+    hipError_t e = fft_lines(data, mesh[2], 1, pairs, -1, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_r2c_pairs, dim3(pairs), dim3(256), sizeof(float2) * (size_t)mesh[2], s, data, mesh[2]);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = fft_lines(data, mesh[1], H, mesh[0], -1, s);
+    if (e != hipSuccess) return e;
+    return fft_lines(data, mesh[0], mesh[1] * H, 1, -1, s);
 }
 
 }  // namespace qnep

@@ -50,9 +50,16 @@ __device__ inline int wrap_index(int j, int n) {
     return j < 0 ? j + n : j;
 }
 
+// float offset of mesh point (j0, j1, j2) in the input of the real-input transform:
+// lines j1 = 2p and 2p + 1 interleaved, (x[j0][2p][m], x[j0][2p+1][m]) one complex element
+__device__ inline size_t pair_index(int j0, int j1, int j2, const MeshGeom &g) {
+    return ((size_t)j0 * g.n[1] + (j1 & ~1)) * g.n[2] + 2 * (size_t)j2 + (j1 & 1);
+}
+
+// pairs = 1: rho in the interleaved layout of pair_index
 __global__ __launch_bounds__(256) void k_spread(int N, const float4 *__restrict__ xyzt, Cell c, MeshGeom g,
                                                 const float *__restrict__ qraw, const double *__restrict__ scalars,
-                                                float *__restrict__ rho) {
+                                                float *__restrict__ rho, int pairs) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const float q = qraw[i] + (float)scalars[S_DELTA];
@@ -73,9 +80,14 @@ __global__ __launch_bounds__(256) void k_spread(int N, const float4 *__restrict_
 #pragma unroll
         for (int b = 0; b < 5; ++b) {
             const float qab = qa * w[1][b];
-            const size_t row = ((size_t)j0[a] * g.n[1] + j1[b]) * g.n[2];
+            if (pairs) {
 #pragma unroll
-            for (int e = 0; e < 5; ++e) atomicAdd(&rho[row + j2[e]], qab * w[2][e]);
+                for (int e = 0; e < 5; ++e) atomicAdd(&rho[pair_index(j0[a], j1[b], j2[e], g)], qab * w[2][e]);
+            } else {
+                const size_t row = ((size_t)j0[a] * g.n[1] + j1[b]) * g.n[2];
+#pragma unroll
+                for (int e = 0; e < 5; ++e) atomicAdd(&rho[row + j2[e]], qab * w[2][e]);
+            }
         }
     }
 }
@@ -91,8 +103,9 @@ __global__ void k_real_to_complex(int64_t M, const float *__restrict__ rho, floa
 // reach the brick: the bins (unwrapped, so periodic images are explicit) whose atoms
 // have u in [M0 - 5/2, M0 + P + 3/2) in mesh units, read as rows along c split per
 // image.  Each copy adds the part of its stencil inside the brick to an LDS tile,
-// and the brick is stored once as the complex FFT input (rho, 0): every mesh point
-// is written by exactly one work-group.  Positions are taken unwrapped (the sorted
+// and the brick is stored once as the FFT input (the real mesh with pairs of lines
+// interleaved for the real-input transform, else (rho, 0)): every mesh point is
+// written by exactly one work-group.  Positions are taken unwrapped (the sorted
 // copies lie in the cell up to rounding), so a copy sits next to the bin it is
 // listed in.
 constexpr int SB_P = 16;      // largest brick edge (mesh points)
@@ -135,7 +148,8 @@ __device__ inline void sb_exscan2(int &x, int &y, int &tx, int &ty) {
 __global__ __launch_bounds__(256) void k_spread_bricks(const float4 *__restrict__ xyzt, Cell c, MeshGeom g,
                                                        int nc0, int nc1, int nc2, BrickGeom bg,
                                                        const int *__restrict__ start, const float *__restrict__ qraw,
-                                                       const double *__restrict__ scalars, float2 *__restrict__ out) {
+                                                       const double *__restrict__ scalars, float2 *__restrict__ out,
+                                                       int real_out) {
     __shared__ unsigned long long tile[SB_P * SB_P * SB_P];  // fixed point
     __shared__ int sbeg[SB_SEGS], spre[SB_SEGS + 1], scode[SB_SEGS];
     const int nc[3] = {nc0, nc1, nc2};
@@ -233,8 +247,12 @@ __global__ __launch_bounds__(256) void k_spread_bricks(const float4 *__restrict_
     __syncthreads();
     for (int p = threadIdx.x; p < TP; p += blockDim.x) {
         const int x = p / (bg.P[1] * bg.P[2]), y = (p / bg.P[2]) % bg.P[1], z = p % bg.P[2];
-        if (x < Pa[0] && y < Pa[1] && z < Pa[2])
-            out[((size_t)(M0[0] + x) * g.n[1] + (M0[1] + y)) * g.n[2] + (M0[2] + z)] = make_float2((float)from_fixed(tile[p]), 0.0f);
+        if (x < Pa[0] && y < Pa[1] && z < Pa[2]) {
+            const size_t idx = ((size_t)(M0[0] + x) * g.n[1] + (M0[1] + y)) * g.n[2] + (M0[2] + z);
+            const float v = (float)from_fixed(tile[p]);
+            if (real_out) reinterpret_cast<float *>(out)[pair_index(M0[0] + x, M0[1] + y, M0[2] + z, g)] = v;
+            else out[idx] = make_float2(v, 0.0f);
+        }
     }
 }
 
@@ -273,18 +291,77 @@ __device__ inline void gopt_axis(float x, float &num, float &den) {
 // Pointwise in k: energy and virial partials, then the two packed spectra
 //   A <- i X (k~_z + 1)  (inverse: E_z + i phi'),  B <- i X k~_x - X k~_y  (inverse: E_x + i E_y)
 // with X = S G_opt and k~ the derivative wave vector (zero index at a Nyquist plane).
-// A work-group takes whole rows along c (the row's a and b factors once per row).  S is
-// read from Sk; A and B are written interleaved, AB[point] = (A, B).
-__global__ __launch_bounds__(256) void k_influence(MeshGeom g, Cell c, float alpha, double vol,
-                                                   const float2 *__restrict__ Sk, float4 *__restrict__ AB,
-                                                   double *__restrict__ partials) {
-    const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
-    const float gk = (float)(2.0 * PI_D / vol), ia2 = 1.0f / (4.0f * alpha * alpha), cB0 = 2.0f * ia2;
-    const float in2 = 1.0f / (float)n2;
-    float kz[3];
+// A work-group takes whole rows along c (the row's a and b factors once per row).  A
+// and B are written interleaved, AB[point] = (A, B).
+
+// the a and b parts of one row (j0, j1) of the mesh in k
+struct InflRow {
+    float kr[3], ktr[3], f01;
+    int nv0, nv1;
+};
+
+__device__ inline InflRow infl_row(int j0, int j1, const MeshGeom &g, const Cell &c) {
+    InflRow r;
+    const int n0 = g.n[0], n1 = g.n[1];
+    r.nv0 = 2 * j0 < n0 ? j0 : j0 - n0;
+    r.nv1 = 2 * j1 < n1 ? j1 : j1 - n1;
+    const int nt0 = ((n0 & 1) == 0 && 2 * r.nv0 == -n0) ? 0 : r.nv0;
+    const int nt1 = ((n1 & 1) == 0 && 2 * r.nv1 == -n1) ? 0 : r.nv1;
 #pragma unroll
-    for (int b = 0; b < 3; ++b) kz[b] = (float)(2.0 * PI_D * c.hinv[3 * b + 2]);
-    __shared__ float fc[1024];  // the c factor num / den of G_opt per index along c (n2 <= 1024)
+    for (int b = 0; b < 3; ++b) {
+        r.kr[b] = (float)(2.0 * PI_D * (c.hinv[3 * b] * r.nv0 + c.hinv[3 * b + 1] * r.nv1));
+        r.ktr[b] = (float)(2.0 * PI_D * (c.hinv[3 * b] * nt0 + c.hinv[3 * b + 1] * nt1));
+    }
+    float num0, den0, num1, den1;
+    gopt_axis((float)r.nv0 / (float)n0, num0, den0);
+    gopt_axis((float)r.nv1 / (float)n1, num1, den1);
+    r.f01 = (num0 * num1) / (den0 * den1);
+    return r;
+}
+
+struct InflConst {
+    float gk, ia2, cB0, kz[3];
+};
+
+// the point (row, j2) with transform S: adds its energy and virial terms to acc and
+// returns its (A, B)
+__device__ inline float4 infl_point(const InflRow &r, const InflConst &q, int j2, int n2, const float *fc, float2 S,
+                                    float (&acc)[10]) {
+    const int nv2 = 2 * j2 < n2 ? j2 : j2 - n2;
+    if (r.nv0 == 0 && r.nv1 == 0 && nv2 == 0) return make_float4(0.f, 0.f, 0.f, 0.f);
+    const int nt2 = ((n2 & 1) == 0 && 2 * nv2 == -n2) ? 0 : nv2;
+    float k[3], kt[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        k[b] = fmaf(q.kz[b], (float)nv2, r.kr[b]);
+        kt[b] = fmaf(q.kz[b], (float)nt2, r.ktr[b]);
+    }
+    const float k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+    const float ik2 = 1.0f / k2;
+    const float Gopt = q.gk * __expf(-k2 * q.ia2) * ik2 * (r.f01 * fc[j2]);
+    const float e = (float)KE * Gopt * (S.x * S.x + S.y * S.y);
+    const float cB = q.cB0 + 2.0f * ik2;
+    acc[0] += e;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) acc[1 + 3 * a + b] += e * ((a == b ? 1.0f : 0.0f) - cB * k[a] * k[b]);
+    const float2 X = make_float2(S.x * Gopt, S.y * Gopt);
+    const float2 iX = make_float2(-X.y, X.x);
+    return make_float4(iX.x * (kt[2] + 1.0f), iX.y * (kt[2] + 1.0f), iX.x * kt[0] - X.x * kt[1],
+                       iX.y * kt[0] - X.y * kt[1]);
+}
+
+// constants and the c factor num / den of G_opt per index along c (n2 <= 1024) in fc
+__device__ inline InflConst infl_setup(const MeshGeom &g, const Cell &c, float alpha, double vol, float *fc) {
+    InflConst q;
+    q.gk = (float)(2.0 * PI_D / vol);
+    q.ia2 = 1.0f / (4.0f * alpha * alpha);
+    q.cB0 = 2.0f * q.ia2;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) q.kz[b] = (float)(2.0 * PI_D * c.hinv[3 * b + 2]);
+    const int n2 = g.n[2];
+    const float in2 = 1.0f / (float)n2;
     for (int j2 = threadIdx.x; j2 < n2; j2 += blockDim.x) {
         const int nv2 = 2 * j2 < n2 ? j2 : j2 - n2;
         float num2, den2;
@@ -292,51 +369,23 @@ __global__ __launch_bounds__(256) void k_influence(MeshGeom g, Cell c, float alp
         fc[j2] = num2 / den2;
     }
     __syncthreads();
+    return q;
+}
+
+// S from the full complex transform Sk
+__global__ __launch_bounds__(256) void k_influence(MeshGeom g, Cell c, float alpha, double vol,
+                                                   const float2 *__restrict__ Sk, float4 *__restrict__ AB,
+                                                   double *__restrict__ partials) {
+    const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
+    __shared__ float fc[1024];
+    const InflConst q = infl_setup(g, c, alpha, vol, fc);
     float acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};  // over this thread's few points, then FP64
     for (int row = blockIdx.x; row < n0 * n1; row += gridDim.x) {
         const int j0 = row / n1, j1 = row - j0 * n1;
-        const int nv0 = 2 * j0 < n0 ? j0 : j0 - n0, nv1 = 2 * j1 < n1 ? j1 : j1 - n1;
-        const int nt0 = ((n0 & 1) == 0 && 2 * nv0 == -n0) ? 0 : nv0;
-        const int nt1 = ((n1 & 1) == 0 && 2 * nv1 == -n1) ? 0 : nv1;
-        float kr[3], ktr[3];
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            kr[b] = (float)(2.0 * PI_D * (c.hinv[3 * b] * nv0 + c.hinv[3 * b + 1] * nv1));
-            ktr[b] = (float)(2.0 * PI_D * (c.hinv[3 * b] * nt0 + c.hinv[3 * b + 1] * nt1));
-        }
-        float num0, den0, num1, den1;
-        gopt_axis((float)nv0 / (float)n0, num0, den0);
-        gopt_axis((float)nv1 / (float)n1, num1, den1);
-        const float f01 = (num0 * num1) / (den0 * den1);
+        const InflRow r = infl_row(j0, j1, g, c);
         for (int j2 = threadIdx.x; j2 < n2; j2 += blockDim.x) {
             const size_t idx = (size_t)row * n2 + j2;
-            const int nv2 = 2 * j2 < n2 ? j2 : j2 - n2;
-            const float2 S = Sk[idx];
-            if (nv0 == 0 && nv1 == 0 && nv2 == 0) {
-                AB[idx] = make_float4(0.f, 0.f, 0.f, 0.f);
-                continue;
-            }
-            const int nt2 = ((n2 & 1) == 0 && 2 * nv2 == -n2) ? 0 : nv2;
-            float k[3], kt[3];
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                k[b] = fmaf(kz[b], (float)nv2, kr[b]);
-                kt[b] = fmaf(kz[b], (float)nt2, ktr[b]);
-            }
-            const float k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
-            const float ik2 = 1.0f / k2;
-            const float Gopt = gk * __expf(-k2 * ia2) * ik2 * (f01 * fc[j2]);
-            const float e = (float)KE * Gopt * (S.x * S.x + S.y * S.y);
-            const float cB = cB0 + 2.0f * ik2;
-            acc[0] += e;
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) acc[1 + 3 * a + b] += e * ((a == b ? 1.0f : 0.0f) - cB * k[a] * k[b]);
-            const float2 X = make_float2(S.x * Gopt, S.y * Gopt);
-            const float2 iX = make_float2(-X.y, X.x);
-            AB[idx] = make_float4(iX.x * (kt[2] + 1.0f), iX.y * (kt[2] + 1.0f), iX.x * kt[0] - X.x * kt[1],
-                                  iX.y * kt[0] - X.y * kt[1]);
+            AB[idx] = infl_point(r, q, j2, n2, fc, Sk[idx], acc);
         }
     }
     double red[10];
@@ -345,12 +394,64 @@ __global__ __launch_bounds__(256) void k_influence(MeshGeom g, Cell c, float alp
     block_partials<10>(red, partials);
 }
 
+// S(k0, k1, j2) from the half spectrum T[j0][j1][k2], k2 < H = n2 / 2, of the real-input
+// transform (row = the row of (k0, k1), mrow = the row of (-k0, -k1)): T itself for
+// 0 < j2 < H, conj T(-k) for j2 > H, and for j2 = 0 and H the two values packed in slot 0,
+// (P + conj P') / 2 and (P - conj P') / 2i with P, P' slot 0 of the row and the mirrored row
+__device__ inline float2 half_fetch(const float2 *__restrict__ T, int row, int mrow, int j2, int n2) {
+    const int H = n2 / 2;
+    if (j2 == 0 || j2 == H) {
+        const float2 P = T[(size_t)row * H], Pm = T[(size_t)mrow * H];
+        return j2 == H ? make_float2(0.5f * (P.y + Pm.y), -0.5f * (P.x - Pm.x))
+                       : make_float2(0.5f * (P.x + Pm.x), 0.5f * (P.y - Pm.y));
+    }
+    if (j2 < H) return T[(size_t)row * H + j2];
+    const float2 v = T[(size_t)mrow * H + (n2 - j2)];
+    return make_float2(v.x, -v.y);
+}
+
+// S from the half spectrum of the real-input transform: every row reads its own slots
+// and, for j2 > n2 / 2, those of the mirrored row (each slot is read twice, every output
+// point written by its own row)
+__global__ __launch_bounds__(256) void k_influence_half(MeshGeom g, Cell c, float alpha, double vol,
+                                                        const float2 *__restrict__ T, float4 *__restrict__ AB,
+                                                        double *__restrict__ partials) {
+    const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
+    __shared__ float fc[1024];
+    const InflConst q = infl_setup(g, c, alpha, vol, fc);
+    float acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int row = blockIdx.x; row < n0 * n1; row += gridDim.x) {
+        const int j0 = row / n1, j1 = row - j0 * n1;
+        const int mrow = (j0 == 0 ? 0 : n0 - j0) * n1 + (j1 == 0 ? 0 : n1 - j1);
+        const InflRow r = infl_row(j0, j1, g, c);
+        for (int j2 = threadIdx.x; j2 < n2; j2 += blockDim.x)
+            AB[(size_t)row * n2 + j2] = infl_point(r, q, j2, n2, fc, half_fetch(T, row, mrow, j2, n2), acc);
+    }
+    double red[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) red[k] = acc[k];
+    block_partials<10>(red, partials);
+}
+
+// the full transform S[j0][j1][j2] from the half spectrum (for the per-atom virial)
+__global__ __launch_bounds__(256) void k_expand_half(MeshGeom g, const float2 *__restrict__ T,
+                                                     float2 *__restrict__ Sk) {
+    const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
+    const size_t M = (size_t)n0 * n1 * n2;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < M; idx += (size_t)gridDim.x * blockDim.x) {
+        const int j2 = (int)(idx % n2), row = (int)(idx / n2);
+        const int j0 = row / n1, j1 = row - j0 * n1;
+        const int mrow = (j0 == 0 ? 0 : n0 - j0) * n1 + (j1 == 0 ? 0 : n1 - j1);
+        Sk[idx] = half_fetch(T, row, mrow, j2, n2);
+    }
+}
+
 // Per-atom reciprocal virial (Eq. 39): X B_ab with X = S G_opt and the stress kernel
 // B = I - (2/(4 alpha^2) + 2/k^2) k k, for the six components packed two per complex
 // spectrum (each X B_ab is Hermitian, so its inverse transform is real):
 //   V0 = X B_xx + i X B_yy,  V1 = X B_zz + i X B_xy,  V2 = X B_xz + i X B_yz.
 __global__ __launch_bounds__(256) void k_influence_virial(MeshGeom g, Cell c, float alpha, double vol,
-                                                          const float2 *__restrict__ Sk, float2 *__restrict__ V) {
+                                                          const float2 *Sk, float2 *V) {  // Sk may alias V + 2M
     const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
     const size_t M = (size_t)n0 * n1 * n2;
     const float gk = (float)(2.0 * PI_D / vol), ia2 = 1.0f / (4.0f * alpha * alpha), cB0 = 2.0f * ia2;
@@ -499,11 +600,17 @@ __global__ __launch_bounds__(256) void k_gather_virial(int N, const float4 *__re
     }
 }
 
+hipError_t fft3d_r2c(float2 *data, const int *mesh, hipStream_t s);
+bool fft_r2c_supported(const int *mesh);
+
 hipError_t launch_pppm(const Plan &p) {
     MeshGeom g{{p.mesh[0], p.mesh[1], p.mesh[2]}};
     const int64_t M = p.mesh_pts;
     const int G = (p.N + 255) / 256;
     const int GM = (int)((M + 255) / 256);
+    // a mesh with even point counts along b and c takes the real-input transform and the
+    // half spectrum; otherwise the complex transform of (rho, 0)
+    const bool half = fft_r2c_supported(p.mesh);
     hipError_t e;
     if (p.bricks) {
         BrickGeom bg;
@@ -513,27 +620,42 @@ hipError_t launch_pppm(const Plan &p) {
         }
         const int nbricks = bg.nb[0] * bg.nb[1] * bg.nb[2];
         hipLaunchKernelGGL(k_spread_bricks, dim3(nbricks), dim3(256), 0, p.stream, p.xyzt, p.cell, g, p.nc[0],
-                           p.nc[1], p.nc[2], bg, p.cell_start, p.qraw, p.scalars, p.meshA);
+                           p.nc[1], p.nc[2], bg, p.cell_start, p.qraw, p.scalars, p.meshA, half ? 1 : 0);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         stage_mark(p, ST_SPREAD, 1);
+    } else if (half) {
+        e = fill_zero(p.meshA, sizeof(float) * (size_t)M, p.stream);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_spread, dim3(G), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, g, p.qraw, p.scalars,
+                           reinterpret_cast<float *>(p.meshA), 1);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        stage_mark(p, ST_SPREAD, 2);
     } else {
         e = fill_zero(p.rho, sizeof(float) * (size_t)M, p.stream);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_spread, dim3(G), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, g, p.qraw, p.scalars,
-                           p.rho);
+                           p.rho, 0);
         hipLaunchKernelGGL(k_real_to_complex, dim3(GM), dim3(256), 0, p.stream, M, p.rho, p.meshA);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         stage_mark(p, ST_SPREAD, 3);
     }
-    e = fft3d(p.meshA, nullptr, p.mesh, -1, p.stream);
+    e = half ? fft3d_r2c(p.meshA, p.mesh, p.stream) : fft3d(p.meshA, nullptr, p.mesh, -1, p.stream);
     if (e != hipSuccess) return e;
-    stage_mark(p, ST_FFT_FWD, 3);
+    stage_mark(p, ST_FFT_FWD, half ? 4 : 3);  // real input: c, the pair split, b, a
     const int rows = p.mesh[0] * p.mesh[1];
-    const int GI = rows < 4096 ? rows : 4096;
-    hipLaunchKernelGGL(k_influence, dim3(GI), dim3(256), 0, p.stream, g, p.cell, (float)p.alpha, p.vol, p.meshA,
-                       (float4 *)p.meshAB, p.partials);
+    int GI;
+    if (half) {
+        GI = rows < 4096 ? rows : 4096;
+        hipLaunchKernelGGL(k_influence_half, dim3(GI), dim3(256), 0, p.stream, g, p.cell, (float)p.alpha, p.vol,
+                           p.meshA, (float4 *)p.meshAB, p.partials);
+    } else {
+        GI = rows < 4096 ? rows : 4096;
+        hipLaunchKernelGGL(k_influence, dim3(GI), dim3(256), 0, p.stream, g, p.cell, (float)p.alpha, p.vol, p.meshA,
+                           (float4 *)p.meshAB, p.partials);
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = reduce_partials(p, GI, 10, S_UK, false);  // S_UK, S_WK[9]
@@ -547,9 +669,17 @@ hipError_t launch_pppm(const Plan &p) {
                        p.scalars, (const float4 *)p.meshAB, p.phi, p.Fst);
     stage_mark(p, ST_GATHER);
     if (p.out.virial_atom) {
-        // six more inverse transforms, two per packed complex mesh (Eq. 39)
+        // six more inverse transforms, two per packed complex mesh (Eq. 39); from the half
+        // spectrum, S is first expanded into the third of those meshes (each point of it
+        // is read before the kernel overwrites it)
+        const float2 *Sk = p.meshA;
+        if (half) {
+            hipLaunchKernelGGL(k_expand_half, dim3(GM < 8192 ? GM : 8192), dim3(256), 0, p.stream, g, p.meshA,
+                               p.meshV + 2 * (size_t)M);
+            Sk = p.meshV + 2 * (size_t)M;
+        }
         hipLaunchKernelGGL(k_influence_virial, dim3(GM < 8192 ? GM : 8192), dim3(256), 0, p.stream, g, p.cell,
-                           (float)p.alpha, p.vol, p.meshA, p.meshV);
+                           (float)p.alpha, p.vol, Sk, p.meshV);
         e = hipGetLastError();
         for (int v = 0; v < 3 && e == hipSuccess; ++v) e = fft3d(p.meshV + (size_t)v * M, nullptr, p.mesh, +1, p.stream);
         if (e != hipSuccess) return e;
