@@ -314,21 +314,24 @@ def test_per_atom_virial(torch_dev, orc, case):
         assert np.array_equal(g0[k], g[k]), k
 
 
-def test_spread_atomic_fallback(torch_dev, orc):
+@pytest.mark.parametrize("n", [3, 4])
+def test_spread_atomic_fallback(torch_dev, orc, n):
     """A mesh so coarse against the bins that a brick's bin rows or segments would not
     fit the per-work-group tables: the charge assignment takes the atomic path (float
     atomics into a real mesh).  Garnet-768 (20.6 A, bins of 3.4 x 3.4 x 1.6 A) with a
-    3^3 mesh: 16 x 16 rows and 32 bins along c per brick, 1024 segments > 512."""
+    3^3 mesh: 16 x 16 rows and 32 bins along c per brick, 1024 segments > 512.  The 3^3
+    mesh takes the complex transform of (rho, 0); the 4^3 mesh (even along b and c) the
+    real-input transform, the atomic spread writing its interleaved line pairs."""
     w = inputs.workload(2, "crop")
     es = copy.copy(w.es)
-    es.mesh = (3, 3, 3)
+    es.mesh = (n, n, n)
     nc = [int(np.floor(w.system.cell[a, a] / (3.0 if a < 2 else 1.5))) for a in range(3)]
-    cnt = [int(np.floor((3 + 4.02) * nc[a] / 3)) + 2 for a in range(3)]
+    cnt = [int(np.floor((n + 4.02) * nc[a] / n)) + 2 for a in range(3)]
     assert cnt[0] * cnt[1] * ((cnt[2] - 1) // nc[2] + 2) > 512  # the brick tables do not fit
-    _say("case garnet-768 PPPM 3^3 (atomic charge assignment)")
+    _say(f"case garnet-768 PPPM {n}^3 (atomic charge assignment)")
     g = run_gpu(w.hp, es, w.system, w.theta)
     r = _oracle(orc, w.hp, es, w.system, w.theta)
-    compare(g, r, w.system.n, label="garnet768-pppm3-atomic")
+    compare(g, r, w.system.n, label=f"garnet768-pppm{n}-atomic")
 
 
 # ------------------------------------------------------------------ isolated systems (Eqs. 26, 27)
