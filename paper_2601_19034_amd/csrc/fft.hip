@@ -7,6 +7,7 @@
 // work-group in LDS; the roots of the small DFTs are compile-time constants.  Lines
 // are stored in LDS with a stride of L + 1 elements so that the transposing loads and
 // stores of the strided axes (consecutive lanes = consecutive lines) hit distinct banks.
+#include "fft256.h"
 #include "plan.h"
 
 namespace qnep {
@@ -47,7 +48,6 @@ bool fft_length_supported(int n) {
     return n >= 1 && n <= 1024 && make_plan(n, p);
 }
 
-__device__ inline float2 cmul(float2 a, float2 b) { return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
 
 // cos and sin of 2 pi k / R for the small radices
 template <int R>
@@ -83,13 +83,6 @@ struct Roots<8> {
 // small DFT of length R: out_m = sum_r a_r w^{r m}, w = e^{SG 2 pi i / R}, SG = +-1.
 // Radices 3 and 5 by the definition with constant roots; 2, 4 and 8 as butterflies
 // (8 = two radix-4 transforms of the even and odd inputs joined by w^m).
-__device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-template <int SG>
-__device__ inline float2 mul_i(float2 a) {  // (SG i) a
-    return make_float2(-(float)SG * a.y, (float)SG * a.x);
-}
-
 template <int R, int SG>
 struct SmallDft {
     __device__ static void run(float2 (&a)[R]) {
@@ -118,14 +111,6 @@ struct SmallDft<2, SG> {
         a[1] = csub(t, a[1]);
     }
 };
-template <int SG>
-__device__ inline void dft4(float2 a0, float2 a1, float2 a2, float2 a3, float2 (&o)[4]) {
-    const float2 t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3), t3 = mul_i<SG>(csub(a1, a3));
-    o[0] = cadd(t0, t2);
-    o[1] = cadd(t1, t3);
-    o[2] = csub(t0, t2);
-    o[3] = csub(t1, t3);
-}
 template <int SG>
 struct SmallDft<4, SG> {
     __device__ static void run(float2 (&a)[4]) {
@@ -278,33 +263,6 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_axis(float2 *__restrict__ d
 //   mode 0 (S == 1): lane = 16 line + t;  mode 1 (S a multiple of 16): lane = 16 t + line
 //   (16 consecutive `in`);  mode 2 (S = 2, 4, 8): lane = S (t + 16 o) + in (16 / S
 //   consecutive `o` with all their `in`).
-constexpr int F256_LS = 16 * 17 + 1;  // LDS stride of one line (padded rows of 17)
-
-template <int SG>
-__device__ inline float2 w16(int e) {  // e^{SG 2 pi i e / 16}, e < 16
-    constexpr float c[16] = {1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f,
-                             0.0f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f,
-                             -1.0f, -0.92387953251128674f, -0.70710678118654752f, -0.38268343236508977f,
-                             0.0f, 0.38268343236508977f, 0.70710678118654752f, 0.92387953251128674f};
-    return make_float2(c[e], (float)SG * c[(e + 12) & 15]);  // sin(x) = cos(x - pi/2)
-}
-
-template <int SG>
-__device__ inline void dft16(float2 (&a)[16]) {
-    float2 y[4][4];  // y[n1][k1] = sum_n2 a[n1 + 4 n2] w4^{n2 k1}
-#pragma unroll
-    for (int n1 = 0; n1 < 4; ++n1) dft4<SG>(a[n1], a[n1 + 4], a[n1 + 8], a[n1 + 12], y[n1]);
-#pragma unroll
-    for (int k1 = 0; k1 < 4; ++k1) {
-        float2 z[4], o[4];
-#pragma unroll
-        for (int n1 = 0; n1 < 4; ++n1) z[n1] = (n1 * k1 == 0) ? y[n1][k1] : cmul(y[n1][k1], w16<SG>(n1 * k1));
-        dft4<SG>(z[0], z[1], z[2], z[3], o);
-#pragma unroll
-        for (int k2 = 0; k2 < 4; ++k2) a[k1 + 4 * k2] = o[k2];
-    }
-}
-
 template <int SG>
 __global__ __launch_bounds__(256) void k_fft256(float2 *__restrict__ data, int S, int nouter, int mode) {
     __shared__ float2 tw[256];
@@ -346,17 +304,7 @@ __global__ __launch_bounds__(256) void k_fft256(float2 *__restrict__ data, int S
     float2 a[16];
 #pragma unroll
     for (int m = 0; m < 16; ++m) a[m] = ok ? data[base + (size_t)(t + 16 * m) * stride] : make_float2(0.f, 0.f);
-    dft16<SG>(a);
-    __syncthreads();  // twiddle table ready
-#pragma unroll
-    for (int k1 = 1; k1 < 16; ++k1) a[k1] = cmul(a[k1], tw[t * k1]);
-    float2 *row = xch + cl * F256_LS;
-#pragma unroll
-    for (int k1 = 0; k1 < 16; ++k1) row[k1 * 17 + t] = a[k1];
-    __syncthreads();
-#pragma unroll
-    for (int n1 = 0; n1 < 16; ++n1) a[n1] = row[t * 17 + n1];
-    dft16<SG>(a);
+    line256<SG>(a, t, tw, xch + cl * F256_LS);
     if (ok) {
 #pragma unroll
         for (int k2 = 0; k2 < 16; ++k2) data[base + (size_t)(t + 16 * k2) * stride] = a[k2];
@@ -420,6 +368,14 @@ hipError_t fft3d(float2 *data, float2 * /*tmp*/, const int *mesh, int sign, hipS
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+// The inverse passes along b and c (in that order) of `inner` interleaved transforms;
+// the pass along a is done by the caller.
+hipError_t fft3d_bc(float2 *data, const int *mesh, int sign, hipStream_t s, int inner) {
+    hipError_t e = fft_lines(data, mesh[1], inner * mesh[2], mesh[0], sign, s);
+    if (e != hipSuccess) return e;
+    return fft_lines(data, mesh[2], inner, mesh[0] * mesh[1], sign, s);
 }
 
 // ---------------------------------------------------------------- real input

@@ -7,6 +7,7 @@
 //   potential mesh for the dynamic-charge force (Eq. 38), gathered with the same W.
 // Two packed complex inverse transforms, interleaved per mesh point and run through
 // the same launches, give (E_z + i phi) and (E_x + i E_y).
+#include "fft256.h"
 #include "plan.h"
 
 namespace qnep {
@@ -433,6 +434,59 @@ __global__ __launch_bounds__(256) void k_influence_half(MeshGeom g, Cell c, floa
     block_partials<10>(red, partials);
 }
 
+// The influence function fused with the first inverse pass, along a, for n0 = 256 (the
+// mesh is then transformed along b and c): a work-group takes row j1, the 8 points j2 in
+// [8 j2b, 8 j2b + 8) along c and every j0, i.e. the 16 interleaved lines (A and B of
+// each point) of the transform along a, in the thread layout of the length-256 kernel:
+// line cl = lane % 16 holds part cl % 2 of point j2 = 8 j2b + cl / 2, thread t = lane / 16
+// holds j0 = t + 16 m.  The two threads of a point evaluate alternate j0 (m of their
+// parity) and exchange the part they do not keep, so every point is evaluated once.
+// The a and b factors of the 256 rows (j0, j1) are tabulated in LDS.
+__global__ __launch_bounds__(256) void k_influence_a256(MeshGeom g, Cell c, float alpha, double vol,
+                                                        const float2 *__restrict__ T, float4 *__restrict__ AB,
+                                                        double *__restrict__ partials) {
+    const int n1 = g.n[1], n2 = g.n[2];
+    // the row table and the c factors are read only before the transform's first barrier,
+    // after which its exchange area reuses their LDS
+    static_assert(256 * sizeof(InflRow) + 1024 * sizeof(float) <= 16 * F256_LS * sizeof(float2), "LDS overlay");
+    __shared__ __align__(16) float2 xch[16 * F256_LS];
+    __shared__ float2 tw[256];
+    InflRow *rtab = reinterpret_cast<InflRow *>(xch);
+    float *fc = reinterpret_cast<float *>(rtab + 256);
+    const int j1 = blockIdx.x / (n2 / 8), j2b = blockIdx.x - j1 * (n2 / 8);
+    {
+        float sn, cs;
+        sincospif((float)threadIdx.x / 128.0f, &sn, &cs);
+        tw[threadIdx.x] = make_float2(cs, sn);  // e^{+2 pi i m / 256}
+        rtab[threadIdx.x] = infl_row(threadIdx.x, j1, g, c);
+    }
+    const InflConst q = infl_setup(g, c, alpha, vol, fc);  // ends with a barrier
+    const int lane = threadIdx.x, cl = lane & 15, t = lane >> 4, part = cl & 1, j2 = 8 * j2b + (cl >> 1);
+    const int mj1 = j1 == 0 ? 0 : n1 - j1;
+    float acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    float2 a[16];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int j0 = t + 16 * (2 * k + part);
+        const int row = j0 * n1 + j1, mrow = ((256 - j0) & 255) * n1 + mj1;
+        const float4 R = infl_point(rtab[j0], q, j2, n2, fc, half_fetch(T, row, mrow, j2, n2), acc);
+        const float2 own = part ? make_float2(R.z, R.w) : make_float2(R.x, R.y);
+        const float2 other = part ? make_float2(R.x, R.y) : make_float2(R.z, R.w);
+        const float2 recv = make_float2(__shfl_xor(other.x, 1, 64), __shfl_xor(other.y, 1, 64));
+        a[2 * k] = part ? recv : own;
+        a[2 * k + 1] = part ? own : recv;
+    }
+    line256<1>(a, t, tw, xch + cl * F256_LS);
+    const size_t S = (size_t)n1 * n2 * 2, base = ((size_t)j1 * n2 + j2) * 2 + part;
+    float2 *d = reinterpret_cast<float2 *>(AB);
+#pragma unroll
+    for (int k2 = 0; k2 < 16; ++k2) d[base + (size_t)(t + 16 * k2) * S] = a[k2];
+    double red[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) red[k] = acc[k];
+    block_partials<10>(red, partials);
+}
+
 // the full transform S[j0][j1][j2] from the half spectrum (for the per-atom virial)
 __global__ __launch_bounds__(256) void k_expand_half(MeshGeom g, const float2 *__restrict__ T,
                                                      float2 *__restrict__ Sk) {
@@ -601,6 +655,7 @@ __global__ __launch_bounds__(256) void k_gather_virial(int N, const float4 *__re
 }
 
 hipError_t fft3d_r2c(float2 *data, const int *mesh, hipStream_t s);
+hipError_t fft3d_bc(float2 *data, const int *mesh, int sign, hipStream_t s, int inner);
 bool fft_r2c_supported(const int *mesh);
 
 hipError_t launch_pppm(const Plan &p) {
@@ -646,8 +701,14 @@ hipError_t launch_pppm(const Plan &p) {
     if (e != hipSuccess) return e;
     stage_mark(p, ST_FFT_FWD, half ? 4 : 3);  // real input: c, the pair split, b, a
     const int rows = p.mesh[0] * p.mesh[1];
+    // n0 = 256: the influence function and the first inverse pass (along a) in one kernel
+    const bool fused = half && p.mesh[0] == 256 && p.mesh[2] % 8 == 0;
     int GI;
-    if (half) {
+    if (fused) {
+        GI = p.mesh[1] * (p.mesh[2] / 8);
+        hipLaunchKernelGGL(k_influence_a256, dim3(GI), dim3(256), 0, p.stream, g, p.cell, (float)p.alpha, p.vol,
+                           p.meshA, (float4 *)p.meshAB, p.partials);
+    } else if (half) {
         GI = rows < 4096 ? rows : 4096;
         hipLaunchKernelGGL(k_influence_half, dim3(GI), dim3(256), 0, p.stream, g, p.cell, (float)p.alpha, p.vol,
                            p.meshA, (float4 *)p.meshAB, p.partials);
@@ -661,9 +722,10 @@ hipError_t launch_pppm(const Plan &p) {
     e = reduce_partials(p, GI, 10, S_UK, false);  // S_UK, S_WK[9]
     if (e != hipSuccess) return e;
     stage_mark(p, ST_INFLUENCE, 2);
-    e = fft3d(p.meshAB, nullptr, p.mesh, +1, p.stream, 2);  // both spectra in the same launches
+    // both spectra in the same launches
+    e = fused ? fft3d_bc(p.meshAB, p.mesh, +1, p.stream, 2) : fft3d(p.meshAB, nullptr, p.mesh, +1, p.stream, 2);
     if (e != hipSuccess) return e;
-    stage_mark(p, ST_FFT_INV, 3);
+    stage_mark(p, ST_FFT_INV, fused ? 2 : 3);
     const int GG = (int)(((int64_t)p.N * GA_LANES + 255) / 256);
     hipLaunchKernelGGL(k_gather, dim3(GG), dim3(256), 0, p.stream, p.N, p.xyzt, p.cell, g, p.qraw,
                        p.scalars, (const float4 *)p.meshAB, p.phi, p.Fst);
