@@ -412,13 +412,61 @@ __global__ __launch_bounds__(256) void k_r2c_pairs(float2 *__restrict__ data, in
     }
 }
 
+// n2 = 256: the pass along c fused with the pair split -- k_fft256<-1> in mode 0 (16
+// lines per work-group, lane = 16 line + t), then each line's spectrum goes through LDS
+// and is split into the two half spectra as in k_r2c_pairs
+__global__ __launch_bounds__(256) void k_fft256_pairs(float2 *__restrict__ data, int nlines) {
+    __shared__ float2 tw[256];
+    __shared__ float2 xch[16 * F256_LS];
+    {
+        float sn, cs;
+        sincospif((float)threadIdx.x / 128.0f, &sn, &cs);
+        tw[threadIdx.x] = make_float2(cs, -sn);  // e^{-2 pi i m / 256}
+    }
+    const int cl = threadIdx.x >> 4, t = threadIdx.x & 15;
+    const int o = xcd_block() * 16 + cl;
+    const bool ok = o < nlines;
+    float2 *line = data + (size_t)(ok ? o : 0) * 256;
+    float2 a[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) a[m] = ok ? line[t + 16 * m] : make_float2(0.f, 0.f);
+    float2 *row = xch + cl * F256_LS;
+    line256<-1>(a, t, tw, row);
+    __syncthreads();  // every thread is done with the exchange area
+#pragma unroll
+    for (int k2 = 0; k2 < 16; ++k2) row[t + 16 * k2] = a[k2];
+    __syncthreads();
+    if (!ok) return;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int k = t + 16 * j;
+        float2 X, Y;
+        if (k == 0) {
+            const float2 z0 = row[0], zh = row[128];
+            X = make_float2(z0.x, zh.x);
+            Y = make_float2(z0.y, zh.y);
+        } else {
+            const float2 p = row[k], q = row[256 - k];
+            X = make_float2(0.5f * (p.x + q.x), 0.5f * (p.y - q.y));
+            Y = make_float2(0.5f * (p.y + q.y), -0.5f * (p.x - q.x));
+        }
+        line[k] = X;
+        line[128 + k] = Y;
+    }
+}
+
 bool fft_r2c_supported(const int *mesh) { return mesh[1] % 2 == 0 && mesh[2] % 2 == 0 && mesh[2] >= 2; }
 
 hipError_t fft3d_r2c(float2 *data, const int *mesh, hipStream_t s) {
     const int H = mesh[2] / 2, pairs = mesh[0] * (mesh[1] / 2);
-    hipError_t e = fft_lines(data, mesh[2], 1, pairs, -1, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_r2c_pairs, dim3(pairs), dim3(256), sizeof(float2) * (size_t)mesh[2], s, data, mesh[2]);
+    hipError_t e;
+    if (mesh[2] == 256) {
+        hipLaunchKernelGGL(k_fft256_pairs, dim3((pairs + 15) / 16), dim3(256), 0, s, data, pairs);
+    } else {
+        e = fft_lines(data, mesh[2], 1, pairs, -1, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_r2c_pairs, dim3(pairs), dim3(256), sizeof(float2) * (size_t)mesh[2], s, data, mesh[2]);
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = fft_lines(data, mesh[1], H, mesh[0], -1, s);

@@ -699,7 +699,7 @@ hipError_t launch_pppm(const Plan &p) {
     }
     e = half ? fft3d_r2c(p.meshA, p.mesh, p.stream) : fft3d(p.meshA, nullptr, p.mesh, -1, p.stream);
     if (e != hipSuccess) return e;
-    stage_mark(p, ST_FFT_FWD, half ? 4 : 3);  // real input: c, the pair split, b, a
+    stage_mark(p, ST_FFT_FWD, half && p.mesh[2] != 256 ? 4 : 3);  // real input: c, the pair split, b, a
     const int rows = p.mesh[0] * p.mesh[1];
     // n0 = 256: the influence function and the first inverse pass (along a) in one kernel
     const bool fused = half && p.mesh[0] == 256 && p.mesh[2] % 8 == 0;
