@@ -453,7 +453,9 @@ __global__ __launch_bounds__(256) void k_influence_a256(MeshGeom g, Cell c, floa
     __shared__ float2 tw[256];
     InflRow *rtab = reinterpret_cast<InflRow *>(xch);
     float *fc = reinterpret_cast<float *>(rtab + 256);
-    const int j1 = blockIdx.x / (n2 / 8), j2b = blockIdx.x - j1 * (n2 / 8);
+    // consecutive j2 blocks of a row on one XCD: the two halves of a 128-byte line of the
+    // half spectrum are read by neighbouring work-groups
+    const int lb = xcd_block(), j1 = lb / (n2 / 8), j2b = lb - j1 * (n2 / 8);
     {
         float sn, cs;
         sincospif((float)threadIdx.x / 128.0f, &sn, &cs);
