@@ -244,6 +244,63 @@ __device__ inline int stencil_segments(const Stencil &st, const Cell &c, const A
     return live ? __shfl(incl, LANES - 1, LANES) : 0;
 }
 
+// As stencil_segments, for rn <= RPL LANES (a lane takes at most RPL rows): the trimmed
+// range of each row is computed once and kept in registers between the counting pass and
+// the pass that writes the table.  Fewer instructions for more registers: it pays where
+// the caller's register count leaves the occupancy unchanged (the real-space sum).
+template <int LANES, int RPL>
+__device__ inline int stencil_segments_kept(const Stencil &st, const Cell &c, const AtomBin &b, bool live, int sub,
+                                       int r0, int rn, const int *__restrict__ start, int2 *seg) {
+    const int nc0 = st.nc[0], nc1 = st.nc[1], nc2 = st.nc[2], w1n = 2 * st.m[1] + 1;
+    const int nimg = 2 * st.R + 1;
+    const int rpl = (rn + LANES - 1) / LANES;  // rows per lane, contiguous: the table keeps row order
+    const int rb = r0 + sub * rpl, re = min(rb + rpl, r0 + rn);
+    int zl[RPL], zh[RPL], z0[RPL], z1[RPL];
+    bool ok[RPL];
+    int cnt = 0;
+    {
+        int d0 = rb / w1n, d1 = rb - (rb / w1n) * w1n;  // row rb at offsets (d0, d1); later rows by counting
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+            ok[q] = live && rb + q < re && stencil_row(st, c, b, d0, d1, zl[q], zh[q]);
+            z0[q] = ok[q] ? image_index(zl[q], nc2) : 0;
+            z1[q] = ok[q] ? image_index(zh[q], nc2) : -1;
+            cnt += z1[q] - z0[q] + 1;
+            if (++d1 == w1n) {
+                d1 = 0;
+                ++d0;
+            }
+        }
+    }
+    int incl = cnt;
+#pragma unroll
+    for (int o = 1; o < LANES; o <<= 1) {
+        const int v = __shfl_up(incl, o, LANES);
+        if (sub >= o) incl += v;
+    }
+    int pos = incl - cnt;
+    int d0 = rb / w1n, d1 = rb - (rb / w1n) * w1n;
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+        if (ok[q]) {
+            const int u0 = b.ci[0] + d0 - st.m[0], i0 = image_index(u0, nc0), b0 = u0 - i0 * nc0;
+            const int u1 = b.ci[1] + d1 - st.m[1], i1 = image_index(u1, nc1), b1 = u1 - i1 * nc1;
+            const int rowbase = row_rank(b0, b1, nc0, nc1) * nc2;
+            for (int i2 = z0[q]; i2 <= z1[q]; ++i2) {
+                const int za = max(zl[q], i2 * nc2) - i2 * nc2, zb = min(zh[q], i2 * nc2 + nc2 - 1) - i2 * nc2;
+                const int jb = start[rowbase + za], je = start[rowbase + zb + 1];
+                const uint32_t img = (uint32_t)(((i0 + st.R) * nimg + (i1 + st.R)) * nimg + (i2 + st.R));
+                seg[pos++] = make_int2(jb, (int)((uint32_t)(je - jb) | (img << SEG_LEN_BITS)));
+            }
+        }
+        if (++d1 == w1n) {
+            d1 = 0;
+            ++d0;
+        }
+    }
+    return live ? __shfl(incl, LANES - 1, LANES) : 0;
+}
+
 // lattice shift n of image index k in [0, (2R+1)^3)
 __device__ inline void image_of(int k, int R, int &n0, int &n1, int &n2) {
     const int nimg = 2 * R + 1;

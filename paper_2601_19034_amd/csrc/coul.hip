@@ -90,8 +90,8 @@ __global__ __launch_bounds__(256) void k_real_space(int N, const float4 *__restr
     // an atom's segment table is written and read by the atom's own lanes (one wave)
     for (int r0 = 0; r0 < st.nrows; r0 += st.rows_chunk) {  // the same trip count in every lane
         wave_lds_sync();  // the previous chunk's walk is done with the table
-        const int ns = stencil_segments<RS_LANES>(st, c, ab, live, sub, r0, min(st.rows_chunk, st.nrows - r0),
-                                                  start, seg[a]);
+        const int ns = stencil_segments_kept<RS_LANES, RS_SEG / 2 / RS_LANES>(
+            st, c, ab, live, sub, r0, min(st.rows_chunk, st.nrows - r0), start, seg[a]);
         wave_lds_sync();
         // this lane takes candidates sub, sub + RS_LANES, ... of the concatenation, two
         // per pass with both loads issued before either is used
