@@ -136,6 +136,23 @@ def test_water192_pppm(torch_dev, orc):
     compare(g, r, w.system.n, label="water192-pppm")
 
 
+@pytest.mark.parametrize("mesh", [(256, 12, 24), (256, 10, 20), (24, 20, 20), (20, 15, 16)])
+def test_water192_pppm_transform_forms(torch_dev, orc, mesh):
+    """The mesh shapes select the transform: even point counts along b and c take the
+    real-input forward transform and the half spectrum, 256 points along a with c a
+    multiple of 8 also the influence function fused with the inverse pass along a
+    ((256, 12, 24)); (256, 10, 20) the half spectrum without the fusion, (24, 20, 20)
+    the half spectrum with the general FFT kernel, (20, 15, 16) (odd along b) the
+    complex transform of (rho, 0)."""
+    w = inputs.workload(0)
+    es = copy.copy(w.es)
+    es.method, es.mesh, es.order = 1, mesh, 5
+    _say(f"case water-192 PPPM {mesh}")
+    g = run_gpu(w.hp, es, w.system, w.theta)
+    r = _oracle(orc, w.hp, es, w.system, w.theta)
+    compare(g, r, w.system.n, label=f"water192-pppm-{mesh[0]}x{mesh[1]}x{mesh[2]}")
+
+
 def test_water3000_pppm_and_ewald(torch_dev, orc):
     w = inputs.workload(1, "crop")
     _say("case water-3000 PPPM 32^3")
