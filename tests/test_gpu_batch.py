@@ -209,7 +209,7 @@ def test_batch_full_population_and_tuner(torch_dev, orc, wl):
 
 
 # BF16 network on the matrix cores (FP32 accumulation): both forms are held to the
-# spec force bound of 5 meV/A (and the single-structure bounds of the rest)
+# target force bound of 5 meV/A (and the single-structure bounds of the rest)
 TOL_BF16 = {"bf16": dict(e=2e-4, f=5e-3, w=5e-4, q=5e-4), "bf16x3": dict(e=2e-4, f=5e-3, w=5e-4, q=5e-4)}
 
 

@@ -1,7 +1,7 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle, element by
 element, on seeded workloads that span several tiles and ragged tails.
 
-Tolerances for the FP32 path (spec target: forces within 1e-4 eV/A of the
+Tolerances for the FP32 path (target: forces within 1e-4 eV/A of the
 FP64 oracle); the other bounds follow from FP32 rounding of per-atom terms summed
 in FP64:
   energy        |dE| / N        <= 2e-6 eV/atom
@@ -258,7 +258,7 @@ def test_water24000_full(torch_dev, orc):
 
 
 # BF16 network on the matrix cores (FP32 accumulation), both forms held to the
-# spec force target of 5 meV/A.  The forward product splits both operands in
+# target force bound of 5 meV/A.  The forward product splits both operands in
 # both forms, so the energy and the charges keep about 16 mantissa bits (p: that
 # rounding unit in the polarization bound).
 TOL_BF16X3 = dict(e=2e-4, f=5e-3, w=5e-4, q=5e-4, z=5e-3, p=2.0 ** -16)
