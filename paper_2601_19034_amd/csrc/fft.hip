@@ -379,7 +379,7 @@ hipError_t fft3d_bc(float2 *data, const int *mesh, int sign, hipStream_t s, int 
 }
 
 // ---------------------------------------------------------------- real input
-// Forward transform of a real mesh x[j0][j1][j2] (n1 and n2 even).  Lines j1 = 2p and
+// Forward transform of a real mesh x[j0][j1][j2] (n1 even, n2 = 256).  Lines j1 = 2p and
 // 2p + 1 are given as one complex line z_m = x[j0][2p][m] + i x[j0][2p+1][m] (the pair
 // interleaved, complex element (j0 n1 / 2 + p) n2 + m) and transformed together along
 // c; the two real lines' spectra are X_k = (Z_k + conj Z_{-k}) / 2 and
@@ -390,31 +390,11 @@ hipError_t fft3d_bc(float2 *data, const int *mesh, int sign, hipStream_t s, int 
 //   S(k0, k1, k2) = T[k0][k1][k2] for 0 < k2 < H, and with P = T[k0][k1][0],
 //   P' = T[-k0][-k1][0]: S(k0, k1, 0) = (P + conj P') / 2, S(k0, k1, H) = (P - conj P') / 2i.
 // The pair's n2 complex elements are exactly the two half lines, so this is in place.
-__global__ __launch_bounds__(256) void k_r2c_pairs(float2 *__restrict__ data, int n2) {
-    extern __shared__ float2 zl[];
-    const int H = n2 / 2;
-    float2 *line = data + (size_t)blockIdx.x * n2;
-    for (int m = threadIdx.x; m < n2; m += blockDim.x) zl[m] = line[m];
-    __syncthreads();
-    for (int k = threadIdx.x; k < H; k += blockDim.x) {
-        float2 X, Y;
-        if (k == 0) {
-            const float2 z0 = zl[0], zh = zl[H];
-            X = make_float2(z0.x, zh.x);  // X_0 + i X_H
-            Y = make_float2(z0.y, zh.y);  // Y_0 + i Y_H
-        } else {
-            const float2 a = zl[k], b = zl[n2 - k];  // Z_k, Z_{-k}
-            X = make_float2(0.5f * (a.x + b.x), 0.5f * (a.y - b.y));
-            Y = make_float2(0.5f * (a.y + b.y), -0.5f * (a.x - b.x));
-        }
-        line[k] = X;
-        line[H + k] = Y;
-    }
-}
-
-// n2 = 256: the pass along c fused with the pair split -- k_fft256<-1> in mode 0 (16
-// lines per work-group, lane = 16 line + t), then each line's spectrum goes through LDS
-// and is split into the two half spectra as in k_r2c_pairs
+//
+// The pass along c (n2 = 256) and the pair split: k_fft256<-1> in mode 0 (16 lines per
+// work-group, lane = 16 line + t), then each line's spectrum goes through LDS and is
+// split into the two real lines' half spectra, X_k and Y_k for k < 128 (X_0 + i X_128
+// and Y_0 + i Y_128 in slot 0)
 __global__ __launch_bounds__(256) void k_fft256_pairs(float2 *__restrict__ data, int nlines) {
     __shared__ float2 tw[256];
     __shared__ float2 xch[16 * F256_LS];
@@ -455,19 +435,15 @@ __global__ __launch_bounds__(256) void k_fft256_pairs(float2 *__restrict__ data,
     }
 }
 
-bool fft_r2c_supported(const int *mesh) { return mesh[1] % 2 == 0 && mesh[2] % 2 == 0 && mesh[2] >= 2; }
+// Meshes of 256 points along c (even along b) only: there the pass along c and the split
+// are one kernel; with the general kernel the extra launch cost more than the halved
+// bytes saved on 64- and 128-point meshes.
+bool fft_r2c_supported(const int *mesh) { return mesh[1] % 2 == 0 && mesh[2] == 256; }
 
 hipError_t fft3d_r2c(float2 *data, const int *mesh, hipStream_t s) {
-    const int H = mesh[2] / 2, pairs = mesh[0] * (mesh[1] / 2);
-    hipError_t e;
-    if (mesh[2] == 256) {
-        hipLaunchKernelGGL(k_fft256_pairs, dim3((pairs + 15) / 16), dim3(256), 0, s, data, pairs);
-    } else {
-        e = fft_lines(data, mesh[2], 1, pairs, -1, s);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_r2c_pairs, dim3(pairs), dim3(256), sizeof(float2) * (size_t)mesh[2], s, data, mesh[2]);
-    }
-    e = hipGetLastError();
+    const int H = mesh[2] / 2, pairs = mesh[0] * (mesh[1] / 2);  // mesh[2] = 256
+    hipLaunchKernelGGL(k_fft256_pairs, dim3((pairs + 15) / 16), dim3(256), 0, s, data, pairs);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = fft_lines(data, mesh[1], H, mesh[0], -1, s);
     if (e != hipSuccess) return e;

@@ -665,7 +665,7 @@ hipError_t launch_pppm(const Plan &p) {
     const int64_t M = p.mesh_pts;
     const int G = (p.N + 255) / 256;
     const int GM = (int)((M + 255) / 256);
-    // a mesh with even point counts along b and c takes the real-input transform and the
+    // a mesh of 256 points along c (even along b) takes the real-input transform and the
     // half spectrum; otherwise the complex transform of (rho, 0)
     const bool half = fft_r2c_supported(p.mesh);
     hipError_t e;
@@ -701,7 +701,7 @@ hipError_t launch_pppm(const Plan &p) {
     }
     e = half ? fft3d_r2c(p.meshA, p.mesh, p.stream) : fft3d(p.meshA, nullptr, p.mesh, -1, p.stream);
     if (e != hipSuccess) return e;
-    stage_mark(p, ST_FFT_FWD, half && p.mesh[2] != 256 ? 4 : 3);  // real input: c, the pair split, b, a
+    stage_mark(p, ST_FFT_FWD, 3);  // real input: c with the pair split, b, a
     const int rows = p.mesh[0] * p.mesh[1];
     // n0 = 256: the influence function and the first inverse pass (along a) in one kernel
     const bool fused = half && p.mesh[0] == 256 && p.mesh[2] % 8 == 0;

@@ -136,14 +136,13 @@ def test_water192_pppm(torch_dev, orc):
     compare(g, r, w.system.n, label="water192-pppm")
 
 
-@pytest.mark.parametrize("mesh", [(256, 12, 24), (256, 10, 20), (24, 20, 20), (20, 15, 16)])
+@pytest.mark.parametrize("mesh", [(256, 12, 256), (24, 20, 256), (24, 20, 20), (20, 15, 256)])
 def test_water192_pppm_transform_forms(torch_dev, orc, mesh):
-    """The mesh shapes select the transform: even point counts along b and c take the
-    real-input forward transform and the half spectrum, 256 points along a with c a
-    multiple of 8 also the influence function fused with the inverse pass along a
-    ((256, 12, 24)); (256, 10, 20) the half spectrum without the fusion, (24, 20, 20)
-    the half spectrum with the general FFT kernel, (20, 15, 16) (odd along b) the
-    complex transform of (rho, 0)."""
+    """The mesh shapes select the transform: 256 points along c and an even count along
+    b take the real-input forward transform and the half spectrum, with 256 points along
+    a also the influence function fused with the inverse pass along a ((256, 12, 256));
+    (24, 20, 256) the half spectrum without the fusion; (24, 20, 20) and (20, 15, 256)
+    (odd along b) the complex transform of (rho, 0)."""
     w = inputs.workload(0)
     es = copy.copy(w.es)
     es.method, es.mesh, es.order = 1, mesh, 5
@@ -331,24 +330,27 @@ def test_per_atom_virial(torch_dev, orc, case):
         assert np.array_equal(g0[k], g[k]), k
 
 
-@pytest.mark.parametrize("n", [3, 4])
-def test_spread_atomic_fallback(torch_dev, orc, n):
+@pytest.mark.parametrize("mesh", [(3, 3, 3), (4, 2, 256)])
+def test_spread_atomic_fallback(torch_dev, orc, mesh):
     """A mesh so coarse against the bins that a brick's bin rows or segments would not
     fit the per-work-group tables: the charge assignment takes the atomic path (float
     atomics into a real mesh).  Garnet-768 (20.6 A, bins of 3.4 x 3.4 x 1.6 A) with a
-    3^3 mesh: 16 x 16 rows and 32 bins along c per brick, 1024 segments > 512.  The 3^3
-    mesh takes the complex transform of (rho, 0); the 4^3 mesh (even along b and c) the
-    real-input transform, the atomic spread writing its interleaved line pairs."""
+    3^3 mesh: 16 x 16 rows and 32 bins along c per brick, 1024 segments > 512; with
+    (4, 2, 256): 14 x 20 = 280 rows > 256.  The 3^3 mesh takes the complex transform of
+    (rho, 0); (4, 2, 256) the real-input transform, the atomic spread writing its
+    interleaved line pairs."""
     w = inputs.workload(2, "crop")
     es = copy.copy(w.es)
-    es.mesh = (n, n, n)
+    es.mesh = mesh
     nc = [int(np.floor(w.system.cell[a, a] / (3.0 if a < 2 else 1.5))) for a in range(3)]
-    cnt = [int(np.floor((n + 4.02) * nc[a] / n)) + 2 for a in range(3)]
-    assert cnt[0] * cnt[1] * ((cnt[2] - 1) // nc[2] + 2) > 512  # the brick tables do not fit
-    _say(f"case garnet-768 PPPM {n}^3 (atomic charge assignment)")
+    P = [min(16, m) for m in mesh]
+    cnt = [int(np.floor((P[a] + 4.02) * nc[a] / mesh[a])) + 2 for a in range(3)]
+    rows = cnt[0] * cnt[1]
+    assert rows > 256 or rows * ((cnt[2] - 1) // nc[2] + 2) > 512  # the brick tables do not fit
+    _say(f"case garnet-768 PPPM {mesh} (atomic charge assignment)")
     g = run_gpu(w.hp, es, w.system, w.theta)
     r = _oracle(orc, w.hp, es, w.system, w.theta)
-    compare(g, r, w.system.n, label=f"garnet768-pppm{n}-atomic")
+    compare(g, r, w.system.n, label=f"garnet768-pppm{mesh[0]}x{mesh[1]}x{mesh[2]}-atomic")
 
 
 # ------------------------------------------------------------------ isolated systems (Eqs. 26, 27)
