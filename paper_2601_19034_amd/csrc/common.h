@@ -246,8 +246,8 @@ __device__ inline int stencil_segments(const Stencil &st, const Cell &c, const A
 
 // As stencil_segments, for rn <= RPL LANES (a lane takes at most RPL rows): the trimmed
 // range of each row is computed once and kept in registers between the counting pass and
-// the pass that writes the table.  Fewer instructions for more registers: it pays where
-// the caller's register count leaves the occupancy unchanged (the real-space sum).
+// the pass that writes the table.  Fewer instructions for more registers: the callers
+// bound their register count to keep their occupancy (launch bounds).
 template <int LANES, int RPL>
 __device__ inline int stencil_segments_kept(const Stencil &st, const Cell &c, const AtomBin &b, bool live, int sub,
                                        int r0, int rn, const int *__restrict__ start, int2 *seg) {

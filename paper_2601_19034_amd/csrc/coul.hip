@@ -61,7 +61,7 @@ __device__ __forceinline__ void rs_pair(const float4 &pi, const float4 &pj, cons
     acc[9] = fmaf(by, dz, acc[9]);
 }
 
-__global__ __launch_bounds__(256) void k_real_space(int N, const float4 *__restrict__ xyzq, Cell c, Stencil st,
+__global__ __launch_bounds__(256, 7) void k_real_space(int N, const float4 *__restrict__ xyzq, Cell c, Stencil st,
                                                     const int *__restrict__ start, double rc2,
                                                     const float *__restrict__ qraw,
                                                     const double *__restrict__ scalars, float alpha,

@@ -144,7 +144,7 @@ constexpr uint32_t LS_MASK = (1u << LS_LANES) - 1u;  // one lane group in a ball
 constexpr int LS_APB = 256 / LS_LANES;  // atoms per work-group
 constexpr int LS_SEG = 64;              // segments of one atom held in LDS at a time
 
-__global__ __launch_bounds__(256) void k_lists(int N, const float4 *__restrict__ xyzt, Cell c, Stencil st,
+__global__ __launch_bounds__(256, 6) void k_lists(int N, const float4 *__restrict__ xyzt, Cell c, Stencil st,
                                                const int *__restrict__ start, double rc2, int cap,
                                                uint32_t *__restrict__ list, int *__restrict__ cnt, double rs2,
                                                int cap_sub, uint32_t *__restrict__ sub,
@@ -175,8 +175,8 @@ __global__ __launch_bounds__(256) void k_lists(int N, const float4 *__restrict__
     // an atom's segment table is written and read by the atom's own lanes (one wave)
     for (int r0 = 0; r0 < st.nrows; r0 += st.rows_chunk) {
         wave_lds_sync();  // the previous chunk's walk is done with the table
-        const int ns = stencil_segments<LS_LANES>(st, c, ab, live, ln, r0, min(st.rows_chunk, st.nrows - r0),
-                                                  start, seg[a]);
+        const int ns = stencil_segments_kept<LS_LANES, LS_SEG / 2 / LS_LANES>(
+            st, c, ab, live, ln, r0, min(st.rows_chunk, st.nrows - r0), start, seg[a]);
         wave_lds_sync();
         SegWalk wk(seg[a], ns, ln);
         while (wk.valid()) {
