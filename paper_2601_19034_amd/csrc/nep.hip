@@ -517,30 +517,41 @@ __global__ __launch_bounds__(256) void k_angular_forces(
     block_partials<9>(w, partials);
 }
 
-// slot of `want` in atom j's angular list (-1 if absent); rows are 16-byte aligned.
-// The first FS_AHEAD 16-byte groups of the row are loaded together with nj (one
-// round trip covers lists of up to 4 FS_AHEAD entries); longer rows continue in order.
+// The slot of `want` in atom j's angular list (-1 if absent); rows are 16-byte aligned.
+// The first FS_AHEAD 16-byte groups of the row are loaded together with its length (one
+// round trip covers lists of up to 4 FS_AHEAD entries; longer rows continue in order),
+// in a separate step, so that the row of the next pair can be loaded while the current
+// pair's slot is read.
 constexpr int FS_AHEAD = 6;
 
-__device__ inline int find_slot(const uint32_t *__restrict__ listA, const int *__restrict__ cntA, int j, int capA,
-                                uint32_t want) {
+struct RowProbe {
+    uint4 v[FS_AHEAD];
+    int nj;
+};
+
+__device__ inline void probe_load(const uint32_t *__restrict__ listA, const int *__restrict__ cntA, int j, int capA,
+                                  RowProbe &rp) {
     const uint4 *row = reinterpret_cast<const uint4 *>(listA + (size_t)j * capA);
     const int ng = capA / 4 < FS_AHEAD ? capA / 4 : FS_AHEAD;
-    uint4 v[FS_AHEAD];
 #pragma unroll
-    for (int t = 0; t < FS_AHEAD; ++t) v[t] = t < ng ? row[t] : make_uint4(0u, 0u, 0u, 0u);
-    const int nj = cntA[j];
-    // entries at or past nj are stale and must not match
+    for (int t = 0; t < FS_AHEAD; ++t) rp.v[t] = t < ng ? row[t] : make_uint4(0u, 0u, 0u, 0u);
+    rp.nj = cntA[j];
+}
+
+__device__ inline int probe_match(const uint32_t *__restrict__ listA, int j, int capA, const RowProbe &rp,
+                                  uint32_t want) {
+    const int ng = capA / 4 < FS_AHEAD ? capA / 4 : FS_AHEAD, nj = rp.nj;
 #pragma unroll
     for (int t = 0; t < FS_AHEAD; ++t) {
         const int b = 4 * t;
         if (t < ng) {
-            if (v[t].x == want && b < nj) return b;
-            if (v[t].y == want && b + 1 < nj) return b + 1;
-            if (v[t].z == want && b + 2 < nj) return b + 2;
-            if (v[t].w == want && b + 3 < nj) return b + 3;
+            if (rp.v[t].x == want && b < nj) return b;
+            if (rp.v[t].y == want && b + 1 < nj) return b + 1;
+            if (rp.v[t].z == want && b + 2 < nj) return b + 2;
+            if (rp.v[t].w == want && b + 3 < nj) return b + 3;
         }
     }
+    const uint4 *row = reinterpret_cast<const uint4 *>(listA + (size_t)j * capA);
     for (int t4 = ng; 4 * t4 < nj; ++t4) {
         const uint4 u = row[t4];
         const int b = 4 * t4;
@@ -593,15 +604,26 @@ __global__ __launch_bounds__(256) void k_assemble(
         const float4 pi = xyzt[i];
         const int nA = cntA[i];
         const uint32_t *lrow = listA + (size_t)i * capA;
-        uint32_t e_next = sub < nA ? lrow[sub] : 0u;  // the next entry is loaded one pass ahead
+        // list entries two passes ahead, the start of the neighbour's row one pass ahead
+        uint32_t e_next = sub < nA ? lrow[sub] : 0u, e_nn = sub + AS_LANES < nA ? lrow[sub + AS_LANES] : 0u;
+        RowProbe rp_next;
+        if (sub < nA) probe_load(listA, cntA, nb_index(e_next), capA, rp_next);
         for (int sl = sub; sl < nA; sl += AS_LANES) {
             const uint32_t e = e_next;
-            if (sl + AS_LANES < nA) e_next = lrow[sl + AS_LANES];
+            const RowProbe rp = rp_next;
             const int j = nb_index(e);
-            const int found = find_slot(listA, cntA, j, capA, nb_reverse(e, i));
+            const int found = probe_match(listA, j, capA, rp, nb_reverse(e, i));
+            float4 fji = make_float4(0.f, 0.f, 0.f, 0.f), aji = fji;
+            if (found >= 0) {
+                fji = pairFA[((size_t)j * capA + found) * 2];
+                aji = pairFA[((size_t)j * capA + found) * 2 + 1];
+            }
+            if (sl + AS_LANES < nA) {
+                e_next = e_nn;
+                probe_load(listA, cntA, nb_index(e_next), capA, rp_next);
+            }
+            if (sl + 2 * AS_LANES < nA) e_nn = lrow[sl + 2 * AS_LANES];
             if (found < 0) continue;  // pair at the cutoff on one side only: contributes zero
-            const float4 fji = pairFA[((size_t)j * capA + found) * 2];
-            const float4 aji = pairFA[((size_t)j * capA + found) * 2 + 1];
             acc[0] -= fji.x;
             acc[1] -= fji.y;
             acc[2] -= fji.z;
