@@ -326,7 +326,7 @@ def main():
                     help="run three 1 GiB device copies first (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "one structure is evaluated on one GPU in this build; run with --gpus 1"}))
+        print(json.dumps({"error": "the library evaluates one structure on one GPU; run with --gpus 1"}))
         sys.exit(2)
 
     import torch
